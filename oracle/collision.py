@@ -1,0 +1,191 @@
+"""Node-versus-triangle contact detection (oracle, brute force, FP64).  TEST INFRASTRUCTURE ONLY.
+
+Sec. III-C matches every robot node against every triangle of the cavity mesh
+and builds, for each detected contact, the constraint of eq. 3: with the wall
+normal n_i oriented away from the robot and a point X_I of the triangle's plane,
+the node must stay on the robot's side of that plane.  Stacking the contacts
+gives the rows A_c and the gaps b_c of eq. 8-10.
+
+Reading of the unstated detection rule (the GPU path implements the same rule):
+* triangle normal n_t = unit((v1 - v0) x (v2 - v0)) points into the lumen, so
+  the paper's n_i is -n_t; signed wall distance s = n_t . (p - v0); the
+  closest point c of the triangle to the node and its Voronoi region (face,
+  edge or vertex) follow Ericson 2005, Real-Time Collision Detection, Sec. 5.1.5;
+* face contacts: every triangle whose closest point lies in its face region
+  and with -r_c <= s <= r_c + delta (r_c = robot radius, delta = detection
+  margin).  A node may carry several: near a concave facet edge a single
+  constraint would let the node slide along one plane into its neighbour's
+  half-space and the Newton iterates would cycle.  Row: n_t on the node's
+  translations (the node-only case of the shape functions of eq. 4-6); gap
+  g = s - r_c (b_c, eq. 10);
+* edge/vertex fallback: a node with no face contact that lies in front of a
+  triangle (s > 0) within r_c + delta of its closest edge or vertex point gets
+  one contact, the nearest such point (ties to the lowest triangle index),
+  with normal (p - c)/|p - c| and gap |p - c| - r_c.  Without it a node whose
+  centre sits r_c off a convex ridge of the wall lies in neither face region
+  and slips through the wedge between them;
+* the clamped base node and nodes held by the insertion guide are never
+  contact nodes.  Contacts are ordered by node, then triangle index.
+"""
+from __future__ import annotations
+
+import numpy as np
+from scipy.spatial import cKDTree
+
+AMBIG_TOL = 1e-9   # metres: decisions closer than this to a threshold are flagged
+
+
+class Mesh:
+    """Triangle soup with per-triangle planes and altitudes (precomputed once)."""
+
+    def __init__(self, verts, tris):
+        self.V = np.asarray(verts, float)
+        self.T = np.asarray(tris, np.int64)
+        self.v0 = self.V[self.T[:, 0]]
+        self.v1 = self.V[self.T[:, 1]]
+        self.v2 = self.V[self.T[:, 2]]
+        nrm = np.cross(self.v1 - self.v0, self.v2 - self.v0)
+        area2 = np.linalg.norm(nrm, axis=1)
+        self.n = nrm / area2[:, None]
+        # altitude from each vertex to its opposite edge, for barycentric -> metres
+        e_opp = [np.linalg.norm(self.v2 - self.v1, axis=1),
+                 np.linalg.norm(self.v2 - self.v0, axis=1),
+                 np.linalg.norm(self.v1 - self.v0, axis=1)]
+        self.alt = np.stack([area2 / e for e in e_opp], axis=1)
+        cen = (self.v0 + self.v1 + self.v2) / 3.0
+        self.centroid = cen
+        self.circum = np.max(np.stack([np.linalg.norm(self.v0 - cen, axis=1),
+                                       np.linalg.norm(self.v1 - cen, axis=1),
+                                       np.linalg.norm(self.v2 - cen, axis=1)], 1), axis=1)
+        self._tree = None
+
+    @property
+    def tree(self):
+        if self._tree is None:
+            self._tree = cKDTree(self.centroid)
+        return self._tree
+
+
+FACE, EDGE_AB, EDGE_AC, EDGE_BC, VERT_A, VERT_B, VERT_C = range(7)
+
+
+def closest_points(p, mesh, idx):
+    """Closest point of each triangle idx to p, its Voronoi region, and the smallest
+    distance (m) of p's classification quantities to a region boundary."""
+    a, b, c = mesh.v0[idx], mesh.v1[idx], mesh.v2[idx]
+    ab = b - a
+    ac = c - a
+    bc = c - b
+    lab = np.linalg.norm(ab, axis=1)
+    lac = np.linalg.norm(ac, axis=1)
+    lbc = np.linalg.norm(bc, axis=1)
+    dot = lambda u, v: np.einsum("ij,ij->i", u, v)
+    ap = p[None, :] - a
+    bp = p[None, :] - b
+    cp = p[None, :] - c
+    d1, d2 = dot(ab, ap), dot(ac, ap)
+    d3, d4 = dot(ab, bp), dot(ac, bp)
+    d5, d6 = dot(ab, cp), dot(ac, cp)
+    va = d3 * d6 - d5 * d4
+    vb = d5 * d2 - d1 * d6
+    vc = d1 * d4 - d3 * d2
+    n = len(idx)
+    region = np.full(n, FACE)
+    cpt = np.empty((n, 3))
+    done = np.zeros(n, bool)
+
+    def take(mask, reg, pts):
+        m = mask & ~done
+        region[m] = reg
+        cpt[m] = pts[m]
+        done[m] = True
+
+    take((d1 <= 0) & (d2 <= 0), VERT_A, a)
+    take((d3 >= 0) & (d4 <= d3), VERT_B, b)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        v = d1 / (d1 - d3)
+        take((vc <= 0) & (d1 >= 0) & (d3 <= 0), EDGE_AB, a + v[:, None] * ab)
+        take((d6 >= 0) & (d5 <= d6), VERT_C, c)
+        w = d2 / (d2 - d6)
+        take((vb <= 0) & (d2 >= 0) & (d6 <= 0), EDGE_AC, a + w[:, None] * ac)
+        w2 = (d4 - d3) / ((d4 - d3) + (d5 - d6))
+        take((va <= 0) & ((d4 - d3) >= 0) & ((d5 - d6) >= 0), EDGE_BC, b + w2[:, None] * bc)
+        den = 1.0 / (va + vb + vc)
+        vf = (vb * den)[:, None]
+        wf = (vc * den)[:, None]
+        take(np.ones(n, bool), FACE, a + ab * vf + ac * wf)
+        area2 = np.linalg.norm(np.cross(ab, ac), axis=1)
+        margin = np.min(np.abs(np.stack([
+            d1 / lab, d2 / lac, d3 / lab, (d4 - d3) / lbc, d6 / lac, (d5 - d6) / lbc,
+            va / (area2 * lbc), vb / (area2 * lac), vc / (area2 * lab)])), axis=0)
+    return cpt, region, margin
+
+
+def detect(P, mesh, r_c, delta, cull=True, first_node=1, skip=None):
+    """Contacts of one robot: list of dicts (node, tri, kind, n, gap, ambiguous).
+
+    kind is 0 for a face contact and 1 for the edge/vertex fallback.  Brute force
+    over all triangles, or over the k-d-tree superset of triangles whose
+    circumscribing ball can reach the detection band when cull=True (same result).
+    A node whose decisions lie within AMBIG_TOL metres of a threshold gets
+    ambiguous=True on its entries (and an entry with tri=-1 if it has none).
+    """
+    out = []
+    band = r_c + delta
+    reach = band + float(np.max(mesh.circum)) + 1e-6
+    for i in range(first_node, P.shape[0]):
+        if skip is not None and skip[i]:
+            continue
+        p = P[i]
+        if cull:
+            idx = np.asarray(mesh.tree.query_ball_point(p, reach), dtype=np.int64)
+            idx.sort()
+        else:
+            idx = np.arange(mesh.T.shape[0])
+        if idx.size == 0:
+            continue
+        s = np.einsum("ij,ij->i", mesh.n[idx], p[None, :] - mesh.v0[idx])
+        cpt, region, margin = closest_points(p, mesh, idx)
+        dist = np.linalg.norm(p[None, :] - cpt, axis=1)
+        face = (region == FACE) & (s >= -r_c) & (s <= band)
+        # decisions within AMBIG_TOL of a threshold, for triangles that can matter
+        near = (dist <= band + AMBIG_TOL) & (s >= -r_c - AMBIG_TOL)
+        amb = bool(np.any(near & (margin <= AMBIG_TOL)))
+        amb |= bool(np.any((region == FACE) & ((np.abs(s + r_c) <= AMBIG_TOL)
+                                               | (np.abs(s - band) <= AMBIG_TOL))))
+        node_out = []
+        for k in np.nonzero(face)[0]:
+            t = int(idx[k])
+            node_out.append(dict(node=i, tri=t, kind=0, n=mesh.n[t].copy(),
+                                 gap=float(s[k] - r_c)))
+        if not node_out:
+            feat = (region != FACE) & (s > 0.0) & (dist <= band)
+            amb |= bool(np.any((region != FACE) & (np.abs(dist - band) <= AMBIG_TOL)))
+            amb |= bool(np.any((region != FACE) & (np.abs(s) <= AMBIG_TOL) & (dist <= band)))
+            if np.any(feat):
+                ks = np.nonzero(feat)[0]
+                order = np.lexsort((idx[ks], dist[ks]))
+                k = ks[order[0]]
+                if order.size > 1:
+                    k2 = ks[order[1]]
+                    if (abs(dist[k2] - dist[k]) <= AMBIG_TOL
+                            and np.linalg.norm(cpt[k2] - cpt[k]) > AMBIG_TOL):
+                        amb = True
+                t = int(idx[k])
+                node_out.append(dict(node=i, tri=t, kind=1, n=(p - cpt[k]) / dist[k],
+                                     gap=float(dist[k] - r_c)))
+        for c in node_out:
+            c["ambiguous"] = amb
+        if not node_out and amb:
+            node_out.append(dict(node=i, tri=-1, kind=-1, n=None, gap=np.nan, ambiguous=True))
+        out.extend(node_out)
+    return out
+
+
+def contact_set(contacts):
+    """The (node, triangle, kind) keys of the detected contacts (ambiguous misses dropped)."""
+    return tuple((c["node"], c["tri"], c["kind"]) for c in contacts if c["tri"] >= 0)
+
+
+def active(contacts):
+    return [c for c in contacts if c["tri"] >= 0]

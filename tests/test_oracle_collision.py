@@ -1,0 +1,85 @@
+"""Pins of the oracle's contact detection: hand-computed triangles, a faceted tube,
+brute force against a dense-sampling closest point, and culled against unculled."""
+import numpy as np
+import pytest
+
+from oracle import collision
+from workloads import straight_cylinder_mesh, make_config
+
+
+def one_triangle():
+    V = np.array([[0, 0, 0], [0.01, 0, 0], [0, 0.01, 0]], float)
+    T = np.array([[0, 1, 2]])
+    return collision.Mesh(V, T)          # normal +z
+
+
+def test_single_triangle_face_contact_by_hand():
+    m = one_triangle()
+    assert np.allclose(m.n[0], [0, 0, 1])
+    P = np.array([[0, 0, -1.0], [0.002, 0.003, 0.0021]])
+    c = collision.detect(P, m, r_c=1.5e-3, delta=1e-3)
+    assert len(c) == 1 and c[0]["node"] == 1 and c[0]["tri"] == 0 and c[0]["kind"] == 0
+    assert c[0]["gap"] == pytest.approx(0.0021 - 1.5e-3, abs=1e-18)
+    assert np.allclose(c[0]["n"], [0, 0, 1])
+    # outside the band (s > r_c + delta) and behind it (s < -r_c): nothing
+    for z in (2.6e-3, -1.6e-3):
+        assert collision.detect(np.array([[0, 0, -1.0], [0.002, 0.003, z]]), m, 1.5e-3, 1e-3) == []
+
+
+def test_single_triangle_edge_and_vertex_fallback_by_hand():
+    m = one_triangle()
+    # beyond edge AB (y < 0), in front of the plane: closest point on the edge
+    p = np.array([0.004, -0.001, 0.0015])
+    c = collision.detect(np.array([[0, 0, -1.0], p]), m, 1.5e-3, 1e-3)
+    assert len(c) == 1 and c[0]["kind"] == 1
+    d = np.hypot(0.001, 0.0015)
+    assert c[0]["gap"] == pytest.approx(d - 1.5e-3, abs=1e-18)
+    assert np.allclose(c[0]["n"], np.array([0, -0.001, 0.0015]) / d)
+    # beyond vertex A: closest point is the vertex
+    p = np.array([-0.001, -0.001, 0.001])
+    c = collision.detect(np.array([[0, 0, -1.0], p]), m, 1.5e-3, 1e-3)
+    assert len(c) == 1 and c[0]["kind"] == 1
+    assert c[0]["gap"] == pytest.approx(np.linalg.norm(p) - 1.5e-3, abs=1e-18)
+
+
+def test_closest_point_regions_against_dense_sampling():
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        V = rng.normal(size=(3, 3)) * 0.01
+        m = collision.Mesh(V, np.array([[0, 1, 2]]))
+        p = rng.normal(size=3) * 0.01
+        cpt, region, _ = collision.closest_points(p, m, np.array([0]))
+        u, v = np.meshgrid(np.linspace(0, 1, 401), np.linspace(0, 1, 401))
+        ok = u + v <= 1
+        S = V[0] + u[ok, None] * (V[1] - V[0]) + v[ok, None] * (V[2] - V[0])
+        dmin = np.min(np.linalg.norm(S - p, axis=1))
+        d = np.linalg.norm(cpt[0] - p)
+        assert d <= dmin + 1e-12
+        assert d >= dmin - 3e-4 * np.max(np.linalg.norm(V - V.mean(0), axis=1))
+
+
+def test_sixteen_gon_tube_facet_distance():
+    """Straight 16-gon tube of vertex radius 4 mm: facet planes at 4 cos(pi/16) = 3.9231 mm."""
+    V, T = straight_cylinder_mesh(radius=4e-3, axis_xy=(0.0, 0.0))
+    m = collision.Mesh(V, T)
+    ang = np.pi / 16        # mid-facet direction of facet 0
+    for off in (1.5e-3, 2.0e-3, 2.4e-3):
+        p = np.array([off * np.cos(ang), off * np.sin(ang), 0.1])
+        c = collision.detect(np.array([[0, 0, 0], p]), m, 1.5e-3, 1e-3)
+        gaps = sorted(ct["gap"] for ct in c)
+        assert len(c) >= 1
+        assert gaps[0] == pytest.approx(4e-3 * np.cos(np.pi / 16) - off - 1.5e-3, abs=1e-15)
+
+
+def test_culled_equals_brute_force_on_branching_mesh():
+    rb, V, T = make_config(1)
+    m = collision.Mesh(V, T)
+    rng = np.random.default_rng(11)
+    # points near the wall: mesh vertices pushed inward along random directions
+    vid = rng.choice(len(V), size=60, replace=False)
+    cen = m.centroid[rng.choice(len(T), size=60, replace=False)]
+    P = np.concatenate([[[0, 0, -1.0]], V[vid] * 0.9 + 0.1 * cen], axis=0)
+    a = collision.detect(P, m, 1.5e-3, 1e-3, cull=True)
+    b = collision.detect(P, m, 1.5e-3, 1e-3, cull=False)
+    assert collision.contact_set(a) == collision.contact_set(b)
+    assert len(collision.contact_set(a)) > 10
