@@ -1,0 +1,181 @@
+"""Benchmark: batched contact-FEM solves per second on one MI355X.
+
+Workload (the batched configuration): 4096 robots with 50..400 elements
+(L = 0.6 m, stiff shaft + 70 mm tube tip), tensions U(0,3) N ramped over 10
+load steps and insertion depths U(0.1,0.5) m over 100 load steps, sharing one
+50k-triangle branching lumen.  One bench step = the whole quasi-static
+insertion (all load steps) of the whole batch from the straight reference
+state, inputs resident on the GPU.  A solve = one converged load step of one
+robot; value = converged solves / wall time of the timed steps.
+
+Prints one JSON line (see --help).  Extra fields: per-kernel HIP-event times,
+the roofline of the dominant kernel, the FP64 oracle timed on the host on a
+bounded sample, and the plain FP64 single-robot GPU path on a sample of the
+same robots (the configuration-0 design run one robot at a time).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "contact-FEM solves/sec, batched+mixed vs plain FP64 at 1e-5 rel tip error"
+HBM_PEAK_GBS = 8000.0
+# algorithmic HBM bytes per node of one element-update launch (FP64): read the node
+# state (7 doubles), write F (6), the symmetric diagonal block (21) and the coupling block (36)
+ELEM_BYTES_PER_NODE = 8 * (7 + 6 + 21 + 36)
+
+
+def run_schedule(ctx, rb, n_load_steps, X0):
+    from workloads import load_schedule
+    ctx.fem_set_state(X0)
+    for k in range(1, n_load_steps + 1):
+        d, t = load_schedule(rb, k)
+        ctx.fem_set_actuation(0, t.ravel(), d)
+        ctx.fem_solve(1, state=False, info=False)
+
+
+def solves_of(ctx):
+    out = ctx.fem_solve(0, state=False, info=True)
+    info = out["info"]
+    return (sum(i["steps_converged"] for i in info), sum(i["steps_total"] for i in info),
+            sum(i["iters_total"] for i in info), info)
+
+
+def cpu_baseline(rb, V, T, n_robots, n_steps):
+    """The FP64 oracle on a bounded sample: n_robots robots x n_steps load steps."""
+    from oracle import solver, collision
+    from workloads import load_schedule
+    try:
+        from threadpoolctl import threadpool_limits
+        lim = threadpool_limits(1)
+    except Exception:
+        lim = None
+    mesh = collision.Mesh(V, T)
+    sub = rb.subset(np.arange(n_robots))
+    robs = solver.robots_from_batch(sub, mesh)
+    t0 = time.perf_counter()
+    conv = 0
+    for b, rob in enumerate(robs):
+        sched = lambda k, b=b: (lambda d, t: (d[b], t[b]))(*load_schedule(sub, k))
+        _, _, traj = solver.solve_robot(rob, sched, n_steps, tol=1e-10, stag_tol=1e-9, max_iter=100)
+        conv += sum(1 for s in traj if s["info"]["status"] == solver.OK)
+    dt = time.perf_counter() - t0
+    return dict(value=conv / dt, unit="solves/s", cores=1, kind="oracle",
+                sample=f"{n_robots} robots x {n_steps} load steps of the batched workload "
+                       f"({conv} converged solves in {dt:.1f} s, 1 BLAS thread)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--robots", type=int, default=4096)
+    ap.add_argument("--load-steps", type=int, default=100)
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--max-newton", type=int, default=60)
+    ap.add_argument("--capacity", type=int, default=64)
+    ap.add_argument("--cpu-robots", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--single-robots", type=int, default=4)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-single", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (robots are "
+              "independent: a multi-GPU run would shard the batch, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2503_06922_amd import fem
+    from workloads import make_config
+
+    rb_all, V, T = make_config(3)
+    rb = rb_all.subset(np.arange(args.robots)) if args.robots < rb_all.n_robots else rb_all
+    prec = fem.FEM_MIXED if args.precision == "mixed" else fem.FEM_FP64
+    ctx = fem.Context(fem.params_from_batch(rb, precision=prec, newton_tol=1e-10, stag_tol=1e-9,
+                                            max_newton=args.max_newton,
+                                            contact_capacity=args.capacity, profile=1))
+    ctx.fem_set_lumen(V, T)
+    ctx.fem_set_actuation(0, np.zeros(3 * rb.n_robots), np.zeros(rb.n_robots))
+    X0 = ctx.fem_get_state()
+
+    for _ in range(args.warmup):
+        run_schedule(ctx, rb, args.load_steps, X0)
+    for k in range(3):
+        ctx.fem_profile(k, reset=True)
+    # timed region: whole-batch insertions; each fem_solve returns after its stream synchronises
+    ctx.fem_set_state(X0)  # resets the per-robot counters
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run_schedule(ctx, rb, args.load_steps, X0)
+    dt = time.perf_counter() - t0
+    prof = [ctx.fem_profile(k) for k in range(3)]
+    # counters cover the last schedule only (fem_set_state resets them): scale to all steps
+    conv, total, iters, info = solves_of(ctx)
+    solves = conv * args.steps
+    value = solves / dt
+    node_launches = sum((i["iters_total"] + i["steps_total"]) * (int(rb.n_elem[b]) + 1)
+                        for b, i in enumerate(info)) * args.steps
+    names = ["elem_kernel", "collide_kernel", "solve_kernel"]
+    kern = {names[k]: dict(total_ms=prof[k][0], launches=prof[k][1],
+                           avg_us=1e3 * prof[k][0] / max(prof[k][1], 1)) for k in range(3)}
+    dom = max(range(3), key=lambda k: prof[k][0])
+    # roofline of the element update (HBM-bound by design): algorithmic bytes per launch
+    el_launches = max(prof[0][1], 1)
+    avg_nodes = node_launches / el_launches
+    el_avg_s = prof[0][0] / 1e3 / el_launches
+    el_gbs = ELEM_BYTES_PER_NODE * avg_nodes / el_avg_s / 1e9
+    roof = dict(bound="hbm", kernel="elem_kernel", achieved=el_gbs, peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=el_gbs / HBM_PEAK_GBS, traffic=None,
+                bytes_per_node=ELEM_BYTES_PER_NODE, avg_active_nodes=avg_nodes)
+
+    res = {
+        "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 tangent+screen / f64" if prec == fem.FEM_MIXED else "f64",
+        "data": "synthetic",
+        "config": {"workload": "batched insertion: %d robots x %d load steps, 50-400 elements, "
+                               "50k-triangle branching lumen" % (rb.n_robots, args.load_steps),
+                   "robots": int(rb.n_robots), "load_steps": args.load_steps,
+                   "precision": args.precision, "max_newton": args.max_newton,
+                   "nodes": int(ctx.n_nodes)},
+        "converged_fraction": conv / max(total, 1),
+        "newton_iters_per_solve": iters / max(total, 1),
+        "kernels": kern, "dominant_kernel": names[dom],
+        "roofline": roof,
+    }
+    if not args.no_single:
+        # plain FP64 path of configuration 0: one robot per context, run one after another
+        t_single = 0.0
+        conv_single = 0
+        for b in range(args.single_robots):
+            sub = rb.subset([b])
+            c1 = fem.Context(fem.params_from_batch(sub, precision=fem.FEM_FP64, newton_tol=1e-10,
+                                                   stag_tol=1e-9, max_newton=args.max_newton,
+                                                   contact_capacity=args.capacity))
+            c1.fem_set_lumen(V, T)
+            c1.fem_set_actuation(0, np.zeros(3), np.zeros(1))
+            X1 = c1.fem_get_state()
+            t1 = time.perf_counter()
+            run_schedule(c1, sub, args.load_steps, X1)
+            t_single += time.perf_counter() - t1
+            conv_single += solves_of(c1)[0]
+            c1.close()
+        res["fp64_single_solves_per_s"] = conv_single / t_single
+        res["ratio_vs_fp64_single"] = value / res["fp64_single_solves_per_s"]
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(rb, V, T, args.cpu_robots, args.cpu_steps)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,184 @@
+/*
+ * accfem.h - C ABI of the MI355X (gfx950) contact-FEM library.
+ *
+ * The library solves the quasi-static equilibrium of cable-driven continuum
+ * robots discretised into co-rotational beam elements (Sec. II-B, eq. 1) under
+ * cable actuation carried to the tip (Sec. II-E, eq. 16-18), a clamped and
+ * inserted base (fixed-node constraints, eq. 14-15) and frictionless contacts
+ * with a triangulated lumen wall (Sec. II-C, eq. 3-13).  Every load step runs a
+ * Newton iteration whose linear steps are the quadratic programs of eq. 23,
+ * solved exactly with a block-tridiagonal Cholesky factorisation, a
+ * contact-space Schur complement and a finite active-set method, followed by
+ * the step-size limit of eq. 25-27.  Many independent robots ("a batch")
+ * are solved together on one GPU.
+ *
+ * Conventions
+ *  - Units are SI.  Nodes of robot b are numbered 0..n_elem[b] from the base;
+ *    node state arrays concatenate robots in order, 7 doubles per node:
+ *    (px, py, pz, qw, qx, qy, qz) = position and unit quaternion of the node
+ *    triad (columns: tangent, section y, section z).
+ *  - Ownership: the caller owns every array.  Inputs are copied during the
+ *    call; nothing is retained.  Outputs are written into caller buffers.
+ *    When fem_params.io_on_device is 1, every array argument of the calls
+ *    below is a device pointer on the context's device; otherwise host memory.
+ *  - A context is not thread-safe.  Separate contexts are independent.
+ *  - Errors: a negative fem_status and a message from fem_last_error().
+ *    Invalid sizes, NULL pointers or non-positive material give FEM_E_INVAL
+ *    and leave the context unchanged.
+ */
+#ifndef ACCFEM_H
+#define ACCFEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fem_ctx fem_ctx;
+
+typedef enum {
+  FEM_OK = 0,
+  FEM_E_INVAL = -1,    /* bad argument */
+  FEM_E_NOMEM = -2,    /* device allocation failed */
+  FEM_E_HIP = -3,      /* HIP runtime error */
+  FEM_E_STATE = -4,    /* call out of order (lumen / actuation not set) */
+  FEM_E_NOCONV = -5    /* results written, some robots did not converge: see info */
+} fem_status;
+
+typedef enum { FEM_FP64 = 0, FEM_MIXED = 1 } fem_precision;
+
+/* Actuation kinds (eq. 16-18).  CABLES: values[b*n_cables + j] = tension T_j (N)
+ * of cable j, attached at radius cable_radius and angle cable_angle[j] in the
+ * tip section; the tip node receives the follower moment sum_j d_j x F_j with
+ * F_j = -T_j e_x (the pull is carried inside the cable-tube pair, so it adds no
+ * net axial force).  TIP_WRENCH_LOCAL: values[b*6..] = (F, M) in the tip frame
+ * (follower).  TIP_WRENCH_GLOBAL: values[b*6..] = (F, M) in global axes. */
+typedef enum {
+  FEM_ACT_CABLES = 0,
+  FEM_ACT_TIP_WRENCH_LOCAL = 1,
+  FEM_ACT_TIP_WRENCH_GLOBAL = 2
+} fem_act_kind;
+
+/* Per-robot status in fem_solve_info.status */
+enum {
+  FEM_ROBOT_OK = 0,        /* last load step converged */
+  FEM_ROBOT_NOCONV = 1,    /* max_newton iterations without convergence */
+  FEM_ROBOT_LCPFAIL = 2,   /* the contact active-set method did not terminate */
+  FEM_ROBOT_NONSPD = 3,    /* a Cholesky pivot was not positive */
+  FEM_ROBOT_OVERFLOW = 4   /* more contacts than contact_capacity */
+};
+
+typedef struct {
+  int32_t n_robots;           /* B >= 1 */
+  const int32_t* n_elem;      /* [B] elements per robot, >= 1 (host) */
+  const double* length;       /* [B] centreline length (host) */
+  const double* base_pos;     /* [B*3] base node position before insertion (host) */
+  const double* base_dir;     /* [B*3] centreline direction at the base (host) */
+  const double* base_up;      /* [B*3] section y-axis at the base, not parallel to base_dir (host) */
+  double r_out, r_in, E, nu;  /* tube section and material */
+  double tip_len;             /* > 0: only the distal tip_len uses (r_out, r_in, E); */
+  double shaft_E, shaft_A, shaft_I; /* elements proximal to it use this shaft */
+  int32_t n_cables;           /* 1..8 */
+  double cable_radius;        /* r of the cable attachment in the tip section */
+  const double* cable_angle;  /* [n_cables] angles in the tip section (host) */
+  double contact_radius;      /* r_c: robot radius offset of the wall constraint */
+  double contact_margin;      /* delta: detection band beyond r_c */
+  double beta0;               /* step-size limit (max node translation per step) */
+  double guide_len;           /* straight insertion guide from the initial base; 0 = none.
+                                 Requires base_dir along a coordinate axis. */
+  double newton_tol;          /* residual 2-norm over free DOFs (N, N m) */
+  double stag_tol;            /* accept a stagnating residual below this */
+  int32_t max_newton;         /* Newton iterations per load step */
+  int32_t contact_capacity;   /* max contacts per robot (<= 256) */
+  double grid_cell;           /* uniform-grid cell size for the lumen, 0 = automatic */
+  fem_precision precision;    /* FEM_FP64 or FEM_MIXED */
+  void* hip_stream;           /* hipStream_t to run on, or NULL for the null stream */
+  int32_t io_on_device;       /* 1: array arguments of later calls are device pointers */
+  int32_t profile;            /* 1: time every kernel launch with HIP events (fem_profile) */
+} fem_params;
+
+typedef struct {
+  int32_t status;           /* FEM_ROBOT_* of the last load step */
+  int32_t iters;            /* Newton iterations of the last load step */
+  int32_t n_contacts;       /* contacts of the last iterate */
+  int32_t n_limited;        /* step-limited iterations in the last load step */
+  double res_norm;          /* residual norm at the last check */
+  int32_t steps_converged;  /* converged load steps since fem_create / fem_set_state */
+  int32_t steps_total;      /* load steps since fem_create / fem_set_state */
+  int64_t iters_total;      /* Newton iterations since fem_create / fem_set_state */
+} fem_solve_info;
+
+typedef struct {
+  int32_t robot, node, tri; /* node index within its robot; triangle index of the lumen */
+  int32_t kind;             /* 0 = face contact, 1 = edge/vertex contact */
+  double n[3];              /* unit normal pointing from the wall into the lumen */
+  double gap;               /* gap at the last iterate (m) */
+  double force;             /* contact force magnitude y >= 0 (N) of the last linear step */
+} fem_contact;
+
+/* Create a context for a batch of robots; allocates device memory for all of
+ * them and places every robot in its straight reference configuration (S_0). */
+fem_status fem_create(const fem_params* p, fem_ctx** out);
+
+/* Free the context and all its device memory.  NULL is ignored. */
+void fem_destroy(fem_ctx* c);
+
+/* Message of the last error on this context (static storage while c lives). */
+const char* fem_last_error(const fem_ctx* c);
+
+/* Upload the lumen mesh (Sec. II-C): verts [n_verts*3], tris [n_tris*3] with
+ * winding (v1-v0)x(v2-v0) pointing into the lumen.  Builds the triangle planes
+ * and the uniform grid used by contact detection.  n_tris may be 0 (no wall). */
+fem_status fem_set_lumen(fem_ctx* c, const double* verts, int64_t n_verts,
+                         const int32_t* tris, int64_t n_tris);
+
+/* Set the actuation and insertion depth reached at the end of the next
+ * fem_solve call.  values: [B*n_cables] (CABLES) or [B*6] (tip wrench kinds);
+ * insertion_depth: [B] or NULL (= 0).  The kind must not change between calls. */
+fem_status fem_set_actuation(fem_ctx* c, fem_act_kind kind, const double* values,
+                             const double* insertion_depth);
+
+/* Run n_load_steps quasi-static load steps.  Load step j applies
+ * prev + (target - prev) * j / n_load_steps of the actuation and depth, where
+ * prev is what the previous call reached (0 initially) and target the values
+ * of fem_set_actuation.  Each load step starts from the previous state.
+ * node_state [total_nodes*7] and info [B] may be NULL.  Returns FEM_E_NOCONV
+ * if any robot's last load step did not converge (outputs still written). */
+fem_status fem_solve(fem_ctx* c, int32_t n_load_steps, double* node_state,
+                     fem_solve_info* info);
+
+/* Contacts of the last iterate of robot `robot` (-1 = all robots, in order).
+ * Writes min(total, capacity) entries; *n_out = total even if larger. */
+fem_status fem_contacts(const fem_ctx* c, int32_t robot, fem_contact* out,
+                        int32_t capacity, int32_t* n_out);
+
+/* Copy the node state [total_nodes*7] out of / into the context.  fem_set_state
+ * also resets the per-robot statistics; quaternions are renormalised. */
+fem_status fem_get_state(const fem_ctx* c, double* node_state);
+fem_status fem_set_state(fem_ctx* c, const double* node_state);
+
+/* Evaluate the element update and contact detection at the current state under
+ * the actuation and depth set by the last fem_set_actuation (no Newton step):
+ * F [total_nodes*6] = internal force minus actuation per node, KD and KS
+ * [total_nodes*36] = row-major 6x6 diagonal block of each node and its
+ * coupling block K[i, i+1] of the QP tangent (eq. 20-23).  Any output may be
+ * NULL.  Afterwards fem_contacts returns the detected contacts (force 0).
+ * Intended for verification of the element and detection kernels. */
+fem_status fem_eval(fem_ctx* c, double* F, double* KD, double* KS);
+
+/* Kernel timing of a context created with profile = 1: for kernel class k
+ * (0 = element update, 1 = contact detection, 2 = Newton step / solve) the
+ * accumulated device time in ms measured with HIP events on the context's
+ * stream, and the number of launches, since the last call with reset = 1. */
+fem_status fem_profile(fem_ctx* c, int32_t kernel, double* total_ms, int64_t* launches,
+                       int32_t reset);
+
+/* Total number of nodes over the batch (sum of n_elem + 1), or -1 for NULL. */
+int64_t fem_total_nodes(const fem_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ACCFEM_H */

@@ -225,12 +225,22 @@ def step_limit(beta0, n_switch):
     return beta0 * max(BETA_MIN_FRAC, 0.5 ** (n_switch // BETA_HALVING))
 
 
+def stagnation_tol(robot, stag_tol):
+    """Residual level below which a stagnating residual is accepted: stag_tol, raised to ten
+    times the rounding floor of the out-of-balance force, eps * max(EA)/l0 * (1 m) *
+    sqrt(DOFs) - node coordinates of order 1 m carry eps m of rounding, which the axial
+    stiffness turns into force."""
+    floor = np.finfo(float).eps * float(np.max(robot.EA)) / robot.l0 * np.sqrt(6.0 * (robot.n_elem + 1))
+    return max(stag_tol, 10.0 * floor)
+
+
 def solve_load_step(robot, P, R, base_target, act_kind, act_values, tol=1e-10,
                     stag_tol=1e-9, max_iter=200, guided=None):
     """Newton iteration of one quasi-static load step from (P, R).
 
     Returns (P, R, contacts, y, info) with info = dict(status, iters, n_limited, res_norm).
     """
+    stag_tol = stagnation_tol(robot, stag_tol)
     resid = lambda P_, R_: out_of_balance(robot, P_, R_, act_kind, act_values)
     prev = None
     rn_prev = np.inf

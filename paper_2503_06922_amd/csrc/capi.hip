@@ -1,0 +1,770 @@
+// Host orchestration and the C ABI (include/accfem.h): context and device
+// memory, lumen upload with its uniform grid, load stepping and the Newton loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/accfem.h"
+#include "fem_device.h"
+
+namespace accfem {
+void launch_elem(const Dev& d, hipStream_t s);
+void launch_collide(const Dev& d, hipStream_t s);
+void launch_solve(const Dev& d, int it, hipStream_t s);
+void launch_gather(const Dev& d, hipStream_t s);
+void launch_tri_setup(const double* V, const int32_t* tri, int64_t T, double* tv, double* tn,
+                      float* tvf, float* tnf, hipStream_t s);
+
+// ------------------------------------------------------------------ setup kernels
+// straight reference configuration S_0 and the per-element rigidities
+__global__ void init_state_kernel(Dev d, double r_out, double r_in, double E, double nu,
+                                  double tip_len, double shE, double shA, double shI,
+                                  const double* length) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= d.Ntot) return;
+  const int r = d.robot_of[g];
+  const int64_t o = d.off[r], n = d.off[r + 1] - o, i = g - o;
+  const double l0 = d.l0[r];
+  V3 t = v3(d.base_dir[3 * r], d.base_dir[3 * r + 1], d.base_dir[3 * r + 2]);
+  V3 u = v3(d.base_up[3 * r], d.base_up[3 * r + 1], d.base_up[3 * r + 2]);
+  u = u - dot(u, t) * t;
+  u = (1.0 / norm(u)) * u;
+  V3 b = cross(t, u);
+  const int64_t N = d.Ntot;
+  V3 p = v3(d.base_pos[3 * r], d.base_pos[3 * r + 1], d.base_pos[3 * r + 2]) + ((double)i * l0) * t;
+  d.X[g] = p.x; d.X[N + g] = p.y; d.X[2 * N + g] = p.z;
+  // quaternion of R = [t u b] (columns), Shepperd's method
+  const double m00 = t.x, m01 = u.x, m02 = b.x, m10 = t.y, m11 = u.y, m12 = b.y, m20 = t.z,
+               m21 = u.z, m22 = b.z;
+  double w, x, y, z;
+  const double tr = m00 + m11 + m22;
+  if (tr > 0.0) {
+    double s = 2.0 * sqrt(tr + 1.0);
+    w = 0.25 * s; x = (m21 - m12) / s; y = (m02 - m20) / s; z = (m10 - m01) / s;
+  } else if (m00 > m11 && m00 > m22) {
+    double s = 2.0 * sqrt(1.0 + m00 - m11 - m22);
+    w = (m21 - m12) / s; x = 0.25 * s; y = (m01 + m10) / s; z = (m02 + m20) / s;
+  } else if (m11 > m22) {
+    double s = 2.0 * sqrt(1.0 + m11 - m00 - m22);
+    w = (m02 - m20) / s; x = (m01 + m10) / s; y = 0.25 * s; z = (m12 + m21) / s;
+  } else {
+    double s = 2.0 * sqrt(1.0 + m22 - m00 - m11);
+    w = (m10 - m01) / s; x = (m02 + m20) / s; y = (m12 + m21) / s; z = 0.25 * s;
+  }
+  d.X[3 * N + g] = w; d.X[4 * N + g] = x; d.X[5 * N + g] = y; d.X[6 * N + g] = z;
+  if (i < n - 1) {
+    // tube section: A = pi (ro^2 - ri^2), I = pi/4 (ro^4 - ri^4), J = 2 I, G = E / 2(1 + nu)
+    const double PI = 3.14159265358979323846;
+    double A = PI * (r_out * r_out - r_in * r_in);
+    double I = PI / 4.0 * (r_out * r_out * r_out * r_out - r_in * r_in * r_in * r_in);
+    double Ee = E;
+    const double mid = ((double)i + 0.5) * l0;
+    if (tip_len > 0.0 && mid < length[r] - tip_len) { A = shA; I = shI; Ee = shE; }
+    const double G = Ee / (2.0 * (1.0 + nu));
+    d.EA[g] = Ee * A;
+    d.EI[g] = Ee * I;
+    d.GJ[g] = G * 2.0 * I;
+  }
+}
+
+// load step j of n: interpolate actuation and depth, reset per-robot Newton state
+__global__ void set_load_kernel(Dev d, const double* act_prev, const double* act_tgt,
+                                double* act_cur, const double* dep_prev, const double* dep_tgt,
+                                double* dep_cur, int j, int n) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= d.B) return;
+  const double f = (double)j / (double)n;
+  for (int k = 0; k < d.act_nv; ++k) {
+    const int64_t q = (int64_t)r * d.act_nv + k;
+    act_cur[q] = (j == n) ? act_tgt[q] : act_prev[q] + (act_tgt[q] - act_prev[q]) * f;
+  }
+  dep_cur[r] = (j == n) ? dep_tgt[r] : dep_prev[r] + (dep_tgt[r] - dep_prev[r]) * f;
+  d.st_status[r] = 1;
+  d.st_done[r] = 0;
+  d.st_ncp[r] = 0;
+  d.st_nc[r] = 0;
+  d.st_limited[r] = 1;
+  d.st_nlim[r] = 0;
+  d.st_nswitch[r] = 0;
+  d.st_iters[r] = 0;
+  d.st_rnprev[r] = INFINITY;
+  d.st_rn[r] = INFINITY;
+}
+
+__global__ void finalize_kernel(Dev d, int32_t* steps_conv, int32_t* steps_tot, int64_t* iters_tot) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= d.B) return;
+  if (!d.st_done[r]) {  // loop ended without a final test (cannot happen with max_newton + 1 passes)
+    d.st_status[r] = 1;
+    d.st_done[r] = 1;
+  }
+  steps_tot[r] += 1;
+  steps_conv[r] += (d.st_status[r] == 0) ? 1 : 0;
+  iters_tot[r] += d.st_iters[r];
+}
+
+__global__ void renorm_kernel(Dev d) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= d.Ntot) return;
+  const int64_t N = d.Ntot;
+  double w = d.X[3 * N + g], x = d.X[4 * N + g], y = d.X[5 * N + g], z = d.X[6 * N + g];
+  double inv = 1.0 / sqrt(w * w + x * x + y * y + z * z);
+  d.X[3 * N + g] = w * inv; d.X[4 * N + g] = x * inv; d.X[5 * N + g] = y * inv; d.X[6 * N + g] = z * inv;
+}
+
+// node-major [g][7] <-> SoA [k][g]
+__global__ void aos_to_soa(const double* in, double* out, int64_t N, int K) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  for (int k = 0; k < K; ++k) out[k * N + g] = in[g * K + k];
+}
+__global__ void soa_to_aos(const double* in, double* out, int64_t N, int K) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  for (int k = 0; k < K; ++k) out[g * K + k] = in[k * N + g];
+}
+
+}  // namespace accfem
+
+using namespace accfem;
+
+struct fem_ctx {
+  std::string err;
+  int B = 0;
+  int64_t Ntot = 0;
+  int io_dev = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  fem_params p{};
+  std::vector<int64_t> h_off;
+  std::vector<double> h_len;
+  std::vector<int32_t> h_nelem;
+  std::vector<void*> allocs;
+  Dev d{};
+  int act_kind = -1;
+  int act_nv = 0;
+  double* act_prev = nullptr;
+  double* act_tgt = nullptr;
+  double* act_cur = nullptr;
+  double* dep_prev = nullptr;
+  double* dep_tgt = nullptr;
+  double* dep_cur = nullptr;
+  int32_t* steps_conv = nullptr;
+  int32_t* steps_tot = nullptr;
+  int64_t* iters_tot = nullptr;
+  double* length_d = nullptr;
+  bool lumen_set = false;
+  bool act_set = false;
+  // lumen buffers (reallocated by fem_set_lumen)
+  std::vector<void*> mesh_allocs;
+  // per-kernel event timing
+  bool profile = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double prof_ms[3] = {0, 0, 0};
+  int64_t prof_n[3] = {0, 0, 0};
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+fem_status fail(fem_ctx* c, fem_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+#define HIP_TRY(ctx, expr)                                                          \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return fail(ctx, FEM_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename T>
+fem_status dalloc(fem_ctx* c, T** ptr, size_t count, std::vector<void*>& list) {
+  void* p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc(&p, count * sizeof(T));
+  if (e != hipSuccess) return fail(c, FEM_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  list.push_back(p);
+  *ptr = static_cast<T*>(p);
+  return FEM_OK;
+}
+
+#define ALLOC(ptr, count)                                     \
+  do {                                                        \
+    fem_status s_ = dalloc(c, &(ptr), (size_t)(count), c->allocs); \
+    if (s_ != FEM_OK) return s_;                              \
+  } while (0)
+
+fem_status copy_in(fem_ctx* c, void* dst, const void* src, size_t bytes) {
+  HIP_TRY(c, hipMemcpyAsync(dst, src, bytes, c->io_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                            c->stream));
+  return FEM_OK;
+}
+
+fem_status copy_out(const fem_ctx* cc, void* dst, const void* src, size_t bytes) {
+  fem_ctx* c = const_cast<fem_ctx*>(cc);
+  HIP_TRY(c, hipMemcpyAsync(dst, src, bytes, c->io_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return FEM_OK;
+}
+
+inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// launch with optional HIP-event timing of kernel class k
+template <typename Fn>
+fem_status timed(fem_ctx* c, int k, Fn&& launch) {
+  if (!c->profile) {
+    launch();
+    return FEM_OK;
+  }
+  HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
+  launch();
+  HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
+  HIP_TRY(c, hipEventSynchronize(c->ev1));
+  float ms = 0.f;
+  HIP_TRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  c->prof_ms[k] += ms;
+  c->prof_n[k] += 1;
+  return FEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fem_last_error(const fem_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+int64_t fem_total_nodes(const fem_ctx* c) { return c ? c->Ntot : -1; }
+
+void fem_destroy(fem_ctx* c) {
+  if (!c) return;
+  hipSetDevice(c->device);
+  if (c->stream) hipStreamSynchronize(c->stream);
+  for (void* p : c->mesh_allocs) hipFree(p);
+  for (void* p : c->allocs) hipFree(p);
+  if (c->ev0) hipEventDestroy(c->ev0);
+  if (c->ev1) hipEventDestroy(c->ev1);
+  delete c;
+}
+
+static fem_status create_impl(fem_ctx* c, const fem_params* p);
+
+fem_status fem_create(const fem_params* p, fem_ctx** out) {
+  g_create_err.clear();
+  if (!p || !out) { g_create_err = "NULL params or out"; return FEM_E_INVAL; }
+  *out = nullptr;
+  fem_ctx* c = new fem_ctx();
+  fem_status s = create_impl(c, p);
+  if (s != FEM_OK) {
+    g_create_err = c->err;
+    fem_destroy(c);
+    return s;
+  }
+  *out = c;
+  return FEM_OK;
+}
+
+static fem_status create_impl(fem_ctx* c, const fem_params* p) {
+  auto bad = [&](const std::string& m) { return fail(c, FEM_E_INVAL, m); };
+  if (p->n_robots < 1 || !p->n_elem || !p->length || !p->base_pos || !p->base_dir || !p->base_up)
+    return bad("n_robots < 1 or NULL robot arrays");
+  if (!(p->r_out > p->r_in) || !(p->r_in >= 0.0) || !(p->E > 0.0) || !(p->nu > -1.0 && p->nu < 0.5))
+    return bad("section or material out of range");
+  if (p->tip_len > 0.0 && !(p->shaft_E > 0.0 && p->shaft_A > 0.0 && p->shaft_I > 0.0))
+    return bad("shaft material out of range");
+  if (p->n_cables < 1 || p->n_cables > 8 || !p->cable_angle) return bad("n_cables must be 1..8");
+  if (!(p->contact_radius >= 0.0) || !(p->contact_margin > 0.0) || !(p->beta0 > 0.0))
+    return bad("contact radius, margin or beta0 out of range");
+  if (p->max_newton < 1 || p->contact_capacity < 1 || p->contact_capacity > 256)
+    return bad("max_newton or contact_capacity out of range");
+  if (!(p->newton_tol > 0.0) || !(p->stag_tol >= 0.0)) return bad("tolerances out of range");
+  c->p = *p;
+  c->B = p->n_robots;
+  c->io_dev = p->io_on_device ? 1 : 0;
+  c->stream = (hipStream_t)p->hip_stream;
+  hipGetDevice(&c->device);
+  c->h_off.assign(c->B + 1, 0);
+  c->h_nelem.assign(p->n_elem, p->n_elem + c->B);
+  c->h_len.assign(p->length, p->length + c->B);
+  std::vector<double> bp(p->base_pos, p->base_pos + 3 * c->B), bd(3 * c->B), bu(p->base_up, p->base_up + 3 * c->B);
+  std::vector<int32_t> gaxis(c->B, -1);
+  std::vector<double> l0(c->B), stag(c->B);
+  for (int r = 0; r < c->B; ++r) {
+    if (c->h_nelem[r] < 1 || !(c->h_len[r] > 0.0)) return bad("n_elem < 1 or length <= 0");
+    c->h_off[r + 1] = c->h_off[r] + c->h_nelem[r] + 1;
+    l0[r] = c->h_len[r] / c->h_nelem[r];
+    {
+      // stagnation level: stag_tol raised to ten times the rounding floor of the
+      // out-of-balance force, eps * max(EA)/l0 * (1 m) * sqrt(DOFs)
+      const double PI = 3.14159265358979323846;
+      double ea = p->E * PI * (p->r_out * p->r_out - p->r_in * p->r_in);
+      bool shaft = false;
+      if (p->tip_len > 0.0)
+        for (int e = 0; e < c->h_nelem[r] && !shaft; ++e)
+          shaft = ((double)e + 0.5) * l0[r] < c->h_len[r] - p->tip_len;
+      if (shaft) ea = std::max(ea, p->shaft_E * p->shaft_A);
+      const double floor_r = 2.220446049250313e-16 * ea / l0[r] * std::sqrt(6.0 * (c->h_nelem[r] + 1));
+      stag[r] = std::max(p->stag_tol, 10.0 * floor_r);
+    }
+    double nn = std::sqrt(p->base_dir[3 * r] * p->base_dir[3 * r] + p->base_dir[3 * r + 1] * p->base_dir[3 * r + 1] +
+                          p->base_dir[3 * r + 2] * p->base_dir[3 * r + 2]);
+    if (!(nn > 0.0)) return bad("zero base_dir");
+    int ax = -1;
+    for (int k = 0; k < 3; ++k) {
+      bd[3 * r + k] = p->base_dir[3 * r + k] / nn;
+      if (std::fabs(std::fabs(bd[3 * r + k]) - 1.0) < 1e-15) ax = k;
+    }
+    if (p->guide_len > 0.0) {
+      if (ax < 0) return bad("guide_len > 0 needs base_dir along a coordinate axis");
+      gaxis[r] = ax;
+    }
+    double cx = bd[3 * r + 1] * bu[3 * r + 2] - bd[3 * r + 2] * bu[3 * r + 1];
+    double cy = bd[3 * r + 2] * bu[3 * r] - bd[3 * r] * bu[3 * r + 2];
+    double cz = bd[3 * r] * bu[3 * r + 1] - bd[3 * r + 1] * bu[3 * r];
+    if (!(cx * cx + cy * cy + cz * cz > 1e-24)) return bad("base_up parallel to base_dir");
+  }
+  c->Ntot = c->h_off[c->B];
+  const int64_t N = c->Ntot;
+  const int B = c->B;
+  const int cap = p->contact_capacity;
+  Dev& d = c->d;
+  d.B = B;
+  d.Ntot = N;
+  // robots
+  int64_t* off_d; int32_t* robot_of; double *l0_d, *bp_d, *bd_d, *bu_d; int32_t* gax_d;
+  ALLOC(off_d, B + 1); ALLOC(robot_of, N); ALLOC(l0_d, B); ALLOC(bp_d, 3 * B); ALLOC(bd_d, 3 * B);
+  ALLOC(bu_d, 3 * B); ALLOC(gax_d, B);
+  std::vector<int32_t> h_robot_of(N);
+  for (int r = 0; r < B; ++r)
+    for (int64_t g = c->h_off[r]; g < c->h_off[r + 1]; ++g) h_robot_of[g] = r;
+  HIP_TRY(c, hipMemcpy(off_d, c->h_off.data(), (B + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(robot_of, h_robot_of.data(), N * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(l0_d, l0.data(), B * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(bp_d, bp.data(), 3 * B * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(bd_d, bd.data(), 3 * B * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(bu_d, bu.data(), 3 * B * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(gax_d, gaxis.data(), B * sizeof(int32_t), hipMemcpyHostToDevice));
+  double* stag_d;
+  ALLOC(stag_d, B);
+  HIP_TRY(c, hipMemcpy(stag_d, stag.data(), B * sizeof(double), hipMemcpyHostToDevice));
+  d.stag_r = stag_d;
+  d.off = off_d; d.robot_of = robot_of; d.l0 = l0_d; d.base_pos = bp_d; d.base_dir = bd_d;
+  d.base_up = bu_d; d.guide_axis = gax_d;
+  ALLOC(c->length_d, B);
+  HIP_TRY(c, hipMemcpy(c->length_d, c->h_len.data(), B * sizeof(double), hipMemcpyHostToDevice));
+  double *EA, *EI, *GJ;
+  ALLOC(EA, N); ALLOC(EI, N); ALLOC(GJ, N);
+  d.EA = EA; d.EI = EI; d.GJ = GJ;
+  // cables
+  double *cc, *cs;
+  ALLOC(cc, p->n_cables); ALLOC(cs, p->n_cables);
+  std::vector<double> hc(p->n_cables), hs(p->n_cables);
+  for (int j = 0; j < p->n_cables; ++j) { hc[j] = std::cos(p->cable_angle[j]); hs[j] = std::sin(p->cable_angle[j]); }
+  HIP_TRY(c, hipMemcpy(cc, hc.data(), p->n_cables * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(cs, hs.data(), p->n_cables * sizeof(double), hipMemcpyHostToDevice));
+  d.n_cables = p->n_cables; d.cable_radius = p->cable_radius; d.cable_cos = cc; d.cable_sin = cs;
+  // actuation buffers (max 8 values per robot)
+  const int NV = 8;
+  ALLOC(c->act_prev, NV * B); ALLOC(c->act_tgt, NV * B); ALLOC(c->act_cur, NV * B);
+  ALLOC(c->dep_prev, B); ALLOC(c->dep_tgt, B); ALLOC(c->dep_cur, B);
+  HIP_TRY(c, hipMemset(c->act_prev, 0, NV * B * sizeof(double)));
+  HIP_TRY(c, hipMemset(c->act_tgt, 0, NV * B * sizeof(double)));
+  HIP_TRY(c, hipMemset(c->act_cur, 0, NV * B * sizeof(double)));
+  HIP_TRY(c, hipMemset(c->dep_prev, 0, B * sizeof(double)));
+  HIP_TRY(c, hipMemset(c->dep_tgt, 0, B * sizeof(double)));
+  HIP_TRY(c, hipMemset(c->dep_cur, 0, B * sizeof(double)));
+  d.act_cur = c->act_cur; d.depth_cur = c->dep_cur; d.act_kind = 0; d.act_nv = p->n_cables;
+  d.guide_len = p->guide_len;
+  d.r_c = p->contact_radius; d.delta = p->contact_margin; d.beta0 = p->beta0;
+  d.newton_tol = p->newton_tol; d.stag_tol = p->stag_tol; d.max_newton = p->max_newton;
+  d.cap = cap;
+  d.mixed = (p->precision == FEM_MIXED) ? 1 : 0;
+  // state and per-iteration buffers
+  ALLOC(d.X, 7 * N); ALLOC(d.F, 6 * N); ALLOC(d.KD, 36 * N); ALLOC(d.KS, 36 * N);
+  ALLOC(d.LD, 36 * N); ALLOC(d.LS, 36 * N);
+  ALLOC(d.CC, N); ALLOC(d.CT, MAXC * N); ALLOC(d.CK, MAXC * N); ALLOC(d.CN, 3 * MAXC * N);
+  ALLOC(d.CG, MAXC * N);
+  HIP_TRY(c, hipMemset(d.CC, 0, N * sizeof(int32_t)));
+  HIP_TRY(c, hipMemset(d.KS, 0, 36 * N * sizeof(double)));
+  const int64_t BC = (int64_t)B * cap;
+  ALLOC(d.ct_node, BC); ALLOC(d.ct_tri, BC); ALLOC(d.ct_kind, BC); ALLOC(d.ct_n, 3 * BC);
+  ALLOC(d.ct_gap, BC); ALLOC(d.ct_y, BC);
+  ALLOC(d.cp_node, BC); ALLOC(d.cp_tri, BC); ALLOC(d.cp_kind, BC); ALLOC(d.cp_n, 3 * BC);
+  ALLOC(d.cp_gap, BC); ALLOC(d.cp_y, BC);
+  std::vector<int64_t> zoff(B);
+  int64_t zt = 0;
+  for (int r = 0; r < B; ++r) { zoff[r] = zt; zt += (int64_t)(1 + cap) * 6 * (c->h_nelem[r] + 1); }
+  int64_t* zoff_d;
+  ALLOC(zoff_d, B);
+  HIP_TRY(c, hipMemcpy(zoff_d, zoff.data(), B * sizeof(int64_t), hipMemcpyHostToDevice));
+  d.zoff = zoff_d;
+  ALLOC(d.Z, zt);
+  ALLOC(d.W, (int64_t)B * cap * cap + (int64_t)B * (cap * cap + 3 * cap));
+  ALLOC(d.q, BC);
+  ALLOC(d.st_status, B); ALLOC(d.st_done, B); ALLOC(d.st_nc, B); ALLOC(d.st_ncp, B);
+  ALLOC(d.st_limited, B); ALLOC(d.st_nlim, B); ALLOC(d.st_nswitch, B); ALLOC(d.st_iters, B);
+  ALLOC(d.st_rn, B); ALLOC(d.st_rnprev, B); ALLOC(d.n_done, 1);
+  HIP_TRY(c, hipMemset(d.st_status, 0, B * sizeof(int32_t)));
+  HIP_TRY(c, hipMemset(d.st_done, 0, B * sizeof(int32_t)));
+  HIP_TRY(c, hipMemset(d.st_nc, 0, B * sizeof(int32_t)));
+  HIP_TRY(c, hipMemset(d.st_ncp, 0, B * sizeof(int32_t)));
+  HIP_TRY(c, hipMemset(d.st_nlim, 0, B * sizeof(int32_t)));
+  HIP_TRY(c, hipMemset(d.st_iters, 0, B * sizeof(int32_t)));
+  HIP_TRY(c, hipMemset(d.st_rn, 0, B * sizeof(double)));
+  ALLOC(c->steps_conv, B); ALLOC(c->steps_tot, B); ALLOC(c->iters_tot, B);
+  HIP_TRY(c, hipMemset(c->steps_conv, 0, B * sizeof(int32_t)));
+  HIP_TRY(c, hipMemset(c->steps_tot, 0, B * sizeof(int32_t)));
+  HIP_TRY(c, hipMemset(c->iters_tot, 0, B * sizeof(int64_t)));
+  // empty mesh until fem_set_lumen
+  d.n_tris = 0;
+  d.g_dim[0] = d.g_dim[1] = d.g_dim[2] = 0;
+  d.g_h = 1.0;
+  d.g_org[0] = d.g_org[1] = d.g_org[2] = 0.0;
+  d.tv = nullptr; d.tn = nullptr; d.tvf = nullptr; d.tnf = nullptr;
+  d.cell_start = nullptr; d.cell_tris = nullptr;
+  if (p->profile) {
+    c->profile = true;
+    HIP_TRY(c, hipEventCreate(&c->ev0));
+    HIP_TRY(c, hipEventCreate(&c->ev1));
+  }
+  hipLaunchKernelGGL(init_state_kernel, dim3(nblk(N, 256)), dim3(256), 0, c->stream, d, p->r_out,
+                     p->r_in, p->E, p->nu, p->tip_len, p->shaft_E, p->shaft_A, p->shaft_I,
+                     (const double*)c->length_d);
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return FEM_OK;
+}
+
+fem_status fem_set_lumen(fem_ctx* c, const double* verts, int64_t n_verts, const int32_t* tris,
+                         int64_t n_tris) {
+  if (!c) return FEM_E_INVAL;
+  if (n_tris < 0 || n_verts < 0 || (n_tris > 0 && (!verts || !tris || n_verts < 3)))
+    return fail(c, FEM_E_INVAL, "bad mesh sizes or NULL arrays");
+  if (n_tris > (int64_t)1 << 30) return fail(c, FEM_E_INVAL, "too many triangles");
+  hipSetDevice(c->device);
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (void* p : c->mesh_allocs) hipFree(p);
+  c->mesh_allocs.clear();
+  Dev& d = c->d;
+  d.n_tris = 0;
+  if (n_tris == 0) {
+    c->lumen_set = true;
+    return FEM_OK;
+  }
+  // host copies for validation and the grid
+  std::vector<double> hv(3 * n_verts);
+  std::vector<int32_t> ht(3 * n_tris);
+  if (c->io_dev) {
+    HIP_TRY(c, hipMemcpy(hv.data(), verts, hv.size() * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(ht.data(), tris, ht.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+  } else {
+    std::memcpy(hv.data(), verts, hv.size() * sizeof(double));
+    std::memcpy(ht.data(), tris, ht.size() * sizeof(int32_t));
+  }
+  for (int64_t k = 0; k < 3 * n_tris; ++k)
+    if (ht[k] < 0 || ht[k] >= n_verts) return fail(c, FEM_E_INVAL, "triangle vertex index out of range");
+  for (int64_t t = 0; t < n_tris; ++t) {
+    const double* a = &hv[3 * (int64_t)ht[3 * t]];
+    const double* b = &hv[3 * (int64_t)ht[3 * t + 1]];
+    const double* e = &hv[3 * (int64_t)ht[3 * t + 2]];
+    double u[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]}, v[3] = {e[0] - a[0], e[1] - a[1], e[2] - a[2]};
+    double n2 = std::pow(u[1] * v[2] - u[2] * v[1], 2) + std::pow(u[2] * v[0] - u[0] * v[2], 2) +
+                std::pow(u[0] * v[1] - u[1] * v[0], 2);
+    if (!(n2 > 0.0)) return fail(c, FEM_E_INVAL, "degenerate triangle " + std::to_string(t));
+  }
+  double *V_d, *tv, *tn;
+  int32_t* T_d;
+  float *tvf, *tnf;
+  auto A = [&](auto** ptr, size_t count) { return dalloc(c, ptr, count, c->mesh_allocs); };
+  if (A(&V_d, 3 * n_verts) || A(&T_d, 3 * n_tris) || A(&tv, 9 * n_tris) || A(&tn, 3 * n_tris) ||
+      A(&tvf, 9 * n_tris) || A(&tnf, 3 * n_tris))
+    return FEM_E_NOMEM;
+  HIP_TRY(c, hipMemcpy(V_d, hv.data(), hv.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(T_d, ht.data(), ht.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  launch_tri_setup(V_d, T_d, n_tris, tv, tn, tvf, tnf, c->stream);
+  HIP_TRY(c, hipGetLastError());
+  // uniform grid: every triangle in each cell its box grown by the band overlaps
+  const double band = c->p.contact_radius + c->p.contact_margin;
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int64_t k = 0; k < n_verts; ++k)
+    for (int j = 0; j < 3; ++j) { lo[j] = std::min(lo[j], hv[3 * k + j]); hi[j] = std::max(hi[j], hv[3 * k + j]); }
+  double h = c->p.grid_cell > 0.0 ? c->p.grid_cell : band;
+  int dim[3];
+  for (;;) {
+    int64_t cells = 1;
+    for (int j = 0; j < 3; ++j) {
+      dim[j] = (int)std::ceil((hi[j] - lo[j] + 2.0 * band) / h) + 1;
+      cells *= dim[j];
+    }
+    if (cells <= (int64_t)64 << 20) break;
+    h *= 1.25;
+  }
+  double org[3] = {lo[0] - band, lo[1] - band, lo[2] - band};
+  const int64_t ncell = (int64_t)dim[0] * dim[1] * dim[2];
+  std::vector<int32_t> cnt(ncell + 1, 0);
+  auto cell_range = [&](int64_t t, int* c0, int* c1) {
+    for (int j = 0; j < 3; ++j) {
+      double mn = 1e300, mx = -1e300;
+      for (int k = 0; k < 3; ++k) {
+        double x = hv[3 * (int64_t)ht[3 * t + k] + j];
+        mn = std::min(mn, x);
+        mx = std::max(mx, x);
+      }
+      c0[j] = std::max(0, (int)std::floor((mn - band - org[j]) / h));
+      c1[j] = std::min(dim[j] - 1, (int)std::floor((mx + band - org[j]) / h));
+    }
+  };
+  int64_t total = 0;
+  for (int64_t t = 0; t < n_tris; ++t) {
+    int c0[3], c1[3];
+    cell_range(t, c0, c1);
+    for (int z = c0[2]; z <= c1[2]; ++z)
+      for (int y = c0[1]; y <= c1[1]; ++y)
+        for (int x = c0[0]; x <= c1[0]; ++x) { ++cnt[((int64_t)z * dim[1] + y) * dim[0] + x + 1]; ++total; }
+  }
+  if (total > ((int64_t)1 << 31) - 1) return fail(c, FEM_E_INVAL, "grid too large; raise grid_cell");
+  for (int64_t k = 0; k < ncell; ++k) cnt[k + 1] += cnt[k];
+  std::vector<int32_t> fillp(cnt.begin(), cnt.end() - 1), lst(std::max<int64_t>(total, 1));
+  for (int64_t t = 0; t < n_tris; ++t) {
+    int c0[3], c1[3];
+    cell_range(t, c0, c1);
+    for (int z = c0[2]; z <= c1[2]; ++z)
+      for (int y = c0[1]; y <= c1[1]; ++y)
+        for (int x = c0[0]; x <= c1[0]; ++x) lst[fillp[((int64_t)z * dim[1] + y) * dim[0] + x]++] = (int32_t)t;
+  }
+  int32_t *cs_d, *ct_d;
+  if (A(&cs_d, ncell + 1) || A(&ct_d, lst.size())) return FEM_E_NOMEM;
+  HIP_TRY(c, hipMemcpy(cs_d, cnt.data(), (ncell + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(ct_d, lst.data(), lst.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  d.n_tris = n_tris;
+  d.tv = tv; d.tn = tn; d.tvf = tvf; d.tnf = tnf;
+  d.g_h = h;
+  for (int j = 0; j < 3; ++j) { d.g_org[j] = org[j]; d.g_dim[j] = dim[j]; }
+  d.cell_start = cs_d; d.cell_tris = ct_d;
+  c->lumen_set = true;
+  return FEM_OK;
+}
+
+fem_status fem_set_actuation(fem_ctx* c, fem_act_kind kind, const double* values,
+                             const double* insertion_depth) {
+  if (!c) return FEM_E_INVAL;
+  if (kind < FEM_ACT_CABLES || kind > FEM_ACT_TIP_WRENCH_GLOBAL || !values)
+    return fail(c, FEM_E_INVAL, "bad actuation kind or NULL values");
+  const int nv = (kind == FEM_ACT_CABLES) ? c->p.n_cables : 6;
+  if (c->act_kind >= 0 && c->act_kind != (int)kind)
+    return fail(c, FEM_E_INVAL, "actuation kind cannot change");
+  hipSetDevice(c->device);
+  c->act_kind = kind;
+  c->act_nv = nv;
+  c->d.act_kind = kind;
+  c->d.act_nv = nv;
+  fem_status s = copy_in(c, c->act_tgt, values, (size_t)c->B * nv * sizeof(double));
+  if (s != FEM_OK) return s;
+  if (insertion_depth) {
+    s = copy_in(c, c->dep_tgt, insertion_depth, (size_t)c->B * sizeof(double));
+    if (s != FEM_OK) return s;
+  } else {
+    HIP_TRY(c, hipMemsetAsync(c->dep_tgt, 0, c->B * sizeof(double), c->stream));
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->act_set = true;
+  return FEM_OK;
+}
+
+fem_status fem_get_state(const fem_ctx* cc, double* node_state) {
+  fem_ctx* c = const_cast<fem_ctx*>(cc);
+  if (!c || !node_state) return FEM_E_INVAL;
+  hipSetDevice(c->device);
+  double* tmp = c->d.F;  // scratch of 6N is too small for 7N: use LD (36N)
+  tmp = c->d.LD;
+  hipLaunchKernelGGL(soa_to_aos, dim3(nblk(c->Ntot, 256)), dim3(256), 0, c->stream, c->d.X, tmp,
+                     c->Ntot, 7);
+  HIP_TRY(c, hipGetLastError());
+  return copy_out(c, node_state, tmp, (size_t)c->Ntot * 7 * sizeof(double));
+}
+
+fem_status fem_set_state(fem_ctx* c, const double* node_state) {
+  if (!c || !node_state) return FEM_E_INVAL;
+  hipSetDevice(c->device);
+  double* tmp = c->d.LD;
+  fem_status s = copy_in(c, tmp, node_state, (size_t)c->Ntot * 7 * sizeof(double));
+  if (s != FEM_OK) return s;
+  hipLaunchKernelGGL(aos_to_soa, dim3(nblk(c->Ntot, 256)), dim3(256), 0, c->stream, tmp, c->d.X,
+                     c->Ntot, 7);
+  hipLaunchKernelGGL(renorm_kernel, dim3(nblk(c->Ntot, 256)), dim3(256), 0, c->stream, c->d);
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipMemsetAsync(c->steps_conv, 0, c->B * sizeof(int32_t), c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->steps_tot, 0, c->B * sizeof(int32_t), c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->iters_tot, 0, c->B * sizeof(int64_t), c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return FEM_OK;
+}
+
+fem_status fem_solve(fem_ctx* c, int32_t n_load_steps, double* node_state, fem_solve_info* info) {
+  if (!c) return FEM_E_INVAL;
+  if (n_load_steps < 0) return fail(c, FEM_E_INVAL, "n_load_steps < 0");
+  if (!c->lumen_set) return fail(c, FEM_E_STATE, "fem_set_lumen was not called");
+  if (!c->act_set) return fail(c, FEM_E_STATE, "fem_set_actuation was not called");
+  hipSetDevice(c->device);
+  Dev& d = c->d;
+  const int B = c->B;
+  const int max_it = c->p.max_newton;
+  for (int j = 1; j <= n_load_steps; ++j) {
+    hipLaunchKernelGGL(set_load_kernel, dim3(nblk(B, 256)), dim3(256), 0, c->stream, d,
+                       (const double*)c->act_prev, (const double*)c->act_tgt, c->act_cur,
+                       (const double*)c->dep_prev, (const double*)c->dep_tgt, c->dep_cur, j,
+                       n_load_steps);
+    HIP_TRY(c, hipMemsetAsync(d.n_done, 0, sizeof(int32_t), c->stream));
+    for (int it = 0; it <= max_it; ++it) {
+      fem_status s;
+      if ((s = timed(c, 0, [&] { launch_elem(d, c->stream); })) != FEM_OK) return s;
+      if ((s = timed(c, 1, [&] { launch_collide(d, c->stream); })) != FEM_OK) return s;
+      if ((s = timed(c, 2, [&] { launch_solve(d, it, c->stream); })) != FEM_OK) return s;
+      HIP_TRY(c, hipGetLastError());
+      int32_t nd = 0;
+      HIP_TRY(c, hipMemcpyAsync(&nd, d.n_done, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+      if (nd >= B) break;
+    }
+    hipLaunchKernelGGL(finalize_kernel, dim3(nblk(B, 256)), dim3(256), 0, c->stream, d,
+                       c->steps_conv, c->steps_tot, c->iters_tot);
+    HIP_TRY(c, hipGetLastError());
+  }
+  if (n_load_steps > 0) {
+    HIP_TRY(c, hipMemcpyAsync(c->act_prev, c->act_tgt, (size_t)B * 8 * sizeof(double),
+                              hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->dep_prev, c->dep_tgt, (size_t)B * sizeof(double),
+                              hipMemcpyDeviceToDevice, c->stream));
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  bool any_fail = false;
+  std::vector<int32_t> st(B);
+  HIP_TRY(c, hipMemcpy(st.data(), d.st_status, B * sizeof(int32_t), hipMemcpyDeviceToHost));
+  for (int r = 0; r < B; ++r) any_fail |= (st[r] != 0);
+  if (info) {
+    std::vector<int32_t> it(B), nc(B), nl(B), sc(B), stt(B);
+    std::vector<double> rn(B);
+    std::vector<int64_t> itt(B);
+    HIP_TRY(c, hipMemcpy(it.data(), d.st_iters, B * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(nc.data(), d.st_ncp, B * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(nl.data(), d.st_nlim, B * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(rn.data(), d.st_rn, B * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(sc.data(), c->steps_conv, B * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(stt.data(), c->steps_tot, B * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(itt.data(), c->iters_tot, B * sizeof(int64_t), hipMemcpyDeviceToHost));
+    std::vector<fem_solve_info> hi(B);
+    for (int r = 0; r < B; ++r) {
+      hi[r].status = st[r]; hi[r].iters = it[r]; hi[r].n_contacts = nc[r]; hi[r].n_limited = nl[r];
+      hi[r].res_norm = rn[r]; hi[r].steps_converged = sc[r]; hi[r].steps_total = stt[r];
+      hi[r].iters_total = itt[r];
+    }
+    if (c->io_dev) {
+      HIP_TRY(c, hipMemcpy(info, hi.data(), B * sizeof(fem_solve_info), hipMemcpyHostToDevice));
+    } else {
+      std::memcpy(info, hi.data(), B * sizeof(fem_solve_info));
+    }
+  }
+  if (node_state) {
+    fem_status s = fem_get_state(c, node_state);
+    if (s != FEM_OK) return s;
+  }
+  return any_fail ? FEM_E_NOCONV : FEM_OK;
+}
+
+fem_status fem_profile(fem_ctx* c, int32_t kernel, double* total_ms, int64_t* launches,
+                       int32_t reset) {
+  if (!c) return FEM_E_INVAL;
+  if (kernel < 0 || kernel > 2) return fail(c, FEM_E_INVAL, "kernel class must be 0..2");
+  if (!c->profile) return fail(c, FEM_E_STATE, "context was created without profile = 1");
+  if (total_ms) *total_ms = c->prof_ms[kernel];
+  if (launches) *launches = c->prof_n[kernel];
+  if (reset) {
+    c->prof_ms[kernel] = 0.0;
+    c->prof_n[kernel] = 0;
+  }
+  return FEM_OK;
+}
+
+fem_status fem_eval(fem_ctx* c, double* F, double* KD, double* KS) {
+  if (!c) return FEM_E_INVAL;
+  if (!c->lumen_set) return fail(c, FEM_E_STATE, "fem_set_lumen was not called");
+  if (!c->act_set) return fail(c, FEM_E_STATE, "fem_set_actuation was not called");
+  hipSetDevice(c->device);
+  Dev& d = c->d;
+  hipLaunchKernelGGL(set_load_kernel, dim3(nblk(c->B, 256)), dim3(256), 0, c->stream, d,
+                     (const double*)c->act_prev, (const double*)c->act_tgt, c->act_cur,
+                     (const double*)c->dep_prev, (const double*)c->dep_tgt, c->dep_cur, 1, 1);
+  launch_elem(d, c->stream);
+  launch_collide(d, c->stream);
+  launch_gather(d, c->stream);
+  HIP_TRY(c, hipGetLastError());
+  struct { double* dst; double* src; int K; } outs[3] = {{F, d.F, 6}, {KD, d.KD, 36}, {KS, d.KS, 36}};
+  for (auto& o : outs) {
+    if (!o.dst) continue;
+    hipLaunchKernelGGL(soa_to_aos, dim3(nblk(c->Ntot, 256)), dim3(256), 0, c->stream, o.src, d.LS,
+                       c->Ntot, o.K);
+    HIP_TRY(c, hipGetLastError());
+    fem_status s = copy_out(c, o.dst, d.LS, (size_t)c->Ntot * o.K * sizeof(double));
+    if (s != FEM_OK) return s;
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return FEM_OK;
+}
+
+fem_status fem_contacts(const fem_ctx* cc, int32_t robot, fem_contact* out, int32_t capacity,
+                        int32_t* n_out) {
+  fem_ctx* c = const_cast<fem_ctx*>(cc);
+  if (!c || !n_out || capacity < 0 || (capacity > 0 && !out)) return FEM_E_INVAL;
+  if (robot < -1 || robot >= c->B) return fail(c, FEM_E_INVAL, "robot index out of range");
+  hipSetDevice(c->device);
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const int B = c->B, cap = c->p.contact_capacity;
+  const Dev& d = c->d;
+  std::vector<int32_t> ncp(B);
+  HIP_TRY(c, hipMemcpy(ncp.data(), d.st_ncp, B * sizeof(int32_t), hipMemcpyDeviceToHost));
+  const int r0 = robot < 0 ? 0 : robot, r1 = robot < 0 ? B : robot + 1;
+  int64_t total = 0;
+  for (int r = r0; r < r1; ++r) total += ncp[r];
+  *n_out = (int32_t)std::min<int64_t>(total, INT32_MAX);
+  std::vector<fem_contact> h;
+  h.reserve(std::min<int64_t>(total, capacity));
+  std::vector<int32_t> nd(cap), tr(cap), kd(cap);
+  std::vector<double> nn(3 * cap), gp(cap), yy(cap);
+  for (int r = r0; r < r1 && (int64_t)h.size() < capacity; ++r) {
+    const int n = ncp[r];
+    if (n == 0) continue;
+    const int64_t cb = (int64_t)r * cap;
+    HIP_TRY(c, hipMemcpy(nd.data(), d.cp_node + cb, n * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(tr.data(), d.cp_tri + cb, n * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(kd.data(), d.cp_kind + cb, n * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(nn.data(), d.cp_n + 3 * cb, 3 * n * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(gp.data(), d.cp_gap + cb, n * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(yy.data(), d.cp_y + cb, n * sizeof(double), hipMemcpyDeviceToHost));
+    for (int k = 0; k < n && (int64_t)h.size() < capacity; ++k) {
+      fem_contact ct;
+      ct.robot = r; ct.node = nd[k]; ct.tri = tr[k]; ct.kind = kd[k];
+      ct.n[0] = nn[3 * k]; ct.n[1] = nn[3 * k + 1]; ct.n[2] = nn[3 * k + 2];
+      ct.gap = gp[k]; ct.force = yy[k];
+      h.push_back(ct);
+    }
+  }
+  if (!h.empty()) {
+    if (c->io_dev) {
+      HIP_TRY(c, hipMemcpy(out, h.data(), h.size() * sizeof(fem_contact), hipMemcpyHostToDevice));
+    } else {
+      std::memcpy(out, h.data(), h.size() * sizeof(fem_contact));
+    }
+  }
+  return FEM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,204 @@
+// Element update: internal forces and the QP tangent of the co-rotational beam
+// elements, assembled node-centrically into the block-tridiagonal system.
+//
+// Element e = (a, b) with node positions p and triads R (from unit quaternions):
+//   chord c = p_b - p_a, l = |c|, e1 = c/l; mean section y-axis q = (R_a y + R_b y)/2;
+//   e3 = unit(e1 x q), e2 = e3 x e1, R_e = [e1 e2 e3]                (Battini-Pacoste frame)
+//   local rotations th_a = log(R_e^T R_a), th_b = log(R_e^T R_b); stretch u = l - l0
+//   generalised stresses s = K7 (th_a, u, th_b) with the Euler-Bernoulli stiffness
+//   internal force = gradient of 1/2 d.K7 d through the element-frame spin and the
+//   inverse left Jacobian of the log map (exact, self-equilibrated).
+// The QP tangent of eq. 20-23 is the constant local stiffness turned into the
+// element frame, K_e = Rcal K_l Rcal^T.  With equal bending stiffness about both
+// section axes its 3x3 blocks depend on e1 only:
+//   diag(x, y, y) -> y I + (x - y) e1 e1^T,   local skew blocks -> +-k2 [e1]x.
+// One thread per node computes its two adjacent elements and writes the node's
+// out-of-balance force F_i (6), diagonal block D_i (6x6) and coupling K[i, i+1].
+#include "fem_device.h"
+
+namespace accfem {
+
+// theta/sin(theta) * vee(Q - Q^T)/2 : log of a rotation matrix near the identity
+__device__ __forceinline__ V3 so3_log(const double* Q) {
+  V3 v = v3(0.5 * (Q[7] - Q[5]), 0.5 * (Q[2] - Q[6]), 0.5 * (Q[3] - Q[1]));
+  double c = 0.5 * (Q[0] + Q[4] + Q[8] - 1.0);
+  double s = norm(v);
+  double th = atan2(s, c);
+  double f;
+  if (th < 1e-3) {
+    double t2 = th * th;
+    f = 1.0 + t2 * (1.0 / 6.0 + t2 * (7.0 / 360.0 + t2 * (31.0 / 15120.0)));
+  } else {
+    f = th / s;
+  }
+  return f * v;
+}
+
+// J_l(theta)^-T s = s + 1/2 theta x s + beta(theta) theta x (theta x s)
+__device__ __forceinline__ V3 jl_inv_T(V3 th, V3 s) {
+  double t2 = dot(th, th);
+  double beta;
+  if (t2 < 1e-4) {
+    beta = 1.0 / 12.0 + t2 * (1.0 / 720.0 + t2 * (1.0 / 30240.0));
+  } else {
+    double t = sqrt(t2);
+    beta = 1.0 / t2 - (1.0 + cos(t)) / (2.0 * t * sin(t));
+  }
+  V3 ts = cross(th, s);
+  return s + 0.5 * ts + beta * cross(th, ts);
+}
+
+struct NodeState { V3 p; double R[9]; };
+
+__device__ __forceinline__ NodeState load_node(const Dev& d, int64_t g) {
+  NodeState n;
+  const int64_t N = d.Ntot;
+  n.p = v3(d.X[g], d.X[N + g], d.X[2 * N + g]);
+  quat_to_mat(d.X[3 * N + g], d.X[4 * N + g], d.X[5 * N + g], d.X[6 * N + g], n.R);
+  return n;
+}
+
+// Internal force of element (a, b): fa = (force, moment) at a, fb at b.
+__device__ void element_force(const NodeState& A, const NodeState& Bn, double l0, double EA,
+                              double EI, double GJ, double* fa, double* fb, V3* e1_out) {
+  V3 c = Bn.p - A.p;
+  double l = norm(c);
+  V3 e1 = (1.0 / l) * c;
+  V3 qa = col(A.R, 1), qb = col(Bn.R, 1);
+  V3 q = 0.5 * (qa + qb);
+  V3 r = cross(e1, q);
+  V3 e3 = (1.0 / norm(r)) * r;
+  V3 e2 = cross(e3, e1);
+  // Q = R_e^T R_node
+  double Qa[9], Qb[9];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    V3 ca = col(A.R, j), cb = col(Bn.R, j);
+    Qa[j] = dot(e1, ca); Qa[3 + j] = dot(e2, ca); Qa[6 + j] = dot(e3, ca);
+    Qb[j] = dot(e1, cb); Qb[3 + j] = dot(e2, cb); Qb[6 + j] = dot(e3, cb);
+  }
+  V3 ta = so3_log(Qa), tb = so3_log(Qb);
+  double u = l - l0;
+  double gt = GJ / l0, eb = EI / l0;
+  V3 sa = v3(gt * (ta.x - tb.x), eb * (4.0 * ta.y + 2.0 * tb.y), eb * (4.0 * ta.z + 2.0 * tb.z));
+  V3 sb = v3(gt * (tb.x - ta.x), eb * (2.0 * ta.y + 4.0 * tb.y), eb * (2.0 * ta.z + 4.0 * tb.z));
+  double Nx = EA / l0 * u;
+  V3 ma = jl_inv_T(ta, sa), mb = jl_inv_T(tb, sb);
+  V3 m = ma + mb;
+  double q1 = dot(q, e1), q2 = dot(q, e2);
+  V3 fpb = Nx * e1 + ((m.x * q1 / q2 + m.y) / l) * e3 - (m.z / l) * e2;
+  double c1 = m.x / (2.0 * q2);
+  V3 Ma = ma.x * e1 + ma.y * e2 + ma.z * e3;
+  V3 Mb = mb.x * e1 + mb.y * e2 + mb.z * e3;
+  V3 fta = Ma - c1 * cross(qa, e3);
+  V3 ftb = Mb - c1 * cross(qb, e3);
+  fa[0] = -fpb.x; fa[1] = -fpb.y; fa[2] = -fpb.z; fa[3] = fta.x; fa[4] = fta.y; fa[5] = fta.z;
+  fb[0] = fpb.x;  fb[1] = fpb.y;  fb[2] = fpb.z;  fb[3] = ftb.x; fb[4] = ftb.y; fb[5] = ftb.z;
+  *e1_out = e1;
+}
+
+// 3x3 block y I + (x - y) e e^T added into the 6x6 matrix M (row major) at (r0, c0)
+__device__ __forceinline__ void add_iso(double* M, int r0, int c0, V3 e, double x, double y) {
+  double ev[3] = {e.x, e.y, e.z};
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      M[(r0 + i) * 6 + c0 + j] += (i == j ? y : 0.0) + (x - y) * ev[i] * ev[j];
+}
+
+// s [e]x added at (r0, c0)
+__device__ __forceinline__ void add_skew(double* M, int r0, int c0, V3 e, double s) {
+  M[(r0 + 0) * 6 + c0 + 1] += -s * e.z; M[(r0 + 0) * 6 + c0 + 2] += s * e.y;
+  M[(r0 + 1) * 6 + c0 + 0] += s * e.z;  M[(r0 + 1) * 6 + c0 + 2] += -s * e.x;
+  M[(r0 + 2) * 6 + c0 + 0] += -s * e.y; M[(r0 + 2) * 6 + c0 + 1] += s * e.x;
+}
+
+__global__ void __launch_bounds__(256) elem_kernel(Dev d) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= d.Ntot) return;
+  const int r = d.robot_of[g];
+  if (d.st_done[r]) return;
+  const int64_t o = d.off[r];
+  const int64_t n = d.off[r + 1] - o;
+  const int64_t i = g - o;
+  const double l0 = d.l0[r];
+  const int64_t N = d.Ntot;
+
+  double F[6] = {0, 0, 0, 0, 0, 0};
+  double D[36];
+  double S[36];
+#pragma unroll
+  for (int k = 0; k < 36; ++k) { D[k] = 0.0; S[k] = 0.0; }
+
+  NodeState me = load_node(d, g);
+  if (i > 0) {  // element (i-1, i): this node is its end b
+    NodeState A = load_node(d, g - 1);
+    double EA = d.EA[g - 1], EI = d.EI[g - 1], GJ = d.GJ[g - 1];
+    double fa[6], fb[6];
+    V3 e1;
+    element_force(A, me, l0, EA, EI, GJ, fa, fb, &e1);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) F[k] += fb[k];
+    const double a = EA / l0, t = GJ / l0, k1 = 12.0 * EI / (l0 * l0 * l0),
+                 k2 = 6.0 * EI / (l0 * l0), k3 = 4.0 * EI / l0;
+    add_iso(D, 0, 0, e1, a, k1);
+    add_skew(D, 0, 3, e1, k2);
+    add_skew(D, 3, 0, e1, -k2);
+    add_iso(D, 3, 3, e1, t, k3);
+  }
+  if (i < n - 1) {  // element (i, i+1): this node is its end a
+    NodeState Bn = load_node(d, g + 1);
+    double EA = d.EA[g], EI = d.EI[g], GJ = d.GJ[g];
+    double fa[6], fb[6];
+    V3 e1;
+    element_force(me, Bn, l0, EA, EI, GJ, fa, fb, &e1);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) F[k] += fa[k];
+    const double a = EA / l0, t = GJ / l0, k1 = 12.0 * EI / (l0 * l0 * l0),
+                 k2 = 6.0 * EI / (l0 * l0), k3 = 4.0 * EI / l0, k4 = 2.0 * EI / l0;
+    add_iso(D, 0, 0, e1, a, k1);
+    add_skew(D, 0, 3, e1, -k2);
+    add_skew(D, 3, 0, e1, k2);
+    add_iso(D, 3, 3, e1, t, k3);
+    // coupling K[a, b]
+    add_iso(S, 0, 0, e1, -a, -k1);
+    add_skew(S, 0, 3, e1, -k2);
+    add_skew(S, 3, 0, e1, -k2);
+    add_iso(S, 3, 3, e1, -t, k4);
+  } else {  // tip node: subtract the actuation load (eq. 18)
+    const double* v = d.act_cur + (int64_t)r * d.act_nv;
+    V3 Fl = v3(0, 0, 0), Ml = v3(0, 0, 0);
+    if (d.act_kind == 0) {
+      for (int j = 0; j < d.n_cables; ++j) {
+        // M_j = d_j x F_j with d_j = rc (0, cos, sin), F_j = -T_j e_x
+        double T = v[j];
+        Ml = Ml + (T * d.cable_radius) * v3(0.0, -d.cable_sin[j], d.cable_cos[j]);
+      }
+    } else {
+      Fl = v3(v[0], v[1], v[2]);
+      Ml = v3(v[3], v[4], v[5]);
+    }
+    V3 Fg, Mg;
+    if (d.act_kind == 2) {
+      Fg = Fl; Mg = Ml;
+    } else {
+      Fg = Fl.x * col(me.R, 0) + Fl.y * col(me.R, 1) + Fl.z * col(me.R, 2);
+      Mg = Ml.x * col(me.R, 0) + Ml.y * col(me.R, 1) + Ml.z * col(me.R, 2);
+    }
+    F[0] -= Fg.x; F[1] -= Fg.y; F[2] -= Fg.z;
+    F[3] -= Mg.x; F[4] -= Mg.y; F[5] -= Mg.z;
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) d.F[k * N + g] = F[k];
+#pragma unroll
+  for (int k = 0; k < 36; ++k) { d.KD[k * N + g] = D[k]; d.KS[k * N + g] = S[k]; }
+}
+
+void launch_elem(const Dev& d, hipStream_t s) {
+  const int T = 256;
+  const int64_t blocks = (d.Ntot + T - 1) / T;
+  hipLaunchKernelGGL(elem_kernel, dim3((unsigned)blocks), dim3(T), 0, s, d);
+}
+
+}  // namespace accfem

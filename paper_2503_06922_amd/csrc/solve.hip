@@ -1,0 +1,590 @@
+// Per-robot Newton step: contact gather, convergence test, block-tridiagonal
+// Cholesky of the QP tangent, multi-right-hand-side solves, contact-space Schur
+// complement, exact contact forces by an active-set method, step-size limit and
+// state update.  One wavefront (64 lanes) per robot.
+//
+// Linear step (eq. 20-23): with the base node prescribed (clamp + insertion,
+// eq. 14-15) and the lateral DOFs of guided nodes prescribed on the guide axis,
+//     K dx = -r + A^T y,   0 <= y  _|_  g + A dx >= 0,
+// where A has one row n_c^T on the translations of each contact node.  With
+// K = L L^T (6x6 blocks, serial over nodes), dx_free = -K^-1 r, Z = K^-1 A^T,
+// W = A Z (SPD) and q = g + A dx_free, the contact forces solve LCP(q, W); the
+// primal active-set method used here (Lawson-Hanson style, with a dense
+// Cholesky of the active block) terminates finitely for SPD W.  Then
+// dx = dx_free + Z y, and if max_i |dp_i| > beta the step and y are scaled by
+// beta / max_i |dp_i| (eq. 25-27), beta = beta0 halved every 10 contact-set
+// changes within the load step (down to beta0/64).
+//
+// Convergence (checked at the start of the next iteration, after the state
+// update, element update and detection): residual F - A_prev^T y_prev over the
+// free DOFs (guided lateral DOFs excluded) below newton_tol, or below stag_tol
+// and no longer halving; the last step unlimited; the detected contact set equal
+// to the solved one; and no gap below -1e-9 m.  The stagnation level is stag_tol
+// raised to ten times the rounding floor eps * max(EA)/l0 * (1 m) * sqrt(DOFs).
+#include "fem_device.h"
+
+namespace accfem {
+
+constexpr int NT = SOLVE_THREADS;
+
+__device__ __forceinline__ double warp_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ double warp_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ double warp_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ int warp_sum_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// is the lateral DOF k (0..2) of node i prescribed by the guide?
+__device__ __forceinline__ bool guided_dof(const Dev& d, int r, int64_t i, int k) {
+  const int ax = d.guide_axis[r];
+  if (ax < 0 || i == 0 || k >= 3 || k == ax) return false;
+  return (double)i * d.l0[r] + d.depth_cur[r] < d.guide_len;
+}
+
+// compact the per-node detection output of robot r into its contact list
+__device__ void gather_contacts(const Dev& d, int r, int* nc_out, bool* overflow) {
+  const int lane = threadIdx.x;
+  const int64_t o = d.off[r], n = d.off[r + 1] - o;
+  const int64_t N = d.Ntot;
+  const int64_t chunk = (n + NT - 1) / NT;
+  const int64_t i0 = min(n, (int64_t)lane * chunk), i1 = min(n, i0 + chunk);
+  int cnt = 0, ovf = 0;
+  for (int64_t i = i0; i < i1; ++i) {
+    int c = d.CC[o + i];
+    if (c > MAXC) { ovf = 1; c = MAXC; }
+    cnt += c;
+  }
+  // exclusive scan over the wavefront
+  int incl = cnt;
+#pragma unroll
+  for (int s = 1; s < 64; s <<= 1) {
+    int v = __shfl_up(incl, s);
+    if (lane >= s) incl += v;
+  }
+  const int total = __shfl(incl, 63);
+  int pos = incl - cnt;
+  ovf = warp_sum_i(ovf);
+  const int cap = d.cap;
+  if (total <= cap && ovf == 0) {
+    const int64_t base = (int64_t)r * cap;
+    for (int64_t i = i0; i < i1; ++i) {
+      const int64_t g = o + i;
+      const int c = d.CC[g];
+      for (int s = 0; s < c; ++s, ++pos) {
+        d.ct_node[base + pos] = (int32_t)i;
+        d.ct_tri[base + pos] = d.CT[s * N + g];
+        d.ct_kind[base + pos] = d.CK[s * N + g];
+        d.ct_gap[base + pos] = d.CG[s * N + g];
+        d.ct_n[3 * (base + pos) + 0] = d.CN[(3 * s + 0) * N + g];
+        d.ct_n[3 * (base + pos) + 1] = d.CN[(3 * s + 1) * N + g];
+        d.ct_n[3 * (base + pos) + 2] = d.CN[(3 * s + 2) * N + g];
+      }
+    }
+  }
+  *nc_out = total;
+  *overflow = (total > cap) || (ovf != 0);
+}
+
+__device__ __forceinline__ void finish(const Dev& d, int r, int status, int iters, double rn) {
+  if (threadIdx.x == 0) {
+    d.st_status[r] = status;
+    d.st_done[r] = 1;
+    d.st_iters[r] = iters;
+    d.st_rn[r] = rn;
+    atomicAdd(d.n_done, 1);
+  }
+}
+
+// dense Cholesky in place (row major, ld), returns false on a non-positive pivot
+__device__ bool chol_dense(double* A, int n, int ld) {
+  for (int k = 0; k < n; ++k) {
+    double s = A[k * ld + k];
+    for (int j = 0; j < k; ++j) s -= A[k * ld + j] * A[k * ld + j];
+    if (!(s > 0.0)) return false;
+    const double lkk = sqrt(s);
+    A[k * ld + k] = lkk;
+    for (int i = k + 1; i < n; ++i) {
+      double t = A[i * ld + k];
+      for (int j = 0; j < k; ++j) t -= A[i * ld + j] * A[k * ld + j];
+      A[i * ld + k] = t / lkk;
+    }
+  }
+  return true;
+}
+
+// solve L L^T x = b in place (dense, row major)
+__device__ void chol_solve_dense(const double* L, int n, int ld, double* b) {
+  for (int i = 0; i < n; ++i) {
+    double t = b[i];
+    for (int j = 0; j < i; ++j) t -= L[i * ld + j] * b[j];
+    b[i] = t / L[i * ld + i];
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double t = b[i];
+    for (int j = i + 1; j < n; ++j) t -= L[j * ld + i] * b[j];
+    b[i] = t / L[i * ld + i];
+  }
+}
+
+// LCP(q, W) with W SPD: minimise 1/2 y.W y + q.y over y >= 0 by a primal active set.
+// scratch: [cap*cap + 3*cap] doubles.  Returns false if it did not terminate.
+__device__ bool lcp_active_set(const double* W, const double* q, int n, int ldw, double* y,
+                               double* scratch) {
+  double* A = scratch;                 // factor of W_PP, n x n (ld n)
+  double* z = scratch + n * n;
+  int* P = (int*)(z + n);              // active indices (n ints)
+  int* inP = P + n;                    // flags (n ints)
+  for (int i = 0; i < n; ++i) { y[i] = 0.0; inP[i] = 0; }
+  int np = 0;
+  double qmax = 0.0;
+  for (int i = 0; i < n; ++i) qmax = fmax(qmax, fabs(q[i]));
+  const double tolw = 1e-12 * qmax;
+  for (int outer = 0; outer < 4 * n + 8; ++outer) {
+    // most violated inactive constraint
+    int t = -1;
+    double wt = -tolw;
+    for (int i = 0; i < n; ++i) {
+      if (inP[i]) continue;
+      double w = q[i];
+      for (int j = 0; j < np; ++j) w += W[i * ldw + P[j]] * y[P[j]];
+      if (w < wt) { wt = w; t = i; }
+    }
+    if (t < 0) return true;
+    P[np++] = t;
+    inP[t] = 1;
+    for (int inner = 0; inner < 4 * n + 8; ++inner) {
+      for (int a = 0; a < np; ++a)
+        for (int b = 0; b < np; ++b) A[a * np + b] = W[P[a] * ldw + P[b]];
+      if (!chol_dense(A, np, np)) return false;
+      for (int a = 0; a < np; ++a) z[a] = -q[P[a]];
+      chol_solve_dense(A, np, np, z);
+      bool pos = true;
+      for (int a = 0; a < np; ++a) pos = pos && (z[a] > 0.0);
+      if (pos) {
+        for (int a = 0; a < np; ++a) y[P[a]] = z[a];
+        break;
+      }
+      double alpha = 1.0;
+      for (int a = 0; a < np; ++a) {
+        if (z[a] <= 0.0) {
+          const double yi = y[P[a]];
+          const double al = yi / (yi - z[a]);
+          alpha = fmin(alpha, al);
+        }
+      }
+      int m = 0;
+      for (int a = 0; a < np; ++a) {
+        const int i = P[a];
+        double yn = y[i] + alpha * (z[a] - y[i]);
+        if (yn <= 0.0) { y[i] = 0.0; inP[i] = 0; continue; }
+        y[i] = yn;
+        P[m++] = i;
+      }
+      np = m;
+      if (np == 0) break;
+    }
+  }
+  return false;
+}
+
+__global__ void __launch_bounds__(NT) solve_kernel(Dev d, int it) {
+  const int r = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (d.st_done[r]) return;
+  const int64_t o = d.off[r], n = d.off[r + 1] - o;
+  const int64_t N = d.Ntot;
+  const int64_t nf = n - 1;            // free nodes 1..n-1 -> f = 0..nf-1
+  const int cap = d.cap;
+  const int64_t cb = (int64_t)r * cap;
+
+  int nc;
+  bool ovf;
+  gather_contacts(d, r, &nc, &ovf);
+  if (ovf) {
+    if (lane == 0) d.st_nc[r] = nc;
+    finish(d, r, 4, it, d.st_rn[r]);
+    return;
+  }
+  __syncthreads();
+  if (lane == 0) d.st_nc[r] = nc;
+
+  // ---------------------------------------------------------------- convergence test
+  if (it > 0) {
+    const int ncp = d.st_ncp[r];
+    int diff = (nc != ncp) ? 1 : 0;
+    if (!diff) {
+      for (int c = lane; c < nc; c += NT)
+        diff |= (d.ct_node[cb + c] != d.cp_node[cb + c]) | (d.ct_tri[cb + c] != d.cp_tri[cb + c]) |
+                (d.ct_kind[cb + c] != d.cp_kind[cb + c]);
+      diff = warp_sum_i(diff);
+    }
+    double gmin = 1e300;
+    for (int c = lane; c < nc; c += NT) gmin = fmin(gmin, d.ct_gap[cb + c]);
+    gmin = warp_min(gmin);
+    // residual over free nodes with the previous contact forces
+    const int64_t chunk = (nf + NT - 1) / NT;
+    const int64_t f0 = min(nf, (int64_t)lane * chunk), f1 = min(nf, f0 + chunk);
+    double ss = 0.0;
+    int cp = 0;
+    while (cp < ncp && d.cp_node[cb + cp] < f0 + 1) ++cp;
+    for (int64_t f = f0; f < f1; ++f) {
+      const int64_t i = f + 1, g = o + i;
+      double rv[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) rv[k] = d.F[k * N + g];
+      while (cp < ncp && d.cp_node[cb + cp] == i) {
+        const double y = d.cp_y[cb + cp];
+        rv[0] -= y * d.cp_n[3 * (cb + cp) + 0];
+        rv[1] -= y * d.cp_n[3 * (cb + cp) + 1];
+        rv[2] -= y * d.cp_n[3 * (cb + cp) + 2];
+        ++cp;
+      }
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+        if (!guided_dof(d, r, i, k)) ss += rv[k] * rv[k];
+    }
+    ss = warp_sum(ss);
+    const double rn = sqrt(ss);
+    const double rn_prev = d.st_rnprev[r];
+    const bool same = (diff == 0);
+    const bool conv = same && !d.st_limited[r] && gmin >= -1e-9 &&
+                      (rn <= d.newton_tol || (rn <= d.stag_r[r] && rn > 0.5 * rn_prev));
+    __syncthreads();
+    if (lane == 0) {
+      d.st_nswitch[r] += same ? 0 : 1;
+      d.st_rnprev[r] = rn;
+      d.st_rn[r] = rn;
+    }
+    if (conv) {
+      // report the solved contacts with the gaps of the final state
+      for (int c = lane; c < nc; c += NT) d.cp_gap[cb + c] = d.ct_gap[cb + c];
+      finish(d, r, 0, it, rn);
+      return;
+    }
+    if (it >= d.max_newton) {
+      finish(d, r, 1, it, rn);
+      return;
+    }
+  }
+  __syncthreads();
+
+  // ---------------------------------------------------------------- right-hand side
+  double* Zr = d.Z + d.zoff[r];
+  const int64_t ld = 6 * n;             // column stride of Z
+  const int ncol = 1 + nc;
+  const int64_t b0 = 0;                 // base node g = o
+  const double bd[3] = {d.base_dir[3 * r], d.base_dir[3 * r + 1], d.base_dir[3 * r + 2]};
+  double dx0[3];
+  {
+    const double dep = d.depth_cur[r];
+    for (int k = 0; k < 3; ++k) dx0[k] = d.base_pos[3 * r + k] + dep * bd[k] - d.X[k * N + o + b0];
+  }
+  // col 0 = -F over free DOFs; contact columns = n_c at the contact node
+  for (int64_t f = lane; f < nf; f += NT) {
+    const int64_t g = o + f + 1;
+    for (int k = 0; k < 6; ++k) Zr[6 * f + k] = -d.F[k * N + g];
+  }
+  for (int c = 0; c < nc; ++c)
+    for (int64_t j = lane; j < 6 * nf; j += NT) Zr[(int64_t)(1 + c) * ld + j] = 0.0;
+  __syncthreads();
+  for (int c = lane; c < nc; c += NT) {
+    const int64_t f = d.ct_node[cb + c] - 1;
+    for (int k = 0; k < 3; ++k) Zr[(int64_t)(1 + c) * ld + 6 * f + k] = d.ct_n[3 * (cb + c) + k];
+  }
+  // prescribed increments: base coupling into node 1, guided lateral DOFs
+  if (lane == 0) {
+    // rows of node 1 (f = 0): -= K[1,0] dx0 = S_0^T dx0 (S_0 = K[0,1] stored at the base)
+    for (int a = 0; a < 6; ++a) {
+      double s = 0.0;
+      for (int b = 0; b < 3; ++b) s += d.KS[(b * 6 + a) * N + o] * dx0[b];
+      Zr[a] -= s;
+    }
+  }
+  __syncthreads();
+  // guided nodes: rhs -= K xp over the block-tridiagonal neighbourhood, then rhs = xp
+  {
+    // xp at node i (free index f = i-1), lateral DOFs only
+    for (int64_t f = lane; f < nf; f += NT) {
+      const int64_t i = f + 1;
+      double acc[6] = {0, 0, 0, 0, 0, 0};
+      bool any = false;
+      for (int64_t jn = i - 1; jn <= i + 1; ++jn) {
+        if (jn < 1 || jn >= n) continue;
+        for (int k = 0; k < 3; ++k) {
+          if (!guided_dof(d, r, jn, k)) continue;
+          const double xp = d.base_pos[3 * r + k] - d.X[k * N + o + jn];
+          any = true;
+          for (int a = 0; a < 6; ++a) {
+            double kij;
+            if (jn == i) kij = d.KD[(a * 6 + k) * N + o + i];
+            else if (jn == i + 1) kij = d.KS[(a * 6 + k) * N + o + i];        // K[i, i+1]
+            else kij = d.KS[(k * 6 + a) * N + o + jn];                         // K[i, i-1] = K[i-1, i]^T
+            acc[a] += kij * xp;
+          }
+        }
+      }
+      if (any) {
+        for (int a = 0; a < 6; ++a) Zr[6 * f + a] -= acc[a];
+      }
+    }
+  }
+  __syncthreads();
+  for (int64_t f = lane; f < nf; f += NT) {
+    const int64_t i = f + 1;
+    for (int k = 0; k < 3; ++k)
+      if (guided_dof(d, r, i, k)) Zr[6 * f + k] = d.base_pos[3 * r + k] - d.X[k * N + o + i];
+  }
+  __syncthreads();
+
+  // ---------------------------------------------------------------- block Cholesky (lane 0)
+  __shared__ int s_fail;
+  if (lane == 0) {
+    s_fail = 0;
+    double Lp[36];   // L[f, f-1]
+    for (int f = 0; f < nf && !s_fail; ++f) {
+      const int64_t i = f + 1, g = o + i;
+      bool gd[6];
+      for (int k = 0; k < 6; ++k) gd[k] = guided_dof(d, r, i, k);
+      double A[36];
+      for (int a = 0; a < 6; ++a)
+        for (int b = 0; b < 6; ++b) {
+          double v = d.KD[(a * 6 + b) * N + g];
+          if (gd[a] || gd[b]) v = (a == b) ? 1.0 : 0.0;
+          A[a * 6 + b] = v;
+        }
+      if (f > 0) {
+        for (int a = 0; a < 6; ++a)
+          for (int b = 0; b <= a; ++b) {
+            double s = 0.0;
+            for (int k = 0; k < 6; ++k) s += Lp[a * 6 + k] * Lp[b * 6 + k];
+            A[a * 6 + b] -= s;
+          }
+      }
+      // Cholesky of the 6x6 block (lower triangle of A)
+      for (int k = 0; k < 6; ++k) {
+        double s = A[k * 6 + k];
+        for (int j = 0; j < k; ++j) s -= A[k * 6 + j] * A[k * 6 + j];
+        if (!(s > 0.0)) { s_fail = 1; break; }
+        const double lkk = sqrt(s);
+        A[k * 6 + k] = lkk;
+        for (int a = k + 1; a < 6; ++a) {
+          double t = A[a * 6 + k];
+          for (int j = 0; j < k; ++j) t -= A[a * 6 + j] * A[k * 6 + j];
+          A[a * 6 + k] = t / lkk;
+        }
+      }
+      if (s_fail) break;
+      for (int a = 0; a < 6; ++a)
+        for (int b = 0; b < 6; ++b) d.LD[(a * 6 + b) * N + g] = (b <= a) ? A[a * 6 + b] : 0.0;
+      if (f + 1 < nf) {
+        // X = S^T L^-T with S = K[i, i+1] (rows of prescribed DOFs of i and columns of
+        // prescribed DOFs of i+1 removed): row a of X solves L x = S[:, a]
+        bool gn[6];
+        for (int k = 0; k < 6; ++k) gn[k] = guided_dof(d, r, i + 1, k);
+        for (int a = 0; a < 6; ++a) {
+          double x[6];
+          for (int b = 0; b < 6; ++b) {
+            double sv = (gd[b] || gn[a]) ? 0.0 : d.KS[(b * 6 + a) * N + g];
+            double t = sv;
+            for (int j = 0; j < b; ++j) t -= A[b * 6 + j] * x[j];
+            x[b] = t / A[b * 6 + b];
+          }
+          for (int b = 0; b < 6; ++b) { Lp[a * 6 + b] = x[b]; d.LS[(a * 6 + b) * N + g] = x[b]; }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (s_fail) {
+    finish(d, r, 3, it, d.st_rn[r]);
+    return;
+  }
+
+  // ---------------------------------------------------------------- substitutions (lane = column)
+  for (int c = lane; c < ncol; c += NT) {
+    double* z = Zr + (int64_t)c * ld;
+    double yp[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t f = 0; f < nf; ++f) {
+      const int64_t g = o + f + 1;
+      double b[6];
+      for (int a = 0; a < 6; ++a) b[a] = z[6 * f + a];
+      if (f > 0) {
+        const int64_t gp = g - 1;   // L[f, f-1] stored at the previous node
+        for (int a = 0; a < 6; ++a) {
+          double s = 0.0;
+          for (int k = 0; k < 6; ++k) s += d.LS[(a * 6 + k) * N + gp] * yp[k];
+          b[a] -= s;
+        }
+      }
+      for (int a = 0; a < 6; ++a) {
+        double t = b[a];
+        for (int k = 0; k < a; ++k) t -= d.LD[(a * 6 + k) * N + g] * b[k];
+        b[a] = t / d.LD[(a * 6 + a) * N + g];
+      }
+      for (int a = 0; a < 6; ++a) { z[6 * f + a] = b[a]; yp[a] = b[a]; }
+    }
+    double xn[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t f = nf - 1; f >= 0; --f) {
+      const int64_t g = o + f + 1;
+      double b[6];
+      for (int a = 0; a < 6; ++a) b[a] = z[6 * f + a];
+      if (f + 1 < nf) {
+        // - L[f+1, f]^T x_{f+1}; L[f+1, f] stored at node g
+        for (int a = 0; a < 6; ++a) {
+          double s = 0.0;
+          for (int k = 0; k < 6; ++k) s += d.LS[(k * 6 + a) * N + g] * xn[k];
+          b[a] -= s;
+        }
+      }
+      for (int a = 5; a >= 0; --a) {
+        double t = b[a];
+        for (int k = a + 1; k < 6; ++k) t -= d.LD[(k * 6 + a) * N + g] * b[k];
+        b[a] = t / d.LD[(a * 6 + a) * N + g];
+      }
+      for (int a = 0; a < 6; ++a) { z[6 * f + a] = b[a]; xn[a] = b[a]; }
+    }
+  }
+  __syncthreads();
+
+  // ---------------------------------------------------------------- Schur complement + LCP
+  double* W = d.W + (int64_t)r * cap * cap;
+  double* qv = d.q + cb;
+  for (int e = lane; e < nc * nc; e += NT) {
+    const int a = e / nc, b = e % nc;
+    const int64_t f = d.ct_node[cb + a] - 1;
+    const double* zb = Zr + (int64_t)(1 + b) * ld + 6 * f;
+    W[a * cap + b] = d.ct_n[3 * (cb + a)] * zb[0] + d.ct_n[3 * (cb + a) + 1] * zb[1] +
+                     d.ct_n[3 * (cb + a) + 2] * zb[2];
+  }
+  for (int a = lane; a < nc; a += NT) {
+    const int64_t f = d.ct_node[cb + a] - 1;
+    const double* z0 = Zr + 6 * f;
+    qv[a] = d.ct_gap[cb + a] + d.ct_n[3 * (cb + a)] * z0[0] + d.ct_n[3 * (cb + a) + 1] * z0[1] +
+            d.ct_n[3 * (cb + a) + 2] * z0[2];
+  }
+  __syncthreads();
+  __shared__ int s_lcp_ok;
+  double* y = d.ct_y + cb;
+  if (lane == 0) {
+    s_lcp_ok = 1;
+    if (nc > 0) {
+      double* scratch = d.W + (int64_t)d.B * cap * cap + (int64_t)r * (cap * cap + 3 * cap);
+      s_lcp_ok = lcp_active_set(W, qv, nc, cap, y, scratch) ? 1 : 0;
+    }
+  }
+  __syncthreads();
+  if (!s_lcp_ok) {
+    finish(d, r, 2, it, d.st_rn[r]);
+    return;
+  }
+
+  // ---------------------------------------------------------------- step, limit, update
+  for (int64_t j = lane; j < 6 * nf; j += NT) {
+    double v = Zr[j];
+    for (int c = 0; c < nc; ++c) v += y[c] * Zr[(int64_t)(1 + c) * ld + j];
+    Zr[j] = v;
+  }
+  __syncthreads();
+  double mx = 0.0;
+  for (int64_t f = lane; f < nf; f += NT) {
+    const double* z = Zr + 6 * f;
+    mx = fmax(mx, sqrt(z[0] * z[0] + z[1] * z[1] + z[2] * z[2]));
+  }
+  mx = warp_max(mx);
+  mx = fmax(mx, sqrt(dx0[0] * dx0[0] + dx0[1] * dx0[1] + dx0[2] * dx0[2]));
+  const int nsw = d.st_nswitch[r];
+  const double beta = d.beta0 * fmax(1.0 / 64.0, ldexp(1.0, -(nsw / 10)));
+  const bool limited = mx > beta;
+  const double sc = limited ? beta / mx : 1.0;
+  // base node: translation only
+  if (lane == 0) {
+    for (int k = 0; k < 3; ++k) d.X[k * N + o] += sc * dx0[k];
+  }
+  for (int64_t f = lane; f < nf; f += NT) {
+    const int64_t g = o + f + 1;
+    const double* z = Zr + 6 * f;
+    for (int k = 0; k < 3; ++k) d.X[k * N + g] += sc * z[k];
+    const double wx = sc * z[3], wy = sc * z[4], wz = sc * z[5];
+    const double th = sqrt(wx * wx + wy * wy + wz * wz);
+    double cw, sw;
+    if (th < 1e-8) {
+      cw = 1.0 - th * th / 8.0;
+      sw = 0.5 - th * th / 48.0;          // sin(th/2)/th
+    } else {
+      cw = cos(0.5 * th);
+      sw = sin(0.5 * th) / th;
+    }
+    const double ew = cw, ex = sw * wx, ey = sw * wy, ez = sw * wz;
+    const double qw = d.X[3 * N + g], qx = d.X[4 * N + g], qy = d.X[5 * N + g], qz = d.X[6 * N + g];
+    double nw = ew * qw - ex * qx - ey * qy - ez * qz;
+    double nx = ew * qx + ex * qw + ey * qz - ez * qy;
+    double ny = ew * qy - ex * qz + ey * qw + ez * qx;
+    double nz = ew * qz + ex * qy - ey * qx + ez * qw;
+    const double inv = 1.0 / sqrt(nw * nw + nx * nx + ny * ny + nz * nz);
+    d.X[3 * N + g] = nw * inv; d.X[4 * N + g] = nx * inv; d.X[5 * N + g] = ny * inv; d.X[6 * N + g] = nz * inv;
+  }
+  // the solved contacts become the previous list (forces scaled with the step)
+  for (int c = lane; c < nc; c += NT) {
+    d.cp_node[cb + c] = d.ct_node[cb + c];
+    d.cp_tri[cb + c] = d.ct_tri[cb + c];
+    d.cp_kind[cb + c] = d.ct_kind[cb + c];
+    d.cp_gap[cb + c] = d.ct_gap[cb + c];
+    d.cp_y[cb + c] = sc * y[c];
+    for (int k = 0; k < 3; ++k) d.cp_n[3 * (cb + c) + k] = d.ct_n[3 * (cb + c) + k];
+  }
+  if (lane == 0) {
+    d.st_ncp[r] = nc;
+    d.st_limited[r] = limited ? 1 : 0;
+    d.st_nlim[r] += limited ? 1 : 0;
+    d.st_iters[r] = it + 1;
+  }
+}
+
+// detection-only path: compact the per-node contacts of every robot (no step)
+__global__ void __launch_bounds__(NT) gather_kernel(Dev d) {
+  const int r = blockIdx.x;
+  int nc;
+  bool ovf;
+  gather_contacts(d, r, &nc, &ovf);
+  __syncthreads();
+  const int cap = d.cap;
+  const int64_t cb = (int64_t)r * cap;
+  if (!ovf) {
+    for (int c = threadIdx.x; c < nc; c += NT) {
+      d.cp_node[cb + c] = d.ct_node[cb + c];
+      d.cp_tri[cb + c] = d.ct_tri[cb + c];
+      d.cp_kind[cb + c] = d.ct_kind[cb + c];
+      d.cp_gap[cb + c] = d.ct_gap[cb + c];
+      d.cp_y[cb + c] = 0.0;
+      for (int k = 0; k < 3; ++k) d.cp_n[3 * (cb + c) + k] = d.ct_n[3 * (cb + c) + k];
+    }
+  }
+  if (threadIdx.x == 0) {
+    d.st_ncp[r] = ovf ? 0 : nc;
+    d.st_nc[r] = nc;
+  }
+}
+
+void launch_solve(const Dev& d, int it, hipStream_t s) {
+  hipLaunchKernelGGL(solve_kernel, dim3(d.B), dim3(NT), 0, s, d, it);
+}
+
+void launch_gather(const Dev& d, hipStream_t s) {
+  hipLaunchKernelGGL(gather_kernel, dim3(d.B), dim3(NT), 0, s, d);
+}
+
+}  // namespace accfem
