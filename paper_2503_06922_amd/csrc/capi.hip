@@ -707,13 +707,19 @@ fem_status fem_eval(fem_ctx* c, double* F, double* KD, double* KS) {
   launch_collide(d, c->stream);
   launch_gather(d, c->stream);
   HIP_TRY(c, hipGetLastError());
-  struct { double* dst; double* src; int K; } outs[3] = {{F, d.F, 6}, {KD, d.KD, 36}, {KS, d.KS, 36}};
-  for (auto& o : outs) {
-    if (!o.dst) continue;
-    hipLaunchKernelGGL(soa_to_aos, dim3(nblk(c->Ntot, 256)), dim3(256), 0, c->stream, o.src, d.LS,
-                       c->Ntot, o.K);
+  if (F) {
+    hipLaunchKernelGGL(soa_to_aos, dim3(nblk(c->Ntot, 256)), dim3(256), 0, c->stream, d.F, d.LS,
+                       c->Ntot, 6);
     HIP_TRY(c, hipGetLastError());
-    fem_status s = copy_out(c, o.dst, d.LS, (size_t)c->Ntot * o.K * sizeof(double));
+    fem_status s = copy_out(c, F, d.LS, (size_t)c->Ntot * 6 * sizeof(double));
+    if (s != FEM_OK) return s;
+  }
+  if (KD) {
+    fem_status s = copy_out(c, KD, d.KD, (size_t)c->Ntot * 36 * sizeof(double));
+    if (s != FEM_OK) return s;
+  }
+  if (KS) {
+    fem_status s = copy_out(c, KS, d.KS, (size_t)c->Ntot * 36 * sizeof(double));
     if (s != FEM_OK) return s;
   }
   HIP_TRY(c, hipStreamSynchronize(c->stream));

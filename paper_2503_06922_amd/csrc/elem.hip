@@ -13,7 +13,8 @@
 // section axes its 3x3 blocks depend on e1 only:
 //   diag(x, y, y) -> y I + (x - y) e1 e1^T,   local skew blocks -> +-k2 [e1]x.
 // One thread per node computes its two adjacent elements and writes the node's
-// out-of-balance force F_i (6), diagonal block D_i (6x6) and coupling K[i, i+1].
+// out-of-balance force F_i (6, component-major) and the diagonal block D_i and
+// coupling block K[i, i+1] (6x6 each, node-major: the per-robot sweeps read them in node order).
 #include "fem_device.h"
 
 namespace accfem {
@@ -192,7 +193,7 @@ __global__ void __launch_bounds__(256) elem_kernel(Dev d) {
 #pragma unroll
   for (int k = 0; k < 6; ++k) d.F[k * N + g] = F[k];
 #pragma unroll
-  for (int k = 0; k < 36; ++k) { d.KD[k * N + g] = D[k]; d.KS[k * N + g] = S[k]; }
+  for (int k = 0; k < 36; ++k) { d.KD[g * 36 + k] = D[k]; d.KS[g * 36 + k] = S[k]; }
 }
 
 void launch_elem(const Dev& d, hipStream_t s) {

@@ -4,13 +4,13 @@
 //   node state   X[k*Ntot + g], k = 0..6 : px py pz qw qx qy qz      (FP64)
 //   rigidities   EA[g], EI[g], GJ[g]     : element g -> g+1 (the tip slot is unused)
 //   out-of-bal.  F[k*Ntot + g], k = 0..5 : internal force minus actuation
-//   tangent      KD[k*Ntot + g], k = 0..35: 6x6 diagonal block of node g (row major)
-//                KS[k*Ntot + g], k = 0..35: 6x6 block K[g, g+1]
-//   factor       LD[k*Ntot + g], LS[k*Ntot + g]: Cholesky blocks L[g,g] and L[g+1,g]
+//   tangent      KD[g*36 + k], k = 0..35: 6x6 diagonal block of node g (row major, node-major)
+//                KS[g*36 + k]           : 6x6 block K[g, g+1]
+//   factor       LD[g*36 + k], LS[g*36 + k]: Cholesky blocks L[g,g] and L[g+1,g]
 //   node contacts (detection output, up to MAXC per node): CC[g], CT/CK/CG[s*Ntot+g],
 //                CN[(3*s+d)*Ntot + g]
 //   per-robot contact lists, solutions and Schur matrices live at per-robot
-//   offsets (see RobotConst).
+//   offsets (robot r: contacts at r*cap, right-hand sides / solutions at zoff[r]).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>

@@ -26,6 +26,8 @@
 namespace accfem {
 
 constexpr int NT = SOLVE_THREADS;
+constexpr int CH = 16;                     // nodes per staged chunk
+constexpr int PF = (CH * 36 + NT - 1) / NT;  // prefetch registers per lane and array
 
 __device__ __forceinline__ double warp_sum(double v) {
 #pragma unroll
@@ -310,7 +312,7 @@ __global__ void __launch_bounds__(NT) solve_kernel(Dev d, int it) {
     // rows of node 1 (f = 0): -= K[1,0] dx0 = S_0^T dx0 (S_0 = K[0,1] stored at the base)
     for (int a = 0; a < 6; ++a) {
       double s = 0.0;
-      for (int b = 0; b < 3; ++b) s += d.KS[(b * 6 + a) * N + o] * dx0[b];
+      for (int b = 0; b < 3; ++b) s += d.KS[o * 36 + b * 6 + a] * dx0[b];
       Zr[a] -= s;
     }
   }
@@ -330,9 +332,9 @@ __global__ void __launch_bounds__(NT) solve_kernel(Dev d, int it) {
           any = true;
           for (int a = 0; a < 6; ++a) {
             double kij;
-            if (jn == i) kij = d.KD[(a * 6 + k) * N + o + i];
-            else if (jn == i + 1) kij = d.KS[(a * 6 + k) * N + o + i];        // K[i, i+1]
-            else kij = d.KS[(k * 6 + a) * N + o + jn];                         // K[i, i-1] = K[i-1, i]^T
+            if (jn == i) kij = d.KD[(o + i) * 36 + a * 6 + k];
+            else if (jn == i + 1) kij = d.KS[(o + i) * 36 + a * 6 + k];     // K[i, i+1]
+            else kij = d.KS[(o + jn) * 36 + k * 6 + a];                      // K[i, i-1] = K[i-1, i]^T
             acc[a] += kij * xp;
           }
         }
@@ -350,61 +352,89 @@ __global__ void __launch_bounds__(NT) solve_kernel(Dev d, int it) {
   }
   __syncthreads();
 
-  // ---------------------------------------------------------------- block Cholesky (lane 0)
+  // ---------------------------------------------------------------- block Cholesky
+  // Serial over nodes; inside a node lane L < 36 owns entry (a, b) = (L / 6, L % 6):
+  //   A = D_i - L[f,f-1] L[f,f-1]^T,  L[f,f] = chol(A),  L[f+1,f] = S_i^T L[f,f]^-T
+  // with S_i = K[i, i+1]; rows/columns of prescribed DOFs are replaced by the identity.
+  // The blocks of CH nodes are staged in LDS per chunk; the next chunk is loaded into
+  // registers while the current one is factored, which hides the HBM latency.
+  __shared__ double sA[36], sL[36], sX[36], sLp[36], sS[36];
+  __shared__ double sKD[CH * 36], sKS[CH * 36];
   __shared__ int s_fail;
-  if (lane == 0) {
-    s_fail = 0;
-    double Lp[36];   // L[f, f-1]
-    for (int f = 0; f < nf && !s_fail; ++f) {
-      const int64_t i = f + 1, g = o + i;
-      bool gd[6];
-      for (int k = 0; k < 6; ++k) gd[k] = guided_dof(d, r, i, k);
-      double A[36];
-      for (int a = 0; a < 6; ++a)
-        for (int b = 0; b < 6; ++b) {
-          double v = d.KD[(a * 6 + b) * N + g];
-          if (gd[a] || gd[b]) v = (a == b) ? 1.0 : 0.0;
-          A[a * 6 + b] = v;
-        }
-      if (f > 0) {
-        for (int a = 0; a < 6; ++a)
-          for (int b = 0; b <= a; ++b) {
-            double s = 0.0;
-            for (int k = 0; k < 6; ++k) s += Lp[a * 6 + k] * Lp[b * 6 + k];
-            A[a * 6 + b] -= s;
-          }
+  {
+    const int a = lane / 6, b = lane % 6;
+    if (lane < 36) { sLp[lane] = 0.0; sL[lane] = 0.0; sX[lane] = 0.0; }
+    if (lane == 0) s_fail = 0;
+    double pd[PF], ps[PF];
+    auto fetch = [&](int64_t f0) {
+      const int64_t cnt = min((int64_t)CH, nf - f0) * 36;
+      const double* kd = d.KD + (o + 1 + f0) * 36;
+      const double* ks = d.KS + (o + 1 + f0) * 36;
+#pragma unroll
+      for (int u = 0; u < PF; ++u) {
+        const int64_t idx = lane + (int64_t)u * NT;
+        pd[u] = idx < cnt ? kd[idx] : 0.0;
+        ps[u] = idx < cnt ? ks[idx] : 0.0;
       }
-      // Cholesky of the 6x6 block (lower triangle of A)
-      for (int k = 0; k < 6; ++k) {
-        double s = A[k * 6 + k];
-        for (int j = 0; j < k; ++j) s -= A[k * 6 + j] * A[k * 6 + j];
-        if (!(s > 0.0)) { s_fail = 1; break; }
-        const double lkk = sqrt(s);
-        A[k * 6 + k] = lkk;
-        for (int a = k + 1; a < 6; ++a) {
-          double t = A[a * 6 + k];
-          for (int j = 0; j < k; ++j) t -= A[a * 6 + j] * A[k * 6 + j];
-          A[a * 6 + k] = t / lkk;
+    };
+    fetch(0);
+    for (int64_t f0 = 0; f0 < nf && !s_fail; f0 += CH) {
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < PF; ++u) { sKD[lane + u * NT] = pd[u]; sKS[lane + u * NT] = ps[u]; }
+      __syncthreads();
+      if (f0 + CH < nf) fetch(f0 + CH);
+      const int64_t f1 = min(nf, f0 + CH);
+      for (int64_t f = f0; f < f1; ++f) {
+        const int64_t i = f + 1, g = o + i;
+        const int lf = (int)(f - f0) * 36;
+        const bool last = (f + 1 == nf);
+        if (lane < 36) {
+          double dv = sKD[lf + lane];
+          if (guided_dof(d, r, i, a) || guided_dof(d, r, i, b)) dv = (a == b) ? 1.0 : 0.0;
+          double acc = dv;
+#pragma unroll
+          for (int k = 0; k < 6; ++k) acc -= sLp[a * 6 + k] * sLp[b * 6 + k];
+          sA[lane] = acc;
+          double sv = last ? 0.0 : sKS[lf + lane];             // K[i, i+1](a, b)
+          if (!last && (guided_dof(d, r, i, a) || guided_dof(d, r, i + 1, b))) sv = 0.0;
+          sS[lane] = sv;
         }
-      }
-      if (s_fail) break;
-      for (int a = 0; a < 6; ++a)
-        for (int b = 0; b < 6; ++b) d.LD[(a * 6 + b) * N + g] = (b <= a) ? A[a * 6 + b] : 0.0;
-      if (f + 1 < nf) {
-        // X = S^T L^-T with S = K[i, i+1] (rows of prescribed DOFs of i and columns of
-        // prescribed DOFs of i+1 removed): row a of X solves L x = S[:, a]
-        bool gn[6];
-        for (int k = 0; k < 6; ++k) gn[k] = guided_dof(d, r, i + 1, k);
-        for (int a = 0; a < 6; ++a) {
-          double x[6];
-          for (int b = 0; b < 6; ++b) {
-            double sv = (gd[b] || gn[a]) ? 0.0 : d.KS[(b * 6 + a) * N + g];
-            double t = sv;
-            for (int j = 0; j < b; ++j) t -= A[b * 6 + j] * x[j];
-            x[b] = t / A[b * 6 + b];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          if (lane == k * 7) {
+            double t = sA[lane];
+            for (int j = 0; j < k; ++j) t -= sL[k * 6 + j] * sL[k * 6 + j];
+            if (!(t > 0.0)) { s_fail = 1; t = 1.0; }
+            sL[lane] = sqrt(t);
           }
-          for (int b = 0; b < 6; ++b) { Lp[a * 6 + b] = x[b]; d.LS[(a * 6 + b) * N + g] = x[b]; }
+          __syncthreads();
+          if (lane < 36 && b == k && a > k) {
+            double t = sA[lane];
+            for (int j = 0; j < k; ++j) t -= sL[a * 6 + j] * sL[k * 6 + j];
+            sL[lane] = t / sL[k * 7];
+          }
+          __syncthreads();
         }
+        if (!last) {
+          // row a of X solves L x = S[:, a]
+#pragma unroll
+          for (int bb = 0; bb < 6; ++bb) {
+            if (lane < 36 && b == bb) {
+              double t = sS[bb * 6 + a];
+              for (int j = 0; j < bb; ++j) t -= sL[bb * 6 + j] * sX[a * 6 + j];
+              sX[lane] = t / sL[bb * 7];
+            }
+            __syncthreads();
+          }
+        }
+        if (lane < 36) {
+          d.LD[g * 36 + lane] = sL[lane];
+          if (!last) d.LS[g * 36 + lane] = sX[lane];
+          sLp[lane] = last ? 0.0 : sX[lane];
+        }
+        __syncthreads();
       }
     }
   }
@@ -414,48 +444,120 @@ __global__ void __launch_bounds__(NT) solve_kernel(Dev d, int it) {
     return;
   }
 
-  // ---------------------------------------------------------------- substitutions (lane = column)
-  for (int c = lane; c < ncol; c += NT) {
-    double* z = Zr + (int64_t)c * ld;
-    double yp[6] = {0, 0, 0, 0, 0, 0};
-    for (int64_t f = 0; f < nf; ++f) {
-      const int64_t g = o + f + 1;
-      double b[6];
-      for (int a = 0; a < 6; ++a) b[a] = z[6 * f + a];
-      if (f > 0) {
-        const int64_t gp = g - 1;   // L[f, f-1] stored at the previous node
-        for (int a = 0; a < 6; ++a) {
-          double s = 0.0;
-          for (int k = 0; k < 6; ++k) s += d.LS[(a * 6 + k) * N + gp] * yp[k];
-          b[a] -= s;
+  // ---------------------------------------------------------------- substitutions
+  // six lanes per right-hand side (lane = row of the 6-block), ten columns per pass;
+  // factor blocks are staged per chunk of CH nodes like above (forward: LD[f], LS[f-1];
+  // backward: LD[f], LS[f]).
+  for (int c0 = 0; c0 < ncol; c0 += 10) {
+    const int grp = lane / 6, a = lane % 6, base = min(grp, 9) * 6;
+    const int c = c0 + grp;
+    const bool act = (lane < 60) && (c < ncol);
+    double* z = Zr + (int64_t)(act ? c : 0) * ld;
+    double pd[PF], ps[PF];
+    // forward sweep: chunk f0 needs LD of nodes f0..f1-1 and LS of nodes f0-1..f1-2
+    auto fetchF = [&](int64_t f0) {
+      const int64_t cnt = min((int64_t)CH, nf - f0) * 36;
+      const double* ldp = d.LD + (o + 1 + f0) * 36;
+      const double* lsp = d.LS + (o + f0) * 36;          // node f0-1 (the base slot when f0 = 0)
+#pragma unroll
+      for (int u = 0; u < PF; ++u) {
+        const int64_t idx = lane + (int64_t)u * NT;
+        pd[u] = idx < cnt ? ldp[idx] : 0.0;
+        ps[u] = idx < cnt ? lsp[idx] : 0.0;
+      }
+    };
+    double yprev = 0.0;
+    fetchF(0);
+    for (int64_t f0 = 0; f0 < nf; f0 += CH) {
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < PF; ++u) { sKD[lane + u * NT] = pd[u]; sKS[lane + u * NT] = ps[u]; }
+      __syncthreads();
+      if (f0 + CH < nf) fetchF(f0 + CH);
+      const int64_t f1 = min(nf, f0 + CH);
+      double zc[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) zc[u] = (act && f0 + u < f1) ? z[6 * (f0 + u) + a] : 0.0;
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int64_t f = f0 + u;
+        if (f >= f1) break;
+        double bv = zc[u];
+        if (f > 0) {
+          const double* Ls = sKS + u * 36 + a * 6;        // L[f, f-1] row a
+#pragma unroll
+          for (int k = 0; k < 6; ++k) {
+            const double yk = __shfl(yprev, base + k);
+            bv -= Ls[k] * yk;
+          }
         }
+        const double* Ld = sKD + u * 36;
+        double y = 0.0;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          if (a == k) y = bv / Ld[k * 7];
+          const double yk = __shfl(y, base + k);
+          if (a > k) bv -= Ld[a * 6 + k] * yk;
+        }
+        zc[u] = y;
+        yprev = y;
       }
-      for (int a = 0; a < 6; ++a) {
-        double t = b[a];
-        for (int k = 0; k < a; ++k) t -= d.LD[(a * 6 + k) * N + g] * b[k];
-        b[a] = t / d.LD[(a * 6 + a) * N + g];
-      }
-      for (int a = 0; a < 6; ++a) { z[6 * f + a] = b[a]; yp[a] = b[a]; }
+#pragma unroll
+      for (int u = 0; u < CH; ++u)
+        if (act && f0 + u < f1) z[6 * (f0 + u) + a] = zc[u];
     }
-    double xn[6] = {0, 0, 0, 0, 0, 0};
-    for (int64_t f = nf - 1; f >= 0; --f) {
-      const int64_t g = o + f + 1;
-      double b[6];
-      for (int a = 0; a < 6; ++a) b[a] = z[6 * f + a];
-      if (f + 1 < nf) {
-        // - L[f+1, f]^T x_{f+1}; L[f+1, f] stored at node g
-        for (int a = 0; a < 6; ++a) {
-          double s = 0.0;
-          for (int k = 0; k < 6; ++k) s += d.LS[(k * 6 + a) * N + g] * xn[k];
-          b[a] -= s;
+    // backward sweep over chunks from the tip: chunk [f0, f1) needs LD and LS of f0..f1-1
+    auto fetchB = [&](int64_t f0, int64_t f1) {
+      const int64_t cnt = (f1 - f0) * 36;
+      const double* ldp = d.LD + (o + 1 + f0) * 36;
+      const double* lsp = d.LS + (o + 1 + f0) * 36;
+#pragma unroll
+      for (int u = 0; u < PF; ++u) {
+        const int64_t idx = lane + (int64_t)u * NT;
+        pd[u] = idx < cnt ? ldp[idx] : 0.0;
+        ps[u] = idx < cnt ? lsp[idx] : 0.0;
+      }
+    };
+    double xnext = 0.0;
+    const int64_t nch = (nf + CH - 1) / CH;
+    fetchB((nch - 1) * CH, nf);
+    for (int64_t ch = nch - 1; ch >= 0; --ch) {
+      const int64_t f0 = ch * CH, f1 = min(nf, f0 + CH);
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < PF; ++u) { sKD[lane + u * NT] = pd[u]; sKS[lane + u * NT] = ps[u]; }
+      __syncthreads();
+      if (ch > 0) fetchB(f0 - CH, f0);
+      double zc[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) zc[u] = (act && f0 + u < f1) ? z[6 * (f0 + u) + a] : 0.0;
+#pragma unroll
+      for (int u = CH - 1; u >= 0; --u) {
+        const int64_t f = f0 + u;
+        if (f >= f1) continue;
+        double bv = zc[u];
+        if (f + 1 < nf) {
+          const double* Ls = sKS + u * 36;                // L[f+1, f]; its column a
+#pragma unroll
+          for (int k = 0; k < 6; ++k) {
+            const double xk = __shfl(xnext, base + k);
+            bv -= Ls[k * 6 + a] * xk;
+          }
         }
+        const double* Ld = sKD + u * 36;
+        double x = 0.0;
+#pragma unroll
+        for (int k = 5; k >= 0; --k) {
+          if (a == k) x = bv / Ld[k * 7];
+          const double xk = __shfl(x, base + k);
+          if (a < k) bv -= Ld[k * 6 + a] * xk;
+        }
+        zc[u] = x;
+        xnext = x;
       }
-      for (int a = 5; a >= 0; --a) {
-        double t = b[a];
-        for (int k = a + 1; k < 6; ++k) t -= d.LD[(k * 6 + a) * N + g] * b[k];
-        b[a] = t / d.LD[(a * 6 + a) * N + g];
-      }
-      for (int a = 0; a < 6; ++a) { z[6 * f + a] = b[a]; xn[a] = b[a]; }
+#pragma unroll
+      for (int u = 0; u < CH; ++u)
+        if (act && f0 + u < f1) z[6 * (f0 + u) + a] = zc[u];
     }
   }
   __syncthreads();
