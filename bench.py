@@ -109,7 +109,7 @@ def main():
 
     for _ in range(args.warmup):
         run_schedule(ctx, rb, args.load_steps, X0)
-    for k in range(3):
+    for k in range(6):
         ctx.fem_profile(k, reset=True)
     # timed region: whole-batch insertions; each fem_solve returns after its stream synchronises
     ctx.fem_set_state(X0)  # resets the per-robot counters
@@ -117,17 +117,18 @@ def main():
     for _ in range(args.steps):
         run_schedule(ctx, rb, args.load_steps, X0)
     dt = time.perf_counter() - t0
-    prof = [ctx.fem_profile(k) for k in range(3)]
+    prof = [ctx.fem_profile(k) for k in range(6)]
     # counters cover the last schedule only (fem_set_state resets them): scale to all steps
     conv, total, iters, info = solves_of(ctx)
     solves = conv * args.steps
     value = solves / dt
     node_launches = sum((i["iters_total"] + i["steps_total"]) * (int(rb.n_elem[b]) + 1)
                         for b, i in enumerate(info)) * args.steps
-    names = ["elem_kernel", "collide_kernel", "solve_kernel"]
+    names = ["elem_kernel", "collide_kernel", "check_rhs_kernel", "factor_kernel", "subst_kernel",
+             "update_kernel"]
     kern = {names[k]: dict(total_ms=prof[k][0], launches=prof[k][1],
-                           avg_us=1e3 * prof[k][0] / max(prof[k][1], 1)) for k in range(3)}
-    dom = max(range(3), key=lambda k: prof[k][0])
+                           avg_us=1e3 * prof[k][0] / max(prof[k][1], 1)) for k in range(6)}
+    dom = max(range(6), key=lambda k: prof[k][0])
     # roofline of the element update (HBM-bound by design): algorithmic bytes per launch
     el_launches = max(prof[0][1], 1)
     avg_nodes = node_launches / el_launches

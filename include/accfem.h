@@ -168,7 +168,9 @@ fem_status fem_set_state(fem_ctx* c, const double* node_state);
 fem_status fem_eval(fem_ctx* c, double* F, double* KD, double* KS);
 
 /* Kernel timing of a context created with profile = 1: for kernel class k
- * (0 = element update, 1 = contact detection, 2 = Newton step / solve) the
+ * (0 = element update, 1 = contact detection, 2..5 = the Newton step's phases:
+ * convergence test + right-hand sides, block Cholesky, substitutions, contact
+ * Schur complement + LCP + update) the
  * accumulated device time in ms measured with HIP events on the context's
  * stream, and the number of launches, since the last call with reset = 1. */
 fem_status fem_profile(fem_ctx* c, int32_t kernel, double* total_ms, int64_t* launches,

@@ -15,7 +15,7 @@
 namespace accfem {
 void launch_elem(const Dev& d, hipStream_t s);
 void launch_collide(const Dev& d, hipStream_t s);
-void launch_solve(const Dev& d, int it, hipStream_t s);
+void launch_solve_phase(const Dev& d, int phase, int it, hipStream_t s);
 void launch_gather(const Dev& d, hipStream_t s);
 void launch_tri_setup(const double* V, const int32_t* tri, int64_t T, double* tv, double* tn,
                       float* tvf, float* tnf, hipStream_t s);
@@ -165,8 +165,8 @@ struct fem_ctx {
   // per-kernel event timing
   bool profile = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  double prof_ms[3] = {0, 0, 0};
-  int64_t prof_n[3] = {0, 0, 0};
+  double prof_ms[6] = {0, 0, 0, 0, 0, 0};
+  int64_t prof_n[6] = {0, 0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -628,7 +628,8 @@ fem_status fem_solve(fem_ctx* c, int32_t n_load_steps, double* node_state, fem_s
       fem_status s;
       if ((s = timed(c, 0, [&] { launch_elem(d, c->stream); })) != FEM_OK) return s;
       if ((s = timed(c, 1, [&] { launch_collide(d, c->stream); })) != FEM_OK) return s;
-      if ((s = timed(c, 2, [&] { launch_solve(d, it, c->stream); })) != FEM_OK) return s;
+      for (int ph = 0; ph < 4; ++ph)
+        if ((s = timed(c, 2 + ph, [&] { launch_solve_phase(d, ph, it, c->stream); })) != FEM_OK) return s;
       HIP_TRY(c, hipGetLastError());
       int32_t nd = 0;
       HIP_TRY(c, hipMemcpyAsync(&nd, d.n_done, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
@@ -683,7 +684,7 @@ fem_status fem_solve(fem_ctx* c, int32_t n_load_steps, double* node_state, fem_s
 fem_status fem_profile(fem_ctx* c, int32_t kernel, double* total_ms, int64_t* launches,
                        int32_t reset) {
   if (!c) return FEM_E_INVAL;
-  if (kernel < 0 || kernel > 2) return fail(c, FEM_E_INVAL, "kernel class must be 0..2");
+  if (kernel < 0 || kernel > 5) return fail(c, FEM_E_INVAL, "kernel class must be 0..5");
   if (!c->profile) return fail(c, FEM_E_STATE, "context was created without profile = 1");
   if (total_ms) *total_ms = c->prof_ms[kernel];
   if (launches) *launches = c->prof_n[kernel];

@@ -108,7 +108,8 @@ __global__ void __launch_bounds__(256) collide_kernel(Dev d) {
   int cnt = 0;
   if (i == 0 || d.n_tris == 0) { d.CC[g] = 0; return; }
   if (d.guide_axis[r] >= 0) {
-    double s = (double)i * d.l0[r] + d.depth_cur[r];
+    // reference arc length i*l0 + depth, without contraction (same decision as the solver)
+    const double s = __dadd_rn(__dmul_rn((double)i, d.l0[r]), d.depth_cur[r]);
     if (s < d.guide_len) { d.CC[g] = 0; return; }
   }
   P3<double> p{d.X[g], d.X[N + g], d.X[2 * N + g]};

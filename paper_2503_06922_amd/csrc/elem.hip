@@ -98,21 +98,28 @@ __device__ void element_force(const NodeState& A, const NodeState& Bn, double l0
   *e1_out = e1;
 }
 
-// 3x3 block y I + (x - y) e e^T added into the 6x6 matrix M (row major) at (r0, c0)
-__device__ __forceinline__ void add_iso(double* M, int r0, int c0, V3 e, double x, double y) {
-  double ev[3] = {e.x, e.y, e.z};
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j)
-      M[(r0 + i) * 6 + c0 + j] += (i == j ? y : 0.0) + (x - y) * ev[i] * ev[j];
+// Entry (i, j) of the 3x3 blocks used by the QP tangent:
+//   iso(e; x, y) = y I + (x - y) e e^T,   skew(e; s) = s [e]x
+__device__ __forceinline__ double iso_ij(int i, int j, const double* e, double x, double y) {
+  return (i == j ? y : 0.0) + (x - y) * e[i] * e[j];
+}
+__device__ __forceinline__ double skew_ij(int i, int j, const double* e, double s) {
+  // [e]x = [[0, -ez, ey], [ez, 0, -ex], [-ey, ex, 0]]
+  if (i == j) return 0.0;
+  const int k = 3 - i - j;                       // the remaining axis
+  const double sg = ((j - i + 3) % 3 == 1) ? -1.0 : 1.0;
+  return s * sg * e[k];
 }
 
-// s [e]x added at (r0, c0)
-__device__ __forceinline__ void add_skew(double* M, int r0, int c0, V3 e, double s) {
-  M[(r0 + 0) * 6 + c0 + 1] += -s * e.z; M[(r0 + 0) * 6 + c0 + 2] += s * e.y;
-  M[(r0 + 1) * 6 + c0 + 0] += s * e.z;  M[(r0 + 1) * 6 + c0 + 2] += -s * e.x;
-  M[(r0 + 2) * 6 + c0 + 0] += -s * e.y; M[(r0 + 2) * 6 + c0 + 1] += s * e.x;
+struct ElemK { double e[3]; double a, t, k1, k2, k3, k4; bool on; };
+
+__device__ __forceinline__ ElemK elem_coeffs(V3 e1, double l0, double EA, double EI, double GJ) {
+  ElemK k;
+  k.e[0] = e1.x; k.e[1] = e1.y; k.e[2] = e1.z;
+  k.a = EA / l0; k.t = GJ / l0; k.k1 = 12.0 * EI / (l0 * l0 * l0); k.k2 = 6.0 * EI / (l0 * l0);
+  k.k3 = 4.0 * EI / l0; k.k4 = 2.0 * EI / l0;
+  k.on = true;
+  return k;
 }
 
 __global__ void __launch_bounds__(256) elem_kernel(Dev d) {
@@ -127,46 +134,27 @@ __global__ void __launch_bounds__(256) elem_kernel(Dev d) {
   const int64_t N = d.Ntot;
 
   double F[6] = {0, 0, 0, 0, 0, 0};
-  double D[36];
-  double S[36];
-#pragma unroll
-  for (int k = 0; k < 36; ++k) { D[k] = 0.0; S[k] = 0.0; }
-
+  ElemK L{}, R{};
+  L.on = false;
+  R.on = false;
   NodeState me = load_node(d, g);
   if (i > 0) {  // element (i-1, i): this node is its end b
     NodeState A = load_node(d, g - 1);
-    double EA = d.EA[g - 1], EI = d.EI[g - 1], GJ = d.GJ[g - 1];
     double fa[6], fb[6];
     V3 e1;
-    element_force(A, me, l0, EA, EI, GJ, fa, fb, &e1);
+    element_force(A, me, l0, d.EA[g - 1], d.EI[g - 1], d.GJ[g - 1], fa, fb, &e1);
 #pragma unroll
     for (int k = 0; k < 6; ++k) F[k] += fb[k];
-    const double a = EA / l0, t = GJ / l0, k1 = 12.0 * EI / (l0 * l0 * l0),
-                 k2 = 6.0 * EI / (l0 * l0), k3 = 4.0 * EI / l0;
-    add_iso(D, 0, 0, e1, a, k1);
-    add_skew(D, 0, 3, e1, k2);
-    add_skew(D, 3, 0, e1, -k2);
-    add_iso(D, 3, 3, e1, t, k3);
+    L = elem_coeffs(e1, l0, d.EA[g - 1], d.EI[g - 1], d.GJ[g - 1]);
   }
   if (i < n - 1) {  // element (i, i+1): this node is its end a
     NodeState Bn = load_node(d, g + 1);
-    double EA = d.EA[g], EI = d.EI[g], GJ = d.GJ[g];
     double fa[6], fb[6];
     V3 e1;
-    element_force(me, Bn, l0, EA, EI, GJ, fa, fb, &e1);
+    element_force(me, Bn, l0, d.EA[g], d.EI[g], d.GJ[g], fa, fb, &e1);
 #pragma unroll
     for (int k = 0; k < 6; ++k) F[k] += fa[k];
-    const double a = EA / l0, t = GJ / l0, k1 = 12.0 * EI / (l0 * l0 * l0),
-                 k2 = 6.0 * EI / (l0 * l0), k3 = 4.0 * EI / l0, k4 = 2.0 * EI / l0;
-    add_iso(D, 0, 0, e1, a, k1);
-    add_skew(D, 0, 3, e1, -k2);
-    add_skew(D, 3, 0, e1, k2);
-    add_iso(D, 3, 3, e1, t, k3);
-    // coupling K[a, b]
-    add_iso(S, 0, 0, e1, -a, -k1);
-    add_skew(S, 0, 3, e1, -k2);
-    add_skew(S, 3, 0, e1, -k2);
-    add_iso(S, 3, 3, e1, -t, k4);
+    R = elem_coeffs(e1, l0, d.EA[g], d.EI[g], d.GJ[g]);
   } else {  // tip node: subtract the actuation load (eq. 18)
     const double* v = d.act_cur + (int64_t)r * d.act_nv;
     V3 Fl = v3(0, 0, 0), Ml = v3(0, 0, 0);
@@ -192,8 +180,36 @@ __global__ void __launch_bounds__(256) elem_kernel(Dev d) {
   }
 #pragma unroll
   for (int k = 0; k < 6; ++k) d.F[k * N + g] = F[k];
+  // Diagonal block: K_bb of the left element + K_aa of the right element; coupling
+  // block K[i, i+1] = K_ab of the right element.  Entries are generated as stored.
+  double2* KD2 = reinterpret_cast<double2*>(d.KD + g * 36);
+  double2* KS2 = reinterpret_cast<double2*>(d.KS + g * 36);
 #pragma unroll
-  for (int k = 0; k < 36; ++k) { d.KD[g * 36 + k] = D[k]; d.KS[g * 36 + k] = S[k]; }
+  for (int p = 0; p < 18; ++p) {
+    double dv[2], sv[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int k = 2 * p + h, row = k / 6, cl = k % 6;
+      const int I = row / 3, J = cl / 3, ii = row % 3, jj = cl % 3;
+      double dd = 0.0, ss = 0.0;
+      if (L.on) {
+        if (I == 0 && J == 0) dd += iso_ij(ii, jj, L.e, L.a, L.k1);
+        if (I == 0 && J == 1) dd += skew_ij(ii, jj, L.e, L.k2);
+        if (I == 1 && J == 0) dd += skew_ij(ii, jj, L.e, -L.k2);
+        if (I == 1 && J == 1) dd += iso_ij(ii, jj, L.e, L.t, L.k3);
+      }
+      if (R.on) {
+        if (I == 0 && J == 0) { dd += iso_ij(ii, jj, R.e, R.a, R.k1); ss = iso_ij(ii, jj, R.e, -R.a, -R.k1); }
+        if (I == 0 && J == 1) { dd += skew_ij(ii, jj, R.e, -R.k2); ss = skew_ij(ii, jj, R.e, -R.k2); }
+        if (I == 1 && J == 0) { dd += skew_ij(ii, jj, R.e, R.k2); ss = skew_ij(ii, jj, R.e, -R.k2); }
+        if (I == 1 && J == 1) { dd += iso_ij(ii, jj, R.e, R.t, R.k3); ss = iso_ij(ii, jj, R.e, -R.t, R.k4); }
+      }
+      dv[h] = dd;
+      sv[h] = ss;
+    }
+    KD2[p] = make_double2(dv[0], dv[1]);
+    KS2[p] = make_double2(sv[0], sv[1]);
+  }
 }
 
 void launch_elem(const Dev& d, hipStream_t s) {

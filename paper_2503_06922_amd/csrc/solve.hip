@@ -28,6 +28,10 @@ namespace accfem {
 constexpr int NT = SOLVE_THREADS;
 constexpr int CH = 16;                     // nodes per staged chunk
 constexpr int PF = (CH * 36 + NT - 1) / NT;  // prefetch registers per lane and array
+constexpr int CHF = 4;                     // chunk of the factorisation sweep (register budget)
+constexpr int PFF = (CHF * 36 + NT - 1) / NT;
+constexpr int CHS = 8;                     // chunk of the substitution sweeps (register budget)
+constexpr int PFS = (CHS * 36 + NT - 1) / NT;
 
 __device__ __forceinline__ double warp_sum(double v) {
 #pragma unroll
@@ -50,11 +54,30 @@ __device__ __forceinline__ int warp_sum_i(int v) {
   return v;
 }
 
-// is the lateral DOF k (0..2) of node i prescribed by the guide?
-__device__ __forceinline__ bool guided_dof(const Dev& d, int r, int64_t i, int k) {
-  const int ax = d.guide_axis[r];
-  if (ax < 0 || i == 0 || k >= 3 || k == ax) return false;
-  return (double)i * d.l0[r] + d.depth_cur[r] < d.guide_len;
+// Nodes 1..last of robot r are inside the insertion guide at this load step
+// (reference arc length i*l0 + depth < guide_len, evaluated without contraction so
+// the decision matches an unfused multiply-add); their lateral DOFs are prescribed.
+struct Guide {
+  int ax;        // guide axis (coordinate index), -1 if no guide
+  int64_t last;  // last guided node index, 0 if none
+  __device__ __forceinline__ bool dof(int64_t i, int k) const {
+    return ax >= 0 && i >= 1 && i <= last && k < 3 && k != ax;
+  }
+};
+
+__device__ Guide make_guide(const Dev& d, int r, int64_t n) {
+  Guide G;
+  G.ax = d.guide_axis[r];
+  int64_t last = 0;
+  if (G.ax >= 0) {
+    const double l0 = d.l0[r], dep = d.depth_cur[r];
+    for (int64_t i = 1 + threadIdx.x; i < n; i += SOLVE_THREADS)
+      if (__dadd_rn(__dmul_rn((double)i, l0), dep) < d.guide_len) last = max(last, i);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) last = max(last, (int64_t)__shfl_xor((long long)last, o));
+  }
+  G.last = last;
+  return G;
 }
 
 // compact the per-node detection output of robot r into its contact list
@@ -203,7 +226,8 @@ __device__ bool lcp_active_set(const double* W, const double* q, int n, int ldw,
   return false;
 }
 
-__global__ void __launch_bounds__(NT) solve_kernel(Dev d, int it) {
+// phase 1: contact gather, convergence test, right-hand sides (col 0 = -r, contact columns)
+__global__ void __launch_bounds__(NT) check_rhs_kernel(Dev d, int it) {
   const int r = blockIdx.x;
   const int lane = threadIdx.x;
   if (d.st_done[r]) return;
@@ -212,6 +236,7 @@ __global__ void __launch_bounds__(NT) solve_kernel(Dev d, int it) {
   const int64_t nf = n - 1;            // free nodes 1..n-1 -> f = 0..nf-1
   const int cap = d.cap;
   const int64_t cb = (int64_t)r * cap;
+  const Guide G = make_guide(d, r, n);
 
   int nc;
   bool ovf;
@@ -257,7 +282,7 @@ __global__ void __launch_bounds__(NT) solve_kernel(Dev d, int it) {
       }
 #pragma unroll
       for (int k = 0; k < 6; ++k)
-        if (!guided_dof(d, r, i, k)) ss += rv[k] * rv[k];
+        if (!G.dof(i, k)) ss += rv[k] * rv[k];
     }
     ss = warp_sum(ss);
     const double rn = sqrt(ss);
@@ -327,7 +352,7 @@ __global__ void __launch_bounds__(NT) solve_kernel(Dev d, int it) {
       for (int64_t jn = i - 1; jn <= i + 1; ++jn) {
         if (jn < 1 || jn >= n) continue;
         for (int k = 0; k < 3; ++k) {
-          if (!guided_dof(d, r, jn, k)) continue;
+          if (!G.dof(jn, k)) continue;
           const double xp = d.base_pos[3 * r + k] - d.X[k * N + o + jn];
           any = true;
           for (int a = 0; a < 6; ++a) {
@@ -348,162 +373,193 @@ __global__ void __launch_bounds__(NT) solve_kernel(Dev d, int it) {
   for (int64_t f = lane; f < nf; f += NT) {
     const int64_t i = f + 1;
     for (int k = 0; k < 3; ++k)
-      if (guided_dof(d, r, i, k)) Zr[6 * f + k] = d.base_pos[3 * r + k] - d.X[k * N + o + i];
+      if (G.dof(i, k)) Zr[6 * f + k] = d.base_pos[3 * r + k] - d.X[k * N + o + i];
   }
   __syncthreads();
+}
 
-  // ---------------------------------------------------------------- block Cholesky
-  // Serial over nodes; inside a node lane L < 36 owns entry (a, b) = (L / 6, L % 6):
-  //   A = D_i - L[f,f-1] L[f,f-1]^T,  L[f,f] = chol(A),  L[f+1,f] = S_i^T L[f,f]^-T
-  // with S_i = K[i, i+1]; rows/columns of prescribed DOFs are replaced by the identity.
-  // The blocks of CH nodes are staged in LDS per chunk; the next chunk is loaded into
-  // registers while the current one is factored, which hides the HBM latency.
-  __shared__ double sA[36], sL[36], sX[36], sLp[36], sS[36];
-  __shared__ double sKD[CH * 36], sKS[CH * 36];
-  __shared__ int s_fail;
-  {
-    const int a = lane / 6, b = lane % 6;
-    if (lane < 36) { sLp[lane] = 0.0; sL[lane] = 0.0; sX[lane] = 0.0; }
-    if (lane == 0) s_fail = 0;
-    double pd[PF], ps[PF];
-    auto fetch = [&](int64_t f0) {
-      const int64_t cnt = min((int64_t)CH, nf - f0) * 36;
-      const double* kd = d.KD + (o + 1 + f0) * 36;
-      const double* ks = d.KS + (o + 1 + f0) * 36;
+// phase 2: block-tridiagonal Cholesky of the QP tangent.
+// Serial over the robot's nodes; per node, lane L < 36 owns entry (a, b) = (L / 6, L % 6):
+//   A = D_i - X_prev X_prev^T   (X_prev = L[f, f-1], rows held redundantly by the lanes of a row)
+//   every lane gathers A's lower triangle by shuffles and factors it in registers,
+//   L[f, f] = chol(A);  row a of X = L[f+1, f] solves L x = S_i[:, a]  (S_i = K[i, i+1]).
+// Rows/columns of prescribed DOFs are replaced by the identity.  Blocks are staged through
+// LDS per chunk of CHF nodes with the next chunk prefetched into registers.
+__global__ void __launch_bounds__(NT) factor_kernel(Dev d, int it) {
+  const int r = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (d.st_done[r]) return;
+  const int64_t o = d.off[r], n = d.off[r + 1] - o;
+  const int64_t nf = n - 1;
+  const Guide G = make_guide(d, r, n);
+  __shared__ double sKD[PFF * NT], sKS[PFF * NT];
+  const int la = lane < 36 ? lane : 35;       // lanes 36..63 mirror lane 35 (results unused)
+  const int a = la / 6, b = la % 6;
+  double Xa[6] = {0, 0, 0, 0, 0, 0};          // row a of L[f, f-1]
+  bool fail = false;
+  double pd[PFF], ps[PFF];
+  auto fetch = [&](int64_t f0) {
+    const int64_t cnt = min((int64_t)CHF, nf - f0) * 36;
+    const double* kd = d.KD + (o + 1 + f0) * 36;
+    const double* ks = d.KS + (o + 1 + f0) * 36;
 #pragma unroll
-      for (int u = 0; u < PF; ++u) {
-        const int64_t idx = lane + (int64_t)u * NT;
-        pd[u] = idx < cnt ? kd[idx] : 0.0;
-        ps[u] = idx < cnt ? ks[idx] : 0.0;
+    for (int u = 0; u < PFF; ++u) {
+      const int64_t idx = lane + (int64_t)u * NT;
+      pd[u] = idx < cnt ? kd[idx] : 0.0;
+      ps[u] = idx < cnt ? ks[idx] : 0.0;
+    }
+  };
+  fetch(0);
+  for (int64_t f0 = 0; f0 < nf; f0 += CHF) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PFF; ++u) { sKD[lane + u * NT] = pd[u]; sKS[lane + u * NT] = ps[u]; }
+    __syncthreads();
+    if (f0 + CHF < nf) fetch(f0 + CHF);
+    const int64_t f1 = min(nf, f0 + CHF);
+    for (int64_t f = f0; f < f1; ++f) {
+      const int64_t i = f + 1, g = o + i;
+      const int lf = (int)(f - f0) * 36;
+      const bool last = (f + 1 == nf);
+      double dv = sKD[lf + la];
+      if (G.dof(i, a) || G.dof(i, b)) dv = (a == b) ? 1.0 : 0.0;
+      double sv = last ? 0.0 : sKS[lf + la];                 // K[i, i+1](a, b)
+      if (!last && (G.dof(i, a) || G.dof(i + 1, b))) sv = 0.0;
+      // A(a, b) = D(a, b) - X_prev[a,:] . X_prev[b,:]
+      double acc = dv;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) acc -= Xa[k] * __shfl(Xa[k], b * 6);
+      // lower triangle of A in every lane, then Cholesky in registers
+      double Lm[21];
+#pragma unroll
+      for (int p = 0, q = 0; p < 6; ++p)
+#pragma unroll
+        for (int c = 0; c <= p; ++c, ++q) Lm[q] = __shfl(acc, p * 6 + c);
+      double rd[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        const int kk = k * (k + 1) / 2;
+        double dk = Lm[kk + k];
+#pragma unroll
+        for (int j = 0; j < k; ++j) dk -= Lm[kk + j] * Lm[kk + j];
+        if (!(dk > 0.0)) { fail = true; dk = 1.0; }
+        const double lkk = sqrt(dk);
+        rd[k] = 1.0 / lkk;
+        Lm[kk + k] = lkk;
+#pragma unroll
+        for (int p = k + 1; p < 6; ++p) {
+          const int pp = p * (p + 1) / 2;
+          double t = Lm[pp + k];
+#pragma unroll
+          for (int j = 0; j < k; ++j) t -= Lm[pp + j] * Lm[kk + j];
+          Lm[pp + k] = t * rd[k];
+        }
       }
-    };
-    fetch(0);
-    for (int64_t f0 = 0; f0 < nf && !s_fail; f0 += CH) {
-      __syncthreads();
+      // row a of X: forward substitution L x = S[:, a]
+      double sc[6];
 #pragma unroll
-      for (int u = 0; u < PF; ++u) { sKD[lane + u * NT] = pd[u]; sKS[lane + u * NT] = ps[u]; }
-      __syncthreads();
-      if (f0 + CH < nf) fetch(f0 + CH);
-      const int64_t f1 = min(nf, f0 + CH);
-      for (int64_t f = f0; f < f1; ++f) {
-        const int64_t i = f + 1, g = o + i;
-        const int lf = (int)(f - f0) * 36;
-        const bool last = (f + 1 == nf);
-        if (lane < 36) {
-          double dv = sKD[lf + lane];
-          if (guided_dof(d, r, i, a) || guided_dof(d, r, i, b)) dv = (a == b) ? 1.0 : 0.0;
-          double acc = dv;
+      for (int j = 0; j < 6; ++j) sc[j] = __shfl(sv, j * 6 + a);
 #pragma unroll
-          for (int k = 0; k < 6; ++k) acc -= sLp[a * 6 + k] * sLp[b * 6 + k];
-          sA[lane] = acc;
-          double sv = last ? 0.0 : sKS[lf + lane];             // K[i, i+1](a, b)
-          if (!last && (guided_dof(d, r, i, a) || guided_dof(d, r, i + 1, b))) sv = 0.0;
-          sS[lane] = sv;
-        }
-        __syncthreads();
+      for (int k = 0; k < 6; ++k) {
+        const int kk = k * (k + 1) / 2;
+        double t = sc[k];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) {
-          if (lane == k * 7) {
-            double t = sA[lane];
-            for (int j = 0; j < k; ++j) t -= sL[k * 6 + j] * sL[k * 6 + j];
-            if (!(t > 0.0)) { s_fail = 1; t = 1.0; }
-            sL[lane] = sqrt(t);
-          }
-          __syncthreads();
-          if (lane < 36 && b == k && a > k) {
-            double t = sA[lane];
-            for (int j = 0; j < k; ++j) t -= sL[a * 6 + j] * sL[k * 6 + j];
-            sL[lane] = t / sL[k * 7];
-          }
-          __syncthreads();
-        }
-        if (!last) {
-          // row a of X solves L x = S[:, a]
+        for (int j = 0; j < k; ++j) t -= Lm[kk + j] * Xa[j];
+        Xa[k] = last ? 0.0 : t * rd[k];
+      }
+      // select this lane's entries with compile-time indices (keeps the arrays in registers)
+      double lv = 0.0, xv = 0.0;
 #pragma unroll
-          for (int bb = 0; bb < 6; ++bb) {
-            if (lane < 36 && b == bb) {
-              double t = sS[bb * 6 + a];
-              for (int j = 0; j < bb; ++j) t -= sL[bb * 6 + j] * sX[a * 6 + j];
-              sX[lane] = t / sL[bb * 7];
-            }
-            __syncthreads();
-          }
-        }
-        if (lane < 36) {
-          d.LD[g * 36 + lane] = sL[lane];
-          if (!last) d.LS[g * 36 + lane] = sX[lane];
-          sLp[lane] = last ? 0.0 : sX[lane];
-        }
-        __syncthreads();
+      for (int p = 0, q = 0; p < 6; ++p) {
+#pragma unroll
+        for (int c = 0; c <= p; ++c, ++q)
+          if (p == a && c == b) lv = (p == c) ? rd[p] : Lm[q];   // reciprocal on the diagonal
+        if (p == b) xv = Xa[p];
+      }
+      if (lane < 36) {
+        d.LD[g * 36 + lane] = lv;
+        if (!last) d.LS[g * 36 + lane] = xv;
       }
     }
   }
-  __syncthreads();
-  if (s_fail) {
-    finish(d, r, 3, it, d.st_rn[r]);
-    return;
-  }
+  fail = __any(fail ? 1 : 0) != 0;
+  if (fail) finish(d, r, 3, it, d.st_rn[r]);
+}
 
+// phase 3: forward and backward substitution of all right-hand sides
+__global__ void __launch_bounds__(NT) subst_kernel(Dev d) {
+  const int r = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (d.st_done[r]) return;
+  const int64_t o = d.off[r], n = d.off[r + 1] - o;
+  const int64_t N = d.Ntot;
+  const int64_t nf = n - 1;            // free nodes 1..n-1 -> f = 0..nf-1
+  const int cap = d.cap;
+  const int64_t cb = (int64_t)r * cap;
+  const int nc = d.st_nc[r];
+  const int ncol = 1 + nc;
+  double* Zr = d.Z + d.zoff[r];
+  const int64_t ld = 6 * n;
+  __shared__ double sKD[PFS * NT], sKS[PFS * NT];
   // ---------------------------------------------------------------- substitutions
   // six lanes per right-hand side (lane = row of the 6-block), ten columns per pass;
-  // factor blocks are staged per chunk of CH nodes like above (forward: LD[f], LS[f-1];
+  // factor blocks are staged per chunk of CHS nodes like above (forward: LD[f], LS[f-1];
   // backward: LD[f], LS[f]).
   for (int c0 = 0; c0 < ncol; c0 += 10) {
     const int grp = lane / 6, a = lane % 6, base = min(grp, 9) * 6;
     const int c = c0 + grp;
     const bool act = (lane < 60) && (c < ncol);
     double* z = Zr + (int64_t)(act ? c : 0) * ld;
-    double pd[PF], ps[PF];
+    double pd[PFS], ps[PFS];
     // forward sweep: chunk f0 needs LD of nodes f0..f1-1 and LS of nodes f0-1..f1-2
     auto fetchF = [&](int64_t f0) {
-      const int64_t cnt = min((int64_t)CH, nf - f0) * 36;
+      const int64_t cnt = min((int64_t)CHS, nf - f0) * 36;
       const double* ldp = d.LD + (o + 1 + f0) * 36;
       const double* lsp = d.LS + (o + f0) * 36;          // node f0-1 (the base slot when f0 = 0)
 #pragma unroll
-      for (int u = 0; u < PF; ++u) {
+      for (int u = 0; u < PFS; ++u) {
         const int64_t idx = lane + (int64_t)u * NT;
         pd[u] = idx < cnt ? ldp[idx] : 0.0;
         ps[u] = idx < cnt ? lsp[idx] : 0.0;
       }
     };
-    double yprev = 0.0;
+    double yp[6] = {0, 0, 0, 0, 0, 0};   // previous block solution (whole 6-vector per lane)
     fetchF(0);
-    for (int64_t f0 = 0; f0 < nf; f0 += CH) {
+    for (int64_t f0 = 0; f0 < nf; f0 += CHS) {
       __syncthreads();
 #pragma unroll
-      for (int u = 0; u < PF; ++u) { sKD[lane + u * NT] = pd[u]; sKS[lane + u * NT] = ps[u]; }
+      for (int u = 0; u < PFS; ++u) { sKD[lane + u * NT] = pd[u]; sKS[lane + u * NT] = ps[u]; }
       __syncthreads();
-      if (f0 + CH < nf) fetchF(f0 + CH);
-      const int64_t f1 = min(nf, f0 + CH);
-      double zc[CH];
+      if (f0 + CHS < nf) fetchF(f0 + CHS);
+      const int64_t f1 = min(nf, f0 + CHS);
+      double zc[CHS];
 #pragma unroll
-      for (int u = 0; u < CH; ++u) zc[u] = (act && f0 + u < f1) ? z[6 * (f0 + u) + a] : 0.0;
+      for (int u = 0; u < CHS; ++u) zc[u] = (act && f0 + u < f1) ? z[6 * (f0 + u) + a] : 0.0;
 #pragma unroll
-      for (int u = 0; u < CH; ++u) {
+      for (int u = 0; u < CHS; ++u) {
         const int64_t f = f0 + u;
         if (f >= f1) break;
         double bv = zc[u];
         if (f > 0) {
           const double* Ls = sKS + u * 36 + a * 6;        // L[f, f-1] row a
 #pragma unroll
-          for (int k = 0; k < 6; ++k) {
-            const double yk = __shfl(yprev, base + k);
-            bv -= Ls[k] * yk;
-          }
+          for (int k = 0; k < 6; ++k) bv -= Ls[k] * yp[k];
         }
-        const double* Ld = sKD + u * 36;
-        double y = 0.0;
+        double bb[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) bb[k] = __shfl(bv, base + k);
+        const double* Ld = sKD + u * 36;                  // lower triangle, reciprocal diagonal
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-          if (a == k) y = bv / Ld[k * 7];
-          const double yk = __shfl(y, base + k);
-          if (a > k) bv -= Ld[a * 6 + k] * yk;
+          double t = bb[k];
+#pragma unroll
+          for (int j = 0; j < k; ++j) t -= Ld[k * 6 + j] * yp[j];
+          yp[k] = t * Ld[k * 7];
         }
-        zc[u] = y;
-        yprev = y;
+        zc[u] = yp[a];
       }
 #pragma unroll
-      for (int u = 0; u < CH; ++u)
+      for (int u = 0; u < CHS; ++u)
         if (act && f0 + u < f1) z[6 * (f0 + u) + a] = zc[u];
     }
     // backward sweep over chunks from the tip: chunk [f0, f1) needs LD and LS of f0..f1-1
@@ -512,56 +568,75 @@ __global__ void __launch_bounds__(NT) solve_kernel(Dev d, int it) {
       const double* ldp = d.LD + (o + 1 + f0) * 36;
       const double* lsp = d.LS + (o + 1 + f0) * 36;
 #pragma unroll
-      for (int u = 0; u < PF; ++u) {
+      for (int u = 0; u < PFS; ++u) {
         const int64_t idx = lane + (int64_t)u * NT;
         pd[u] = idx < cnt ? ldp[idx] : 0.0;
         ps[u] = idx < cnt ? lsp[idx] : 0.0;
       }
     };
-    double xnext = 0.0;
-    const int64_t nch = (nf + CH - 1) / CH;
-    fetchB((nch - 1) * CH, nf);
+    double xn[6] = {0, 0, 0, 0, 0, 0};   // next block solution (whole 6-vector per lane)
+    const int64_t nch = (nf + CHS - 1) / CHS;
+    fetchB((nch - 1) * CHS, nf);
     for (int64_t ch = nch - 1; ch >= 0; --ch) {
-      const int64_t f0 = ch * CH, f1 = min(nf, f0 + CH);
+      const int64_t f0 = ch * CHS, f1 = min(nf, f0 + CHS);
       __syncthreads();
 #pragma unroll
-      for (int u = 0; u < PF; ++u) { sKD[lane + u * NT] = pd[u]; sKS[lane + u * NT] = ps[u]; }
+      for (int u = 0; u < PFS; ++u) { sKD[lane + u * NT] = pd[u]; sKS[lane + u * NT] = ps[u]; }
       __syncthreads();
-      if (ch > 0) fetchB(f0 - CH, f0);
-      double zc[CH];
+      if (ch > 0) fetchB(f0 - CHS, f0);
+      double zc[CHS];
 #pragma unroll
-      for (int u = 0; u < CH; ++u) zc[u] = (act && f0 + u < f1) ? z[6 * (f0 + u) + a] : 0.0;
+      for (int u = 0; u < CHS; ++u) zc[u] = (act && f0 + u < f1) ? z[6 * (f0 + u) + a] : 0.0;
 #pragma unroll
-      for (int u = CH - 1; u >= 0; --u) {
+      for (int u = CHS - 1; u >= 0; --u) {
         const int64_t f = f0 + u;
         if (f >= f1) continue;
         double bv = zc[u];
         if (f + 1 < nf) {
           const double* Ls = sKS + u * 36;                // L[f+1, f]; its column a
 #pragma unroll
-          for (int k = 0; k < 6; ++k) {
-            const double xk = __shfl(xnext, base + k);
-            bv -= Ls[k * 6 + a] * xk;
-          }
+          for (int k = 0; k < 6; ++k) bv -= Ls[k * 6 + a] * xn[k];
         }
+        double bb[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) bb[k] = __shfl(bv, base + k);
         const double* Ld = sKD + u * 36;
-        double x = 0.0;
 #pragma unroll
         for (int k = 5; k >= 0; --k) {
-          if (a == k) x = bv / Ld[k * 7];
-          const double xk = __shfl(x, base + k);
-          if (a < k) bv -= Ld[k * 6 + a] * xk;
+          double t = bb[k];
+#pragma unroll
+          for (int j = k + 1; j < 6; ++j) t -= Ld[j * 6 + k] * xn[j];
+          xn[k] = t * Ld[k * 7];
         }
-        zc[u] = x;
-        xnext = x;
+        zc[u] = xn[a];
       }
 #pragma unroll
-      for (int u = 0; u < CH; ++u)
+      for (int u = 0; u < CHS; ++u)
         if (act && f0 + u < f1) z[6 * (f0 + u) + a] = zc[u];
     }
   }
   __syncthreads();
+}
 
+// phase 4: contact Schur complement, LCP, step limit and state update
+__global__ void __launch_bounds__(NT) update_kernel(Dev d, int it) {
+  const int r = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (d.st_done[r]) return;
+  const int64_t o = d.off[r], n = d.off[r + 1] - o;
+  const int64_t N = d.Ntot;
+  const int64_t nf = n - 1;            // free nodes 1..n-1 -> f = 0..nf-1
+  const int cap = d.cap;
+  const int64_t cb = (int64_t)r * cap;
+  const int nc = d.st_nc[r];
+  double* Zr = d.Z + d.zoff[r];
+  const int64_t ld = 6 * n;
+  double dx0[3];
+  {
+    const double dep = d.depth_cur[r];
+    for (int k = 0; k < 3; ++k)
+      dx0[k] = d.base_pos[3 * r + k] + dep * d.base_dir[3 * r + k] - d.X[k * N + o];
+  }
   // ---------------------------------------------------------------- Schur complement + LCP
   double* W = d.W + (int64_t)r * cap * cap;
   double* qv = d.q + cb;
@@ -681,8 +756,14 @@ __global__ void __launch_bounds__(NT) gather_kernel(Dev d) {
   }
 }
 
-void launch_solve(const Dev& d, int it, hipStream_t s) {
-  hipLaunchKernelGGL(solve_kernel, dim3(d.B), dim3(NT), 0, s, d, it);
+// phases of one Newton step: 0 check + right-hand sides, 1 factor, 2 substitute, 3 update
+void launch_solve_phase(const Dev& d, int phase, int it, hipStream_t s) {
+  switch (phase) {
+    case 0: hipLaunchKernelGGL(check_rhs_kernel, dim3(d.B), dim3(NT), 0, s, d, it); break;
+    case 1: hipLaunchKernelGGL(factor_kernel, dim3(d.B), dim3(NT), 0, s, d, it); break;
+    case 2: hipLaunchKernelGGL(subst_kernel, dim3(d.B), dim3(NT), 0, s, d); break;
+    default: hipLaunchKernelGGL(update_kernel, dim3(d.B), dim3(NT), 0, s, d, it); break;
+  }
 }
 
 void launch_gather(const Dev& d, hipStream_t s) {
