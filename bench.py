@@ -88,6 +88,7 @@ def main():
     ap.add_argument("--single-robots", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-single", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (robots are "
@@ -154,6 +155,27 @@ def main():
         "kernels": kern, "dominant_kernel": names[dom],
         "roofline": roof,
     }
+    if prec == fem.FEM_MIXED and not args.no_fp64:
+        # the same batch in plain FP64 (batched): throughput and the mixed path's tip error
+        c64 = fem.Context(fem.params_from_batch(rb, precision=fem.FEM_FP64, newton_tol=1e-10,
+                                                stag_tol=1e-9, max_newton=args.max_newton,
+                                                contact_capacity=args.capacity))
+        c64.fem_set_lumen(V, T)
+        c64.fem_set_actuation(0, np.zeros(3 * rb.n_robots), np.zeros(rb.n_robots))
+        t1 = time.perf_counter()
+        run_schedule(c64, rb, args.load_steps, X0)
+        t64 = time.perf_counter() - t1
+        conv64, _, _, info64 = solves_of(c64)
+        Xm = ctx.fem_get_state()
+        X64 = c64.fem_get_state()
+        tips = np.asarray(rb.node_offset[1:]) - 1
+        both = np.array([i["status"] == 0 and j["status"] == 0 for i, j in zip(info, info64)])
+        err = np.linalg.norm(Xm[tips, 0:3] - X64[tips, 0:3], axis=1) / rb.length
+        res["fp64_batched_solves_per_s"] = conv64 / t64
+        res["tip_err_mixed_vs_fp64"] = {"max": float(err[both].max()) if both.any() else None,
+                                        "median": float(np.median(err[both])) if both.any() else None,
+                                        "robots_compared": int(both.sum())}
+        c64.close()
     if not args.no_single:
         # plain FP64 path of configuration 0: one robot per context, run one after another
         t_single = 0.0

@@ -117,6 +117,11 @@ __global__ void renorm_kernel(Dev d) {
   d.X[3 * N + g] = w * inv; d.X[4 * N + g] = x * inv; d.X[5 * N + g] = y * inv; d.X[6 * N + g] = z * inv;
 }
 
+__global__ void f32_to_f64(const float* in, double* out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (double)in[i];
+}
+
 // node-major [g][7] <-> SoA [k][g]
 __global__ void aos_to_soa(const double* in, double* out, int64_t N, int K) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -389,6 +394,8 @@ static fem_status create_impl(fem_ctx* c, const fem_params* p) {
   d.mixed = (p->precision == FEM_MIXED) ? 1 : 0;
   // state and per-iteration buffers
   ALLOC(d.X, 7 * N); ALLOC(d.F, 6 * N); ALLOC(d.KD, 36 * N); ALLOC(d.KS, 36 * N);
+  ALLOC(d.KDf, 36 * N); ALLOC(d.KSf, 36 * N);
+  HIP_TRY(c, hipMemset(d.KSf, 0, 36 * N * sizeof(float)));
   ALLOC(d.LD, 36 * N); ALLOC(d.LS, 36 * N);
   ALLOC(d.CC, N); ALLOC(d.CT, MAXC * N); ALLOC(d.CK, MAXC * N); ALLOC(d.CN, 3 * MAXC * N);
   ALLOC(d.CG, MAXC * N);
@@ -715,12 +722,17 @@ fem_status fem_eval(fem_ctx* c, double* F, double* KD, double* KS) {
     fem_status s = copy_out(c, F, d.LS, (size_t)c->Ntot * 6 * sizeof(double));
     if (s != FEM_OK) return s;
   }
-  if (KD) {
-    fem_status s = copy_out(c, KD, d.KD, (size_t)c->Ntot * 36 * sizeof(double));
-    if (s != FEM_OK) return s;
-  }
-  if (KS) {
-    fem_status s = copy_out(c, KS, d.KS, (size_t)c->Ntot * 36 * sizeof(double));
+  for (int which = 0; which < 2; ++which) {
+    double* dst = which == 0 ? KD : KS;
+    if (!dst) continue;
+    const double* src = which == 0 ? d.KD : d.KS;
+    if (d.mixed) {
+      hipLaunchKernelGGL(f32_to_f64, dim3(nblk(c->Ntot * 36, 256)), dim3(256), 0, c->stream,
+                         (const float*)(which == 0 ? d.KDf : d.KSf), d.LS, c->Ntot * 36);
+      HIP_TRY(c, hipGetLastError());
+      src = d.LS;
+    }
+    fem_status s = copy_out(c, dst, src, (size_t)c->Ntot * 36 * sizeof(double));
     if (s != FEM_OK) return s;
   }
   HIP_TRY(c, hipStreamSynchronize(c->stream));

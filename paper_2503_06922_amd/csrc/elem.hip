@@ -182,8 +182,12 @@ __global__ void __launch_bounds__(256) elem_kernel(Dev d) {
   for (int k = 0; k < 6; ++k) d.F[k * N + g] = F[k];
   // Diagonal block: K_bb of the left element + K_aa of the right element; coupling
   // block K[i, i+1] = K_ab of the right element.  Entries are generated as stored.
+  // In mixed precision the blocks are rounded to FP32 as they are stored (the factorisation
+  // upcasts them and runs in FP64; the out-of-balance force above stays FP64).
   double2* KD2 = reinterpret_cast<double2*>(d.KD + g * 36);
   double2* KS2 = reinterpret_cast<double2*>(d.KS + g * 36);
+  float2* KD2f = reinterpret_cast<float2*>(d.KDf + g * 36);
+  float2* KS2f = reinterpret_cast<float2*>(d.KSf + g * 36);
 #pragma unroll
   for (int p = 0; p < 18; ++p) {
     double dv[2], sv[2];
@@ -207,8 +211,13 @@ __global__ void __launch_bounds__(256) elem_kernel(Dev d) {
       dv[h] = dd;
       sv[h] = ss;
     }
-    KD2[p] = make_double2(dv[0], dv[1]);
-    KS2[p] = make_double2(sv[0], sv[1]);
+    if (d.mixed) {
+      KD2f[p] = make_float2((float)dv[0], (float)dv[1]);
+      KS2f[p] = make_float2((float)sv[0], (float)sv[1]);
+    } else {
+      KD2[p] = make_double2(dv[0], dv[1]);
+      KS2[p] = make_double2(sv[0], sv[1]);
+    }
   }
 }
 

@@ -68,6 +68,8 @@ struct Dev {
   double* F;
   double* KD;
   double* KS;
+  float* KDf;         // mixed precision: the tangent blocks are stored in FP32
+  float* KSf;
   double* LD;
   double* LS;
   int32_t* CC;
@@ -107,6 +109,14 @@ struct Dev {
   int32_t* n_done;      // [1] robots finished in this load step
   int mixed;
 };
+
+// tangent block entries (FP64, or FP32 in mixed precision, upcast for the FP64 factorisation)
+__device__ __forceinline__ double kd_at(const Dev& d, int64_t idx) {
+  return d.mixed ? (double)d.KDf[idx] : d.KD[idx];
+}
+__device__ __forceinline__ double ks_at(const Dev& d, int64_t idx) {
+  return d.mixed ? (double)d.KSf[idx] : d.KS[idx];
+}
 
 // ------------------------------------------------------------------ vectors
 struct V3 { double x, y, z; };

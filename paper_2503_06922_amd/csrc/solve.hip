@@ -337,7 +337,7 @@ __global__ void __launch_bounds__(NT) check_rhs_kernel(Dev d, int it) {
     // rows of node 1 (f = 0): -= K[1,0] dx0 = S_0^T dx0 (S_0 = K[0,1] stored at the base)
     for (int a = 0; a < 6; ++a) {
       double s = 0.0;
-      for (int b = 0; b < 3; ++b) s += d.KS[o * 36 + b * 6 + a] * dx0[b];
+      for (int b = 0; b < 3; ++b) s += ks_at(d, o * 36 + b * 6 + a) * dx0[b];
       Zr[a] -= s;
     }
   }
@@ -357,9 +357,9 @@ __global__ void __launch_bounds__(NT) check_rhs_kernel(Dev d, int it) {
           any = true;
           for (int a = 0; a < 6; ++a) {
             double kij;
-            if (jn == i) kij = d.KD[(o + i) * 36 + a * 6 + k];
-            else if (jn == i + 1) kij = d.KS[(o + i) * 36 + a * 6 + k];     // K[i, i+1]
-            else kij = d.KS[(o + jn) * 36 + k * 6 + a];                      // K[i, i-1] = K[i-1, i]^T
+            if (jn == i) kij = kd_at(d, (o + i) * 36 + a * 6 + k);
+            else if (jn == i + 1) kij = ks_at(d, (o + i) * 36 + a * 6 + k);   // K[i, i+1]
+            else kij = ks_at(d, (o + jn) * 36 + k * 6 + a);                    // K[i, i-1] = K[i-1, i]^T
             acc[a] += kij * xp;
           }
         }
@@ -400,13 +400,12 @@ __global__ void __launch_bounds__(NT) factor_kernel(Dev d, int it) {
   double pd[PFF], ps[PFF];
   auto fetch = [&](int64_t f0) {
     const int64_t cnt = min((int64_t)CHF, nf - f0) * 36;
-    const double* kd = d.KD + (o + 1 + f0) * 36;
-    const double* ks = d.KS + (o + 1 + f0) * 36;
+    const int64_t base = (o + 1 + f0) * 36;
 #pragma unroll
     for (int u = 0; u < PFF; ++u) {
       const int64_t idx = lane + (int64_t)u * NT;
-      pd[u] = idx < cnt ? kd[idx] : 0.0;
-      ps[u] = idx < cnt ? ks[idx] : 0.0;
+      pd[u] = idx < cnt ? kd_at(d, base + idx) : 0.0;
+      ps[u] = idx < cnt ? ks_at(d, base + idx) : 0.0;
     }
   };
   fetch(0);

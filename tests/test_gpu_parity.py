@@ -172,3 +172,84 @@ def test_cfg1_one_step_parity_from_oracle_states():
             checked += 1
         P, R = P1, R1
     assert checked >= 5
+
+
+def test_cfg0_mixed_precision_matches_oracle(cfg0_oracle):
+    """Mixed precision (FP32 tangent blocks and detection screen, FP64 residual and
+    factorisation): same equilibria within 1e-5 relative tip error and the same active sets."""
+    from paper_2503_06922_amd import fem
+    rb, V, T, rob, traj = cfg0_oracle
+    ctx = gpu_context(rb, V, T, precision=fem.FEM_MIXED, newton_tol=1e-13, stag_tol=1e-9,
+                      max_newton=200)
+    Pref, _ = rob.reference()
+    worst = 0.0
+    for k in range(1, rb.n_load_steps + 1):
+        d, t = load_schedule(rb, k)
+        ctx.fem_set_actuation(0, t.ravel(), d)
+        out = ctx.fem_solve(1)
+        o = traj[k - 1]
+        assert out["info"][0]["status"] == 0
+        P = out["state"][:, 0:3]
+        tip = np.linalg.norm(P[-1] - o["P"][-1]) / rob.length
+        worst = max(worst, tip)
+        assert tip <= 1e-5
+        assert displacement_error(P, o["P"], Pref) <= 1e-7
+        compare_contact_keys(ctx.fem_contacts(0), list(zip(o["contacts"], o["y"])), o["P"], rob)
+    print("mixed worst relative tip error", worst)
+
+
+def test_batched_robots_match_oracle_per_robot():
+    """A batch of robots of different lengths in one context: each robot equals its own
+    oracle solve (several insertion load steps through the guide into the airway)."""
+    rb, V, T = make_config(3)
+    sub = rb.subset([0, 1, 2, 3, 5, 8])
+    robs, mesh = oracle_robots(sub, V, T)
+    ctx = gpu_context(sub, V, T, newton_tol=1e-10, stag_tol=1e-9, max_newton=100)
+    n_steps = 6
+    states = [r.reference() for r in robs]
+    for k in range(1, n_steps + 1):
+        d, t = load_schedule(sub, k)
+        ctx.fem_set_actuation(0, t.ravel(), d)
+        out = ctx.fem_solve(1)
+        for b, (sl, rob) in enumerate(zip(robot_slices(sub), robs)):
+            P, R = states[b]
+            P1, R1, cont, y, info = solver.solve_load_step(rob, P, R, rob.base_target(d[b]), 0, t[b],
+                                                           tol=1e-10, stag_tol=1e-9, max_iter=100,
+                                                           guided=rob.guided(d[b]))
+            states[b] = (P1, R1)
+            assert out["info"][b]["status"] == (0 if info["status"] == solver.OK else 1)
+            if info["status"] == solver.OK:
+                Pref = rob.reference()[0]
+                assert displacement_error(out["state"][sl, 0:3], P1, Pref) <= 1e-9
+
+
+def test_edge_cases_single_element_and_no_lumen():
+    """One element, no wall: a dead tip force gives the cantilever closed form of the element."""
+    from paper_2503_06922_amd import fem
+    rb = robots_for_config(0)
+    rb.n_elem[:] = 1
+    ctx = gpu_context(rb, None, None, newton_tol=1e-13, stag_tol=1e-9, max_newton=50)
+    EI = np.pi / 4 * (rb.r_out**4 - rb.r_in**4) * rb.E
+    L = rb.length[0]
+    P = 1e-4 * 3 * EI / L**2
+    ctx.fem_set_actuation(fem.FEM_ACT_TIP_WRENCH_GLOBAL, np.array([P, 0, 0, 0, 0, 0]), None)
+    out = ctx.fem_solve(1)
+    assert out["info"][0]["status"] == 0
+    X = out["state"]
+    assert X.shape == (2, 7)
+    assert X[1, 0] == pytest.approx(P * L**3 / (3 * EI), rel=1e-6)
+    assert ctx.fem_contacts(-1) == []
+
+
+def test_invalid_calls_report_errors():
+    from paper_2503_06922_amd import fem
+    rb = robots_for_config(0)
+    ctx = fem.Context(fem.params_from_batch(rb))
+    with pytest.raises(fem.FemError) as e:
+        ctx.fem_solve(1)
+    assert e.value.status == fem.FEM_E_STATE
+    with pytest.raises(fem.FemError) as e:
+        ctx.fem_set_lumen(np.zeros((3, 3)), np.array([[0, 1, 5]], np.int32))
+    assert e.value.status == fem.FEM_E_INVAL
+    with pytest.raises(fem.FemError):
+        ctx.fem_contacts(7)
