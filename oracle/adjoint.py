@@ -1,1 +1,97 @@
-"""placeholder"""
+"""Gradient of a tip-sensor loss with respect to the cable tensions (oracle).  TEST INFRASTRUCTURE ONLY.
+
+At a converged equilibrium of a load step (Sec. III-A, eq. 19),
+    R(x, T) = F(x) - F_a(x, T) - A^T y = 0,   A_act dx = 0 for the active contacts,
+so a perturbation dT moves the equilibrium by dx with
+    J dx - A_act^T dy = dF_a/dT dT,   A_act dx = 0,   J = d(F - F_a)/dx
+(the consistent Jacobian: material + geometric stiffness of the elements and the
+load stiffness of the follower moment).  For a loss L(x) with gradient g, the
+adjoint pair solves  J^T lam + A_act^T mu = g,  A_act lam = 0,  and then
+    dL/dT_j = lam . dF_a/dT_j.
+Contacts are treated as planes at their current normals (exact for face
+contacts; for the edge/vertex fallback the normal's own variation is left out).
+Fixed DOFs (base node, guided lateral DOFs) are removed.  J is taken by central
+finite differences of the out-of-balance force (banded), the KKT system is
+solved densely.  Independent check: central differences of complete re-solves.
+The same function serves the tip-wrench actuations with u the wrench.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import beam, actuation, solver
+
+
+def free_mask(robot, n_nodes, guided):
+    """Boolean mask over the 6N DOFs: True where the DOF is an unknown."""
+    m = np.ones(6 * n_nodes, bool)
+    m[0:6] = False
+    if guided is not None and np.any(guided):
+        ax = int(np.argmax(np.abs(robot.base_dir)))
+        for i in np.nonzero(guided)[0]:
+            for k in range(3):
+                if k != ax:
+                    m[6 * i + k] = False
+    return m
+
+
+def jacobian(robot, P, R, act_kind, act_values, h=1e-7):
+    """Dense consistent Jacobian d(F - F_a)/dx [6N, 6N] by banded central differences."""
+    resid = lambda P_, R_: solver.out_of_balance(robot, P_, R_, act_kind, act_values)
+    N = P.shape[0]
+    return beam.banded_to_dense(beam.fd_jacobian_banded(resid, P, R, h=h), 6 * N)
+
+
+def loss_gradient_x(P, sensor_nodes, dL_dp):
+    """Scatter dL/dp of the sensor nodes [n_s, 3] into a 6N vector."""
+    g = np.zeros(6 * P.shape[0])
+    for s, i in enumerate(sensor_nodes):
+        g[6 * i:6 * i + 3] += dL_dp[s]
+    return g
+
+
+def tension_gradient(robot, P, R, contacts, y, act_values, sensor_nodes, dL_dp, guided=None,
+                     act_kind=actuation.CABLES, active_tol=0.0):
+    """dL/du [n_values] (cable tensions, or the tip wrench) at a converged state, for the
+    loss gradient dL_dp [n_sensors, 3] at the sensor nodes."""
+    N = P.shape[0]
+    J = jacobian(robot, P, R, act_kind, act_values)
+    m = free_mask(robot, N, guided)
+    Jf = J[np.ix_(m, m)]
+    g = loss_gradient_x(P, sensor_nodes, dL_dp)[m]
+    act = [c for c, yy in zip(contacts, y) if yy > active_tol]
+    idx_free = np.cumsum(m) - 1
+    A = np.zeros((len(act), int(m.sum())))
+    for k, c in enumerate(act):
+        for d in range(3):
+            A[k, idx_free[6 * c["node"] + d]] = c["n"][d]
+    nf = Jf.shape[0]
+    na = A.shape[0]
+    K = np.zeros((nf + na, nf + na))
+    K[:nf, :nf] = Jf.T
+    K[:nf, nf:] = A.T
+    K[nf:, :nf] = A
+    # least squares: the KKT matrix is singular in mu when two active normals of a node
+    # coincide (the two triangles of a flat quad); lam is still unique
+    sol = np.linalg.lstsq(K, np.concatenate([g, np.zeros(na)]), rcond=None)[0]
+    lam = np.zeros(6 * N)
+    lam[m] = sol[:nf]
+    return lam[6 * (N - 1):6 * N] @ load_gradient(robot, R[-1], act_kind)
+
+
+def load_gradient(robot, R_tip, act_kind):
+    """dF_a/du [6, n_values] of the tip load (eq. 18) for the actuation values u."""
+    if act_kind == actuation.CABLES:
+        return actuation.tension_gradient(R_tip, robot.cable_radius, robot.cable_angle)
+    if act_kind == actuation.TIP_LOCAL:
+        G = np.zeros((6, 6))
+        G[0:3, 0:3] = R_tip
+        G[3:6, 3:6] = R_tip
+        return G
+    return np.eye(6)
+
+
+def sensor_loss(P, sensor_nodes, targets):
+    """L = sum_s |p_s - p*_s|^2 and its gradient with respect to the sensor positions."""
+    d = P[np.asarray(sensor_nodes)] - targets
+    return float(np.sum(d * d)), 2.0 * d
