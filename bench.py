@@ -28,9 +28,21 @@ sys.path.insert(0, ROOT)
 
 METRIC = "contact-FEM solves/sec, batched+mixed vs plain FP64 at 1e-5 rel tip error"
 HBM_PEAK_GBS = 8000.0
-# algorithmic HBM bytes per node of one element-update launch (FP64): read the node
-# state (7 doubles), write F (6), the symmetric diagonal block (21) and the coupling block (36)
-ELEM_BYTES_PER_NODE = 8 * (7 + 6 + 21 + 36)
+
+
+def algorithmic_bytes(kernel, sb):
+    """HBM bytes one active node needs in one launch (sb = bytes per tangent-block entry:
+    4 when the blocks are FP32, 8 in FP64).  Symmetric blocks count their 21 unique entries.
+      elem_kernel   reads the node state (7 FP64), writes F (6 FP64), the diagonal block
+                    (21) and the coupling block (36)
+      factor_kernel reads the diagonal (21) and coupling (36) blocks, writes the Cholesky
+                    blocks L[i,i] (21) and L[i+1,i] (36) in FP64
+    """
+    if kernel == "elem_kernel":
+        return 8 * (7 + 6) + sb * (21 + 36)
+    if kernel == "factor_kernel":
+        return sb * (21 + 36) + 8 * (21 + 36)
+    return None
 
 
 def run_schedule(ctx, rb, n_load_steps, X0):
@@ -89,6 +101,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (robots are "
@@ -98,6 +112,14 @@ def main():
     from paper_2503_06922_amd import fem
     from workloads import make_config
 
+    if args.copy_calib_mib > 0:
+        import torch
+        n = args.copy_calib_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     rb_all, V, T = make_config(3)
     rb = rb_all.subset(np.arange(args.robots)) if args.robots < rb_all.n_robots else rb_all
     prec = fem.FEM_MIXED if args.precision == "mixed" else fem.FEM_FP64
@@ -123,21 +145,31 @@ def main():
     conv, total, iters, info = solves_of(ctx)
     solves = conv * args.steps
     value = solves / dt
-    node_launches = sum((i["iters_total"] + i["steps_total"]) * (int(rb.n_elem[b]) + 1)
-                        for b, i in enumerate(info)) * args.steps
     names = ["elem_kernel", "collide_kernel", "check_rhs_kernel", "factor_kernel", "subst_kernel",
              "update_kernel"]
     kern = {names[k]: dict(total_ms=prof[k][0], launches=prof[k][1],
                            avg_us=1e3 * prof[k][0] / max(prof[k][1], 1)) for k in range(6)}
     dom = max(range(6), key=lambda k: prof[k][0])
-    # roofline of the element update (HBM-bound by design): algorithmic bytes per launch
-    el_launches = max(prof[0][1], 1)
-    avg_nodes = node_launches / el_launches
-    el_avg_s = prof[0][0] / 1e3 / el_launches
-    el_gbs = ELEM_BYTES_PER_NODE * avg_nodes / el_avg_s / 1e9
-    roof = dict(bound="hbm", kernel="elem_kernel", achieved=el_gbs, peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=el_gbs / HBM_PEAK_GBS, traffic=None,
-                bytes_per_node=ELEM_BYTES_PER_NODE, avg_active_nodes=avg_nodes)
+    # rooflines: algorithmic bytes per launch / average launch time (HIP events on the
+    # library's stream), for the kernels with a fixed per-node byte count
+    sb = 4 if prec == fem.FEM_MIXED else 8
+    n_nodes = np.asarray(rb.n_elem, np.int64) + 1
+    node_launches = {  # element update runs once more per load step than the factorisation
+        "elem_kernel": sum((i["iters_total"] + i["steps_total"]) * int(n_nodes[b])
+                           for b, i in enumerate(info)) * args.steps,
+        "factor_kernel": sum(i["iters_total"] * int(n_nodes[b]) for b, i in enumerate(info)) * args.steps,
+    }
+    roofs = {}
+    for k, name in ((0, "elem_kernel"), (3, "factor_kernel")):
+        launches = max(prof[k][1], 1)
+        avg_nodes = node_launches[name] / launches
+        avg_s = prof[k][0] / 1e3 / launches
+        bpn = algorithmic_bytes(name, sb)
+        gbs = bpn * avg_nodes / avg_s / 1e9
+        roofs[name] = dict(bound="hbm", kernel=name, achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s",
+                           frac=gbs / HBM_PEAK_GBS, traffic=None, bytes_per_node=bpn,
+                           avg_active_nodes=avg_nodes, avg_launch_us=avg_s * 1e6)
+    roof = roofs.get(names[dom], roofs["factor_kernel"])
 
     res = {
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
@@ -153,7 +185,7 @@ def main():
         "converged_fraction": conv / max(total, 1),
         "newton_iters_per_solve": iters / max(total, 1),
         "kernels": kern, "dominant_kernel": names[dom],
-        "roofline": roof,
+        "roofline": roof, "rooflines": roofs,
     }
     if prec == fem.FEM_MIXED and not args.no_fp64:
         # the same batch in plain FP64 (batched): throughput and the mixed path's tip error

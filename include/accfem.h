@@ -143,6 +143,8 @@ fem_status fem_set_actuation(fem_ctx* c, fem_act_kind kind, const double* values
  * prev + (target - prev) * j / n_load_steps of the actuation and depth, where
  * prev is what the previous call reached (0 initially) and target the values
  * of fem_set_actuation.  Each load step starts from the previous state.
+ * n_load_steps = 0 solves nothing and takes the target as reached, so that it
+ * starts the next ramp (e.g. after fem_set_state with a state at that load).
  * node_state [total_nodes*7] and info [B] may be NULL.  Returns FEM_E_NOCONV
  * if any robot's last load step did not converge (outputs still written). */
 fem_status fem_solve(fem_ctx* c, int32_t n_load_steps, double* node_state,
@@ -152,6 +154,29 @@ fem_status fem_solve(fem_ctx* c, int32_t n_load_steps, double* node_state,
  * Writes min(total, capacity) entries; *n_out = total even if larger. */
 fem_status fem_contacts(const fem_ctx* c, int32_t robot, fem_contact* out,
                         int32_t capacity, int32_t* n_out);
+
+/* Adjoint gradient at the converged state of the last load step (equilibrium of
+ * eq. 19 with the contact conditions of eq. 14-16; the adjoint is an addition to
+ * the method).  For a loss L on node positions, given dL/dp of n_sensors sensor
+ * nodes per robot, writes dL/du for the actuation values u of the last
+ * fem_set_actuation kind: the cable tensions [B*n_cables] for FEM_ACT_CABLES,
+ * else the tip wrench [B*6].  It solves J^T lam + A_act^T mu = dL/dx,
+ * A_act lam = 0 with the exact Jacobian J of the out-of-balance force (element
+ * material and geometric stiffness plus the follower-load stiffness), the active
+ * contacts (force > 0) held as planes at their normals and the base and guided
+ * lateral DOFs fixed, then dL/du_j = lam . dF_a/du_j.  Always FP64.
+ *   sensor_nodes [n_sensors] host memory: node index i >= 0 counts from the base,
+ *                i < 0 from the tip (-1 = tip), the same for every robot
+ *   dL_dp        [B*n_sensors*3] robot-major, then sensor, then x y z
+ *   dL_du        [B*n_cables] or [B*6] output
+ * dL_dp and dL_du follow io_on_device.  The device workspace (about 1 KB per node)
+ * is allocated on the first call and kept by the context.  FEM_E_INVAL: NULL
+ * pointers, n_sensors < 1 or a sensor index outside some robot.  FEM_E_STATE: no
+ * converged-or-not load step solved since creation or the last fem_set_state.
+ * FEM_E_NOCONV: some robot's last load step did not converge, or its adjoint
+ * system was singular; its entries are NaN, the others are valid. */
+fem_status fem_grad(fem_ctx* c, const int32_t* sensor_nodes, int32_t n_sensors,
+                    const double* dL_dp, double* dL_du);
 
 /* Copy the node state [total_nodes*7] out of / into the context.  fem_set_state
  * also resets the per-robot statistics; quaternions are renormalised. */

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libaccfem.so")
-SOURCES = ["elem.hip", "collide.hip", "solve.hip", "capi.hip"]
+SOURCES = ["elem.hip", "collide.hip", "solve.hip", "adjoint.hip", "capi.hip"]
 ARCH = os.environ.get("ACCFEM_ARCH", "gfx950")
 
 CFLAGS = [

@@ -17,6 +17,9 @@ void launch_elem(const Dev& d, hipStream_t s);
 void launch_collide(const Dev& d, hipStream_t s);
 void launch_solve_phase(const Dev& d, int phase, int it, hipStream_t s);
 void launch_gather(const Dev& d, hipStream_t s);
+void launch_adjoint(const Dev& d, const int32_t* sens, int n_s, const double* dLdp, double* JL,
+                    double* JD, double* JU, double* QB, int32_t* KF, double* GP, double* out,
+                    int32_t* rstat, hipStream_t s);
 void launch_tri_setup(const double* V, const int32_t* tri, int64_t T, double* tv, double* tn,
                       float* tvf, float* tnf, hipStream_t s);
 
@@ -165,6 +168,19 @@ struct fem_ctx {
   double* length_d = nullptr;
   bool lumen_set = false;
   bool act_set = false;
+  bool solved = false;  // a load step was solved since creation / the last fem_set_state
+  // adjoint workspace, allocated by the first fem_grad
+  double* aJL = nullptr;
+  double* aJD = nullptr;
+  double* aJU = nullptr;
+  double* aQB = nullptr;
+  int32_t* aKF = nullptr;
+  double* aGP = nullptr;
+  double* aout = nullptr;
+  int32_t* astat = nullptr;
+  int32_t* asens = nullptr;
+  double* adLdp = nullptr;
+  int32_t a_ns_cap = 0;
   // lumen buffers (reallocated by fem_set_lumen)
   std::vector<void*> mesh_allocs;
   // per-kernel event timing
@@ -613,6 +629,7 @@ fem_status fem_set_state(fem_ctx* c, const double* node_state) {
   HIP_TRY(c, hipMemsetAsync(c->steps_tot, 0, c->B * sizeof(int32_t), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->iters_tot, 0, c->B * sizeof(int64_t), c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->solved = false;
   return FEM_OK;
 }
 
@@ -647,12 +664,12 @@ fem_status fem_solve(fem_ctx* c, int32_t n_load_steps, double* node_state, fem_s
                        c->steps_conv, c->steps_tot, c->iters_tot);
     HIP_TRY(c, hipGetLastError());
   }
-  if (n_load_steps > 0) {
-    HIP_TRY(c, hipMemcpyAsync(c->act_prev, c->act_tgt, (size_t)B * 8 * sizeof(double),
-                              hipMemcpyDeviceToDevice, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(c->dep_prev, c->dep_tgt, (size_t)B * sizeof(double),
-                              hipMemcpyDeviceToDevice, c->stream));
-  }
+  // the target is reached: it is the start of the next ramp (also for n_load_steps = 0)
+  if (n_load_steps > 0) c->solved = true;
+  HIP_TRY(c, hipMemcpyAsync(c->act_prev, c->act_tgt, (size_t)B * 8 * sizeof(double),
+                            hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->dep_prev, c->dep_tgt, (size_t)B * sizeof(double),
+                            hipMemcpyDeviceToDevice, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   bool any_fail = false;
   std::vector<int32_t> st(B);
@@ -686,6 +703,52 @@ fem_status fem_solve(fem_ctx* c, int32_t n_load_steps, double* node_state, fem_s
     if (s != FEM_OK) return s;
   }
   return any_fail ? FEM_E_NOCONV : FEM_OK;
+}
+
+fem_status fem_grad(fem_ctx* c, const int32_t* sensor_nodes, int32_t n_sensors,
+                    const double* dL_dp, double* dL_du) {
+  if (!c) return FEM_E_INVAL;
+  if (!sensor_nodes || !dL_dp || !dL_du || n_sensors < 1)
+    return fail(c, FEM_E_INVAL, "fem_grad: NULL pointer or n_sensors < 1");
+  int64_t min_nodes = INT64_MAX;
+  for (int r = 0; r < c->B; ++r) min_nodes = std::min<int64_t>(min_nodes, c->h_off[r + 1] - c->h_off[r]);
+  for (int s = 0; s < n_sensors; ++s) {
+    const int64_t i = sensor_nodes[s];
+    if (i >= min_nodes || i < -min_nodes)
+      return fail(c, FEM_E_INVAL, "fem_grad: sensor node index outside a robot");
+  }
+  if (!c->solved || !c->act_set || !c->lumen_set)
+    return fail(c, FEM_E_STATE, "fem_grad: no load step solved since creation or fem_set_state");
+  hipSetDevice(c->device);
+  const int B = c->B;
+  const int64_t N = c->Ntot;
+  Dev& d = c->d;
+  if (!c->aJL) {
+    ALLOC(c->aJL, N * 36); ALLOC(c->aJD, N * 36); ALLOC(c->aJU, N * 36);
+    ALLOC(c->aQB, N * 9); ALLOC(c->aKF, N); ALLOC(c->aGP, N * 6);
+    ALLOC(c->aout, (int64_t)B * 8); ALLOC(c->astat, B);
+  }
+  if (n_sensors > c->a_ns_cap) {
+    ALLOC(c->asens, n_sensors);
+    ALLOC(c->adLdp, (int64_t)B * n_sensors * 3);
+    c->a_ns_cap = n_sensors;
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->asens, sensor_nodes, n_sensors * sizeof(int32_t), hipMemcpyHostToDevice,
+                            c->stream));
+  fem_status st = copy_in(c, c->adLdp, dL_dp, (size_t)B * n_sensors * 3 * sizeof(double));
+  if (st != FEM_OK) return st;
+  launch_adjoint(d, c->asens, n_sensors, c->adLdp, c->aJL, c->aJD, c->aJU, c->aQB, c->aKF, c->aGP,
+                 c->aout, c->astat, c->stream);
+  HIP_TRY(c, hipGetLastError());
+  st = copy_out(c, dL_du, c->aout, (size_t)B * c->act_nv * sizeof(double));
+  if (st != FEM_OK) return st;
+  std::vector<int32_t> rs(B);
+  HIP_TRY(c, hipMemcpy(rs.data(), c->astat, B * sizeof(int32_t), hipMemcpyDeviceToHost));
+  int n_bad = 0;
+  for (int r = 0; r < B; ++r) n_bad += (rs[r] != 0);
+  if (n_bad) return fail(c, FEM_E_NOCONV, "fem_grad: " + std::to_string(n_bad) +
+                                              " robot(s) not converged or with a singular adjoint system");
+  return FEM_OK;
 }
 
 fem_status fem_profile(fem_ctx* c, int32_t kernel, double* total_ms, int64_t* launches,

@@ -15,39 +15,9 @@
 // One thread per node computes its two adjacent elements and writes the node's
 // out-of-balance force F_i (6, component-major) and the diagonal block D_i and
 // coupling block K[i, i+1] (6x6 each, node-major: the per-robot sweeps read them in node order).
-#include "fem_device.h"
+#include "element_math.h"
 
 namespace accfem {
-
-// theta/sin(theta) * vee(Q - Q^T)/2 : log of a rotation matrix near the identity
-__device__ __forceinline__ V3 so3_log(const double* Q) {
-  V3 v = v3(0.5 * (Q[7] - Q[5]), 0.5 * (Q[2] - Q[6]), 0.5 * (Q[3] - Q[1]));
-  double c = 0.5 * (Q[0] + Q[4] + Q[8] - 1.0);
-  double s = norm(v);
-  double th = atan2(s, c);
-  double f;
-  if (th < 1e-3) {
-    double t2 = th * th;
-    f = 1.0 + t2 * (1.0 / 6.0 + t2 * (7.0 / 360.0 + t2 * (31.0 / 15120.0)));
-  } else {
-    f = th / s;
-  }
-  return f * v;
-}
-
-// J_l(theta)^-T s = s + 1/2 theta x s + beta(theta) theta x (theta x s)
-__device__ __forceinline__ V3 jl_inv_T(V3 th, V3 s) {
-  double t2 = dot(th, th);
-  double beta;
-  if (t2 < 1e-4) {
-    beta = 1.0 / 12.0 + t2 * (1.0 / 720.0 + t2 * (1.0 / 30240.0));
-  } else {
-    double t = sqrt(t2);
-    beta = 1.0 / t2 - (1.0 + cos(t)) / (2.0 * t * sin(t));
-  }
-  V3 ts = cross(th, s);
-  return s + 0.5 * ts + beta * cross(th, ts);
-}
 
 struct NodeState { V3 p; double R[9]; };
 
@@ -59,43 +29,13 @@ __device__ __forceinline__ NodeState load_node(const Dev& d, int64_t g) {
   return n;
 }
 
-// Internal force of element (a, b): fa = (force, moment) at a, fb at b.
-__device__ void element_force(const NodeState& A, const NodeState& Bn, double l0, double EA,
-                              double EI, double GJ, double* fa, double* fb, V3* e1_out) {
-  V3 c = Bn.p - A.p;
-  double l = norm(c);
-  V3 e1 = (1.0 / l) * c;
-  V3 qa = col(A.R, 1), qb = col(Bn.R, 1);
-  V3 q = 0.5 * (qa + qb);
-  V3 r = cross(e1, q);
-  V3 e3 = (1.0 / norm(r)) * r;
-  V3 e2 = cross(e3, e1);
-  // Q = R_e^T R_node
-  double Qa[9], Qb[9];
-#pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    V3 ca = col(A.R, j), cb = col(Bn.R, j);
-    Qa[j] = dot(e1, ca); Qa[3 + j] = dot(e2, ca); Qa[6 + j] = dot(e3, ca);
-    Qb[j] = dot(e1, cb); Qb[3 + j] = dot(e2, cb); Qb[6 + j] = dot(e3, cb);
-  }
-  V3 ta = so3_log(Qa), tb = so3_log(Qb);
-  double u = l - l0;
-  double gt = GJ / l0, eb = EI / l0;
-  V3 sa = v3(gt * (ta.x - tb.x), eb * (4.0 * ta.y + 2.0 * tb.y), eb * (4.0 * ta.z + 2.0 * tb.z));
-  V3 sb = v3(gt * (tb.x - ta.x), eb * (2.0 * ta.y + 4.0 * tb.y), eb * (2.0 * ta.z + 4.0 * tb.z));
-  double Nx = EA / l0 * u;
-  V3 ma = jl_inv_T(ta, sa), mb = jl_inv_T(tb, sb);
-  V3 m = ma + mb;
-  double q1 = dot(q, e1), q2 = dot(q, e2);
-  V3 fpb = Nx * e1 + ((m.x * q1 / q2 + m.y) / l) * e3 - (m.z / l) * e2;
-  double c1 = m.x / (2.0 * q2);
-  V3 Ma = ma.x * e1 + ma.y * e2 + ma.z * e3;
-  V3 Mb = mb.x * e1 + mb.y * e2 + mb.z * e3;
-  V3 fta = Ma - c1 * cross(qa, e3);
-  V3 ftb = Mb - c1 * cross(qb, e3);
-  fa[0] = -fpb.x; fa[1] = -fpb.y; fa[2] = -fpb.z; fa[3] = fta.x; fa[4] = fta.y; fa[5] = fta.z;
-  fb[0] = fpb.x;  fb[1] = fpb.y;  fb[2] = fpb.z;  fb[3] = ftb.x; fb[4] = ftb.y; fb[5] = ftb.z;
-  *e1_out = e1;
+__device__ __forceinline__ void element_force(const NodeState& A, const NodeState& Bn, double l0,
+                                              double EA, double EI, double GJ, double* fa,
+                                              double* fb, V3* e1_out) {
+  V3T<double> e1;
+  element_force_t<double>(V3T<double>{A.p.x, A.p.y, A.p.z}, A.R, V3T<double>{Bn.p.x, Bn.p.y, Bn.p.z},
+                          Bn.R, l0, EA, EI, GJ, fa, fb, &e1);
+  *e1_out = v3(e1.x, e1.y, e1.z);
 }
 
 // Entry (i, j) of the 3x3 blocks used by the QP tangent:

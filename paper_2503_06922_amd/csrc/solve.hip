@@ -378,13 +378,25 @@ __global__ void __launch_bounds__(NT) check_rhs_kernel(Dev d, int it) {
   __syncthreads();
 }
 
+// 1/sqrt(x) for x > 0: the hardware estimate refined by two Newton steps
+// y <- y + y (1/2 - x y^2 / 2) (quadratic convergence from ~23 correct bits to full FP64)
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = fma(y, fma(-h * y, y, 0.5), y);
+  y = fma(y, fma(-h * y, y, 0.5), y);
+  return y;
+}
+
 // phase 2: block-tridiagonal Cholesky of the QP tangent.
 // Serial over the robot's nodes; per node, lane L < 36 owns entry (a, b) = (L / 6, L % 6):
-//   A = D_i - X_prev X_prev^T   (X_prev = L[f, f-1], rows held redundantly by the lanes of a row)
-//   every lane gathers A's lower triangle by shuffles and factors it in registers,
-//   L[f, f] = chol(A);  row a of X = L[f+1, f] solves L x = S_i[:, a]  (S_i = K[i, i+1]).
+//   A = D_i - X_prev X_prev^T   (X_prev = L[f, f-1]; row a kept in registers, row b read from LDS)
+//   every lane reads A's lower triangle from LDS and factors it in registers (right-looking,
+//   reciprocal square roots only), L[f, f] = chol(A);  row a of X = L[f+1, f] solves
+//   L x = S_i[:, a]  (S_i = K[i, i+1], read from the staged chunk).
 // Rows/columns of prescribed DOFs are replaced by the identity.  Blocks are staged through
-// LDS per chunk of CHF nodes with the next chunk prefetched into registers.
+// LDS per chunk of CHF nodes with the next chunk prefetched into registers.  L[f, f] is
+// stored with the reciprocal of its diagonal.
 __global__ void __launch_bounds__(NT) factor_kernel(Dev d, int it) {
   const int r = blockIdx.x;
   const int lane = threadIdx.x;
@@ -393,9 +405,11 @@ __global__ void __launch_bounds__(NT) factor_kernel(Dev d, int it) {
   const int64_t nf = n - 1;
   const Guide G = make_guide(d, r, n);
   __shared__ double sKD[PFF * NT], sKS[PFF * NT];
+  __shared__ double sA[36], sX[36];
   const int la = lane < 36 ? lane : 35;       // lanes 36..63 mirror lane 35 (results unused)
   const int a = la / 6, b = la % 6;
   double Xa[6] = {0, 0, 0, 0, 0, 0};          // row a of L[f, f-1]
+  if (lane < 36) sX[lane] = 0.0;
   bool fail = false;
   double pd[PFF], ps[PFF];
   auto fetch = [&](int64_t f0) {
@@ -422,49 +436,50 @@ __global__ void __launch_bounds__(NT) factor_kernel(Dev d, int it) {
       const bool last = (f + 1 == nf);
       double dv = sKD[lf + la];
       if (G.dof(i, a) || G.dof(i, b)) dv = (a == b) ? 1.0 : 0.0;
-      double sv = last ? 0.0 : sKS[lf + la];                 // K[i, i+1](a, b)
-      if (!last && (G.dof(i, a) || G.dof(i + 1, b))) sv = 0.0;
       // A(a, b) = D(a, b) - X_prev[a,:] . X_prev[b,:]
       double acc = dv;
 #pragma unroll
-      for (int k = 0; k < 6; ++k) acc -= Xa[k] * __shfl(Xa[k], b * 6);
-      // lower triangle of A in every lane, then Cholesky in registers
+      for (int k = 0; k < 6; ++k) acc -= Xa[k] * sX[b * 6 + k];
+      if (lane < 36) sA[lane] = acc;
+      // column a of S_i, prescribed rows and columns removed
+      double sc[6];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        double v = last ? 0.0 : sKS[lf + j * 6 + a];
+        if (!last && (G.dof(i, j) || G.dof(i + 1, a))) v = 0.0;
+        sc[j] = v;
+      }
+      __syncthreads();
       double Lm[21];
 #pragma unroll
       for (int p = 0, q = 0; p < 6; ++p)
 #pragma unroll
-        for (int c = 0; c <= p; ++c, ++q) Lm[q] = __shfl(acc, p * 6 + c);
+        for (int c = 0; c <= p; ++c, ++q) Lm[q] = sA[p * 6 + c];
+      // right-looking Cholesky: scale column k, update the trailing lower triangle
       double rd[6];
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
         const int kk = k * (k + 1) / 2;
         double dk = Lm[kk + k];
-#pragma unroll
-        for (int j = 0; j < k; ++j) dk -= Lm[kk + j] * Lm[kk + j];
         if (!(dk > 0.0)) { fail = true; dk = 1.0; }
-        const double lkk = sqrt(dk);
-        rd[k] = 1.0 / lkk;
-        Lm[kk + k] = lkk;
+        const double rk = rsqrt_nr(dk);
+        rd[k] = rk;
+#pragma unroll
+        for (int p = k + 1; p < 6; ++p) Lm[p * (p + 1) / 2 + k] *= rk;
 #pragma unroll
         for (int p = k + 1; p < 6; ++p) {
           const int pp = p * (p + 1) / 2;
-          double t = Lm[pp + k];
 #pragma unroll
-          for (int j = 0; j < k; ++j) t -= Lm[pp + j] * Lm[kk + j];
-          Lm[pp + k] = t * rd[k];
+          for (int q = k + 1; q <= p; ++q) Lm[pp + q] -= Lm[pp + k] * Lm[q * (q + 1) / 2 + k];
         }
       }
-      // row a of X: forward substitution L x = S[:, a]
-      double sc[6];
-#pragma unroll
-      for (int j = 0; j < 6; ++j) sc[j] = __shfl(sv, j * 6 + a);
+      // row a of X: forward substitution L x = S[:, a] (right-looking)
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
-        const int kk = k * (k + 1) / 2;
-        double t = sc[k];
+        const double x = sc[k] * rd[k];
+        Xa[k] = last ? 0.0 : x;
 #pragma unroll
-        for (int j = 0; j < k; ++j) t -= Lm[kk + j] * Xa[j];
-        Xa[k] = last ? 0.0 : t * rd[k];
+        for (int p = k + 1; p < 6; ++p) sc[p] -= Lm[p * (p + 1) / 2 + k] * x;
       }
       // select this lane's entries with compile-time indices (keeps the arrays in registers)
       double lv = 0.0, xv = 0.0;
@@ -478,38 +493,49 @@ __global__ void __launch_bounds__(NT) factor_kernel(Dev d, int it) {
       if (lane < 36) {
         d.LD[g * 36 + lane] = lv;
         if (!last) d.LS[g * 36 + lane] = xv;
+        sX[lane] = xv;                                          // X[a][b] for the next node
       }
+      __syncthreads();
     }
   }
   fail = __any(fail ? 1 : 0) != 0;
   if (fail) finish(d, r, 3, it, d.st_rn[r]);
 }
 
-// phase 3: forward and backward substitution of all right-hand sides
+// phase 3: forward and backward substitution of all right-hand sides.
+// One lane per right-hand side (column c of Z), NT columns per pass; every lane sweeps
+// the robot's nodes holding its column's whole 6-vector.  Per chunk of CHS nodes the
+// factor blocks (broadcast to all lanes) and the lanes' right-hand-side values are
+// staged through LDS, with the next chunk's loads in flight in registers meanwhile.
 __global__ void __launch_bounds__(NT) subst_kernel(Dev d) {
   const int r = blockIdx.x;
   const int lane = threadIdx.x;
   if (d.st_done[r]) return;
   const int64_t o = d.off[r], n = d.off[r + 1] - o;
-  const int64_t N = d.Ntot;
   const int64_t nf = n - 1;            // free nodes 1..n-1 -> f = 0..nf-1
-  const int cap = d.cap;
-  const int64_t cb = (int64_t)r * cap;
   const int nc = d.st_nc[r];
   const int ncol = 1 + nc;
   double* Zr = d.Z + d.zoff[r];
   const int64_t ld = 6 * n;
   __shared__ double sKD[PFS * NT], sKS[PFS * NT];
-  // ---------------------------------------------------------------- substitutions
-  // six lanes per right-hand side (lane = row of the 6-block), ten columns per pass;
-  // factor blocks are staged per chunk of CHS nodes like above (forward: LD[f], LS[f-1];
-  // backward: LD[f], LS[f]).
-  for (int c0 = 0; c0 < ncol; c0 += 10) {
-    const int grp = lane / 6, a = lane % 6, base = min(grp, 9) * 6;
-    const int c = c0 + grp;
-    const bool act = (lane < 60) && (c < ncol);
+  __shared__ double sZ[CHS * 6 * NT];  // [u][k][lane]
+  for (int c0 = 0; c0 < ncol; c0 += NT) {
+    const int c = c0 + lane;
+    const bool act = c < ncol;
     double* z = Zr + (int64_t)(act ? c : 0) * ld;
-    double pd[PFS], ps[PFS];
+    double pd[PFS], ps[PFS], pz[CHS * 6];
+    auto fetchZ = [&](int64_t f0, int64_t f1) {
+#pragma unroll
+      for (int u = 0; u < CHS; ++u)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) pz[u * 6 + k] = (act && f0 + u < f1) ? z[6 * (f0 + u) + k] : 0.0;
+    };
+    auto stage = [&]() {
+#pragma unroll
+      for (int u = 0; u < PFS; ++u) { sKD[lane + u * NT] = pd[u]; sKS[lane + u * NT] = ps[u]; }
+#pragma unroll
+      for (int q = 0; q < CHS * 6; ++q) sZ[q * NT + lane] = pz[q];
+    };
     // forward sweep: chunk f0 needs LD of nodes f0..f1-1 and LS of nodes f0-1..f1-2
     auto fetchF = [&](int64_t f0) {
       const int64_t cnt = min((int64_t)CHS, nf - f0) * 36;
@@ -521,45 +547,43 @@ __global__ void __launch_bounds__(NT) subst_kernel(Dev d) {
         pd[u] = idx < cnt ? ldp[idx] : 0.0;
         ps[u] = idx < cnt ? lsp[idx] : 0.0;
       }
+      fetchZ(f0, min(nf, f0 + CHS));
     };
-    double yp[6] = {0, 0, 0, 0, 0, 0};   // previous block solution (whole 6-vector per lane)
+    double yp[6] = {0, 0, 0, 0, 0, 0};   // previous block solution
     fetchF(0);
     for (int64_t f0 = 0; f0 < nf; f0 += CHS) {
       __syncthreads();
-#pragma unroll
-      for (int u = 0; u < PFS; ++u) { sKD[lane + u * NT] = pd[u]; sKS[lane + u * NT] = ps[u]; }
+      stage();
       __syncthreads();
       if (f0 + CHS < nf) fetchF(f0 + CHS);
       const int64_t f1 = min(nf, f0 + CHS);
-      double zc[CHS];
-#pragma unroll
-      for (int u = 0; u < CHS; ++u) zc[u] = (act && f0 + u < f1) ? z[6 * (f0 + u) + a] : 0.0;
 #pragma unroll
       for (int u = 0; u < CHS; ++u) {
         const int64_t f = f0 + u;
         if (f >= f1) break;
-        double bv = zc[u];
+        double bv[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) bv[k] = sZ[(u * 6 + k) * NT + lane];
         if (f > 0) {
-          const double* Ls = sKS + u * 36 + a * 6;        // L[f, f-1] row a
+          const double* Ls = sKS + u * 36;                // L[f, f-1]
 #pragma unroll
-          for (int k = 0; k < 6; ++k) bv -= Ls[k] * yp[k];
+          for (int p = 0; p < 6; ++p)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) bv[p] -= Ls[p * 6 + k] * yp[k];
         }
-        double bb[6];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) bb[k] = __shfl(bv, base + k);
         const double* Ld = sKD + u * 36;                  // lower triangle, reciprocal diagonal
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-          double t = bb[k];
+          const double y = bv[k] * Ld[k * 7];
+          yp[k] = y;
 #pragma unroll
-          for (int j = 0; j < k; ++j) t -= Ld[k * 6 + j] * yp[j];
-          yp[k] = t * Ld[k * 7];
+          for (int p = k + 1; p < 6; ++p) bv[p] -= Ld[p * 6 + k] * y;
         }
-        zc[u] = yp[a];
-      }
+        if (act) {
 #pragma unroll
-      for (int u = 0; u < CHS; ++u)
-        if (act && f0 + u < f1) z[6 * (f0 + u) + a] = zc[u];
+          for (int k = 0; k < 6; ++k) z[6 * f + k] = yp[k];
+        }
+      }
     }
     // backward sweep over chunks from the tip: chunk [f0, f1) needs LD and LS of f0..f1-1
     auto fetchB = [&](int64_t f0, int64_t f1) {
@@ -572,49 +596,48 @@ __global__ void __launch_bounds__(NT) subst_kernel(Dev d) {
         pd[u] = idx < cnt ? ldp[idx] : 0.0;
         ps[u] = idx < cnt ? lsp[idx] : 0.0;
       }
+      fetchZ(f0, f1);
     };
-    double xn[6] = {0, 0, 0, 0, 0, 0};   // next block solution (whole 6-vector per lane)
+    double xn[6] = {0, 0, 0, 0, 0, 0};   // next block solution
     const int64_t nch = (nf + CHS - 1) / CHS;
+    __syncthreads();                     // forward stores of this column precede the reloads
     fetchB((nch - 1) * CHS, nf);
     for (int64_t ch = nch - 1; ch >= 0; --ch) {
       const int64_t f0 = ch * CHS, f1 = min(nf, f0 + CHS);
       __syncthreads();
-#pragma unroll
-      for (int u = 0; u < PFS; ++u) { sKD[lane + u * NT] = pd[u]; sKS[lane + u * NT] = ps[u]; }
+      stage();
       __syncthreads();
       if (ch > 0) fetchB(f0 - CHS, f0);
-      double zc[CHS];
-#pragma unroll
-      for (int u = 0; u < CHS; ++u) zc[u] = (act && f0 + u < f1) ? z[6 * (f0 + u) + a] : 0.0;
 #pragma unroll
       for (int u = CHS - 1; u >= 0; --u) {
         const int64_t f = f0 + u;
         if (f >= f1) continue;
-        double bv = zc[u];
+        double bv[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) bv[k] = sZ[(u * 6 + k) * NT + lane];
         if (f + 1 < nf) {
-          const double* Ls = sKS + u * 36;                // L[f+1, f]; its column a
+          const double* Ls = sKS + u * 36;                // L[f+1, f]; b -= L^T x_next
 #pragma unroll
-          for (int k = 0; k < 6; ++k) bv -= Ls[k * 6 + a] * xn[k];
+          for (int k = 0; k < 6; ++k)
+#pragma unroll
+            for (int p = 0; p < 6; ++p) bv[p] -= Ls[k * 6 + p] * xn[k];
         }
-        double bb[6];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) bb[k] = __shfl(bv, base + k);
         const double* Ld = sKD + u * 36;
 #pragma unroll
         for (int k = 5; k >= 0; --k) {
-          double t = bb[k];
+          const double x = bv[k] * Ld[k * 7];
+          xn[k] = x;
 #pragma unroll
-          for (int j = k + 1; j < 6; ++j) t -= Ld[j * 6 + k] * xn[j];
-          xn[k] = t * Ld[k * 7];
+          for (int p = 0; p < k; ++p) bv[p] -= Ld[k * 6 + p] * x;
         }
-        zc[u] = xn[a];
-      }
+        if (act) {
 #pragma unroll
-      for (int u = 0; u < CHS; ++u)
-        if (act && f0 + u < f1) z[6 * (f0 + u) + a] = zc[u];
+          for (int k = 0; k < 6; ++k) z[6 * f + k] = xn[k];
+        }
+      }
     }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
 // phase 4: contact Schur complement, LCP, step limit and state update

@@ -88,10 +88,11 @@ def lib():
         L.fem_eval.argtypes = [P, P, P, P]
         L.fem_profile.argtypes = [P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                   C.c_int32]
+        L.fem_grad.argtypes = [P, P, C.c_int32, P, P]
         L.fem_total_nodes.argtypes = [P]
         L.fem_total_nodes.restype = C.c_int64
         for f in ("fem_create", "fem_set_lumen", "fem_set_actuation", "fem_solve", "fem_contacts",
-                  "fem_get_state", "fem_set_state", "fem_eval", "fem_profile"):
+                  "fem_get_state", "fem_set_state", "fem_eval", "fem_profile", "fem_grad"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -99,7 +100,7 @@ def lib():
 
 EXPORTED = ("fem_create", "fem_destroy", "fem_last_error", "fem_set_lumen", "fem_set_actuation",
             "fem_solve", "fem_contacts", "fem_get_state", "fem_set_state", "fem_eval",
-            "fem_profile", "fem_total_nodes")
+            "fem_profile", "fem_grad", "fem_total_nodes")
 
 
 class FemError(RuntimeError):
@@ -165,6 +166,8 @@ class Context:
         self._h = h
         self.n_nodes = int(L.fem_total_nodes(h))
         self.node_offset = np.concatenate([[0], np.cumsum(k["n_elem"].astype(np.int64) + 1)])
+        self.act_kind = None
+        self.generation = 0  # bumped by every fem_solve / fem_set_state
 
     def _check(self, st, ok=(FEM_OK,)):
         if st not in ok:
@@ -192,6 +195,7 @@ class Context:
         return self._check(lib().fem_set_lumen(self._h, _ptr(V), V.shape[0], _ptr(T), T.shape[0]))
 
     def fem_set_actuation(self, kind, values, depth=None):
+        self.act_kind = int(kind)
         if self.io_on_device:
             return self._check(lib().fem_set_actuation(self._h, int(kind), _ptr(values), _ptr(depth)))
         nv = self.n_cables if kind == FEM_ACT_CABLES else 6
@@ -200,6 +204,7 @@ class Context:
         return self._check(lib().fem_set_actuation(self._h, int(kind), _ptr(v), _ptr(d)))
 
     def fem_solve(self, n_load_steps, state=True, info=True):
+        self.generation += 1
         X = np.empty((self.n_nodes, 7)) if state else None
         I = (fem_solve_info * self.B)() if info else None
         st = lib().fem_solve(self._h, int(n_load_steps), _ptr(X),
@@ -228,6 +233,7 @@ class Context:
         return X
 
     def fem_set_state(self, X):
+        self.generation += 1
         X = _f64(X, self.n_nodes * 7)
         return self._check(lib().fem_set_state(self._h, _ptr(X)))
 
@@ -236,6 +242,25 @@ class Context:
         n = C.c_int64(0)
         self._check(lib().fem_profile(self._h, int(kernel), C.byref(ms), C.byref(n), int(reset)))
         return ms.value, n.value
+
+    def fem_grad(self, sensor_nodes, dL_dp):
+        """dL/du [B, n_values] for dL_dp [B, n_sensors, 3]; NaN rows for robots that failed.
+
+        Returns (gradient, status) with status FEM_OK or FEM_E_NOCONV."""
+        s = np.ascontiguousarray(np.asarray(sensor_nodes, np.int32)).ravel()
+        nv = self.n_cables if self.act_kind == FEM_ACT_CABLES else 6
+        g = _f64(dL_dp, self.B * s.size * 3)
+        out = np.empty((self.B, nv))
+        st = lib().fem_grad(self._h, _ptr(s), int(s.size), _ptr(g), _ptr(out))
+        self._check(st, ok=(FEM_OK, FEM_E_NOCONV))
+        return out, st
+
+    def sensor_rows(self, sensor_nodes):
+        """Row indices [B, n_sensors] into the node state of the given sensor nodes."""
+        off = self.node_offset
+        n = np.diff(off)
+        s = np.asarray(sensor_nodes, np.int64)
+        return off[:-1, None] + np.where(s[None, :] < 0, n[:, None] + s[None, :], s[None, :])
 
     def fem_eval(self):
         F = np.empty((self.n_nodes, 6))

@@ -1,0 +1,213 @@
+"""GPU parity tests of the adjoint gradient (fem_grad) and its torch.autograd wrapper.
+
+The HIP path takes the exact Jacobian (dual numbers through the element force) and
+eliminates the contact and guide constraints in node-local bases; the oracle takes a
+finite-difference Jacobian and a dense KKT solve.  The oracle's own pins (closed-form
+cantilever flexibilities, finite differences of re-solves) live with the CPU tests.
+Bar: 1e-6 relative to the largest gradient entry of the robot.
+"""
+import numpy as np
+import pytest
+
+from oracle import actuation, adjoint, solver
+from workloads import load_schedule, make_config, robots_for_config
+from tests.gpu_helpers import gpu_context, oracle_robots, robot_slices, compare_contact_keys
+
+pytestmark = pytest.mark.gpu
+
+TOL_GRAD = 1e-6
+
+
+def _rel(a, b):
+    return np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(b).max(), 1e-300)
+
+
+def test_grad_closed_form_cantilever():
+    """Unloaded straight cantilever, no lumen: dL/d(tip wrench) is the Euler-Bernoulli
+    flexibility (exact at the nodes for Hermite elements)."""
+    from paper_2503_06922_amd import fem
+    rb = robots_for_config(0)
+    rb.n_elem[:] = 10
+    ctx = gpu_context(rb, None, None, newton_tol=1e-13, stag_tol=1e-9, max_newton=50)
+    ctx.fem_set_actuation(fem.FEM_ACT_TIP_WRENCH_GLOBAL, np.zeros(6), None)
+    ctx.fem_solve(1)
+    EI = np.pi / 4 * (rb.r_out**4 - rb.r_in**4) * rb.E
+    EA = np.pi * (rb.r_out**2 - rb.r_in**2) * rb.E
+    L = rb.length[0]
+    X = ctx.fem_get_state()
+    d = rb.base_dir[0] / np.linalg.norm(rb.base_dir[0])
+    assert np.allclose(X[-1, 0:3], rb.base_pos[0] + L * d, atol=1e-15)
+    # sensors: the tip and node 4, loss = e . p with e along the axis or across it
+    for node in (-1, 4):
+        a = L if node == -1 else node * L / 10
+        side = np.cross(d, rb.base_up[0])
+        for dirn in (d, side / np.linalg.norm(side)):
+            g, st = ctx.fem_grad([node], dirn[None, None, :])
+            assert st == fem.FEM_OK
+            ref = np.zeros(6)
+            if dirn is d:
+                ref[0:3] = d * a / EA
+            else:
+                ref[0:3] = dirn * a * a * (3 * L - a) / (6 * EI)
+                ref[3:6] = np.cross(d, dirn) * a * a / (2 * EI)  # moment turning the axis into dirn
+            assert _rel(g[0], ref) <= 1e-9, (node, g[0], ref)
+
+
+@pytest.fixture(scope="module")
+def cfg0_solved():
+    rb, V, T = make_config(0)
+    robs, mesh = oracle_robots(rb, V, T)
+    rob = robs[0]
+    sched = lambda k: (lambda d, t: (d[0], t[0]))(*load_schedule(rb, k))
+    P, R, traj = solver.solve_robot(rob, sched, rb.n_load_steps, tol=1e-13, stag_tol=1e-9)
+    return rb, V, T, rob, traj
+
+
+def test_grad_cfg0_matches_oracle(cfg0_solved):
+    """Tension gradient of a two-sensor loss at the end of the straight-tube ramp, with
+    active wall contacts and the follower cable moment."""
+    rb, V, T, rob, traj = cfg0_solved
+    ctx = gpu_context(rb, V, T, newton_tol=1e-13, stag_tol=1e-9, max_newton=200)
+    for k in range(1, rb.n_load_steps + 1):
+        d, t = load_schedule(rb, k)
+        ctx.fem_set_actuation(0, t.ravel(), d)
+        out = ctx.fem_solve(1)
+        assert out["info"][0]["status"] == 0
+    o = traj[-1]
+    n_cmp, _ = compare_contact_keys(ctx.fem_contacts(0), list(zip(o["contacts"], o["y"])), o["P"], rob)
+    assert n_cmp >= 2
+    sens = [rob.n_elem - 2, -1]
+    rng = np.random.default_rng(7)
+    dLdp = rng.normal(size=(1, 2, 3))
+    g, st = ctx.fem_grad(sens, dLdp)
+    assert st == 0
+    go = adjoint.tension_gradient(rob, o["P"], o["R"], o["contacts"], o["y"], rb.tensions[0],
+                                  [rob.n_elem - 2, rob.n_elem], dLdp[0])
+    assert _rel(g[0], go) <= TOL_GRAD, (g[0], go)
+
+
+def test_grad_batched_guided_matches_oracle():
+    """Robots of different lengths inserted through the guide into the branching lumen:
+    each robot's gradient equals its own oracle adjoint (guided lateral DOFs fixed)."""
+    rb, V, T = make_config(3)
+    sub = rb.subset([0, 1, 2, 3, 5, 8])
+    robs, mesh = oracle_robots(sub, V, T)
+    ctx = gpu_context(sub, V, T, newton_tol=1e-12, stag_tol=1e-9, max_newton=100)
+    n_steps = 8
+    states = [r.reference() for r in robs]
+    last = [None] * sub.n_robots
+    for k in range(1, n_steps + 1):
+        d, t = load_schedule(sub, k)
+        ctx.fem_set_actuation(0, t.ravel(), d)
+        out = ctx.fem_solve(1)
+        for b, rob in enumerate(robs):
+            P, R = states[b]
+            P1, R1, cont, y, info = solver.solve_load_step(rob, P, R, rob.base_target(d[b]), 0, t[b],
+                                                           tol=1e-12, stag_tol=1e-9, max_iter=100,
+                                                           guided=rob.guided(d[b]))
+            states[b] = (P1, R1)
+            last[b] = (P1, R1, cont, y, info, d[b], t[b])
+    sens = [-1, -3, 5]
+    rng = np.random.default_rng(11)
+    dLdp = rng.normal(size=(sub.n_robots, 3, 3))
+    g, st = ctx.fem_grad(sens, dLdp)
+    compared = 0
+    for b, rob in enumerate(robs):
+        P1, R1, cont, y, info, db, tb = last[b]
+        if out["info"][b]["status"] != 0:
+            assert np.isnan(g[b]).all()
+            continue
+        if info["status"] != solver.OK:
+            continue
+        n = rob.n_elem + 1
+        go = adjoint.tension_gradient(rob, P1, R1, cont, y, tb, [n - 1, n - 3, 5], dLdp[b],
+                                      guided=rob.guided(db))
+        assert _rel(g[b], go) <= TOL_GRAD, (b, g[b], go)
+        compared += 1
+    assert compared >= 4
+
+
+def test_grad_tip_wrench_kinds_match_oracle():
+    """Follower (local) and dead (global) tip wrenches at a large deflection, no lumen:
+    the follower kind exercises the load stiffness of the tip force and moment."""
+    from paper_2503_06922_amd import fem
+    rb = robots_for_config(0)
+    rb.n_elem[:] = 12
+    robs, _ = oracle_robots(rb)
+    rob = robs[0]
+    EI = np.pi / 4 * (rb.r_out**4 - rb.r_in**4) * rb.E
+    L = rb.length[0]
+    w = np.array([0.2, 0.3, -0.1, 0.0, 0.4, 0.8]) * EI / L**2 * np.array([1, 1, 1, L, L, L])
+    rng = np.random.default_rng(3)
+    dLdp = rng.normal(size=(1, 2, 3))
+    for kind, okind in ((fem.FEM_ACT_TIP_WRENCH_LOCAL, actuation.TIP_LOCAL),
+                        (fem.FEM_ACT_TIP_WRENCH_GLOBAL, actuation.TIP_GLOBAL)):
+        ctx = gpu_context(rb, None, None, newton_tol=1e-12, stag_tol=1e-9, max_newton=200)
+        ctx.fem_set_actuation(kind, w, None)
+        out = ctx.fem_solve(10)
+        assert out["info"][0]["status"] == 0
+        P, R, traj = solver.solve_robot(rob, lambda k: (0.0, w * k / 10), 10, act_kind=okind,
+                                        tol=1e-12, stag_tol=1e-9)
+        assert traj[-1]["info"]["status"] == solver.OK
+        g, st = ctx.fem_grad([-1, 6], dLdp)
+        assert st == 0
+        go = adjoint.tension_gradient(rob, P, R, [], np.zeros(0), w, [rob.n_elem, 6], dLdp[0],
+                                      act_kind=okind)
+        assert _rel(g[0], go) <= TOL_GRAD, (kind, g[0], go)
+
+
+def test_autograd_function_matches_gpu_finite_differences(cfg0_solved):
+    """FEMEquilibrium: backward (adjoint) against central differences of GPU re-solves."""
+    import torch
+    from paper_2503_06922_amd.autograd import FEMEquilibrium
+    rb, V, T, rob, _ = cfg0_solved
+    ctx = gpu_context(rb, V, T, newton_tol=1e-13, stag_tol=1e-9, max_newton=200)
+    ctx.fem_set_actuation(0, np.zeros(3), rb.depth)
+    X0 = ctx.fem_get_state()
+    sens = [rob.n_elem - 2, -1]
+    n_steps = rb.n_load_steps
+    target = None
+
+    def loss_of(Tt):
+        nonlocal target
+        pos = FEMEquilibrium.apply(Tt, ctx, sens, rb.depth, n_steps, X0)
+        if target is None:
+            target = pos.detach() + torch.tensor([[[1e-3, -2e-3, 0.5e-3], [-1e-3, 1e-3, 2e-3]]],
+                                                 dtype=pos.dtype, device=pos.device)
+        return ((pos - target) ** 2).sum()
+
+    dev = "cuda" if torch.cuda.is_available() else "cpu"
+    T0 = torch.tensor(rb.tensions, dtype=torch.float64, device=dev, requires_grad=True)
+    L0 = loss_of(T0)
+    L0.backward()
+    g = T0.grad.detach().cpu().numpy()[0]
+    h = 1e-5
+    fd = np.zeros(3)
+    with torch.no_grad():
+        for j in range(3):
+            Tp = T0.detach().clone()
+            Tp[0, j] += h
+            Tm = T0.detach().clone()
+            Tm[0, j] -= h
+            fd[j] = (loss_of(Tp).item() - loss_of(Tm).item()) / (2 * h)
+    assert _rel(g, fd) <= 1e-5, (g, fd)
+
+
+def test_grad_error_paths():
+    from paper_2503_06922_amd import fem
+    rb = robots_for_config(0)
+    ctx = gpu_context(rb, None, None)
+    ctx.fem_set_actuation(0, np.zeros(3), None)
+    with pytest.raises(fem.FemError) as e:
+        ctx.fem_grad([-1], np.zeros((1, 1, 3)))
+    assert e.value.status == -4  # no load step solved yet
+    ctx.fem_solve(1)
+    with pytest.raises(fem.FemError) as e:
+        ctx.fem_grad([rb.n_elem[0] + 1], np.zeros((1, 1, 3)))
+    assert e.value.status == -1  # sensor outside the robot
+    g, st = ctx.fem_grad([-1], np.zeros((1, 1, 3)))
+    assert st == 0 and np.all(g == 0.0)
+    ctx.fem_set_state(ctx.fem_get_state())
+    with pytest.raises(fem.FemError) as e:
+        ctx.fem_grad([-1], np.zeros((1, 1, 3)))
+    assert e.value.status == -4
