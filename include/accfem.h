@@ -46,6 +46,12 @@ typedef enum {
   FEM_E_NOCONV = -5    /* results written, some robots did not converge: see info */
 } fem_status;
 
+/* Arithmetic of the Newton loop.  FEM_FP64: everything in FP64.  FEM_MIXED: the
+ * element chord directions that carry the QP tangent are stored in FP32 (the
+ * tangent blocks are regenerated from them in FP64, so K stays positive definite)
+ * and contact detection screens triangles in FP32 before deciding in FP64; the
+ * residual, the factorisation, the LCP and the state stay FP64, so both converge
+ * to the same equilibrium. */
 typedef enum { FEM_FP64 = 0, FEM_MIXED = 1 } fem_precision;
 
 /* Actuation kinds (eq. 16-18).  CABLES: values[b*n_cables + j] = tension T_j (N)

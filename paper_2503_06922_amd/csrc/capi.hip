@@ -27,7 +27,7 @@ void launch_tri_setup(const double* V, const int32_t* tri, int64_t T, double* tv
 // straight reference configuration S_0 and the per-element rigidities
 __global__ void init_state_kernel(Dev d, double r_out, double r_in, double E, double nu,
                                   double tip_len, double shE, double shA, double shI,
-                                  const double* length) {
+                                  const double* length, double* KC) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= d.Ntot) return;
   const int r = d.robot_of[g];
@@ -72,7 +72,34 @@ __global__ void init_state_kernel(Dev d, double r_out, double r_in, double E, do
     d.EA[g] = Ee * A;
     d.EI[g] = Ee * I;
     d.GJ[g] = G * 2.0 * I;
+    // constants of the QP tangent blocks (Euler-Bernoulli space-frame stiffness)
+    const double EA = d.EA[g], EI = d.EI[g], GJ = d.GJ[g];
+    KC[g] = EA / l0;
+    KC[N + g] = GJ / l0;
+    KC[2 * N + g] = 12.0 * EI / (l0 * l0 * l0);
+    KC[3 * N + g] = 6.0 * EI / (l0 * l0);
+    KC[4 * N + g] = 4.0 * EI / l0;
+    KC[5 * N + g] = 2.0 * EI / l0;
+  } else {
+    for (int k = 0; k < 6; ++k) KC[k * N + g] = 0.0;
+    d.E1[g] = 0.0; d.E1[N + g] = 0.0; d.E1[2 * N + g] = 0.0;
+    d.E1f[g] = 0.0f; d.E1f[N + g] = 0.0f; d.E1f[2 * N + g] = 0.0f;
   }
+}
+
+// node-major 6x6 blocks of the QP tangent from the element chord directions (verification output)
+__global__ void assemble_kernel(Dev d, double* KD, double* KS) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= d.Ntot) return;
+  const int r = d.robot_of[g];
+  const int64_t o = d.off[r], n = d.off[r + 1] - o, i = g - o;
+  const bool left = i > 0, right = i < n - 1;
+  const ElemK KL = load_elem(d, left ? g - 1 : g), KR = load_elem(d, right ? g : g - 1);
+  for (int row = 0; row < 6; ++row)
+    for (int cl = 0; cl < 6; ++cl) {
+      KD[g * 36 + row * 6 + cl] = (left ? k_bb(KL, row, cl) : 0.0) + (right ? k_aa(KR, row, cl) : 0.0);
+      KS[g * 36 + row * 6 + cl] = right ? k_ab(KR, row, cl) : 0.0;
+    }
 }
 
 // load step j of n: interpolate actuation and depth, reset per-robot Newton state
@@ -120,11 +147,6 @@ __global__ void renorm_kernel(Dev d) {
   d.X[3 * N + g] = w * inv; d.X[4 * N + g] = x * inv; d.X[5 * N + g] = y * inv; d.X[6 * N + g] = z * inv;
 }
 
-__global__ void f32_to_f64(const float* in, double* out, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = (double)in[i];
-}
-
 // node-major [g][7] <-> SoA [k][g]
 __global__ void aos_to_soa(const double* in, double* out, int64_t N, int K) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -166,6 +188,7 @@ struct fem_ctx {
   int32_t* steps_tot = nullptr;
   int64_t* iters_tot = nullptr;
   double* length_d = nullptr;
+  double* kc = nullptr;   // per-element tangent constants (written once at creation)
   bool lumen_set = false;
   bool act_set = false;
   bool solved = false;  // a load step was solved since creation / the last fem_set_state
@@ -409,14 +432,15 @@ static fem_status create_impl(fem_ctx* c, const fem_params* p) {
   d.cap = cap;
   d.mixed = (p->precision == FEM_MIXED) ? 1 : 0;
   // state and per-iteration buffers
-  ALLOC(d.X, 7 * N); ALLOC(d.F, 6 * N); ALLOC(d.KD, 36 * N); ALLOC(d.KS, 36 * N);
-  ALLOC(d.KDf, 36 * N); ALLOC(d.KSf, 36 * N);
-  HIP_TRY(c, hipMemset(d.KSf, 0, 36 * N * sizeof(float)));
+  ALLOC(d.X, 7 * N); ALLOC(d.F, 6 * N); ALLOC(d.E1, 3 * N); ALLOC(d.E1f, 3 * N);
+  double* kc = nullptr;
+  ALLOC(kc, 6 * N);
+  d.KC = kc;
+  c->kc = kc;
   ALLOC(d.LD, 36 * N); ALLOC(d.LS, 36 * N);
   ALLOC(d.CC, N); ALLOC(d.CT, MAXC * N); ALLOC(d.CK, MAXC * N); ALLOC(d.CN, 3 * MAXC * N);
   ALLOC(d.CG, MAXC * N);
   HIP_TRY(c, hipMemset(d.CC, 0, N * sizeof(int32_t)));
-  HIP_TRY(c, hipMemset(d.KS, 0, 36 * N * sizeof(double)));
   const int64_t BC = (int64_t)B * cap;
   ALLOC(d.ct_node, BC); ALLOC(d.ct_tri, BC); ALLOC(d.ct_kind, BC); ALLOC(d.ct_n, 3 * BC);
   ALLOC(d.ct_gap, BC); ALLOC(d.ct_y, BC);
@@ -460,7 +484,7 @@ static fem_status create_impl(fem_ctx* c, const fem_params* p) {
   }
   hipLaunchKernelGGL(init_state_kernel, dim3(nblk(N, 256)), dim3(256), 0, c->stream, d, p->r_out,
                      p->r_in, p->E, p->nu, p->tip_len, p->shaft_E, p->shaft_A, p->shaft_I,
-                     (const double*)c->length_d);
+                     (const double*)c->length_d, c->kc);
   HIP_TRY(c, hipGetLastError());
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return FEM_OK;
@@ -785,18 +809,18 @@ fem_status fem_eval(fem_ctx* c, double* F, double* KD, double* KS) {
     fem_status s = copy_out(c, F, d.LS, (size_t)c->Ntot * 6 * sizeof(double));
     if (s != FEM_OK) return s;
   }
-  for (int which = 0; which < 2; ++which) {
-    double* dst = which == 0 ? KD : KS;
-    if (!dst) continue;
-    const double* src = which == 0 ? d.KD : d.KS;
-    if (d.mixed) {
-      hipLaunchKernelGGL(f32_to_f64, dim3(nblk(c->Ntot * 36, 256)), dim3(256), 0, c->stream,
-                         (const float*)(which == 0 ? d.KDf : d.KSf), d.LS, c->Ntot * 36);
-      HIP_TRY(c, hipGetLastError());
-      src = d.LS;
+  if (KD || KS) {
+    hipLaunchKernelGGL(assemble_kernel, dim3(nblk(c->Ntot, 256)), dim3(256), 0, c->stream, d, d.LD,
+                       d.LS);
+    HIP_TRY(c, hipGetLastError());
+    if (KD) {
+      fem_status s = copy_out(c, KD, d.LD, (size_t)c->Ntot * 36 * sizeof(double));
+      if (s != FEM_OK) return s;
     }
-    fem_status s = copy_out(c, dst, src, (size_t)c->Ntot * 36 * sizeof(double));
-    if (s != FEM_OK) return s;
+    if (KS) {
+      fem_status s = copy_out(c, KS, d.LS, (size_t)c->Ntot * 36 * sizeof(double));
+      if (s != FEM_OK) return s;
+    }
   }
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return FEM_OK;

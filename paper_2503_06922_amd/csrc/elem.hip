@@ -9,12 +9,10 @@
 //   internal force = gradient of 1/2 d.K7 d through the element-frame spin and the
 //   inverse left Jacobian of the log map (exact, self-equilibrated).
 // The QP tangent of eq. 20-23 is the constant local stiffness turned into the
-// element frame, K_e = Rcal K_l Rcal^T.  With equal bending stiffness about both
-// section axes its 3x3 blocks depend on e1 only:
-//   diag(x, y, y) -> y I + (x - y) e1 e1^T,   local skew blocks -> +-k2 [e1]x.
+// element frame, K_e = Rcal K_l Rcal^T; its blocks depend on the chord direction e1
+// only (see ElemK), so the element update stores e1 and the solver generates the blocks.
 // One thread per node computes its two adjacent elements and writes the node's
-// out-of-balance force F_i (6, component-major) and the diagonal block D_i and
-// coupling block K[i, i+1] (6x6 each, node-major: the per-robot sweeps read them in node order).
+// out-of-balance force F_i (6, component-major) and the chord direction of element (i, i+1).
 #include "element_math.h"
 
 namespace accfem {
@@ -38,30 +36,6 @@ __device__ __forceinline__ void element_force(const NodeState& A, const NodeStat
   *e1_out = v3(e1.x, e1.y, e1.z);
 }
 
-// Entry (i, j) of the 3x3 blocks used by the QP tangent:
-//   iso(e; x, y) = y I + (x - y) e e^T,   skew(e; s) = s [e]x
-__device__ __forceinline__ double iso_ij(int i, int j, const double* e, double x, double y) {
-  return (i == j ? y : 0.0) + (x - y) * e[i] * e[j];
-}
-__device__ __forceinline__ double skew_ij(int i, int j, const double* e, double s) {
-  // [e]x = [[0, -ez, ey], [ez, 0, -ex], [-ey, ex, 0]]
-  if (i == j) return 0.0;
-  const int k = 3 - i - j;                       // the remaining axis
-  const double sg = ((j - i + 3) % 3 == 1) ? -1.0 : 1.0;
-  return s * sg * e[k];
-}
-
-struct ElemK { double e[3]; double a, t, k1, k2, k3, k4; bool on; };
-
-__device__ __forceinline__ ElemK elem_coeffs(V3 e1, double l0, double EA, double EI, double GJ) {
-  ElemK k;
-  k.e[0] = e1.x; k.e[1] = e1.y; k.e[2] = e1.z;
-  k.a = EA / l0; k.t = GJ / l0; k.k1 = 12.0 * EI / (l0 * l0 * l0); k.k2 = 6.0 * EI / (l0 * l0);
-  k.k3 = 4.0 * EI / l0; k.k4 = 2.0 * EI / l0;
-  k.on = true;
-  return k;
-}
-
 __global__ void __launch_bounds__(256) elem_kernel(Dev d) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= d.Ntot) return;
@@ -74,9 +48,6 @@ __global__ void __launch_bounds__(256) elem_kernel(Dev d) {
   const int64_t N = d.Ntot;
 
   double F[6] = {0, 0, 0, 0, 0, 0};
-  ElemK L{}, R{};
-  L.on = false;
-  R.on = false;
   NodeState me = load_node(d, g);
   if (i > 0) {  // element (i-1, i): this node is its end b
     NodeState A = load_node(d, g - 1);
@@ -85,7 +56,6 @@ __global__ void __launch_bounds__(256) elem_kernel(Dev d) {
     element_force(A, me, l0, d.EA[g - 1], d.EI[g - 1], d.GJ[g - 1], fa, fb, &e1);
 #pragma unroll
     for (int k = 0; k < 6; ++k) F[k] += fb[k];
-    L = elem_coeffs(e1, l0, d.EA[g - 1], d.EI[g - 1], d.GJ[g - 1]);
   }
   if (i < n - 1) {  // element (i, i+1): this node is its end a
     NodeState Bn = load_node(d, g + 1);
@@ -94,7 +64,12 @@ __global__ void __launch_bounds__(256) elem_kernel(Dev d) {
     element_force(me, Bn, l0, d.EA[g], d.EI[g], d.GJ[g], fa, fb, &e1);
 #pragma unroll
     for (int k = 0; k < 6; ++k) F[k] += fa[k];
-    R = elem_coeffs(e1, l0, d.EA[g], d.EI[g], d.GJ[g]);
+    // the QP tangent of element (i, i+1) is carried by its chord direction
+    if (d.mixed) {
+      d.E1f[g] = (float)e1.x; d.E1f[N + g] = (float)e1.y; d.E1f[2 * N + g] = (float)e1.z;
+    } else {
+      d.E1[g] = e1.x; d.E1[N + g] = e1.y; d.E1[2 * N + g] = e1.z;
+    }
   } else {  // tip node: subtract the actuation load (eq. 18)
     const double* v = d.act_cur + (int64_t)r * d.act_nv;
     V3 Fl = v3(0, 0, 0), Ml = v3(0, 0, 0);
@@ -120,45 +95,6 @@ __global__ void __launch_bounds__(256) elem_kernel(Dev d) {
   }
 #pragma unroll
   for (int k = 0; k < 6; ++k) d.F[k * N + g] = F[k];
-  // Diagonal block: K_bb of the left element + K_aa of the right element; coupling
-  // block K[i, i+1] = K_ab of the right element.  Entries are generated as stored.
-  // In mixed precision the blocks are rounded to FP32 as they are stored (the factorisation
-  // upcasts them and runs in FP64; the out-of-balance force above stays FP64).
-  double2* KD2 = reinterpret_cast<double2*>(d.KD + g * 36);
-  double2* KS2 = reinterpret_cast<double2*>(d.KS + g * 36);
-  float2* KD2f = reinterpret_cast<float2*>(d.KDf + g * 36);
-  float2* KS2f = reinterpret_cast<float2*>(d.KSf + g * 36);
-#pragma unroll
-  for (int p = 0; p < 18; ++p) {
-    double dv[2], sv[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int k = 2 * p + h, row = k / 6, cl = k % 6;
-      const int I = row / 3, J = cl / 3, ii = row % 3, jj = cl % 3;
-      double dd = 0.0, ss = 0.0;
-      if (L.on) {
-        if (I == 0 && J == 0) dd += iso_ij(ii, jj, L.e, L.a, L.k1);
-        if (I == 0 && J == 1) dd += skew_ij(ii, jj, L.e, L.k2);
-        if (I == 1 && J == 0) dd += skew_ij(ii, jj, L.e, -L.k2);
-        if (I == 1 && J == 1) dd += iso_ij(ii, jj, L.e, L.t, L.k3);
-      }
-      if (R.on) {
-        if (I == 0 && J == 0) { dd += iso_ij(ii, jj, R.e, R.a, R.k1); ss = iso_ij(ii, jj, R.e, -R.a, -R.k1); }
-        if (I == 0 && J == 1) { dd += skew_ij(ii, jj, R.e, -R.k2); ss = skew_ij(ii, jj, R.e, -R.k2); }
-        if (I == 1 && J == 0) { dd += skew_ij(ii, jj, R.e, R.k2); ss = skew_ij(ii, jj, R.e, -R.k2); }
-        if (I == 1 && J == 1) { dd += iso_ij(ii, jj, R.e, R.t, R.k3); ss = iso_ij(ii, jj, R.e, -R.t, R.k4); }
-      }
-      dv[h] = dd;
-      sv[h] = ss;
-    }
-    if (d.mixed) {
-      KD2f[p] = make_float2((float)dv[0], (float)dv[1]);
-      KS2f[p] = make_float2((float)sv[0], (float)sv[1]);
-    } else {
-      KD2[p] = make_double2(dv[0], dv[1]);
-      KS2[p] = make_double2(sv[0], sv[1]);
-    }
-  }
 }
 
 void launch_elem(const Dev& d, hipStream_t s) {

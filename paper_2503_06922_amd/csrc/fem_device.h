@@ -4,8 +4,8 @@
 //   node state   X[k*Ntot + g], k = 0..6 : px py pz qw qx qy qz      (FP64)
 //   rigidities   EA[g], EI[g], GJ[g]     : element g -> g+1 (the tip slot is unused)
 //   out-of-bal.  F[k*Ntot + g], k = 0..5 : internal force minus actuation
-//   tangent      KD[g*36 + k], k = 0..35: 6x6 diagonal block of node g (row major, node-major)
-//                KS[g*36 + k]           : 6x6 block K[g, g+1]
+//   tangent      E1[k*Ntot + g], k = 0..2: chord direction of element g -> g+1 (FP64, or
+//                E1f in FP32 in mixed precision); KC[k*Ntot + g], k = 0..5: its constants
 //   factor       LD[g*36 + k], LS[g*36 + k]: Cholesky blocks L[g,g] and L[g+1,g]
 //   node contacts (detection output, up to MAXC per node): CC[g], CT/CK/CG[s*Ntot+g],
 //                CN[(3*s+d)*Ntot + g]
@@ -66,10 +66,9 @@ struct Dev {
   // state
   double* X;
   double* F;
-  double* KD;
-  double* KS;
-  float* KDf;         // mixed precision: the tangent blocks are stored in FP32
-  float* KSf;
+  double* E1;         // element chord directions (the QP tangent, see ElemK)
+  float* E1f;         // mixed precision: the chord directions are stored in FP32
+  const double* KC;   // [6*Ntot] per-element tangent constants a t k1 k2 k3 k4
   double* LD;
   double* LS;
   int32_t* CC;
@@ -110,14 +109,6 @@ struct Dev {
   int mixed;
 };
 
-// tangent block entries (FP64, or FP32 in mixed precision, upcast for the FP64 factorisation)
-__device__ __forceinline__ double kd_at(const Dev& d, int64_t idx) {
-  return d.mixed ? (double)d.KDf[idx] : d.KD[idx];
-}
-__device__ __forceinline__ double ks_at(const Dev& d, int64_t idx) {
-  return d.mixed ? (double)d.KSf[idx] : d.KS[idx];
-}
-
 // ------------------------------------------------------------------ vectors
 struct V3 { double x, y, z; };
 __device__ __forceinline__ V3 v3(double x, double y, double z) { return V3{x, y, z}; }
@@ -138,5 +129,82 @@ __device__ __forceinline__ void quat_to_mat(double w, double x, double y, double
 }
 
 __device__ __forceinline__ V3 col(const double* m, int c) { return V3{m[c], m[3 + c], m[6 + c]}; }
+
+// ------------------------------------------------------------------ QP tangent
+// The QP tangent of eq. 20-23, K_e = Rcal K_l Rcal^T for element g -> g+1, depends only on
+// the element's chord direction e1 and six constants: a = EA/l0, t = GJ/l0, k1 = 12 EI/l0^3,
+// k2 = 6 EI/l0^2, k3 = 4 EI/l0, k4 = 2 EI/l0.  With equal bending stiffness about both
+// section axes its 3x3 blocks are  iso(x, y) = y I + (x - y) e1 e1^T  and  skew(s) = s [e1]x.
+// The element update stores e1 only (FP64, or FP32 in mixed precision, where it is
+// renormalised in FP64 when read: the element matrix then stays exactly positive
+// semi-definite, which rounding the assembled blocks to FP32 would not preserve); the
+// kernels that need block entries generate them.
+struct ElemK { double e[3]; double a, t, k1, k2, k3, k4; };
+
+__device__ __forceinline__ ElemK load_elem(const Dev& d, int64_t g) {
+  const int64_t N = d.Ntot;
+  ElemK k;
+  if (d.mixed) {
+    const double x = d.E1f[g], y = d.E1f[N + g], z = d.E1f[2 * N + g];
+    const double s = 1.0 / sqrt(x * x + y * y + z * z);
+    k.e[0] = x * s; k.e[1] = y * s; k.e[2] = z * s;
+  } else {
+    k.e[0] = d.E1[g]; k.e[1] = d.E1[N + g]; k.e[2] = d.E1[2 * N + g];
+  }
+  k.a = d.KC[g]; k.t = d.KC[N + g]; k.k1 = d.KC[2 * N + g];
+  k.k2 = d.KC[3 * N + g]; k.k3 = d.KC[4 * N + g]; k.k4 = d.KC[5 * N + g];
+  return k;
+}
+
+// e[i] for a runtime index without dynamic register indexing
+__device__ __forceinline__ double sel3(const double* e, int i) {
+  return i == 0 ? e[0] : (i == 1 ? e[1] : e[2]);
+}
+__device__ __forceinline__ double iso_ij(int i, int j, const double* e, double x, double y) {
+  return (i == j ? y : 0.0) + (x - y) * sel3(e, i) * sel3(e, j);
+}
+__device__ __forceinline__ double skew_ij(int i, int j, const double* e, double s) {
+  // [e]x = [[0, -ez, ey], [ez, 0, -ex], [-ey, ex, 0]]
+  if (i == j) return 0.0;
+  const int k = 3 - i - j;                       // the remaining axis
+  const double sg = ((j - i + 3) % 3 == 1) ? -1.0 : 1.0;
+  return s * sg * sel3(e, k);
+}
+
+// entry (row, col), 0..5, of the element's blocks K_aa (first node), K_bb (second node)
+// and K_ab (coupling, first node's rows)
+__device__ __forceinline__ double k_aa(const ElemK& k, int row, int col) {
+  const int I = row / 3, J = col / 3, i = row % 3, j = col % 3;
+  if (I == 0 && J == 0) return iso_ij(i, j, k.e, k.a, k.k1);
+  if (I == 0 && J == 1) return skew_ij(i, j, k.e, -k.k2);
+  if (I == 1 && J == 0) return skew_ij(i, j, k.e, k.k2);
+  return iso_ij(i, j, k.e, k.t, k.k3);
+}
+__device__ __forceinline__ double k_bb(const ElemK& k, int row, int col) {
+  const int I = row / 3, J = col / 3, i = row % 3, j = col % 3;
+  if (I == 0 && J == 0) return iso_ij(i, j, k.e, k.a, k.k1);
+  if (I == 0 && J == 1) return skew_ij(i, j, k.e, k.k2);
+  if (I == 1 && J == 0) return skew_ij(i, j, k.e, -k.k2);
+  return iso_ij(i, j, k.e, k.t, k.k3);
+}
+// the node's diagonal block D (K_bb of the left element + K_aa of the right one) and its
+// coupling block S = K[i, i+1] (K_ab of the right element), row-major, compile-time indices
+__device__ __forceinline__ double k_ab(const ElemK& k, int row, int col);
+__device__ __forceinline__ void node_blocks(const ElemK& L, const ElemK& R, bool left, bool right,
+                                            double* D, double* S) {
+#pragma unroll
+  for (int row = 0; row < 6; ++row)
+#pragma unroll
+    for (int cl = 0; cl < 6; ++cl) {
+      D[row * 6 + cl] = (left ? k_bb(L, row, cl) : 0.0) + (right ? k_aa(R, row, cl) : 0.0);
+      S[row * 6 + cl] = right ? k_ab(R, row, cl) : 0.0;
+    }
+}
+__device__ __forceinline__ double k_ab(const ElemK& k, int row, int col) {
+  const int I = row / 3, J = col / 3, i = row % 3, j = col % 3;
+  if (I == 0 && J == 0) return iso_ij(i, j, k.e, -k.a, -k.k1);
+  if (I == 1 && J == 1) return iso_ij(i, j, k.e, -k.t, k.k4);
+  return skew_ij(i, j, k.e, -k.k2);
+}
 
 }  // namespace accfem

@@ -28,8 +28,7 @@ namespace accfem {
 constexpr int NT = SOLVE_THREADS;
 constexpr int CH = 16;                     // nodes per staged chunk
 constexpr int PF = (CH * 36 + NT - 1) / NT;  // prefetch registers per lane and array
-constexpr int CHF = 4;                     // chunk of the factorisation sweep (register budget)
-constexpr int PFF = (CHF * 36 + NT - 1) / NT;
+constexpr int CHF = 32;                    // nodes per staged chunk of the factorisation sweep
 constexpr int CHS = 8;                     // chunk of the substitution sweeps (register budget)
 constexpr int PFS = (CHS * 36 + NT - 1) / NT;
 
@@ -334,10 +333,11 @@ __global__ void __launch_bounds__(NT) check_rhs_kernel(Dev d, int it) {
   }
   // prescribed increments: base coupling into node 1, guided lateral DOFs
   if (lane == 0) {
-    // rows of node 1 (f = 0): -= K[1,0] dx0 = S_0^T dx0 (S_0 = K[0,1] stored at the base)
+    // rows of node 1 (f = 0): -= K[1,0] dx0 = S_0^T dx0 (S_0 = K[0,1], the base element's K_ab)
+    const ElemK K0 = load_elem(d, o);
     for (int a = 0; a < 6; ++a) {
       double s = 0.0;
-      for (int b = 0; b < 3; ++b) s += ks_at(d, o * 36 + b * 6 + a) * dx0[b];
+      for (int b = 0; b < 3; ++b) s += k_ab(K0, b, a) * dx0[b];
       Zr[a] -= s;
     }
   }
@@ -349,6 +349,11 @@ __global__ void __launch_bounds__(NT) check_rhs_kernel(Dev d, int it) {
       const int64_t i = f + 1;
       double acc[6] = {0, 0, 0, 0, 0, 0};
       bool any = false;
+      if (!G.dof(i - 1, 0) && !G.dof(i - 1, 1) && !G.dof(i - 1, 2) && !G.dof(i, 0) && !G.dof(i, 1) &&
+          !G.dof(i, 2) && (i + 1 >= n || (!G.dof(i + 1, 0) && !G.dof(i + 1, 1) && !G.dof(i + 1, 2))))
+        continue;
+      const ElemK KL = load_elem(d, o + i - 1);                 // element (i-1, i)
+      const ElemK KR = load_elem(d, o + (i + 1 < n ? i : i - 1));  // element (i, i+1) if any
       for (int64_t jn = i - 1; jn <= i + 1; ++jn) {
         if (jn < 1 || jn >= n) continue;
         for (int k = 0; k < 3; ++k) {
@@ -357,9 +362,9 @@ __global__ void __launch_bounds__(NT) check_rhs_kernel(Dev d, int it) {
           any = true;
           for (int a = 0; a < 6; ++a) {
             double kij;
-            if (jn == i) kij = kd_at(d, (o + i) * 36 + a * 6 + k);
-            else if (jn == i + 1) kij = ks_at(d, (o + i) * 36 + a * 6 + k);   // K[i, i+1]
-            else kij = ks_at(d, (o + jn) * 36 + k * 6 + a);                    // K[i, i-1] = K[i-1, i]^T
+            if (jn == i) kij = k_bb(KL, a, k) + (i + 1 < n ? k_aa(KR, a, k) : 0.0);
+            else if (jn == i + 1) kij = k_ab(KR, a, k);          // K[i, i+1]
+            else kij = k_ab(KL, k, a);                           // K[i, i-1] = K[i-1, i]^T
             acc[a] += kij * xp;
           }
         }
@@ -390,13 +395,15 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 
 // phase 2: block-tridiagonal Cholesky of the QP tangent.
 // Serial over the robot's nodes; per node, lane L < 36 owns entry (a, b) = (L / 6, L % 6):
+//   per chunk of CHF nodes, lane u generates node u's blocks D_i and S_i = K[i, i+1] from
+//   the chord directions and constants of its two elements (prefetched into registers
+//   during the previous chunk) and stages them in LDS;
 //   A = D_i - X_prev X_prev^T   (X_prev = L[f, f-1]; row a kept in registers, row b read from LDS)
 //   every lane reads A's lower triangle from LDS and factors it in registers (right-looking,
 //   reciprocal square roots only), L[f, f] = chol(A);  row a of X = L[f+1, f] solves
-//   L x = S_i[:, a]  (S_i = K[i, i+1], read from the staged chunk).
-// Rows/columns of prescribed DOFs are replaced by the identity.  Blocks are staged through
-// LDS per chunk of CHF nodes with the next chunk prefetched into registers.  L[f, f] is
-// stored with the reciprocal of its diagonal.
+//   L x = S_i[:, a].
+// Rows/columns of prescribed DOFs are replaced by the identity.  L[f, f] is stored with the
+// reciprocal of its diagonal.
 __global__ void __launch_bounds__(NT) factor_kernel(Dev d, int it) {
   const int r = blockIdx.x;
   const int lane = threadIdx.x;
@@ -404,35 +411,41 @@ __global__ void __launch_bounds__(NT) factor_kernel(Dev d, int it) {
   const int64_t o = d.off[r], n = d.off[r + 1] - o;
   const int64_t nf = n - 1;
   const Guide G = make_guide(d, r, n);
-  __shared__ double sKD[PFF * NT], sKS[PFF * NT];
+  __shared__ double sKD[CHF * 36], sKS[CHF * 36];
   __shared__ double sA[36], sX[36];
   const int la = lane < 36 ? lane : 35;       // lanes 36..63 mirror lane 35 (results unused)
   const int a = la / 6, b = la % 6;
   double Xa[6] = {0, 0, 0, 0, 0, 0};          // row a of L[f, f-1]
   if (lane < 36) sX[lane] = 0.0;
   bool fail = false;
-  double pd[PFF], ps[PFF];
+  // lane u < CHF prefetches the two elements of free node f0 + u (node i = f0 + u + 1):
+  // element o + f0 + u on its left, o + f0 + u + 1 on its right (none at the tip)
+  ElemK pL, pR;
+  bool pr = false;
   auto fetch = [&](int64_t f0) {
-    const int64_t cnt = min((int64_t)CHF, nf - f0) * 36;
-    const int64_t base = (o + 1 + f0) * 36;
-#pragma unroll
-    for (int u = 0; u < PFF; ++u) {
-      const int64_t idx = lane + (int64_t)u * NT;
-      pd[u] = idx < cnt ? kd_at(d, base + idx) : 0.0;
-      ps[u] = idx < cnt ? ks_at(d, base + idx) : 0.0;
+    const int64_t f = f0 + lane;
+    if (lane < CHF && f < nf) {
+      pL = load_elem(d, o + f);
+      pr = f + 1 < nf;
+      pR = load_elem(d, o + (pr ? f + 1 : f));
     }
   };
   fetch(0);
   for (int64_t f0 = 0; f0 < nf; f0 += CHF) {
     __syncthreads();
+    if (lane < CHF && f0 + lane < nf) {
+      double D[36], S[36];
+      node_blocks(pL, pR, true, pr, D, S);
 #pragma unroll
-    for (int u = 0; u < PFF; ++u) { sKD[lane + u * NT] = pd[u]; sKS[lane + u * NT] = ps[u]; }
+      for (int q = 0; q < 36; ++q) { sKD[lane * 36 + q] = D[q]; sKS[lane * 36 + q] = S[q]; }
+    }
     __syncthreads();
     if (f0 + CHF < nf) fetch(f0 + CHF);
     const int64_t f1 = min(nf, f0 + CHF);
     for (int64_t f = f0; f < f1; ++f) {
       const int64_t i = f + 1, g = o + i;
-      const int lf = (int)(f - f0) * 36;
+      const int u = (int)(f - f0);
+      const int lf = u * 36;
       const bool last = (f + 1 == nf);
       double dv = sKD[lf + la];
       if (G.dof(i, a) || G.dof(i, b)) dv = (a == b) ? 1.0 : 0.0;
@@ -641,6 +654,170 @@ __global__ void __launch_bounds__(NT) subst_kernel(Dev d) {
 }
 
 // phase 4: contact Schur complement, LCP, step limit and state update
+
+constexpr int LCPM = 64;  // contact sets up to this size take the parallel LCP in LDS
+
+__device__ __forceinline__ int pk(int i, int j) {  // packed lower-triangle index, i >= j
+  return i * (i + 1) / 2 + j;
+}
+__device__ __forceinline__ int pks(int i, int j) {  // packed index of a symmetric entry
+  return i >= j ? pk(i, j) : pk(j, i);
+}
+
+// lexicographic minimum of (v, index) over the wavefront; identical in every lane
+__device__ __forceinline__ void wave_argmin(double& v, int& idx) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ov = __shfl_xor(v, o);
+    const int oi = __shfl_xor(idx, o);
+    if (ov < v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+  }
+}
+
+// Primal active-set method (the lane-0 routine lcp_active_set, run by the whole
+// wavefront) for the LCP  w = W y + q >= 0, y >= 0, y.w = 0  with W symmetric positive
+// definite, m <= LCPM.  Lane i owns constraint i.  sW holds W packed (lower, constraint
+// order); sL the Cholesky factor of W_PP packed with rows in active-set order and sRd its
+// reciprocal diagonal; sP the active set in order of entry; sYp the active y by position.
+// Adding the most violated constraint appends one row to the factor; dropping constraints
+// refactors.  `warm` flags a starting active set (the contacts active at the previous
+// iteration); it is used when its own solution is positive, else the start is empty.
+// Returns false on a non-positive pivot or when the iteration limits are reached.
+struct LcpLds {
+  double W[LCPM * (LCPM + 1) / 2];
+  double L[LCPM * (LCPM + 1) / 2];
+  double Rd[LCPM];
+  double Yp[LCPM];
+  double Yc[LCPM];
+  int P[LCPM];
+  int In[LCPM];
+};
+
+__device__ bool lcp_factor(LcpLds& S, int np) {
+  const int lane = threadIdx.x;
+  if (lane < np)
+    for (int b = 0; b <= lane; ++b) S.L[pk(lane, b)] = S.W[pks(S.P[lane], S.P[b])];
+  __syncthreads();
+  bool ok = true;
+  for (int k = 0; k < np; ++k) {
+    const double piv = S.L[pk(k, k)];
+    if (!(piv > 0.0)) ok = false;
+    const double rk = rsqrt_nr(piv > 0.0 ? piv : 1.0);
+    if (lane > k && lane < np) S.L[pk(lane, k)] *= rk;
+    if (lane == 0) S.Rd[k] = rk;
+    __syncthreads();
+    if (lane > k && lane < np) {
+      const double lak = S.L[pk(lane, k)];
+      for (int j = k + 1; j <= lane; ++j) S.L[pk(lane, j)] -= lak * S.L[pk(j, k)];
+    }
+    __syncthreads();
+  }
+  return ok;
+}
+
+// lanes a < np: solve L L^T z = b (b, z by position)
+__device__ __forceinline__ double lcp_solve(const LcpLds& S, int np, double bv) {
+  const int lane = threadIdx.x;
+  for (int k = 0; k < np; ++k) {
+    const double xk = __shfl(bv, k) * S.Rd[k];
+    if (lane == k) bv = xk;
+    else if (lane > k && lane < np) bv -= S.L[pk(lane, k)] * xk;
+  }
+  for (int k = np - 1; k >= 0; --k) {
+    const double zk = __shfl(bv, k) * S.Rd[k];
+    if (lane == k) bv = zk;
+    else if (lane < k) bv -= S.L[pk(k, lane)] * zk;
+  }
+  return bv;
+}
+
+__device__ bool lcp_parallel(LcpLds& S, const double* q, int m, bool warm, double& y_out) {
+  const int lane = threadIdx.x;
+  const double qi = lane < m ? q[lane] : 0.0;
+  const double tolw = 1e-12 * warp_max(fabs(qi));
+  int np = 0;
+  if (lane < LCPM) { S.In[lane] = 0; S.Yc[lane] = 0.0; }
+  // warm start
+  const unsigned long long wm = __ballot(warm && lane < m);
+  if (wm) {
+    const int cnt = __popcll(wm);
+    if (warm && lane < m) S.P[__popcll(wm & ((1ull << lane) - 1ull))] = lane;
+    __syncthreads();
+    bool ok = lcp_factor(S, cnt);
+    if (ok) {
+      const double z = lcp_solve(S, cnt, lane < cnt ? -q[S.P[lane]] : 0.0);
+      ok = __ballot(lane < cnt && !(z > 0.0)) == 0ull;
+      if (ok) {
+        if (lane < cnt) { S.Yp[lane] = z; S.In[S.P[lane]] = 1; }
+        np = cnt;
+      }
+    }
+    __syncthreads();
+  }
+  bool done = false, failed = false;
+  for (int outer = 0; outer < 4 * m + 8 && !done && !failed; ++outer) {
+    // most violated inactive constraint
+    double w = qi;
+    for (int a = 0; a < np; ++a) w += S.W[pks(lane < m ? lane : 0, S.P[a])] * S.Yp[a];
+    double v = (lane < m && !S.In[lane] && w < -tolw) ? w : INFINITY;
+    int t = lane;
+    wave_argmin(v, t);
+    if (!(v < INFINITY)) { done = true; break; }
+    // append t: new factor row l solves L l = W(P, t)
+    double bv = lane < np ? S.W[pks(S.P[lane], t)] : 0.0;
+    for (int k = 0; k < np; ++k) {
+      const double xk = __shfl(bv, k) * S.Rd[k];
+      if (lane == k) bv = xk;
+      else if (lane > k && lane < np) bv -= S.L[pk(lane, k)] * xk;
+    }
+    const double dtt = S.W[pk(t, t)] - warp_sum(lane < np ? bv * bv : 0.0);
+    __syncthreads();
+    if (!(dtt > 0.0)) { failed = true; break; }
+    if (lane < np) S.L[pk(np, lane)] = bv;
+    if (lane == 0) {
+      S.L[pk(np, np)] = 1.0;
+      S.Rd[np] = rsqrt_nr(dtt);
+      S.P[np] = t;
+      S.Yp[np] = 0.0;
+      S.In[t] = 1;
+    }
+    ++np;
+    __syncthreads();
+    for (int inner = 0; inner < 4 * m + 8; ++inner) {
+      const double z = lcp_solve(S, np, lane < np ? -q[S.P[lane]] : 0.0);
+      if (__ballot(lane < np && !(z > 0.0)) == 0ull) {
+        if (lane < np) S.Yp[lane] = z;
+        __syncthreads();
+        break;
+      }
+      // step toward z until the first active y reaches zero
+      const double yp = lane < np ? S.Yp[lane] : 0.0;
+      double al = (lane < np && z <= 0.0) ? yp / (yp - z) : 1.0;
+      al = fmin(1.0, warp_min(al));
+      const double yn = yp + al * (z - yp);
+      const bool keep = lane < np && yn > 0.0;
+      const unsigned long long km = __ballot(keep);
+      const int pidx = lane < np ? S.P[lane] : 0;
+      __syncthreads();
+      if (lane < np && !keep) S.In[pidx] = 0;
+      if (keep) {
+        const int pos = __popcll(km & ((1ull << lane) - 1ull));
+        S.P[pos] = pidx;
+        S.Yp[pos] = yn;
+      }
+      np = __popcll(km);
+      __syncthreads();
+      if (np == 0) break;
+      if (!lcp_factor(S, np)) { failed = true; break; }
+    }
+  }
+  if (failed || !done) return false;
+  if (lane < np) S.Yc[S.P[lane]] = S.Yp[lane];
+  __syncthreads();
+  y_out = lane < m ? S.Yc[lane] : 0.0;
+  return true;
+}
+
 __global__ void __launch_bounds__(NT) update_kernel(Dev d, int it) {
   const int r = blockIdx.x;
   const int lane = threadIdx.x;
@@ -660,44 +837,92 @@ __global__ void __launch_bounds__(NT) update_kernel(Dev d, int it) {
       dx0[k] = d.base_pos[3 * r + k] + dep * d.base_dir[3 * r + k] - d.X[k * N + o];
   }
   // ---------------------------------------------------------------- Schur complement + LCP
+  __shared__ LcpLds S;
+  __shared__ int s_lcp_ok;
+  __shared__ int sAct[LCPM];
+  __shared__ double sYa[LCPM];
   double* W = d.W + (int64_t)r * cap * cap;
   double* qv = d.q + cb;
-  for (int e = lane; e < nc * nc; e += NT) {
-    const int a = e / nc, b = e % nc;
-    const int64_t f = d.ct_node[cb + a] - 1;
-    const double* zb = Zr + (int64_t)(1 + b) * ld + 6 * f;
-    W[a * cap + b] = d.ct_n[3 * (cb + a)] * zb[0] + d.ct_n[3 * (cb + a) + 1] * zb[1] +
-                     d.ct_n[3 * (cb + a) + 2] * zb[2];
-  }
+  double* y = d.ct_y + cb;
   for (int a = lane; a < nc; a += NT) {
     const int64_t f = d.ct_node[cb + a] - 1;
     const double* z0 = Zr + 6 * f;
     qv[a] = d.ct_gap[cb + a] + d.ct_n[3 * (cb + a)] * z0[0] + d.ct_n[3 * (cb + a) + 1] * z0[1] +
             d.ct_n[3 * (cb + a) + 2] * z0[2];
   }
-  __syncthreads();
-  __shared__ int s_lcp_ok;
-  double* y = d.ct_y + cb;
-  if (lane == 0) {
-    s_lcp_ok = 1;
-    if (nc > 0) {
+  if (nc <= LCPM) {
+    // W packed in LDS: lane a computes its row, W(a, b) = n_a . Z_b(node of a), b <= a
+    bool warm = false;
+    if (lane < nc) {
+      const int64_t f = d.ct_node[cb + lane] - 1;
+      const double n0 = d.ct_n[3 * (cb + lane)], n1 = d.ct_n[3 * (cb + lane) + 1],
+                   n2 = d.ct_n[3 * (cb + lane) + 2];
+      for (int b = 0; b <= lane; ++b) {
+        const double* zb = Zr + (int64_t)(1 + b) * ld + 6 * f;
+        S.W[pk(lane, b)] = n0 * zb[0] + n1 * zb[1] + n2 * zb[2];
+      }
+      // active at the previous iteration (same node, triangle and kind, force > 0)
+      const int ncp = d.st_ncp[r];
+      const int nd = d.ct_node[cb + lane], tr = d.ct_tri[cb + lane], kd = d.ct_kind[cb + lane];
+      int lo = 0, hi = ncp;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (d.cp_node[cb + mid] < nd) lo = mid + 1; else hi = mid;
+      }
+      for (int c = lo; c < ncp && d.cp_node[cb + c] == nd; ++c)
+        warm |= (d.cp_tri[cb + c] == tr && d.cp_kind[cb + c] == kd && d.cp_y[cb + c] > 0.0);
+    }
+    __syncthreads();
+    double yl = 0.0;
+    bool ok = true;
+    if (nc > 0) ok = lcp_parallel(S, qv, nc, warm, yl);
+    if (lane < nc) y[lane] = yl;
+    // active contacts for the step
+    const unsigned long long am = __ballot(lane < nc && yl > 0.0);
+    if (lane < nc && yl > 0.0) {
+      const int pos = __popcll(am & ((1ull << lane) - 1ull));
+      sAct[pos] = lane;
+      sYa[pos] = yl;
+    }
+    if (lane == 0) s_lcp_ok = ok ? 1 : 0;
+    __syncthreads();
+    if (!s_lcp_ok) {
+      finish(d, r, 2, it, d.st_rn[r]);
+      return;
+    }
+    const int nact = __popcll(am);
+    for (int64_t j = lane; j < 6 * nf; j += NT) {
+      double v = Zr[j];
+      for (int k = 0; k < nact; ++k) v += sYa[k] * Zr[(int64_t)(1 + sAct[k]) * ld + j];
+      Zr[j] = v;
+    }
+  } else {
+    for (int e = lane; e < nc * nc; e += NT) {
+      const int a = e / nc, b = e % nc;
+      const int64_t f = d.ct_node[cb + a] - 1;
+      const double* zb = Zr + (int64_t)(1 + b) * ld + 6 * f;
+      W[a * cap + b] = d.ct_n[3 * (cb + a)] * zb[0] + d.ct_n[3 * (cb + a) + 1] * zb[1] +
+                       d.ct_n[3 * (cb + a) + 2] * zb[2];
+    }
+    __syncthreads();
+    if (lane == 0) {
       double* scratch = d.W + (int64_t)d.B * cap * cap + (int64_t)r * (cap * cap + 3 * cap);
       s_lcp_ok = lcp_active_set(W, qv, nc, cap, y, scratch) ? 1 : 0;
     }
+    __syncthreads();
+    if (!s_lcp_ok) {
+      finish(d, r, 2, it, d.st_rn[r]);
+      return;
+    }
+    for (int64_t j = lane; j < 6 * nf; j += NT) {
+      double v = Zr[j];
+      for (int c = 0; c < nc; ++c) v += y[c] * Zr[(int64_t)(1 + c) * ld + j];
+      Zr[j] = v;
+    }
   }
   __syncthreads();
-  if (!s_lcp_ok) {
-    finish(d, r, 2, it, d.st_rn[r]);
-    return;
-  }
 
   // ---------------------------------------------------------------- step, limit, update
-  for (int64_t j = lane; j < 6 * nf; j += NT) {
-    double v = Zr[j];
-    for (int c = 0; c < nc; ++c) v += y[c] * Zr[(int64_t)(1 + c) * ld + j];
-    Zr[j] = v;
-  }
-  __syncthreads();
   double mx = 0.0;
   for (int64_t f = lane; f < nf; f += NT) {
     const double* z = Zr + 6 * f;
