@@ -30,19 +30,57 @@ METRIC = "contact-FEM solves/sec, batched+mixed vs plain FP64 at 1e-5 rel tip er
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes(kernel, sb):
-    """HBM bytes one active node needs in one launch (sb = bytes per tangent-block entry:
-    4 when the blocks are FP32, 8 in FP64).  Symmetric blocks count their 21 unique entries.
-      elem_kernel   reads the node state (7 FP64), writes F (6 FP64), the diagonal block
-                    (21) and the coupling block (36)
-      factor_kernel reads the diagonal (21) and coupling (36) blocks, writes the Cholesky
-                    blocks L[i,i] (21) and L[i+1,i] (36) in FP64
+KERNELS = ["elem_kernel", "collide_kernel", "check_rhs_kernel", "factor_kernel", "subst_kernel",
+           "update_kernel"]
+KERNEL_SOURCE = {"elem_kernel": "elem.hip", "collide_kernel": "collide.hip", "check_rhs_kernel": "solve.hip",
+                 "factor_kernel": "solve.hip", "subst_kernel": "solve.hip", "update_kernel": "solve.hip"}
+
+
+def algorithmic_bytes(info, n_nodes, sb, steps):
+    """HBM bytes the kernels with a fixed per-node byte count must move over one schedule.
+
+    sb = bytes of a stored chord-direction component (4 in mixed precision, 8 in FP64).
+      elem_kernel   per active node: read the state (7 FP64), write F (6 FP64) and the chord
+                    direction of its element (3 x sb)
+      factor_kernel per free node and Newton step: read the node's two elements (direction
+                    3 x sb and 6 FP64 constants each; the left one is shared with the previous
+                    node, so one element per node), write the Cholesky blocks L[i,i] (21 unique
+                    FP64) and L[i+1,i] (36 FP64)
+      subst_kernel  per free node and Newton step: read L[i,i] and L[i+1,i] once per sweep
+                    (2 x 57 FP64, one pass of up to 64 right-hand sides), and per right-hand
+                    side read and write its 6 values in each sweep (4 x 6 FP64)
+    Returns {kernel: (bytes per unit, total bytes)}.
     """
-    if kernel == "elem_kernel":
-        return 8 * (7 + 6) + sb * (21 + 36)
-    if kernel == "factor_kernel":
-        return sb * (21 + 36) + 8 * (21 + 36)
-    return None
+    per = {"elem_kernel": 8 * (7 + 6) + 3 * sb,
+           "factor_kernel": 3 * sb + 8 * 6 + 8 * (21 + 36),
+           "subst_kernel": (2 * 8 * 57, 4 * 8 * 6)}
+    elem_nodes = sum((i["iters_total"] + i["steps_total"]) * int(n_nodes[b]) for b, i in enumerate(info))
+    free_steps = sum(i["iters_total"] * (int(n_nodes[b]) - 1) for b, i in enumerate(info))
+    free_rhs = sum(i["rhs_total"] * (int(n_nodes[b]) - 1) for b, i in enumerate(info))
+    return {
+        "elem_kernel": (per["elem_kernel"], per["elem_kernel"] * elem_nodes * steps),
+        "factor_kernel": (per["factor_kernel"], per["factor_kernel"] * free_steps * steps),
+        "subst_kernel": (per["subst_kernel"], (per["subst_kernel"][0] * free_steps
+                                              + per["subst_kernel"][1] * free_rhs) * steps),
+    }
+
+
+def measured_traffic(kernel):
+    """Per-launch HBM bytes of `kernel` from the committed rocprofv3 counter summary, if the
+    kernel's source is unchanged since the counters were taken (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f).get(kernel)
+    if not rec:
+        return None
+    src = os.path.join(ROOT, "paper_2503_06922_amd", "csrc", KERNEL_SOURCE[kernel])
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec.get("source_sha256"):
+            return None
+    return rec.get("bytes_per_launch")
 
 
 def run_schedule(ctx, rb, n_load_steps, X0):
@@ -112,8 +150,9 @@ def main():
     from paper_2503_06922_amd import fem
     from workloads import make_config
 
+    import torch
+    torch.cuda.init()
     if args.copy_calib_mib > 0:
-        import torch
         n = args.copy_calib_mib * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -125,51 +164,55 @@ def main():
     prec = fem.FEM_MIXED if args.precision == "mixed" else fem.FEM_FP64
     ctx = fem.Context(fem.params_from_batch(rb, precision=prec, newton_tol=1e-10, stag_tol=1e-9,
                                             max_newton=args.max_newton,
-                                            contact_capacity=args.capacity, profile=1))
+                                            contact_capacity=args.capacity))
     ctx.fem_set_lumen(V, T)
     ctx.fem_set_actuation(0, np.zeros(3 * rb.n_robots), np.zeros(rb.n_robots))
     X0 = ctx.fem_get_state()
 
     for _ in range(args.warmup):
         run_schedule(ctx, rb, args.load_steps, X0)
-    for k in range(6):
-        ctx.fem_profile(k, reset=True)
     # timed region: whole-batch insertions; each fem_solve returns after its stream synchronises
     ctx.fem_set_state(X0)  # resets the per-robot counters
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         run_schedule(ctx, rb, args.load_steps, X0)
+    torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    prof = [ctx.fem_profile(k) for k in range(6)]
     # counters cover the last schedule only (fem_set_state resets them): scale to all steps
     conv, total, iters, info = solves_of(ctx)
     solves = conv * args.steps
     value = solves / dt
-    names = ["elem_kernel", "collide_kernel", "check_rhs_kernel", "factor_kernel", "subst_kernel",
-             "update_kernel"]
-    kern = {names[k]: dict(total_ms=prof[k][0], launches=prof[k][1],
-                           avg_us=1e3 * prof[k][0] / max(prof[k][1], 1)) for k in range(6)}
-    dom = max(range(6), key=lambda k: prof[k][0])
-    # rooflines: algorithmic bytes per launch / average launch time (HIP events on the
-    # library's stream), for the kernels with a fixed per-node byte count
+
+    # kernel times: one more schedule on a context that brackets every launch with HIP events
+    # on its stream (outside the timed region: the event synchronisation slows the loop)
+    cp = fem.Context(fem.params_from_batch(rb, precision=prec, newton_tol=1e-10, stag_tol=1e-9,
+                                           max_newton=args.max_newton,
+                                           contact_capacity=args.capacity, profile=1))
+    cp.fem_set_lumen(V, T)
+    cp.fem_set_actuation(0, np.zeros(3 * rb.n_robots), np.zeros(rb.n_robots))
+    run_schedule(cp, rb, args.load_steps, X0)
+    prof = [cp.fem_profile(k) for k in range(6)]
+    _, _, _, info_p = solves_of(cp)
+    cp.close()
+    kern = {KERNELS[k]: dict(total_ms=prof[k][0], launches=prof[k][1],
+                             avg_us=1e3 * prof[k][0] / max(prof[k][1], 1)) for k in range(6)}
+    dom = KERNELS[max(range(6), key=lambda k: prof[k][0])]
+    # rooflines: algorithmic bytes per launch / average launch time
     sb = 4 if prec == fem.FEM_MIXED else 8
     n_nodes = np.asarray(rb.n_elem, np.int64) + 1
-    node_launches = {  # element update runs once more per load step than the factorisation
-        "elem_kernel": sum((i["iters_total"] + i["steps_total"]) * int(n_nodes[b])
-                           for b, i in enumerate(info)) * args.steps,
-        "factor_kernel": sum(i["iters_total"] * int(n_nodes[b]) for b, i in enumerate(info)) * args.steps,
-    }
+    alg = algorithmic_bytes(info_p, n_nodes, sb, 1)
     roofs = {}
-    for k, name in ((0, "elem_kernel"), (3, "factor_kernel")):
+    for name, (per_unit, total_bytes) in alg.items():
+        k = KERNELS.index(name)
         launches = max(prof[k][1], 1)
-        avg_nodes = node_launches[name] / launches
         avg_s = prof[k][0] / 1e3 / launches
-        bpn = algorithmic_bytes(name, sb)
-        gbs = bpn * avg_nodes / avg_s / 1e9
+        gbs = total_bytes / launches / avg_s / 1e9
+        tr = measured_traffic(name)
         roofs[name] = dict(bound="hbm", kernel=name, achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s",
-                           frac=gbs / HBM_PEAK_GBS, traffic=None, bytes_per_node=bpn,
-                           avg_active_nodes=avg_nodes, avg_launch_us=avg_s * 1e6)
-    roof = roofs.get(names[dom], roofs["factor_kernel"])
+                           frac=gbs / HBM_PEAK_GBS, traffic=tr, bytes_per_unit=per_unit,
+                           bytes_per_launch=total_bytes / launches, avg_launch_us=avg_s * 1e6)
+    roof = roofs.get(dom) or max(roofs.values(), key=lambda r: r["avg_launch_us"])
 
     res = {
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
@@ -184,7 +227,7 @@ def main():
                    "nodes": int(ctx.n_nodes)},
         "converged_fraction": conv / max(total, 1),
         "newton_iters_per_solve": iters / max(total, 1),
-        "kernels": kern, "dominant_kernel": names[dom],
+        "kernels": kern, "dominant_kernel": dom,
         "roofline": roof, "rooflines": roofs,
     }
     if prec == fem.FEM_MIXED and not args.no_fp64:

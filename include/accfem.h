@@ -113,6 +113,7 @@ typedef struct {
   int32_t steps_converged;  /* converged load steps since fem_create / fem_set_state */
   int32_t steps_total;      /* load steps since fem_create / fem_set_state */
   int64_t iters_total;      /* Newton iterations since fem_create / fem_set_state */
+  int64_t rhs_total;        /* right-hand sides solved (1 + contacts per Newton step), same span */
 } fem_solve_info;
 
 typedef struct {

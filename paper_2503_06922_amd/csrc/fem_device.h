@@ -103,6 +103,7 @@ struct Dev {
   int32_t* st_nlim;
   int32_t* st_nswitch;
   int32_t* st_iters;
+  int64_t* st_rhs;      // right-hand sides solved since creation / the last state reset
   double* st_rn;        // residual norm at the last check
   double* st_rnprev;
   int32_t* n_done;      // [1] robots finished in this load step

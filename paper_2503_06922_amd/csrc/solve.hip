@@ -307,6 +307,7 @@ __global__ void __launch_bounds__(NT) check_rhs_kernel(Dev d, int it) {
     }
   }
   __syncthreads();
+  if (lane == 0) d.st_rhs[r] += 1 + nc;
 
   // ---------------------------------------------------------------- right-hand side
   double* Zr = d.Z + d.zoff[r];
