@@ -70,7 +70,7 @@ __device__ Guide make_guide(const Dev& d, int r, int64_t n) {
   int64_t last = 0;
   if (G.ax >= 0) {
     const double l0 = d.l0[r], dep = d.depth_cur[r];
-    for (int64_t i = 1 + threadIdx.x; i < n; i += SOLVE_THREADS)
+    for (int64_t i = 1 + threadIdx.x % SOLVE_THREADS; i < n; i += SOLVE_THREADS)
       if (__dadd_rn(__dmul_rn((double)i, l0), dep) < d.guide_len) last = max(last, i);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) last = max(last, (int64_t)__shfl_xor((long long)last, o));
@@ -394,8 +394,10 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
   return y;
 }
 
-// phase 2: block-tridiagonal Cholesky of the QP tangent.
-// Serial over the robot's nodes; per node, lane L < 36 owns entry (a, b) = (L / 6, L % 6):
+// phase 2: block-tridiagonal Cholesky of the QP tangent, with the forward substitution of
+// the first NT right-hand sides running one node behind it.
+// Wave 0 factors, serially over the robot's nodes; per node, lane L < 36 owns entry
+// (a, b) = (L / 6, L % 6):
 //   per chunk of CHF nodes, lane u generates node u's blocks D_i and S_i = K[i, i+1] from
 //   the chord directions and constants of its two elements (prefetched into registers
 //   during the previous chunk) and stages them in LDS;
@@ -404,28 +406,66 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 //   reciprocal square roots only), L[f, f] = chol(A);  row a of X = L[f+1, f] solves
 //   L x = S_i[:, a].
 // Rows/columns of prescribed DOFs are replaced by the identity.  L[f, f] is stored with the
-// reciprocal of its diagonal.
-__global__ void __launch_bounds__(NT) factor_kernel(Dev d, int it) {
+// reciprocal of its diagonal.  Wave 0 also puts L[f, f] and L[f+1, f] into small LDS rings;
+// between the same two barriers of node f, wave 1 (one lane per right-hand side) takes node
+// f-1 of the forward sweep, y = L[f-1, f-1]^-1 (b - L[f-1, f-2] y_prev), from the rings.
+__global__ void __launch_bounds__(2 * NT) factor_kernel(Dev d, int it) {
   const int r = blockIdx.x;
-  const int lane = threadIdx.x;
+  const int w = threadIdx.x / NT, lane = threadIdx.x % NT;
   if (d.st_done[r]) return;
   const int64_t o = d.off[r], n = d.off[r + 1] - o;
   const int64_t nf = n - 1;
   const Guide G = make_guide(d, r, n);
   __shared__ double sKD[CHF * 36], sKS[CHF * 36];
   __shared__ double sA[36], sX[36];
+  __shared__ double rD[2][36], rS[3][36];     // L[f, f] by f % 2, L[f+1, f] by f % 3
   const int la = lane < 36 ? lane : 35;       // lanes 36..63 mirror lane 35 (results unused)
   const int a = la / 6, b = la % 6;
   double Xa[6] = {0, 0, 0, 0, 0, 0};          // row a of L[f, f-1]
-  if (lane < 36) sX[lane] = 0.0;
+  if (w == 0 && lane < 36) sX[lane] = 0.0;
   bool fail = false;
-  // lane u < CHF prefetches the two elements of free node f0 + u (node i = f0 + u + 1):
+  // wave 1: forward substitution of right-hand side `lane` (column c of Z)
+  const int ncol = 1 + d.st_nc[r];
+  const bool col = w == 1 && lane < ncol;
+  double* z = d.Z + d.zoff[r] + (int64_t)(col ? lane : 0) * (6 * n);
+  double yp[6] = {0, 0, 0, 0, 0, 0}, zn[6] = {0, 0, 0, 0, 0, 0};
+  auto fwd_load = [&](int64_t j) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) zn[q] = (col && j < nf) ? z[6 * j + q] : 0.0;
+  };
+  auto fwd_step = [&](int64_t j) {            // forward substitution at free node j
+    double bv[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) bv[q] = zn[q];
+    fwd_load(j + 1);
+    if (j > 0) {
+      const double* Ls = rS[(j - 1) % 3];      // L[j, j-1]
+#pragma unroll
+      for (int p = 0; p < 6; ++p)
+#pragma unroll
+        for (int q = 0; q < 6; ++q) bv[p] -= Ls[p * 6 + q] * yp[q];
+    }
+    const double* Ld = rD[j % 2];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const double y = bv[q] * Ld[q * 7];
+      yp[q] = y;
+#pragma unroll
+      for (int p = q + 1; p < 6; ++p) bv[p] -= Ld[p * 6 + q] * y;
+    }
+    if (col) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) z[6 * j + q] = yp[q];
+    }
+  };
+  if (w == 1) fwd_load(0);
+  // lane u < CHF of wave 0 prefetches the two elements of free node f0 + u (node i = f0 + u + 1):
   // element o + f0 + u on its left, o + f0 + u + 1 on its right (none at the tip)
   ElemK pL, pR;
   bool pr = false;
   auto fetch = [&](int64_t f0) {
     const int64_t f = f0 + lane;
-    if (lane < CHF && f < nf) {
+    if (w == 0 && lane < CHF && f < nf) {
       pL = load_elem(d, o + f);
       pr = f + 1 < nf;
       pR = load_elem(d, o + (pr ? f + 1 : f));
@@ -434,89 +474,104 @@ __global__ void __launch_bounds__(NT) factor_kernel(Dev d, int it) {
   fetch(0);
   for (int64_t f0 = 0; f0 < nf; f0 += CHF) {
     __syncthreads();
-    if (lane < CHF && f0 + lane < nf) {
-      double D[36], S[36];
-      node_blocks(pL, pR, true, pr, D, S);
+    if (w == 0 && lane < CHF && f0 + lane < nf) {
 #pragma unroll
-      for (int q = 0; q < 36; ++q) { sKD[lane * 36 + q] = D[q]; sKS[lane * 36 + q] = S[q]; }
+      for (int row = 0; row < 6; ++row)
+#pragma unroll
+        for (int cl = 0; cl < 6; ++cl) {
+          sKD[lane * 36 + row * 6 + cl] = k_bb(pL, row, cl) + (pr ? k_aa(pR, row, cl) : 0.0);
+          sKS[lane * 36 + row * 6 + cl] = pr ? k_ab(pR, row, cl) : 0.0;
+        }
     }
     __syncthreads();
     if (f0 + CHF < nf) fetch(f0 + CHF);
     const int64_t f1 = min(nf, f0 + CHF);
     for (int64_t f = f0; f < f1; ++f) {
       const int64_t i = f + 1, g = o + i;
-      const int u = (int)(f - f0);
-      const int lf = u * 36;
+      const int lf = (int)(f - f0) * 36;
       const bool last = (f + 1 == nf);
-      double dv = sKD[lf + la];
-      if (G.dof(i, a) || G.dof(i, b)) dv = (a == b) ? 1.0 : 0.0;
-      // A(a, b) = D(a, b) - X_prev[a,:] . X_prev[b,:]
-      double acc = dv;
-#pragma unroll
-      for (int k = 0; k < 6; ++k) acc -= Xa[k] * sX[b * 6 + k];
-      if (lane < 36) sA[lane] = acc;
-      // column a of S_i, prescribed rows and columns removed
       double sc[6];
+      if (w == 0) {
+        double dv = sKD[lf + la];
+        if (G.dof(i, a) || G.dof(i, b)) dv = (a == b) ? 1.0 : 0.0;
+        // A(a, b) = D(a, b) - X_prev[a,:] . X_prev[b,:]
+        double acc = dv;
 #pragma unroll
-      for (int j = 0; j < 6; ++j) {
-        double v = last ? 0.0 : sKS[lf + j * 6 + a];
-        if (!last && (G.dof(i, j) || G.dof(i + 1, a))) v = 0.0;
-        sc[j] = v;
-      }
-      __syncthreads();
-      double Lm[21];
+        for (int k = 0; k < 6; ++k) acc -= Xa[k] * sX[b * 6 + k];
+        if (lane < 36) sA[lane] = acc;
+        // column a of S_i, prescribed rows and columns removed
 #pragma unroll
-      for (int p = 0, q = 0; p < 6; ++p)
-#pragma unroll
-        for (int c = 0; c <= p; ++c, ++q) Lm[q] = sA[p * 6 + c];
-      // right-looking Cholesky: scale column k, update the trailing lower triangle
-      double rd[6];
-#pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        const int kk = k * (k + 1) / 2;
-        double dk = Lm[kk + k];
-        if (!(dk > 0.0)) { fail = true; dk = 1.0; }
-        const double rk = rsqrt_nr(dk);
-        rd[k] = rk;
-#pragma unroll
-        for (int p = k + 1; p < 6; ++p) Lm[p * (p + 1) / 2 + k] *= rk;
-#pragma unroll
-        for (int p = k + 1; p < 6; ++p) {
-          const int pp = p * (p + 1) / 2;
-#pragma unroll
-          for (int q = k + 1; q <= p; ++q) Lm[pp + q] -= Lm[pp + k] * Lm[q * (q + 1) / 2 + k];
+        for (int j = 0; j < 6; ++j) {
+          double v = last ? 0.0 : sKS[lf + j * 6 + a];
+          if (!last && (G.dof(i, j) || G.dof(i + 1, a))) v = 0.0;
+          sc[j] = v;
         }
       }
-      // row a of X: forward substitution L x = S[:, a] (right-looking)
+      __syncthreads();
+      if (w == 0) {
+        double Lm[21];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        const double x = sc[k] * rd[k];
-        Xa[k] = last ? 0.0 : x;
+        for (int p = 0, q = 0; p < 6; ++p)
 #pragma unroll
-        for (int p = k + 1; p < 6; ++p) sc[p] -= Lm[p * (p + 1) / 2 + k] * x;
-      }
-      // select this lane's entries with compile-time indices (keeps the arrays in registers)
-      double lv = 0.0, xv = 0.0;
+          for (int c = 0; c <= p; ++c, ++q) Lm[q] = sA[p * 6 + c];
+        // right-looking Cholesky: scale column k, update the trailing lower triangle
+        double rd[6];
 #pragma unroll
-      for (int p = 0, q = 0; p < 6; ++p) {
+        for (int k = 0; k < 6; ++k) {
+          const int kk = k * (k + 1) / 2;
+          double dk = Lm[kk + k];
+          if (!(dk > 0.0)) { fail = true; dk = 1.0; }
+          const double rk = rsqrt_nr(dk);
+          rd[k] = rk;
 #pragma unroll
-        for (int c = 0; c <= p; ++c, ++q)
-          if (p == a && c == b) lv = (p == c) ? rd[p] : Lm[q];   // reciprocal on the diagonal
-        if (p == b) xv = Xa[p];
-      }
-      if (lane < 36) {
-        d.LD[g * 36 + lane] = lv;
-        if (!last) d.LS[g * 36 + lane] = xv;
-        sX[lane] = xv;                                          // X[a][b] for the next node
+          for (int p = k + 1; p < 6; ++p) Lm[p * (p + 1) / 2 + k] *= rk;
+#pragma unroll
+          for (int p = k + 1; p < 6; ++p) {
+            const int pp = p * (p + 1) / 2;
+#pragma unroll
+            for (int q = k + 1; q <= p; ++q) Lm[pp + q] -= Lm[pp + k] * Lm[q * (q + 1) / 2 + k];
+          }
+        }
+        // row a of X: forward substitution L x = S[:, a] (right-looking)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          const double x = sc[k] * rd[k];
+          Xa[k] = last ? 0.0 : x;
+#pragma unroll
+          for (int p = k + 1; p < 6; ++p) sc[p] -= Lm[p * (p + 1) / 2 + k] * x;
+        }
+        // select this lane's entries with compile-time indices (keeps the arrays in registers)
+        double lv = 0.0, xv = 0.0;
+#pragma unroll
+        for (int p = 0, q = 0; p < 6; ++p) {
+#pragma unroll
+          for (int c = 0; c <= p; ++c, ++q)
+            if (p == a && c == b) lv = (p == c) ? rd[p] : Lm[q];   // reciprocal on the diagonal
+          if (p == b) xv = Xa[p];
+        }
+        if (lane < 36) {
+          d.LD[g * 36 + lane] = lv;
+          if (!last) d.LS[g * 36 + lane] = xv;
+          sX[lane] = xv;                                          // X[a][b] for the next node
+          rD[f % 2][lane] = lv;
+          rS[f % 3][lane] = xv;
+        }
+      } else if (f > 0) {
+        fwd_step(f - 1);
       }
       __syncthreads();
     }
   }
-  fail = __any(fail ? 1 : 0) != 0;
-  if (fail) finish(d, r, 3, it, d.st_rn[r]);
+  if (w == 0) {
+    fail = __any(fail ? 1 : 0) != 0;
+    if (fail) finish(d, r, 3, it, d.st_rn[r]);
+  } else {
+    fwd_step(nf - 1);
+  }
 }
 
-// phase 3: forward and backward substitution of all right-hand sides.
+// phase 3: backward substitution of all right-hand sides (and the forward substitution of
+// those beyond the first NT, which phase 2 has already swept forward).
 // One lane per right-hand side (column c of Z), NT columns per pass; every lane sweeps
 // the robot's nodes holding its column's whole 6-vector.  Per chunk of CHS nodes the
 // factor blocks (broadcast to all lanes) and the lanes' right-hand-side values are
@@ -537,6 +592,7 @@ __global__ void __launch_bounds__(NT) subst_kernel(Dev d) {
     const int c = c0 + lane;
     const bool act = c < ncol;
     double* z = Zr + (int64_t)(act ? c : 0) * ld;
+    const bool fwd_done = c0 == 0;       // the first NT columns were swept forward in phase 2
     double pd[PFS], ps[PFS], pz[CHS * 6];
     auto fetchZ = [&](int64_t f0, int64_t f1) {
 #pragma unroll
@@ -564,8 +620,8 @@ __global__ void __launch_bounds__(NT) subst_kernel(Dev d) {
       fetchZ(f0, min(nf, f0 + CHS));
     };
     double yp[6] = {0, 0, 0, 0, 0, 0};   // previous block solution
-    fetchF(0);
-    for (int64_t f0 = 0; f0 < nf; f0 += CHS) {
+    if (!fwd_done) fetchF(0);
+    for (int64_t f0 = 0; f0 < nf && !fwd_done; f0 += CHS) {
       __syncthreads();
       stage();
       __syncthreads();
@@ -1008,7 +1064,7 @@ __global__ void __launch_bounds__(NT) gather_kernel(Dev d) {
 void launch_solve_phase(const Dev& d, int phase, int it, hipStream_t s) {
   switch (phase) {
     case 0: hipLaunchKernelGGL(check_rhs_kernel, dim3(d.B), dim3(NT), 0, s, d, it); break;
-    case 1: hipLaunchKernelGGL(factor_kernel, dim3(d.B), dim3(NT), 0, s, d, it); break;
+    case 1: hipLaunchKernelGGL(factor_kernel, dim3(d.B), dim3(2 * NT), 0, s, d, it); break;
     case 2: hipLaunchKernelGGL(subst_kernel, dim3(d.B), dim3(NT), 0, s, d); break;
     default: hipLaunchKernelGGL(update_kernel, dim3(d.B), dim3(NT), 0, s, d, it); break;
   }
