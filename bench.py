@@ -45,21 +45,24 @@ def algorithmic_bytes(info, n_nodes, sb, steps):
       factor_kernel per free node and Newton step: read the node's two elements (direction
                     3 x sb and 6 FP64 constants each; the left one is shared with the previous
                     node, so one element per node), write the Cholesky blocks L[i,i] (21 unique
-                    FP64) and L[i+1,i] (36 FP64)
-      subst_kernel  per free node and Newton step: read L[i,i] and L[i+1,i] once per sweep
-                    (2 x 57 FP64, one pass of up to 64 right-hand sides), and per right-hand
-                    side read and write its 6 values in each sweep (4 x 6 FP64)
+                    FP64) and L[i+1,i] (36 FP64); its second wavefront sweeps the right-hand
+                    sides forward: read b and write y, 2 x 6 FP64 per node and right-hand side
+      subst_kernel  per free node and Newton step: read L[i,i] and L[i+1,i] once for the
+                    backward sweep (57 FP64), and per right-hand side read y and write x
+                    (2 x 6 FP64); right-hand sides beyond the first 64 (more than 63 contacts,
+                    rare) also get their forward sweep here and are not counted
     Returns {kernel: (bytes per unit, total bytes)}.
     """
     per = {"elem_kernel": 8 * (7 + 6) + 3 * sb,
-           "factor_kernel": 3 * sb + 8 * 6 + 8 * (21 + 36),
-           "subst_kernel": (2 * 8 * 57, 4 * 8 * 6)}
+           "factor_kernel": (3 * sb + 8 * 6 + 8 * (21 + 36), 2 * 8 * 6),
+           "subst_kernel": (8 * 57, 2 * 8 * 6)}
     elem_nodes = sum((i["iters_total"] + i["steps_total"]) * int(n_nodes[b]) for b, i in enumerate(info))
     free_steps = sum(i["iters_total"] * (int(n_nodes[b]) - 1) for b, i in enumerate(info))
     free_rhs = sum(i["rhs_total"] * (int(n_nodes[b]) - 1) for b, i in enumerate(info))
     return {
         "elem_kernel": (per["elem_kernel"], per["elem_kernel"] * elem_nodes * steps),
-        "factor_kernel": (per["factor_kernel"], per["factor_kernel"] * free_steps * steps),
+        "factor_kernel": (per["factor_kernel"], (per["factor_kernel"][0] * free_steps
+                                                + per["factor_kernel"][1] * free_rhs) * steps),
         "subst_kernel": (per["subst_kernel"], (per["subst_kernel"][0] * free_steps
                                               + per["subst_kernel"][1] * free_rhs) * steps),
     }
