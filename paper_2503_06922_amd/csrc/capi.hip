@@ -20,8 +20,10 @@ void launch_gather(const Dev& d, hipStream_t s);
 void launch_adjoint(const Dev& d, const int32_t* sens, int n_s, const double* dLdp, double* JL,
                     double* JD, double* JU, double* QB, int32_t* KF, double* GP, double* out,
                     int32_t* rstat, hipStream_t s);
-void launch_tri_setup(const double* V, const int32_t* tri, int64_t T, double* tv, double* tn,
-                      float* tvf, float* tnf, hipStream_t s);
+void launch_tri_setup(const double* V, const int32_t* tri, int64_t T, double* tv,
+                      double4* tsd, float4* tsf, float4* tqf, hipStream_t s);
+void launch_cell_spheres(const int32_t* cell_tris, int64_t n, const double4* tsd, const float4* tsf,
+                         double4* csd, float4* csf, hipStream_t s);
 
 // ------------------------------------------------------------------ setup kernels
 // straight reference configuration S_0 and the per-element rigidities
@@ -476,8 +478,8 @@ static fem_status create_impl(fem_ctx* c, const fem_params* p) {
   d.g_dim[0] = d.g_dim[1] = d.g_dim[2] = 0;
   d.g_h = 1.0;
   d.g_org[0] = d.g_org[1] = d.g_org[2] = 0.0;
-  d.tv = nullptr; d.tn = nullptr; d.tvf = nullptr; d.tnf = nullptr;
-  d.cell_start = nullptr; d.cell_tris = nullptr;
+  d.tv = nullptr; d.tsd = nullptr; d.tsf = nullptr; d.tqf = nullptr;
+  d.cell_start = nullptr; d.cell_tris = nullptr; d.cell_sd = nullptr; d.cell_sf = nullptr;
   if (p->profile) {
     c->profile = true;
     HIP_TRY(c, hipEventCreate(&c->ev0));
@@ -528,16 +530,17 @@ fem_status fem_set_lumen(fem_ctx* c, const double* verts, int64_t n_verts, const
                 std::pow(u[0] * v[1] - u[1] * v[0], 2);
     if (!(n2 > 0.0)) return fail(c, FEM_E_INVAL, "degenerate triangle " + std::to_string(t));
   }
-  double *V_d, *tv, *tn;
+  double *V_d, *tv;
   int32_t* T_d;
-  float *tvf, *tnf;
+  double4* tsd;
+  float4 *tsf, *tqf;
   auto A = [&](auto** ptr, size_t count) { return dalloc(c, ptr, count, c->mesh_allocs); };
-  if (A(&V_d, 3 * n_verts) || A(&T_d, 3 * n_tris) || A(&tv, 9 * n_tris) || A(&tn, 3 * n_tris) ||
-      A(&tvf, 9 * n_tris) || A(&tnf, 3 * n_tris))
+  if (A(&V_d, 3 * n_verts) || A(&T_d, 3 * n_tris) || A(&tv, 12 * n_tris) ||
+      A(&tsd, n_tris) || A(&tsf, n_tris) || A(&tqf, 4 * n_tris))
     return FEM_E_NOMEM;
   HIP_TRY(c, hipMemcpy(V_d, hv.data(), hv.size() * sizeof(double), hipMemcpyHostToDevice));
   HIP_TRY(c, hipMemcpy(T_d, ht.data(), ht.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-  launch_tri_setup(V_d, T_d, n_tris, tv, tn, tvf, tnf, c->stream);
+  launch_tri_setup(V_d, T_d, n_tris, tv, tsd, tsf, tqf, c->stream);
   HIP_TRY(c, hipGetLastError());
   // uniform grid: every triangle in each cell its box grown by the band overlaps
   const double band = c->p.contact_radius + c->p.contact_margin;
@@ -589,15 +592,21 @@ fem_status fem_set_lumen(fem_ctx* c, const double* verts, int64_t n_verts, const
         for (int x = c0[0]; x <= c1[0]; ++x) lst[fillp[((int64_t)z * dim[1] + y) * dim[0] + x]++] = (int32_t)t;
   }
   int32_t *cs_d, *ct_d;
-  if (A(&cs_d, ncell + 1) || A(&ct_d, lst.size())) return FEM_E_NOMEM;
+  double4* csd;
+  float4* csf;
+  if (A(&cs_d, ncell + 1) || A(&ct_d, lst.size()) || A(&csd, lst.size()) || A(&csf, lst.size()))
+    return FEM_E_NOMEM;
   HIP_TRY(c, hipMemcpy(cs_d, cnt.data(), (ncell + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
   HIP_TRY(c, hipMemcpy(ct_d, lst.data(), lst.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  // each cell entry carries its triangle's bounding spheres (contiguous reads in the cell walk)
+  launch_cell_spheres(ct_d, (int64_t)lst.size(), tsd, tsf, csd, csf, c->stream);
+  HIP_TRY(c, hipGetLastError());
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   d.n_tris = n_tris;
-  d.tv = tv; d.tn = tn; d.tvf = tvf; d.tnf = tnf;
+  d.tv = tv; d.tsd = tsd; d.tsf = tsf; d.tqf = tqf;
   d.g_h = h;
   for (int j = 0; j < 3; ++j) { d.g_org[j] = org[j]; d.g_dim[j] = dim[j]; }
-  d.cell_start = cs_d; d.cell_tris = ct_d;
+  d.cell_start = cs_d; d.cell_tris = ct_d; d.cell_sd = csd; d.cell_sf = csf;
   c->lumen_set = true;
   return FEM_OK;
 }

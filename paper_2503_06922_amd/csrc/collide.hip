@@ -14,7 +14,9 @@
 // robot by the gather step of the solver.
 // In mixed precision the per-triangle tests run in FP32 with the band widened
 // by a rounding allowance, and every triangle that passes is re-tested in FP64,
-// so the contact set is the FP64 one.
+// so the contact set is the FP64 one; in FP64 a bounding-sphere test rejects most
+// triangles first.  The screens read packed per-triangle records (one or four
+// 16-byte loads), the FP64 test the structure-of-arrays vertices.
 #include "fem_device.h"
 
 namespace accfem {
@@ -66,31 +68,37 @@ __device__ __forceinline__ int closest_on_tri(P3<T> p, P3<T> a, P3<T> b, P3<T> c
   return R_FACE;
 }
 
-struct TriTest { int region; double s, dist; P3<double> cp; };
+struct TriTest { int region; double s, dist; P3<double> cp, n; };
 
+// tv packs a triangle as three double4: (a, n.x), (b, n.y), (c, n.z)
 __device__ __forceinline__ TriTest test_tri64(const Dev& d, int64_t t, P3<double> p) {
-  const int64_t T = d.n_tris;
-  P3<double> a{d.tv[t], d.tv[T + t], d.tv[2 * T + t]};
-  P3<double> b{d.tv[3 * T + t], d.tv[4 * T + t], d.tv[5 * T + t]};
-  P3<double> c{d.tv[6 * T + t], d.tv[7 * T + t], d.tv[8 * T + t]};
-  P3<double> n{d.tn[t], d.tn[T + t], d.tn[2 * T + t]};
+  const double4* rec = reinterpret_cast<const double4*>(d.tv + 12 * t);
+  const double4 A = rec[0], B = rec[1], C = rec[2];
+  P3<double> a{A.x, A.y, A.z};
+  P3<double> b{B.x, B.y, B.z};
+  P3<double> c{C.x, C.y, C.z};
   TriTest r;
-  r.s = dotp(n, sub(p, a));
+  r.n = P3<double>{A.w, B.w, C.w};
+  r.s = dotp(r.n, sub(p, a));
   r.region = closest_on_tri(p, a, b, c, &r.cp);
   P3<double> dv = sub(p, r.cp);
   r.dist = sqrt(dotp(dv, dv));
   return r;
 }
 
-// FP32 screen: can triangle t be a face contact or a fallback candidate?
+// FP32 screen: can triangle t be a face contact or a fallback candidate?  Every candidate
+// lies within r_c + delta of its closest point; after the bounding-sphere test of the cell
+// walk, the plane (s >= -r_c) and the FP32 closest point are tested, each widened by a
+// rounding allowance.  tqf packs (n, a, b, c) of a triangle in four float4.
 __device__ __forceinline__ bool screen32(const Dev& d, int64_t t, P3<float> p, float band, float slack) {
-  const int64_t T = d.n_tris;
-  P3<float> a{d.tvf[t], d.tvf[T + t], d.tvf[2 * T + t]};
-  P3<float> n{d.tnf[t], d.tnf[T + t], d.tnf[2 * T + t]};
+  const float4 N = d.tqf[4 * t], A = d.tqf[4 * t + 1];
+  P3<float> a{A.x, A.y, A.z};
+  P3<float> n{N.x, N.y, N.z};
   float s = dotp(n, sub(p, a));
   if (s < -(float)d.r_c - slack || s > band + slack) return false;
-  P3<float> b{d.tvf[3 * T + t], d.tvf[4 * T + t], d.tvf[5 * T + t]};
-  P3<float> c{d.tvf[6 * T + t], d.tvf[7 * T + t], d.tvf[8 * T + t]};
+  const float4 Bv = d.tqf[4 * t + 2], Cv = d.tqf[4 * t + 3];
+  P3<float> b{Bv.x, Bv.y, Bv.z};
+  P3<float> c{Cv.x, Cv.y, Cv.z};
   P3<float> cp;
   closest_on_tri(p, a, b, c, &cp);
   P3<float> dv = sub(p, cp);
@@ -129,27 +137,59 @@ __global__ void __launch_bounds__(256) collide_kernel(Dev d) {
   P3<float> pf{(float)p.x, (float)p.y, (float)p.z};
   // FP32 screen allowance: coordinates ~1 m carry ~1e-7 m of rounding
   const float slack = 1e-5f;
-  for (int32_t k = b0; k < b1; ++k) {
-    const int64_t t = d.cell_tris[k];
-    if (d.mixed && !screen32(d, t, pf, (float)band, slack)) continue;
-    TriTest tt = test_tri64(d, t, p);
-    if (tt.region == R_FACE) {
-      if (tt.s >= -d.r_c && tt.s <= band) {
-        if (cnt < MAXC) {
-          d.CT[cnt * N + g] = (int32_t)t;
-          d.CK[cnt * N + g] = 0;
-          d.CG[cnt * N + g] = tt.s - d.r_c;
-          d.CN[(3 * cnt + 0) * N + g] = d.tn[t];
-          d.CN[(3 * cnt + 1) * N + g] = d.tn[d.n_tris + t];
-          d.CN[(3 * cnt + 2) * N + g] = d.tn[2 * d.n_tris + t];
-        }
-        ++cnt;
+  // the cell list in batches of KB: the indices and the bounding spheres stored with them are
+  // loaded together (one memory round trip per batch), then tested in list order
+  constexpr int KB = 8;
+  for (int32_t k0 = b0; k0 < b1; k0 += KB) {
+    int32_t tk[KB];
+#pragma unroll
+    for (int j = 0; j < KB; ++j) tk[j] = (k0 + j < b1) ? d.cell_tris[k0 + j] : -1;
+    bool near[KB];
+    if (d.mixed) {
+      float4 S[KB];
+#pragma unroll
+      for (int j = 0; j < KB; ++j) S[j] = tk[j] >= 0 ? d.cell_sf[k0 + j] : make_float4(0.f, 0.f, 0.f, -1.f);
+      const float bf = (float)band + slack;
+#pragma unroll
+      for (int j = 0; j < KB; ++j) {
+        const float sx = pf.x - S[j].x, sy = pf.y - S[j].y, sz = pf.z - S[j].z, rr = S[j].w + bf;
+        near[j] = tk[j] >= 0 && sx * sx + sy * sy + sz * sz <= rr * rr;
       }
-    } else if (cnt == 0 && tt.s > 0.0 && tt.dist <= band) {
-      if (best_t < 0 || tt.dist < best_d) {  // cell lists are sorted: ties keep the lower index
-        best_t = (int)t;
-        best_d = tt.dist;
-        best_cp = tt.cp;
+    } else {
+      double4 S[KB];
+#pragma unroll
+      for (int j = 0; j < KB; ++j) S[j] = tk[j] >= 0 ? d.cell_sd[k0 + j] : make_double4(0.0, 0.0, 0.0, -1.0);
+#pragma unroll
+      for (int j = 0; j < KB; ++j) {
+        const double sx = p.x - S[j].x, sy = p.y - S[j].y, sz = p.z - S[j].z;
+        const double rr = (S[j].w + band) * (1.0 + 1e-12);
+        near[j] = tk[j] >= 0 && sx * sx + sy * sy + sz * sz <= rr * rr;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      if (!near[j]) continue;
+      const int64_t t = tk[j];
+      if (d.mixed && !screen32(d, t, pf, (float)band, slack)) continue;
+      TriTest tt = test_tri64(d, t, p);
+      if (tt.region == R_FACE) {
+        if (tt.s >= -d.r_c && tt.s <= band) {
+          if (cnt < MAXC) {
+            d.CT[cnt * N + g] = (int32_t)t;
+            d.CK[cnt * N + g] = 0;
+            d.CG[cnt * N + g] = tt.s - d.r_c;
+            d.CN[(3 * cnt + 0) * N + g] = tt.n.x;
+            d.CN[(3 * cnt + 1) * N + g] = tt.n.y;
+            d.CN[(3 * cnt + 2) * N + g] = tt.n.z;
+          }
+          ++cnt;
+        }
+      } else if (cnt == 0 && tt.s > 0.0 && tt.dist <= band) {
+        if (best_t < 0 || tt.dist < best_d) {  // cell lists are sorted: ties keep the lower index
+          best_t = (int)t;
+          best_d = tt.dist;
+          best_cp = tt.cp;
+        }
       }
     }
   }
@@ -168,7 +208,7 @@ __global__ void __launch_bounds__(256) collide_kernel(Dev d) {
 
 // triangle planes: vertices to SoA, unit inward normals (FP64 and FP32 copies)
 __global__ void tri_setup_kernel(const double* V, const int32_t* tri, int64_t T, double* tv,
-                                 double* tn, float* tvf, float* tnf) {
+                                 double4* tsd, float4* tsf, float4* tqf) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= T) return;
   double v[9];
@@ -179,14 +219,31 @@ __global__ void tri_setup_kernel(const double* V, const int32_t* tri, int64_t T,
     v[3 * k + 1] = V[3 * (int64_t)vi + 1];
     v[3 * k + 2] = V[3 * (int64_t)vi + 2];
   }
-#pragma unroll
-  for (int k = 0; k < 9; ++k) { tv[k * T + t] = v[k]; tvf[k * T + t] = (float)v[k]; }
   V3 e0 = v3(v[3] - v[0], v[4] - v[1], v[5] - v[2]);
   V3 e1 = v3(v[6] - v[0], v[7] - v[1], v[8] - v[2]);
   V3 n = cross(e0, e1);
   double inv = 1.0 / norm(n);
-  tn[t] = n.x * inv; tn[T + t] = n.y * inv; tn[2 * T + t] = n.z * inv;
-  tnf[t] = (float)(n.x * inv); tnf[T + t] = (float)(n.y * inv); tnf[2 * T + t] = (float)(n.z * inv);
+  n = inv * n;
+  const double nn[3] = {n.x, n.y, n.z};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    tv[12 * t + 4 * k] = v[3 * k];
+    tv[12 * t + 4 * k + 1] = v[3 * k + 1];
+    tv[12 * t + 4 * k + 2] = v[3 * k + 2];
+    tv[12 * t + 4 * k + 3] = nn[k];
+  }
+  // bounding sphere about the centroid
+  const V3 cc = v3((v[0] + v[3] + v[6]) / 3.0, (v[1] + v[4] + v[7]) / 3.0, (v[2] + v[5] + v[8]) / 3.0);
+  double R = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) R = fmax(R, norm(v3(v[3 * k], v[3 * k + 1], v[3 * k + 2]) - cc));
+  tsd[t] = make_double4(cc.x, cc.y, cc.z, R);
+  // FP32 copies; the radius is rounded up so that the sphere still contains the triangle
+  tsf[t] = make_float4((float)cc.x, (float)cc.y, (float)cc.z, (float)R * (1.0f + 1e-6f) + 1e-6f);
+  tqf[4 * t] = make_float4((float)n.x, (float)n.y, (float)n.z, 0.0f);
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    tqf[4 * t + 1 + k] = make_float4((float)v[3 * k], (float)v[3 * k + 1], (float)v[3 * k + 2], 0.0f);
 }
 
 void launch_collide(const Dev& d, hipStream_t s) {
@@ -195,12 +252,29 @@ void launch_collide(const Dev& d, hipStream_t s) {
   hipLaunchKernelGGL(collide_kernel, dim3((unsigned)blocks), dim3(T), 0, s, d);
 }
 
-void launch_tri_setup(const double* V, const int32_t* tri, int64_t T, double* tv, double* tn,
-                      float* tvf, float* tnf, hipStream_t s) {
+__global__ void cell_spheres_kernel(const int32_t* cell_tris, int64_t n, const double4* tsd,
+                                    const float4* tsf, double4* csd, float4* csf) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int32_t t = cell_tris[k];
+  csd[k] = tsd[t];
+  csf[k] = tsf[t];
+}
+
+void launch_cell_spheres(const int32_t* cell_tris, int64_t n, const double4* tsd, const float4* tsf,
+                         double4* csd, float4* csf, hipStream_t s) {
+  if (n == 0) return;
+  const int TB = 256;
+  hipLaunchKernelGGL(cell_spheres_kernel, dim3((unsigned)((n + TB - 1) / TB)), dim3(TB), 0, s, cell_tris,
+                     n, tsd, tsf, csd, csf);
+}
+
+void launch_tri_setup(const double* V, const int32_t* tri, int64_t T, double* tv,
+                      double4* tsd, float4* tsf, float4* tqf, hipStream_t s) {
   if (T == 0) return;
   const int TB = 256;
   hipLaunchKernelGGL(tri_setup_kernel, dim3((unsigned)((T + TB - 1) / TB)), dim3(TB), 0, s, V, tri,
-                     T, tv, tn, tvf, tnf);
+                     T, tv, tsd, tsf, tqf);
 }
 
 }  // namespace accfem

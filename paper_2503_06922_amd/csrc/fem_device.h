@@ -53,16 +53,18 @@ struct Dev {
   int cap;                  // contacts per robot
   // mesh
   int64_t n_tris;
-  const double* tv;   // [9*T]: v0x v0y v0z v1x .. v2z, SoA (k*T + t)
-  const double* tn;   // [3*T]
-  const float* tvf;   // [9*T] FP32 copy for the mixed-precision prefilter
-  const float* tnf;   // [3*T]
+  const double* tv;   // [12*T] per triangle, 32-byte aligned: a.xyz n.x, b.xyz n.y, c.xyz n.z
+  const double4* tsd; // [T] bounding sphere (centroid, radius) for the FP64 screen
+  const float4* tsf;  // [T] the same in FP32 (radius rounded up)
+  const float4* tqf;  // [4*T] FP32 normal and vertices a, b, c for the mixed-precision screen
   // grid
   double g_org[3];
   double g_h;
   int g_dim[3];
   const int32_t* cell_start;  // [ncell+1]
   const int32_t* cell_tris;
+  const double4* cell_sd;     // bounding sphere of cell_tris[k] (FP64) ...
+  const float4* cell_sf;      // ... and in FP32
   // state
   double* X;
   double* F;
