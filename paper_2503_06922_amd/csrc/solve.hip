@@ -320,15 +320,17 @@ __global__ void __launch_bounds__(NT) check_rhs_kernel(Dev d, int it) {
     const double dep = d.depth_cur[r];
     for (int k = 0; k < 3; ++k) dx0[k] = d.base_pos[3 * r + k] + dep * bd[k] - d.X[k * N + o + b0];
   }
-  // col 0 = -F over free DOFs; contact columns = n_c at the contact node
+  // col 0 = -F over free DOFs; contact column 1 + c = n_c at the contact node, zero elsewhere.
+  // The factorisation generates the contact columns below NT itself (its forward sweep needs no
+  // stored zeros); only columns from NT on are written here.
   for (int64_t f = lane; f < nf; f += NT) {
     const int64_t g = o + f + 1;
     for (int k = 0; k < 6; ++k) Zr[6 * f + k] = -d.F[k * N + g];
   }
-  for (int c = 0; c < nc; ++c)
+  for (int c = NT - 1; c < nc; ++c)
     for (int64_t j = lane; j < 6 * nf; j += NT) Zr[(int64_t)(1 + c) * ld + j] = 0.0;
   __syncthreads();
-  for (int c = lane; c < nc; c += NT) {
+  for (int c = NT - 1 + lane; c < nc; c += NT) {
     const int64_t f = d.ct_node[cb + c] - 1;
     for (int k = 0; k < 3; ++k) Zr[(int64_t)(1 + c) * ld + 6 * f + k] = d.ct_n[3 * (cb + c) + k];
   }
@@ -408,8 +410,9 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 // Rows/columns of prescribed DOFs are replaced by the identity.  L[f, f] is stored with the
 // reciprocal of its diagonal.  Wave 0 also puts L[f, f] and L[f+1, f] into small LDS rings;
 // between the same two barriers of node f, wave 1 (one lane per right-hand side) takes node
-// f-1 of the forward sweep, y = L[f-1, f-1]^-1 (b - L[f-1, f-2] y_prev), from the rings.
-__global__ void __launch_bounds__(2 * NT) factor_kernel(Dev d, int it) {
+// f-1 of the forward sweep, y = L[f-1, f-1]^-1 (b - L[f-1, f-2] y_prev), from the rings; it
+// reads b of column 0 from Z and generates the contact columns (n_c at the contact node).
+__global__ void __launch_bounds__(2 * NT) __attribute__((amdgpu_waves_per_eu(3))) factor_kernel(Dev d, int it) {
   const int r = blockIdx.x;
   const int w = threadIdx.x / NT, lane = threadIdx.x % NT;
   if (d.st_done[r]) return;
@@ -428,10 +431,32 @@ __global__ void __launch_bounds__(2 * NT) factor_kernel(Dev d, int it) {
   const int ncol = 1 + d.st_nc[r];
   const bool col = w == 1 && lane < ncol;
   double* z = d.Z + d.zoff[r] + (int64_t)(col ? lane : 0) * (6 * n);
+  // column 0 is read from Z; contact column 1 + c is n_c at free node fc, zero elsewhere
+  // (kept in LDS: registers live across the loop also count against wave 0's factorisation)
+  __shared__ int32_t sFC[NT];
+  __shared__ double sNC[3 * NT];
+  if (w == 1) {
+    int32_t fc = -1;
+    double n0 = 0.0, n1 = 0.0, n2 = 0.0;
+    if (col && lane > 0) {
+      const int64_t cb = (int64_t)r * d.cap + (lane - 1);
+      fc = d.ct_node[cb] - 1;
+      n0 = d.ct_n[3 * cb]; n1 = d.ct_n[3 * cb + 1]; n2 = d.ct_n[3 * cb + 2];
+    }
+    sFC[lane] = fc;
+    sNC[lane] = n0; sNC[NT + lane] = n1; sNC[2 * NT + lane] = n2;
+  }
   double yp[6] = {0, 0, 0, 0, 0, 0}, zn[6] = {0, 0, 0, 0, 0, 0};
   auto fwd_load = [&](int64_t j) {
+    if (lane == 0) {
 #pragma unroll
-    for (int q = 0; q < 6; ++q) zn[q] = (col && j < nf) ? z[6 * j + q] : 0.0;
+      for (int q = 0; q < 6; ++q) zn[q] = (col && j < nf) ? z[6 * j + q] : 0.0;
+    } else {
+      const bool here = j == (int64_t)sFC[lane];
+      zn[0] = here ? sNC[lane] : 0.0; zn[1] = here ? sNC[NT + lane] : 0.0;
+      zn[2] = here ? sNC[2 * NT + lane] : 0.0;
+      zn[3] = 0.0; zn[4] = 0.0; zn[5] = 0.0;
+    }
   };
   auto fwd_step = [&](int64_t j) {            // forward substitution at free node j
     double bv[6];
