@@ -87,23 +87,16 @@ __device__ __forceinline__ TriTest test_tri64(const Dev& d, int64_t t, P3<double
 }
 
 // FP32 screen: can triangle t be a face contact or a fallback candidate?  Every candidate
-// lies within r_c + delta of its closest point; after the bounding-sphere test of the cell
-// walk, the plane (s >= -r_c) and the FP32 closest point are tested, each widened by a
-// rounding allowance.  tqf packs (n, a, b, c) of a triangle in four float4.
+// lies within r_c + delta of its closest point and has s >= -r_c; after the bounding-sphere
+// test of the cell walk, the plane test (s in [-r_c, r_c + delta]) is repeated in FP32,
+// widened by a rounding allowance.  (A fallback candidate has s > 0 and a closest point
+// within r_c + delta, so |s| <= r_c + delta holds for it too.)  tqf packs (n, a, b, c).
 __device__ __forceinline__ bool screen32(const Dev& d, int64_t t, P3<float> p, float band, float slack) {
   const float4 N = d.tqf[4 * t], A = d.tqf[4 * t + 1];
   P3<float> a{A.x, A.y, A.z};
   P3<float> n{N.x, N.y, N.z};
-  float s = dotp(n, sub(p, a));
-  if (s < -(float)d.r_c - slack || s > band + slack) return false;
-  const float4 Bv = d.tqf[4 * t + 2], Cv = d.tqf[4 * t + 3];
-  P3<float> b{Bv.x, Bv.y, Bv.z};
-  P3<float> c{Cv.x, Cv.y, Cv.z};
-  P3<float> cp;
-  closest_on_tri(p, a, b, c, &cp);
-  P3<float> dv = sub(p, cp);
-  // any FP64 candidate has s >= -r_c and lies within the band of its closest point
-  return sqrtf(dotp(dv, dv)) <= band + slack;
+  const float s = dotp(n, sub(p, a));
+  return s >= -(float)d.r_c - slack && s <= band + slack;
 }
 
 __global__ void __launch_bounds__(256) collide_kernel(Dev d) {
