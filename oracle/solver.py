@@ -110,11 +110,55 @@ def out_of_balance(robot, P, R, act_kind, act_values):
                                     robot.cable_angle))
 
 
-def detect(robot, P, guided=None):
+def detect(robot, P, guided=None, prev=None):
+    """Contacts of the current iterate.  With prev = (contacts, y) of the previous Newton
+    iterate, its active face contacts that were not detected again persist as the same
+    plane constraint while the node stays within the detection band of that triangle and
+    no detected contact at the node lies on the same plane (see persist_faces)."""
     if robot.mesh is None:
         return []
-    return collision.active(collision.detect(P, robot.mesh, robot.r_c, robot.delta,
-                                             skip=guided))
+    det = collision.active(collision.detect(P, robot.mesh, robot.r_c, robot.delta, skip=guided))
+    if prev is None:
+        return det
+    return persist_faces(robot, P, det, *prev)
+
+
+PLANE_TOL = 1e-9
+
+
+def persist_faces(robot, P, det, cont_prev, y_prev):
+    """Detected contacts plus the persisting faces, ordered by (node, kind, triangle).
+
+    Within a Newton loop the iterate can cross from one triangle's face region into the
+    neighbouring edge or vertex region and back on every step, so that the detected set
+    never settles (a 2-cycle between a face contact and the edge/vertex fallback).  A face
+    contact that carried force (y > 0) in the previous iterate therefore stays, with its
+    plane n_t . (p - v0_t) - r_c as the gap, as long as the node's distance to the
+    triangle is at most r_c + delta; it is dropped when a detected contact at the node has
+    the same plane (normals and gaps equal within PLANE_TOL: coplanar neighbours).
+    """
+    mesh = robot.mesh
+    band = robot.r_c + robot.delta
+    keys = {(c["node"], c["tri"], c["kind"]) for c in det}
+    by_node = {}
+    for c in det:
+        by_node.setdefault(c["node"], []).append(c)
+    extra = []
+    for c, y in zip(cont_prev, y_prev):
+        if not (y > 0.0) or c["kind"] != 0 or (c["node"], c["tri"], 0) in keys:
+            continue
+        i, t = c["node"], c["tri"]
+        p = P[i]
+        cpt, _, _ = collision.closest_points(p, mesh, np.array([t]))
+        if not (np.linalg.norm(p - cpt[0]) <= band):
+            continue
+        gap = float(mesh.n[t] @ (p - mesh.v0[t])) - robot.r_c
+        if any(abs(float(mesh.n[t] @ o["n"]) - 1.0) <= PLANE_TOL and abs(o["gap"] - gap) <= PLANE_TOL
+               for o in by_node.get(i, [])):
+            continue
+        amb = any(o.get("ambiguous", False) for o in by_node.get(i, []))
+        extra.append(dict(node=i, tri=t, kind=0, n=mesh.n[t].copy(), gap=gap, ambiguous=amb))
+    return sorted(det + extra, key=lambda c: (c["node"], c["kind"], c["tri"]))
 
 
 def guide_dofs(robot, P, guided):
@@ -249,7 +293,7 @@ def solve_load_step(robot, P, R, base_target, act_kind, act_values, tol=1e-10,
     rn = np.inf
     for it in range(max_iter + 1):
         F = resid(P, R)
-        contacts = detect(robot, P, guided)
+        contacts = detect(robot, P, guided, None if prev is None else (prev[1], prev[0]))
         if prev is not None:
             y_p, cont_p, lim_p = prev
             rn = float(np.linalg.norm(contact_residual(F, cont_p, y_p, robot, guided)))

@@ -83,3 +83,56 @@ def test_culled_equals_brute_force_on_branching_mesh():
     b = collision.detect(P, m, 1.5e-3, 1e-3, cull=False)
     assert collision.contact_set(a) == collision.contact_set(b)
     assert len(collision.contact_set(a)) > 10
+
+
+def _persist_robot(mesh):
+    from oracle import solver
+    return solver.Robot(2, 0.02, np.zeros(3), np.array([1.0, 0, 0]), np.array([0, 1.0, 0]),
+                        1.0, 1e-3, 1e-3, 1e-3, np.zeros(1), 1.5e-3, 1e-3, 1e-3, mesh=mesh)
+
+
+def test_persisting_face_contact_rules_by_hand():
+    """A convex ridge along x = 0: face 0 (z = 0 for x <= 0) and face 1 tilted down for
+    x >= 0; inward normals point to +z.  A node that was pressed on face 0 and is now past
+    the ridge (in the edge region, no face contact) keeps face 0's plane while it is within
+    the band of that triangle; not once it is farther, nor if the previous force was zero."""
+    from oracle import solver
+    s = np.sin(np.radians(20.0)); c = np.cos(np.radians(20.0))
+    V = np.array([[-0.01, -0.01, 0.0], [0.0, -0.01, 0.0], [0.0, 0.01, 0.0], [-0.01, 0.01, 0.0],
+                  [0.01 * c, -0.01, -0.01 * s], [0.01 * c, 0.01, -0.01 * s]])
+    T = np.array([[0, 1, 2], [0, 2, 3], [1, 4, 5], [1, 5, 2]])
+    mesh = collision.Mesh(V, T)
+    rob = _persist_robot(mesh)
+    r_c, band = rob.r_c, rob.r_c + rob.delta
+    prev = [dict(node=1, tri=0, kind=0, n=mesh.n[0].copy(), gap=0.0)]
+    # node just past the ridge, 1.6 mm above the ridge line: fallback edge contact only
+    P = np.array([[-0.015, 0.0, 0.01], [0.0005, -0.002, 0.0016], [0.015, 0.0, 0.01]])
+    det = solver.detect(rob, P)
+    assert [(c["node"], c["kind"]) for c in det] == [(1, 1)]
+    got = solver.detect(rob, P, prev=(prev, np.array([0.3])))
+    assert [(c["node"], c["tri"], c["kind"]) for c in got] == [(1, 0, 0), (1, det[0]["tri"], 1)]
+    assert got[0]["gap"] == pytest.approx(0.0016 - r_c, abs=1e-15)
+    # no force in the previous iterate: nothing persists
+    assert collision.contact_set(solver.detect(rob, P, prev=(prev, np.array([0.0])))) == \
+        collision.contact_set(det)
+    # farther than the band from triangle 0: nothing persists
+    P2 = P.copy()
+    P2[1] = [band + 0.0005, -0.002, 0.0016]
+    assert collision.contact_set(solver.detect(rob, P2, prev=(prev, np.array([0.3])))) == \
+        collision.contact_set(solver.detect(rob, P2))
+
+
+def test_persisting_face_skips_coplanar_duplicate():
+    """Triangles 0 and 1 are coplanar halves of one quad: a node that moved from the face
+    region of 0 into that of 1 gets face 1 detected, and face 0 (same plane) does not persist."""
+    from oracle import solver
+    V = np.array([[-0.01, -0.01, 0.0], [0.01, -0.01, 0.0], [0.01, 0.01, 0.0], [-0.01, 0.01, 0.0]])
+    T = np.array([[0, 1, 2], [0, 2, 3]])
+    mesh = collision.Mesh(V, T)
+    rob = _persist_robot(mesh)
+    P = np.array([[-0.015, 0.0, 0.01], [-0.004, 0.006, 0.0012], [0.015, 0.0, 0.01]])
+    det = solver.detect(rob, P)
+    assert [(c["node"], c["tri"], c["kind"]) for c in det] == [(1, 1, 0)]
+    prev = [dict(node=1, tri=0, kind=0, n=mesh.n[0].copy(), gap=0.0)]
+    assert collision.contact_set(solver.detect(rob, P, prev=(prev, np.array([0.2])))) == \
+        collision.contact_set(det)
