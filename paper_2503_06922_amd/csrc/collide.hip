@@ -9,9 +9,13 @@
 //   face contacts : region = face and -r_c <= s <= r_c + delta      (all of them)
 //   fallback      : if a node has no face contact, the nearest edge/vertex point
 //                   with s > 0 within r_c + delta (ties to the lowest triangle)
+//   persisting    : a face contact of the previous Newton iterate with force > 0 that is
+//                   not detected again stays as its plane while the node is within
+//                   r_c + delta of the triangle, unless a detected contact at the node
+//                   has the same plane (normals and gaps within PLANE_TOL)
 // The base node and nodes held by the insertion guide are skipped.  Results are
-// written per node (up to MAXC, sorted by triangle index) and compacted per
-// robot by the gather step of the solver.
+// written per node (up to MAXC, ordered by kind then triangle index) and compacted
+// per robot by the gather step of the solver.
 // In mixed precision the per-triangle tests run in FP32 with the band widened
 // by a rounding allowance, and every triangle that passes is re-tested in FP64,
 // so the contact set is the FP64 one; in FP64 a bounding-sphere test rejects most
@@ -22,6 +26,7 @@
 namespace accfem {
 
 enum { R_FACE = 0, R_EDGE = 1, R_VERT = 2 };
+constexpr double PLANE_TOL = 1e-9;   // two contacts lie on the same plane (normals and gaps)
 
 template <typename T>
 struct P3 { T x, y, z; };
@@ -195,6 +200,63 @@ __global__ void __launch_bounds__(256) collide_kernel(Dev d) {
     d.CN[1 * N + g] = (p.y - best_cp.y) * inv;
     d.CN[2 * N + g] = (p.z - best_cp.z) * inv;
     cnt = 1;
+  }
+  // persisting faces: the face contacts of this node that carried force in the previous
+  // iterate and were not detected again stay as their plane while the node is within the
+  // band of that triangle, unless a detected contact at the node lies on the same plane
+  const int ndet = min(cnt, MAXC);
+  const int64_t cb = (int64_t)r * d.cap;
+  const int ncp = d.st_ncp[r];
+  int lo = 0, hi = ncp;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (d.cp_node[cb + mid] < i) lo = mid + 1; else hi = mid;
+  }
+  for (int c = lo; c < ncp && d.cp_node[cb + c] == i; ++c) {
+    if (!(d.cp_y[cb + c] > 0.0) || d.cp_kind[cb + c] != 0) continue;
+    const int32_t t = d.cp_tri[cb + c];
+    bool skip = false;
+    for (int q = 0; q < ndet; ++q) skip |= (d.CK[q * N + g] == 0 && d.CT[q * N + g] == t);
+    if (skip) continue;
+    const TriTest tt = test_tri64(d, t, p);
+    if (!(tt.dist <= band)) continue;
+    const double gap = tt.s - d.r_c;
+    for (int q = 0; q < ndet; ++q) {
+      const double nn = tt.n.x * d.CN[(3 * q) * N + g] + tt.n.y * d.CN[(3 * q + 1) * N + g] +
+                        tt.n.z * d.CN[(3 * q + 2) * N + g];
+      skip |= fabs(nn - 1.0) <= PLANE_TOL && fabs(d.CG[q * N + g] - gap) <= PLANE_TOL;
+    }
+    if (skip) continue;
+    if (cnt < MAXC) {
+      d.CT[cnt * N + g] = t;
+      d.CK[cnt * N + g] = 0;
+      d.CG[cnt * N + g] = gap;
+      d.CN[(3 * cnt + 0) * N + g] = tt.n.x;
+      d.CN[(3 * cnt + 1) * N + g] = tt.n.y;
+      d.CN[(3 * cnt + 2) * N + g] = tt.n.z;
+    }
+    ++cnt;
+  }
+  // order the node's entries by (kind, triangle): insertion sort of at most MAXC
+  const int nst = min(cnt, MAXC);
+  for (int a = 1; a < nst; ++a) {
+    const int32_t ta = d.CT[a * N + g], ka = d.CK[a * N + g];
+    const double ga = d.CG[a * N + g], n0 = d.CN[(3 * a) * N + g], n1 = d.CN[(3 * a + 1) * N + g],
+                 n2 = d.CN[(3 * a + 2) * N + g];
+    int b = a - 1;
+    while (b >= 0 && (d.CK[b * N + g] > ka || (d.CK[b * N + g] == ka && d.CT[b * N + g] > ta))) {
+      d.CT[(b + 1) * N + g] = d.CT[b * N + g];
+      d.CK[(b + 1) * N + g] = d.CK[b * N + g];
+      d.CG[(b + 1) * N + g] = d.CG[b * N + g];
+      for (int k = 0; k < 3; ++k) d.CN[(3 * (b + 1) + k) * N + g] = d.CN[(3 * b + k) * N + g];
+      --b;
+    }
+    d.CT[(b + 1) * N + g] = ta;
+    d.CK[(b + 1) * N + g] = ka;
+    d.CG[(b + 1) * N + g] = ga;
+    d.CN[(3 * (b + 1)) * N + g] = n0;
+    d.CN[(3 * (b + 1) + 1) * N + g] = n1;
+    d.CN[(3 * (b + 1) + 2) * N + g] = n2;
   }
   d.CC[g] = cnt;  // > MAXC flags an overflow for the gather step
 }
