@@ -250,8 +250,11 @@ def main():
         both = np.array([i["status"] == 0 and j["status"] == 0 for i, j in zip(info, info64)])
         err = np.linalg.norm(Xm[tips, 0:3] - X64[tips, 0:3], axis=1) / rb.length
         res["fp64_batched_solves_per_s"] = conv64 / t64
-        res["tip_err_mixed_vs_fp64"] = {"max": float(err[both].max()) if both.any() else None,
-                                        "median": float(np.median(err[both])) if both.any() else None,
+        e = err[both]
+        res["tip_err_mixed_vs_fp64"] = {"max": float(e.max()) if both.any() else None,
+                                        "median": float(np.median(e)) if both.any() else None,
+                                        "p99": float(np.percentile(e, 99)) if both.any() else None,
+                                        "within_1e-5": int(np.sum(e <= 1e-5)),
                                         "robots_compared": int(both.sum())}
         c64.close()
     if not args.no_single:
