@@ -24,6 +24,8 @@ void launch_tri_setup(const double* V, const int32_t* tri, int64_t T, double* tv
                       double4* tsd, float4* tsf, float4* tqf, hipStream_t s);
 void launch_cell_spheres(const int32_t* cell_tris, int64_t n, const double4* tsd, const float4* tsf,
                          double4* csd, float4* csf, hipStream_t s);
+void launch_lcp_check(double* W, const double* q, int m, double* y, double* scratch, int* code,
+                      hipStream_t s);
 
 // ------------------------------------------------------------------ setup kernels
 // straight reference configuration S_0 and the per-element rigidities
@@ -329,7 +331,7 @@ static fem_status create_impl(fem_ctx* c, const fem_params* p) {
   if (p->n_cables < 1 || p->n_cables > 8 || !p->cable_angle) return bad("n_cables must be 1..8");
   if (!(p->contact_radius >= 0.0) || !(p->contact_margin > 0.0) || !(p->beta0 > 0.0))
     return bad("contact radius, margin or beta0 out of range");
-  if (p->max_newton < 1 || p->contact_capacity < 1 || p->contact_capacity > 256)
+  if (p->max_newton < 1 || p->contact_capacity < 1 || p->contact_capacity > 1024)
     return bad("max_newton or contact_capacity out of range");
   if (!(p->newton_tol > 0.0) || !(p->stag_tol >= 0.0)) return bad("tolerances out of range");
   c->p = *p;
@@ -885,6 +887,42 @@ fem_status fem_contacts(const fem_ctx* cc, int32_t robot, fem_contact* out, int3
     }
   }
   return FEM_OK;
+}
+
+fem_status fem_lcp(const double* W, const double* q, int32_t m, double* y, int32_t* path) {
+  if (!W || !q || !y || !path || m < 1 || m > 1024) return FEM_E_INVAL;
+  const int64_t nw = (int64_t)m * m;
+  double* dW = nullptr;     // W, then q, y, scratch (m*m + 3m) in one allocation
+  int* dcode = nullptr;
+  fem_status st = FEM_OK;
+  if (hipMalloc(&dW, (2 * nw + 5 * (int64_t)m) * sizeof(double)) != hipSuccess) return FEM_E_NOMEM;
+  if (hipMalloc(&dcode, sizeof(int)) != hipSuccess) {
+    (void)hipFree(dW);
+    return FEM_E_NOMEM;
+  }
+  double* dq = dW + nw;
+  double* dy = dq + m;
+  double* dscr = dy + m;
+  int code = -1;
+  if (hipMemcpy(dW, W, nw * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(dq, q, m * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+    st = FEM_E_HIP;
+  } else {
+    launch_lcp_check(dW, dq, m, dy, dscr, dcode, nullptr);
+    if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(&code, dcode, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) {
+      st = FEM_E_HIP;
+    } else if (code < 0) {
+      st = FEM_E_NOCONV;
+    } else if (hipMemcpy(y, dy, m * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+      st = FEM_E_HIP;
+    } else {
+      *path = code;
+    }
+  }
+  (void)hipFree(dcode);
+  (void)hipFree(dW);
+  return st;
 }
 
 }  // extern "C"

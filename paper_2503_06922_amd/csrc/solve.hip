@@ -133,98 +133,6 @@ __device__ __forceinline__ void finish(const Dev& d, int r, int status, int iter
   }
 }
 
-// dense Cholesky in place (row major, ld), returns false on a non-positive pivot
-__device__ bool chol_dense(double* A, int n, int ld) {
-  for (int k = 0; k < n; ++k) {
-    double s = A[k * ld + k];
-    for (int j = 0; j < k; ++j) s -= A[k * ld + j] * A[k * ld + j];
-    if (!(s > 0.0)) return false;
-    const double lkk = sqrt(s);
-    A[k * ld + k] = lkk;
-    for (int i = k + 1; i < n; ++i) {
-      double t = A[i * ld + k];
-      for (int j = 0; j < k; ++j) t -= A[i * ld + j] * A[k * ld + j];
-      A[i * ld + k] = t / lkk;
-    }
-  }
-  return true;
-}
-
-// solve L L^T x = b in place (dense, row major)
-__device__ void chol_solve_dense(const double* L, int n, int ld, double* b) {
-  for (int i = 0; i < n; ++i) {
-    double t = b[i];
-    for (int j = 0; j < i; ++j) t -= L[i * ld + j] * b[j];
-    b[i] = t / L[i * ld + i];
-  }
-  for (int i = n - 1; i >= 0; --i) {
-    double t = b[i];
-    for (int j = i + 1; j < n; ++j) t -= L[j * ld + i] * b[j];
-    b[i] = t / L[i * ld + i];
-  }
-}
-
-// LCP(q, W) with W SPD: minimise 1/2 y.W y + q.y over y >= 0 by a primal active set.
-// scratch: [cap*cap + 3*cap] doubles.  Returns false if it did not terminate.
-__device__ bool lcp_active_set(const double* W, const double* q, int n, int ldw, double* y,
-                               double* scratch) {
-  double* A = scratch;                 // factor of W_PP, n x n (ld n)
-  double* z = scratch + n * n;
-  int* P = (int*)(z + n);              // active indices (n ints)
-  int* inP = P + n;                    // flags (n ints)
-  for (int i = 0; i < n; ++i) { y[i] = 0.0; inP[i] = 0; }
-  int np = 0;
-  double qmax = 0.0;
-  for (int i = 0; i < n; ++i) qmax = fmax(qmax, fabs(q[i]));
-  const double tolw = 1e-12 * qmax;
-  for (int outer = 0; outer < 4 * n + 8; ++outer) {
-    // most violated inactive constraint
-    int t = -1;
-    double wt = -tolw;
-    for (int i = 0; i < n; ++i) {
-      if (inP[i]) continue;
-      double w = q[i];
-      for (int j = 0; j < np; ++j) w += W[i * ldw + P[j]] * y[P[j]];
-      if (w < wt) { wt = w; t = i; }
-    }
-    if (t < 0) return true;
-    P[np++] = t;
-    inP[t] = 1;
-    for (int inner = 0; inner < 4 * n + 8; ++inner) {
-      for (int a = 0; a < np; ++a)
-        for (int b = 0; b < np; ++b) A[a * np + b] = W[P[a] * ldw + P[b]];
-      if (!chol_dense(A, np, np)) return false;
-      for (int a = 0; a < np; ++a) z[a] = -q[P[a]];
-      chol_solve_dense(A, np, np, z);
-      bool pos = true;
-      for (int a = 0; a < np; ++a) pos = pos && (z[a] > 0.0);
-      if (pos) {
-        for (int a = 0; a < np; ++a) y[P[a]] = z[a];
-        break;
-      }
-      double alpha = 1.0;
-      for (int a = 0; a < np; ++a) {
-        if (z[a] <= 0.0) {
-          const double yi = y[P[a]];
-          const double al = yi / (yi - z[a]);
-          alpha = fmin(alpha, al);
-        }
-      }
-      int m = 0;
-      for (int a = 0; a < np; ++a) {
-        const int i = P[a];
-        double yn = y[i] + alpha * (z[a] - y[i]);
-        if (yn <= 0.0) { y[i] = 0.0; inP[i] = 0; continue; }
-        y[i] = yn;
-        P[m++] = i;
-      }
-      np = m;
-      if (np == 0) break;
-    }
-  }
-  return false;
-}
-
 // phase 1: contact gather, convergence test, right-hand sides (col 0 = -r, contact columns)
 __global__ void __launch_bounds__(NT) check_rhs_kernel(Dev d, int it) {
   const int r = blockIdx.x;
@@ -320,19 +228,11 @@ __global__ void __launch_bounds__(NT) check_rhs_kernel(Dev d, int it) {
     const double dep = d.depth_cur[r];
     for (int k = 0; k < 3; ++k) dx0[k] = d.base_pos[3 * r + k] + dep * bd[k] - d.X[k * N + o + b0];
   }
-  // col 0 = -F over free DOFs; contact column 1 + c = n_c at the contact node, zero elsewhere.
-  // The factorisation generates the contact columns below NT itself (its forward sweep needs no
-  // stored zeros); only columns from NT on are written here.
+  // col 0 = -F over free DOFs.  The contact columns 1 + c (n_c at the contact node, zero
+  // elsewhere) are never stored: the forward sweeps generate them.
   for (int64_t f = lane; f < nf; f += NT) {
     const int64_t g = o + f + 1;
     for (int k = 0; k < 6; ++k) Zr[6 * f + k] = -d.F[k * N + g];
-  }
-  for (int c = NT - 1; c < nc; ++c)
-    for (int64_t j = lane; j < 6 * nf; j += NT) Zr[(int64_t)(1 + c) * ld + j] = 0.0;
-  __syncthreads();
-  for (int c = NT - 1 + lane; c < nc; c += NT) {
-    const int64_t f = d.ct_node[cb + c] - 1;
-    for (int k = 0; k < 3; ++k) Zr[(int64_t)(1 + c) * ld + 6 * f + k] = d.ct_n[3 * (cb + c) + k];
   }
   // prescribed increments: base coupling into node 1, guided lateral DOFs
   if (lane == 0) {
@@ -597,33 +497,57 @@ __global__ void __launch_bounds__(2 * NT) __attribute__((amdgpu_waves_per_eu(3))
 
 // phase 3: backward substitution of all right-hand sides (and the forward substitution of
 // those beyond the first NT, which phase 2 has already swept forward).
-// One lane per right-hand side (column c of Z), NT columns per pass; every lane sweeps
-// the robot's nodes holding its column's whole 6-vector.  Per chunk of CHS nodes the
-// factor blocks (broadcast to all lanes) and the lanes' right-hand-side values are
+// Block (r, p) takes columns p*NT .. p*NT + NT-1 of robot r's Z, one lane per column; every
+// lane sweeps the robot's nodes holding its column's whole 6-vector.  Per chunk of CHS nodes
+// the factor blocks (broadcast to all lanes) and the lanes' right-hand-side values are
 // staged through LDS, with the next chunk's loads in flight in registers meanwhile.
+// Columns from NT on are contact columns (n_c at the contact node, zero elsewhere): their
+// forward sweep generates the right-hand side instead of reading it, and starts at the
+// chunk of the pass's first contact node (the solution is exactly zero above it).
 __global__ void __launch_bounds__(NT) subst_kernel(Dev d) {
   const int r = blockIdx.x;
   const int lane = threadIdx.x;
   if (d.st_done[r]) return;
-  const int64_t o = d.off[r], n = d.off[r + 1] - o;
-  const int64_t nf = n - 1;            // free nodes 1..n-1 -> f = 0..nf-1
   const int nc = d.st_nc[r];
   const int ncol = 1 + nc;
+  const int c0 = blockIdx.y * NT;
+  if (c0 >= ncol) return;
+  const int64_t o = d.off[r], n = d.off[r + 1] - o;
+  const int64_t nf = n - 1;            // free nodes 1..n-1 -> f = 0..nf-1
   double* Zr = d.Z + d.zoff[r];
   const int64_t ld = 6 * n;
   __shared__ double sKD[PFS * NT], sKS[PFS * NT];
   __shared__ double sZ[CHS * 6 * NT];  // [u][k][lane]
-  for (int c0 = 0; c0 < ncol; c0 += NT) {
+  {
     const int c = c0 + lane;
     const bool act = c < ncol;
     double* z = Zr + (int64_t)(act ? c : 0) * ld;
     const bool fwd_done = c0 == 0;       // the first NT columns were swept forward in phase 2
+    // contact of this lane's column (forward passes only): free node and normal
+    int64_t fcn = nf;
+    double cn0 = 0.0, cn1 = 0.0, cn2 = 0.0;
+    if (!fwd_done && act) {
+      const int64_t ci = (int64_t)r * d.cap + (c - 1);
+      fcn = d.ct_node[ci] - 1;
+      cn0 = d.ct_n[3 * ci]; cn1 = d.ct_n[3 * ci + 1]; cn2 = d.ct_n[3 * ci + 2];
+    }
     double pd[PFS], ps[PFS], pz[CHS * 6];
     auto fetchZ = [&](int64_t f0, int64_t f1) {
 #pragma unroll
       for (int u = 0; u < CHS; ++u)
 #pragma unroll
-        for (int k = 0; k < 6; ++k) pz[u * 6 + k] = (act && f0 + u < f1) ? z[6 * (f0 + u) + k] : 0.0;
+        for (int k = 0; k < 6; ++k)
+          pz[u * 6 + k] = (act && f0 + u < f1 && f0 + u >= (fwd_done ? 0 : fcn)) ? z[6 * (f0 + u) + k] : 0.0;
+    };
+    auto genZ = [&](int64_t f0) {
+#pragma unroll
+      for (int u = 0; u < CHS; ++u) {
+        const bool here = f0 + u == fcn;
+        pz[u * 6 + 0] = here ? cn0 : 0.0;
+        pz[u * 6 + 1] = here ? cn1 : 0.0;
+        pz[u * 6 + 2] = here ? cn2 : 0.0;
+        pz[u * 6 + 3] = 0.0; pz[u * 6 + 4] = 0.0; pz[u * 6 + 5] = 0.0;
+      }
     };
     auto stage = [&]() {
 #pragma unroll
@@ -642,11 +566,18 @@ __global__ void __launch_bounds__(NT) subst_kernel(Dev d) {
         pd[u] = idx < cnt ? ldp[idx] : 0.0;
         ps[u] = idx < cnt ? lsp[idx] : 0.0;
       }
-      fetchZ(f0, min(nf, f0 + CHS));
+      genZ(f0);
     };
     double yp[6] = {0, 0, 0, 0, 0, 0};   // previous block solution
-    if (!fwd_done) fetchF(0);
-    for (int64_t f0 = 0; f0 < nf && !fwd_done; f0 += CHS) {
+    int64_t fs = nf;
+    if (!fwd_done) {
+      int64_t m = fcn;
+#pragma unroll
+      for (int sh = 32; sh > 0; sh >>= 1) m = min(m, (int64_t)__shfl_xor((long long)m, sh));
+      fs = (m / CHS) * CHS;
+      fetchF(fs);
+    }
+    for (int64_t f0 = fs; f0 < nf && !fwd_done; f0 += CHS) {
       __syncthreads();
       stage();
       __syncthreads();
@@ -674,7 +605,7 @@ __global__ void __launch_bounds__(NT) subst_kernel(Dev d) {
 #pragma unroll
           for (int p = k + 1; p < 6; ++p) bv[p] -= Ld[p * 6 + k] * y;
         }
-        if (act) {
+        if (act && f >= fcn) {
 #pragma unroll
           for (int k = 0; k < 6; ++k) z[6 * f + k] = yp[k];
         }
@@ -731,7 +662,6 @@ __global__ void __launch_bounds__(NT) subst_kernel(Dev d) {
         }
       }
     }
-    __syncthreads();
   }
 }
 
@@ -756,9 +686,12 @@ __device__ __forceinline__ void wave_argmin(double& v, int& idx) {
   }
 }
 
-// Primal active-set method (the lane-0 routine lcp_active_set, run by the whole
-// wavefront) for the LCP  w = W y + q >= 0, y >= 0, y.w = 0  with W symmetric positive
-// definite, m <= LCPM.  Lane i owns constraint i.  sW holds W packed (lower, constraint
+// Primal active-set method for the LCP  w = W y + q >= 0, y >= 0, y.w = 0  with W symmetric
+// positive definite, i.e. the convex QP  min 1/2 y.W y + q.y  over y >= 0 (the Lawson-Hanson
+// scheme): add the most violated inactive constraint (most negative w), solve
+// W_PP z = -q_P; if z > 0 take it, else move from y toward z until the first active y
+// reaches zero, drop those and solve again.  This version runs on one wavefront for
+// m <= LCPM with everything in LDS.  Lane i owns constraint i.  sW holds W packed (lower, constraint
 // order); sL the Cholesky factor of W_PP packed with rows in active-set order and sRd its
 // reciprocal diagonal; sP the active set in order of entry; sYp the active y by position.
 // Adding the most violated constraint appends one row to the factor; dropping constraints
@@ -900,111 +833,57 @@ __device__ bool lcp_parallel(LcpLds& S, const double* q, int m, bool warm, doubl
   return true;
 }
 
-__global__ void __launch_bounds__(NT) update_kernel(Dev d, int it) {
-  const int r = blockIdx.x;
+// true when contact i of robot r (node, triangle, kind) carried force at the previous iterate
+__device__ bool prev_active(const Dev& d, int r, int64_t cb, int i) {
+  const int ncp = d.st_ncp[r];
+  const int nd = d.ct_node[cb + i], tr = d.ct_tri[cb + i], kd = d.ct_kind[cb + i];
+  int lo = 0, hi = ncp;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (d.cp_node[cb + mid] < nd) lo = mid + 1; else hi = mid;
+  }
+  bool w = false;
+  for (int c = lo; c < ncp && d.cp_node[cb + c] == nd; ++c)
+    w |= (d.cp_tri[cb + c] == tr && d.cp_kind[cb + c] == kd && d.cp_y[cb + c] > 0.0);
+  return w;
+}
+
+// q_c = gap_c + n_c . dx_free(node of c) for the nc contacts of robot r
+__device__ void contact_q(const Dev& d, int64_t cb, int nc, const double* Zr, double* qv) {
+  for (int a = threadIdx.x; a < nc; a += NT) {
+    const int64_t f = d.ct_node[cb + a] - 1;
+    const double* z0 = Zr + 6 * f;
+    qv[a] = d.ct_gap[cb + a] + d.ct_n[3 * (cb + a)] * z0[0] + d.ct_n[3 * (cb + a) + 1] * z0[1] +
+            d.ct_n[3 * (cb + a) + 2] * z0[2];
+  }
+}
+
+// dx = dx_free + sum over active contacts of y_c Z_c (act/ya: the active contacts in index
+// order), then the step limit and the update of the state; the solved contacts become the
+// previous list.  Called by all NT threads of the robot's block.
+__device__ void take_step(const Dev& d, int r, int it, int nc, int nact, const int* act,
+                          const double* ya) {
   const int lane = threadIdx.x;
-  if (d.st_done[r]) return;
   const int64_t o = d.off[r], n = d.off[r + 1] - o;
   const int64_t N = d.Ntot;
-  const int64_t nf = n - 1;            // free nodes 1..n-1 -> f = 0..nf-1
-  const int cap = d.cap;
-  const int64_t cb = (int64_t)r * cap;
-  const int nc = d.st_nc[r];
+  const int64_t nf = n - 1;
+  const int64_t cb = (int64_t)r * d.cap;
   double* Zr = d.Z + d.zoff[r];
   const int64_t ld = 6 * n;
+  const double* y = d.ct_y + cb;
   double dx0[3];
   {
     const double dep = d.depth_cur[r];
     for (int k = 0; k < 3; ++k)
       dx0[k] = d.base_pos[3 * r + k] + dep * d.base_dir[3 * r + k] - d.X[k * N + o];
   }
-  // ---------------------------------------------------------------- Schur complement + LCP
-  __shared__ LcpLds S;
-  __shared__ int s_lcp_ok;
-  __shared__ int sAct[LCPM];
-  __shared__ double sYa[LCPM];
-  double* W = d.W + (int64_t)r * cap * cap;
-  double* qv = d.q + cb;
-  double* y = d.ct_y + cb;
-  for (int a = lane; a < nc; a += NT) {
-    const int64_t f = d.ct_node[cb + a] - 1;
-    const double* z0 = Zr + 6 * f;
-    qv[a] = d.ct_gap[cb + a] + d.ct_n[3 * (cb + a)] * z0[0] + d.ct_n[3 * (cb + a) + 1] * z0[1] +
-            d.ct_n[3 * (cb + a) + 2] * z0[2];
-  }
-  if (nc <= LCPM) {
-    // W packed in LDS: lane a computes its row, W(a, b) = n_a . Z_b(node of a), b <= a
-    bool warm = false;
-    if (lane < nc) {
-      const int64_t f = d.ct_node[cb + lane] - 1;
-      const double n0 = d.ct_n[3 * (cb + lane)], n1 = d.ct_n[3 * (cb + lane) + 1],
-                   n2 = d.ct_n[3 * (cb + lane) + 2];
-      for (int b = 0; b <= lane; ++b) {
-        const double* zb = Zr + (int64_t)(1 + b) * ld + 6 * f;
-        S.W[pk(lane, b)] = n0 * zb[0] + n1 * zb[1] + n2 * zb[2];
-      }
-      // active at the previous iteration (same node, triangle and kind, force > 0)
-      const int ncp = d.st_ncp[r];
-      const int nd = d.ct_node[cb + lane], tr = d.ct_tri[cb + lane], kd = d.ct_kind[cb + lane];
-      int lo = 0, hi = ncp;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (d.cp_node[cb + mid] < nd) lo = mid + 1; else hi = mid;
-      }
-      for (int c = lo; c < ncp && d.cp_node[cb + c] == nd; ++c)
-        warm |= (d.cp_tri[cb + c] == tr && d.cp_kind[cb + c] == kd && d.cp_y[cb + c] > 0.0);
-    }
-    __syncthreads();
-    double yl = 0.0;
-    bool ok = true;
-    if (nc > 0) ok = lcp_parallel(S, qv, nc, warm, yl);
-    if (lane < nc) y[lane] = yl;
-    // active contacts for the step
-    const unsigned long long am = __ballot(lane < nc && yl > 0.0);
-    if (lane < nc && yl > 0.0) {
-      const int pos = __popcll(am & ((1ull << lane) - 1ull));
-      sAct[pos] = lane;
-      sYa[pos] = yl;
-    }
-    if (lane == 0) s_lcp_ok = ok ? 1 : 0;
-    __syncthreads();
-    if (!s_lcp_ok) {
-      finish(d, r, 2, it, d.st_rn[r]);
-      return;
-    }
-    const int nact = __popcll(am);
-    for (int64_t j = lane; j < 6 * nf; j += NT) {
-      double v = Zr[j];
-      for (int k = 0; k < nact; ++k) v += sYa[k] * Zr[(int64_t)(1 + sAct[k]) * ld + j];
-      Zr[j] = v;
-    }
-  } else {
-    for (int e = lane; e < nc * nc; e += NT) {
-      const int a = e / nc, b = e % nc;
-      const int64_t f = d.ct_node[cb + a] - 1;
-      const double* zb = Zr + (int64_t)(1 + b) * ld + 6 * f;
-      W[a * cap + b] = d.ct_n[3 * (cb + a)] * zb[0] + d.ct_n[3 * (cb + a) + 1] * zb[1] +
-                       d.ct_n[3 * (cb + a) + 2] * zb[2];
-    }
-    __syncthreads();
-    if (lane == 0) {
-      double* scratch = d.W + (int64_t)d.B * cap * cap + (int64_t)r * (cap * cap + 3 * cap);
-      s_lcp_ok = lcp_active_set(W, qv, nc, cap, y, scratch) ? 1 : 0;
-    }
-    __syncthreads();
-    if (!s_lcp_ok) {
-      finish(d, r, 2, it, d.st_rn[r]);
-      return;
-    }
-    for (int64_t j = lane; j < 6 * nf; j += NT) {
-      double v = Zr[j];
-      for (int c = 0; c < nc; ++c) v += y[c] * Zr[(int64_t)(1 + c) * ld + j];
-      Zr[j] = v;
-    }
+  for (int64_t j = lane; j < 6 * nf; j += NT) {
+    double v = Zr[j];
+    for (int k = 0; k < nact; ++k) v += ya[k] * Zr[(int64_t)(1 + act[k]) * ld + j];
+    Zr[j] = v;
   }
   __syncthreads();
 
-  // ---------------------------------------------------------------- step, limit, update
   double mx = 0.0;
   for (int64_t f = lane; f < nf; f += NT) {
     const double* z = Zr + 6 * f;
@@ -1060,6 +939,456 @@ __global__ void __launch_bounds__(NT) update_kernel(Dev d, int it) {
   }
 }
 
+// phase 4 for robots with at most LCPM contacts: W packed in LDS, the wavefront LCP
+__global__ void __launch_bounds__(NT) update_kernel(Dev d, int it) {
+  const int r = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (d.st_done[r]) return;
+  const int nc = d.st_nc[r];
+  if (nc > LCPM) return;               // update_wide_kernel
+  const int64_t o = d.off[r], n = d.off[r + 1] - o;
+  const int64_t cb = (int64_t)r * d.cap;
+  double* Zr = d.Z + d.zoff[r];
+  const int64_t ld = 6 * n;
+  __shared__ LcpLds S;
+  __shared__ int s_lcp_ok;
+  __shared__ int sAct[LCPM];
+  __shared__ double sYa[LCPM];
+  double* qv = d.q + cb;
+  double* y = d.ct_y + cb;
+  contact_q(d, cb, nc, Zr, qv);
+  // W packed in LDS: lane a computes its row, W(a, b) = n_a . Z_b(node of a), b <= a
+  bool warm = false;
+  if (lane < nc) {
+    const int64_t f = d.ct_node[cb + lane] - 1;
+    const double n0 = d.ct_n[3 * (cb + lane)], n1 = d.ct_n[3 * (cb + lane) + 1],
+                 n2 = d.ct_n[3 * (cb + lane) + 2];
+    for (int b = 0; b <= lane; ++b) {
+      const double* zb = Zr + (int64_t)(1 + b) * ld + 6 * f;
+      S.W[pk(lane, b)] = n0 * zb[0] + n1 * zb[1] + n2 * zb[2];
+    }
+    warm = prev_active(d, r, cb, lane);
+  }
+  __syncthreads();
+  double yl = 0.0;
+  bool ok = true;
+  if (nc > 0) ok = lcp_parallel(S, qv, nc, warm, yl);
+  if (lane < nc) y[lane] = yl;
+  // active contacts for the step
+  const unsigned long long am = __ballot(lane < nc && yl > 0.0);
+  if (lane < nc && yl > 0.0) {
+    const int pos = __popcll(am & ((1ull << lane) - 1ull));
+    sAct[pos] = lane;
+    sYa[pos] = yl;
+  }
+  if (lane == 0) s_lcp_ok = ok ? 1 : 0;
+  __syncthreads();
+  if (!s_lcp_ok) {
+    finish(d, r, 2, it, d.st_rn[r]);
+    return;
+  }
+  take_step(d, r, it, nc, __popcll(am), sAct, sYa);
+}
+
+// ---------------------------------------------------------------- wide LCP (nc > LCPM)
+// The same primal active-set method for contact sets beyond LCPM, one wavefront per robot.
+// Constraint i is handled by lane i % NT; active position p by lane p % NT (SP per lane).
+// W is never formed whole: column t, W(i, t), is made available when t first enters the
+// active set (for a robot's contact set it is computed from Z and cached in device memory,
+// column-major, ld = cap).  The Cholesky factor of the active block, packed with rows in
+// order of entry, lives in LDS up to NPW positions; a set that outgrows it is solved again
+// with the factor in device memory (up to every constraint).
+constexpr int NPW = 128;
+constexpr int CAPW = 1024;             // largest contact capacity (host-checked)
+constexpr int SPL = NPW / NT;          // positions per lane, factor in LDS
+constexpr int SPG = CAPW / NT;         // positions per lane, factor in device memory
+
+struct LcpWideLds {
+  double L[NPW * (NPW + 1) / 2];
+  double Rd[NPW];
+  double Yp[NPW];
+  int P[NPW];
+  unsigned char In[CAPW];              // constraint i is in the active set
+  unsigned char Val[CAPW];             // column i of W is available
+};
+
+// where the factor of the active block lives: packed lower L (true off-diagonal entries),
+// reciprocal diagonal Rd, active y and constraint index by position, capacity npmax
+struct LcpWs {
+  double* L;
+  double* Rd;
+  double* Yp;
+  int* P;
+  int npmax;
+};
+
+// W columns and warm-start flags of a robot's contact set: W(i, t) = n_i . Z_t(node of i)
+struct RobotLcpSource {
+  const Dev* d;
+  int r;
+  int64_t cb;
+  const double* Zr;
+  int64_t ld;
+  __device__ void column(LcpWideLds& S, double* Wc, int cap, int m, int t) const {
+    if (S.Val[t]) return;
+    const double* zt = Zr + (int64_t)(1 + t) * ld;
+    double* wt = Wc + (int64_t)t * cap;
+    for (int i = threadIdx.x; i < m; i += NT) {
+      const int64_t f = d->ct_node[cb + i] - 1;
+      wt[i] = d->ct_n[3 * (cb + i)] * zt[6 * f] + d->ct_n[3 * (cb + i) + 1] * zt[6 * f + 1] +
+              d->ct_n[3 * (cb + i) + 2] * zt[6 * f + 2];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) S.Val[t] = 1;
+    __syncthreads();
+  }
+  __device__ bool warm(int i) const { return prev_active(*d, r, cb, i); }
+};
+
+// a given dense W (column-major, ld = cap), no warm start
+struct DenseLcpSource {
+  __device__ void column(LcpWideLds&, double*, int, int, int) const {}
+  __device__ bool warm(int) const { return false; }
+};
+
+template <int SP>
+__device__ __forceinline__ double wide_pick(const double (&v)[SP], int s) {
+  double x = v[0];
+#pragma unroll
+  for (int u = 1; u < SP; ++u)
+    if (s == u) x = v[u];
+  return x;
+}
+
+// L x = b over positions < np, in place (b, x by position)
+template <int SP>
+__device__ __forceinline__ void wide_fwd(const LcpWs& w, int np, double (&bv)[SP]) {
+  const int lane = threadIdx.x;
+  for (int k = 0; k < np; ++k) {
+    const double xk = __shfl(wide_pick<SP>(bv, k / NT), k % NT) * w.Rd[k];
+#pragma unroll
+    for (int s = 0; s < SP; ++s) {
+      if (s * NT >= np) break;
+      if ((s + 1) * NT <= k) continue;
+      const int p = lane + NT * s;
+      if (p == k) bv[s] = xk;
+      else if (p > k && p < np) bv[s] -= w.L[pk(p, k)] * xk;
+    }
+  }
+}
+
+// L^T x = b over positions < np, in place
+template <int SP>
+__device__ __forceinline__ void wide_bwd(const LcpWs& w, int np, double (&bv)[SP]) {
+  const int lane = threadIdx.x;
+  for (int k = np - 1; k >= 0; --k) {
+    const double xk = __shfl(wide_pick<SP>(bv, k / NT), k % NT) * w.Rd[k];
+#pragma unroll
+    for (int s = 0; s < SP; ++s) {
+      if (s * NT > k) break;
+      const int p = lane + NT * s;
+      if (p == k) bv[s] = xk;
+      else if (p < k) bv[s] -= w.L[pk(k, p)] * xk;
+    }
+  }
+}
+
+// Cholesky of W(P, P) over np positions
+template <int SP>
+__device__ bool wide_factor(const LcpWs& w, const double* Wc, int cap, int np) {
+  const int lane = threadIdx.x;
+#pragma unroll
+  for (int s = 0; s < SP; ++s) {
+    const int p = lane + NT * s;
+    if (p < np)
+      for (int b = 0; b <= p; ++b) w.L[pk(p, b)] = Wc[(int64_t)w.P[b] * cap + w.P[p]];
+  }
+  __syncthreads();
+  bool ok = true;
+  for (int k = 0; k < np; ++k) {
+    const double piv = w.L[pk(k, k)];
+    if (!(piv > 0.0)) ok = false;
+    const double rk = rsqrt_nr(piv > 0.0 ? piv : 1.0);
+#pragma unroll
+    for (int s = 0; s < SP; ++s) {
+      const int p = lane + NT * s;
+      if (p > k && p < np) w.L[pk(p, k)] *= rk;
+    }
+    if (lane == 0) w.Rd[k] = rk;
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < SP; ++s) {
+      const int p = lane + NT * s;
+      if (p > k && p < np) {
+        const double lak = w.L[pk(p, k)];
+        for (int j = k + 1; j <= p; ++j) w.L[pk(p, j)] -= lak * w.L[pk(j, k)];
+      }
+    }
+    __syncthreads();
+  }
+  return ok;
+}
+
+// 0: solved (y written), 1: non-positive pivot or iteration limit, 2: active set beyond npmax.
+// fresh: forget the cached columns (a new W).
+template <int SP, class Src>
+__device__ int lcp_wide(const Src& src, LcpWideLds& S, const LcpWs& w, double* Wc, int cap,
+                        const double* q, int m, double* y, bool fresh) {
+  const int lane = threadIdx.x;
+  double qmax = 0.0;
+  for (int i = lane; i < m; i += NT) {
+    qmax = fmax(qmax, fabs(q[i]));
+    S.In[i] = 0;
+    if (fresh) S.Val[i] = 0;
+  }
+  const double tolw = 1e-12 * warp_max(qmax);
+  __syncthreads();
+  int np = 0;
+  // warm start from the constraints the source flags (previous iterate's active contacts)
+  {
+    int cnt = 0;
+    for (int i0 = 0; i0 < m; i0 += NT) {
+      const int i = i0 + lane;
+      const bool wf = i < m && src.warm(i);
+      const unsigned long long wm = __ballot(wf);
+      const int pos = cnt + __popcll(wm & ((1ull << lane) - 1ull));
+      if (wf && pos < w.npmax) w.P[pos] = i;
+      cnt += __popcll(wm);
+    }
+    __syncthreads();
+    if (cnt > 0 && cnt <= w.npmax) {
+      for (int a = 0; a < cnt; ++a) src.column(S, Wc, cap, m, w.P[a]);
+      bool ok = wide_factor<SP>(w, Wc, cap, cnt);
+      if (ok) {
+        double z[SP];
+#pragma unroll
+        for (int s = 0; s < SP; ++s) {
+          const int p = lane + NT * s;
+          z[s] = p < cnt ? -q[w.P[p]] : 0.0;
+        }
+        wide_fwd<SP>(w, cnt, z);
+        wide_bwd<SP>(w, cnt, z);
+        bool bad = false;
+#pragma unroll
+        for (int s = 0; s < SP; ++s) bad |= (lane + NT * s < cnt) && !(z[s] > 0.0);
+        ok = __ballot(bad) == 0ull;
+        if (ok) {
+#pragma unroll
+          for (int s = 0; s < SP; ++s) {
+            const int p = lane + NT * s;
+            if (p < cnt) { w.Yp[p] = z[s]; S.In[w.P[p]] = 1; }
+          }
+          np = cnt;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  bool done = false, failed = false, full = false;
+  for (int outer = 0; outer < 4 * m + 8 && !done && !failed; ++outer) {
+    // most violated inactive constraint: w_i = q_i + sum_a W(i, P_a) y_a
+    double v = INFINITY;
+    int t = 0x7fffffff;
+    for (int i = lane; i < m; i += NT) {
+      double wi = q[i];
+      for (int a = 0; a < np; ++a) wi += Wc[(int64_t)w.P[a] * cap + i] * w.Yp[a];
+      if (!S.In[i] && wi < -tolw && wi < v) { v = wi; t = i; }
+    }
+    wave_argmin(v, t);
+    if (!(v < INFINITY)) { done = true; break; }
+    if (np == w.npmax) { full = true; break; }
+    src.column(S, Wc, cap, m, t);
+    // append t: the new factor row l solves L l = W(P, t)
+    double bv[SP];
+#pragma unroll
+    for (int s = 0; s < SP; ++s) {
+      const int p = lane + NT * s;
+      bv[s] = p < np ? Wc[(int64_t)t * cap + w.P[p]] : 0.0;
+    }
+    wide_fwd<SP>(w, np, bv);
+    double ss = 0.0;
+#pragma unroll
+    for (int s = 0; s < SP; ++s) ss += (lane + NT * s < np) ? bv[s] * bv[s] : 0.0;
+    const double dtt = Wc[(int64_t)t * cap + t] - warp_sum(ss);
+    __syncthreads();
+    if (!(dtt > 0.0)) { failed = true; break; }
+#pragma unroll
+    for (int s = 0; s < SP; ++s) {
+      const int p = lane + NT * s;
+      if (p < np) w.L[pk(np, p)] = bv[s];
+    }
+    if (lane == 0) {
+      w.L[pk(np, np)] = 1.0;
+      w.Rd[np] = rsqrt_nr(dtt);
+      w.P[np] = t;
+      w.Yp[np] = 0.0;
+      S.In[t] = 1;
+    }
+    ++np;
+    __syncthreads();
+    for (int inner = 0; inner < 4 * m + 8; ++inner) {
+      double z[SP];
+#pragma unroll
+      for (int s = 0; s < SP; ++s) {
+        const int p = lane + NT * s;
+        z[s] = p < np ? -q[w.P[p]] : 0.0;
+      }
+      wide_fwd<SP>(w, np, z);
+      wide_bwd<SP>(w, np, z);
+      bool bad = false;
+#pragma unroll
+      for (int s = 0; s < SP; ++s) bad |= (lane + NT * s < np) && !(z[s] > 0.0);
+      if (__ballot(bad) == 0ull) {
+#pragma unroll
+        for (int s = 0; s < SP; ++s) {
+          const int p = lane + NT * s;
+          if (p < np) w.Yp[p] = z[s];
+        }
+        __syncthreads();
+        break;
+      }
+      // step toward z until the first active y reaches zero
+      double al = 1.0;
+#pragma unroll
+      for (int s = 0; s < SP; ++s) {
+        const int p = lane + NT * s;
+        if (p < np && z[s] <= 0.0) {
+          const double yp = w.Yp[p];
+          al = fmin(al, yp / (yp - z[s]));
+        }
+      }
+      al = fmin(1.0, warp_min(al));
+      double yn[SP];
+      int pidx[SP];
+      unsigned long long km[SP];
+#pragma unroll
+      for (int s = 0; s < SP; ++s) {
+        const int p = lane + NT * s;
+        const double yp = p < np ? w.Yp[p] : 0.0;
+        yn[s] = yp + al * (z[s] - yp);
+        pidx[s] = p < np ? w.P[p] : 0;
+        km[s] = __ballot(p < np && yn[s] > 0.0);
+      }
+      __syncthreads();
+      int base = 0;
+#pragma unroll
+      for (int s = 0; s < SP; ++s) {
+        const int p = lane + NT * s;
+        const bool keep = p < np && yn[s] > 0.0;
+        if (p < np && !keep) S.In[pidx[s]] = 0;
+        if (keep) {
+          const int pos = base + __popcll(km[s] & ((1ull << lane) - 1ull));
+          w.P[pos] = pidx[s];
+          w.Yp[pos] = yn[s];
+        }
+        base += __popcll(km[s]);
+      }
+      np = base;
+      __syncthreads();
+      if (np == 0) break;
+      if (!wide_factor<SP>(w, Wc, cap, np)) { failed = true; break; }
+    }
+  }
+  if (full) return 2;
+  if (failed || !done) return 1;
+  for (int i = lane; i < m; i += NT) y[i] = 0.0;
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < SP; ++s) {
+    const int p = lane + NT * s;
+    if (p < np) y[w.P[p]] = w.Yp[p];
+  }
+  __syncthreads();
+  return 0;
+}
+
+// the factor workspace in device memory for m constraints: packed L, Rd, Yp, P
+__device__ __forceinline__ LcpWs global_ws(double* g, int m) {
+  const int64_t nl = (int64_t)m * (m + 1) / 2;
+  return LcpWs{g, g + nl, g + nl + m, (int*)(g + nl + 2 * m), m};
+}
+
+// 0: solved with the factor in LDS, 1: solved with the factor in device memory, -1: failed
+template <class Src>
+__device__ int lcp_wide_any(const Src& src, LcpWideLds& S, double* Wc, int cap, const double* q,
+                            int m, double* y, double* gws) {
+  const LcpWs wl{S.L, S.Rd, S.Yp, S.P, NPW};
+  const int c = lcp_wide<SPL>(src, S, wl, Wc, cap, q, m, y, true);
+  if (c == 0) return 0;
+  if (c == 1) return -1;
+  return lcp_wide<SPG>(src, S, global_ws(gws, m), Wc, cap, q, m, y, false) == 0 ? 1 : -1;
+}
+
+// phase 4 for robots with more than LCPM contacts
+__global__ void __launch_bounds__(NT) update_wide_kernel(Dev d, int it) {
+  const int r = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (d.st_done[r]) return;
+  const int nc = d.st_nc[r];
+  if (nc <= LCPM) return;              // update_kernel
+  const int64_t n = d.off[r + 1] - d.off[r];
+  const int cap = d.cap;
+  const int64_t cb = (int64_t)r * cap;
+  double* Zr = d.Z + d.zoff[r];
+  const int64_t ld = 6 * n;
+  __shared__ LcpWideLds S;
+  double* qv = d.q + cb;
+  double* y = d.ct_y + cb;
+  double* Wc = d.W + (int64_t)r * cap * cap;
+  double* scratch = d.W + (int64_t)d.B * cap * cap + (int64_t)r * (cap * cap + 3 * cap);
+  contact_q(d, cb, nc, Zr, qv);
+  __syncthreads();
+  const RobotLcpSource src{&d, r, cb, Zr, ld};
+  if (lcp_wide_any(src, S, Wc, cap, qv, nc, y, scratch) < 0) {
+    finish(d, r, 2, it, d.st_rn[r]);
+    return;
+  }
+  // active contacts in index order (the factor workspace is free again)
+  int* act = (int*)(scratch + nc);
+  double* ya = scratch;
+  int nact = 0;
+  for (int i0 = 0; i0 < nc; i0 += NT) {
+    const int i = i0 + lane;
+    const double yi = i < nc ? y[i] : 0.0;
+    const unsigned long long am = __ballot(yi > 0.0);
+    if (yi > 0.0) {
+      const int pos = nact + __popcll(am & ((1ull << lane) - 1ull));
+      act[pos] = i;
+      ya[pos] = yi;
+    }
+    nact += __popcll(am);
+  }
+  __syncthreads();
+  take_step(d, r, it, nc, nact, act, ya);
+}
+
+// fem_lcp: the LCP routines above on a given W (column-major, ld = m), one block
+__global__ void __launch_bounds__(NT) lcp_small_kernel(const double* W, const double* q, int m,
+                                                       double* y, int* code) {
+  __shared__ LcpLds S;
+  const int lane = threadIdx.x;
+  if (lane < m)
+    for (int b = 0; b <= lane; ++b) S.W[pk(lane, b)] = W[(int64_t)b * m + lane];
+  __syncthreads();
+  double yl = 0.0;
+  const bool ok = lcp_parallel(S, q, m, false, yl);
+  if (lane < m) y[lane] = yl;
+  if (lane == 0) *code = ok ? 0 : -1;
+}
+
+__global__ void __launch_bounds__(NT) lcp_wide_check_kernel(double* W, const double* q, int m,
+                                                            double* y, double* gws, int* code) {
+  __shared__ LcpWideLds S;
+  const int c = lcp_wide_any(DenseLcpSource{}, S, W, m, q, m, y, gws);
+  if (threadIdx.x == 0) *code = c < 0 ? -1 : 1 + c;
+}
+
+void launch_lcp_check(double* W, const double* q, int m, double* y, double* scratch, int* code,
+                      hipStream_t s) {
+  if (m <= LCPM) hipLaunchKernelGGL(lcp_small_kernel, dim3(1), dim3(NT), 0, s, W, q, m, y, code);
+  else hipLaunchKernelGGL(lcp_wide_check_kernel, dim3(1), dim3(NT), 0, s, W, q, m, y, scratch, code);
+}
+
 // detection-only path: compact the per-node contacts of every robot (no step)
 __global__ void __launch_bounds__(NT) gather_kernel(Dev d) {
   const int r = blockIdx.x;
@@ -1090,8 +1419,11 @@ void launch_solve_phase(const Dev& d, int phase, int it, hipStream_t s) {
   switch (phase) {
     case 0: hipLaunchKernelGGL(check_rhs_kernel, dim3(d.B), dim3(NT), 0, s, d, it); break;
     case 1: hipLaunchKernelGGL(factor_kernel, dim3(d.B), dim3(2 * NT), 0, s, d, it); break;
-    case 2: hipLaunchKernelGGL(subst_kernel, dim3(d.B), dim3(NT), 0, s, d); break;
-    default: hipLaunchKernelGGL(update_kernel, dim3(d.B), dim3(NT), 0, s, d, it); break;
+    case 2: hipLaunchKernelGGL(subst_kernel, dim3(d.B, (d.cap + NT) / NT), dim3(NT), 0, s, d); break;
+    default:
+      hipLaunchKernelGGL(update_kernel, dim3(d.B), dim3(NT), 0, s, d, it);
+      if (d.cap > LCPM) hipLaunchKernelGGL(update_wide_kernel, dim3(d.B), dim3(NT), 0, s, d, it);
+      break;
   }
 }
 

@@ -91,8 +91,9 @@ def lib():
         L.fem_grad.argtypes = [P, P, C.c_int32, P, P]
         L.fem_total_nodes.argtypes = [P]
         L.fem_total_nodes.restype = C.c_int64
+        L.fem_lcp.argtypes = [P, P, C.c_int32, P, C.POINTER(C.c_int32)]
         for f in ("fem_create", "fem_set_lumen", "fem_set_actuation", "fem_solve", "fem_contacts",
-                  "fem_get_state", "fem_set_state", "fem_eval", "fem_profile", "fem_grad"):
+                  "fem_get_state", "fem_set_state", "fem_eval", "fem_profile", "fem_grad", "fem_lcp"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -100,7 +101,7 @@ def lib():
 
 EXPORTED = ("fem_create", "fem_destroy", "fem_last_error", "fem_set_lumen", "fem_set_actuation",
             "fem_solve", "fem_contacts", "fem_get_state", "fem_set_state", "fem_eval",
-            "fem_profile", "fem_grad", "fem_total_nodes")
+            "fem_profile", "fem_grad", "fem_total_nodes", "fem_lcp")
 
 
 class FemError(RuntimeError):
@@ -294,3 +295,19 @@ def state_to_PR(X):
     R[:, 1, 0] = 2 * (x * y + w * z); R[:, 1, 1] = 1 - 2 * (x * x + z * z); R[:, 1, 2] = 2 * (y * z - w * x)
     R[:, 2, 0] = 2 * (x * z - w * y); R[:, 2, 1] = 2 * (y * z + w * x); R[:, 2, 2] = 1 - 2 * (x * x + y * y)
     return P, R
+
+
+def fem_lcp(W, q):
+    """LCP w = W y + q >= 0, y >= 0, y.w = 0 solved by the library's device routines
+    (W symmetric positive definite).  Returns (y, path) with path 0 (LDS active set,
+    m <= 64), 1 (wavefront active set) or 2 (its single-lane fallback)."""
+    W = np.asarray(W, dtype=np.float64)
+    m = W.shape[0]
+    Wc = np.ascontiguousarray(W.T)           # column-major
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    y = np.zeros(m)
+    path = C.c_int32(-1)
+    st = lib().fem_lcp(_ptr(Wc), _ptr(q), m, _ptr(y), C.byref(path))
+    if st != FEM_OK:
+        raise FemError(st, "fem_lcp failed")
+    return y, path.value
