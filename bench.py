@@ -135,7 +135,7 @@ def main():
     ap.add_argument("--load-steps", type=int, default=100)
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--max-newton", type=int, default=60)
-    ap.add_argument("--capacity", type=int, default=64)
+    ap.add_argument("--capacity", type=int, default=256)
     ap.add_argument("--cpu-robots", type=int, default=2)
     ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--single-robots", type=int, default=4)

@@ -17,6 +17,11 @@
 
 namespace accfem {
 
+// device workspace of the wide LCP per robot (the packed factor, its diagonal, y and the
+// active set by position for up to cap positions), in doubles
+__host__ __device__ inline int64_t lcp_ws_doubles(int cap) {
+  return (int64_t)cap * (cap + 1) / 2 + 3 * (int64_t)cap;
+}
 constexpr int MAXC = 8;          // contact candidates kept per node
 constexpr int SOLVE_THREADS = 64;  // one wavefront per robot in the solve kernel
 
@@ -96,6 +101,8 @@ struct Dev {
   double* Z;
   double* W;          // [B*cap*cap]
   double* q;          // [B*cap]
+  int32_t* ac_idx;    // [B*cap] contacts with force > 0 after the LCP, in index order ...
+  double* ac_y;       // ... and their forces
   // per robot iteration state
   int32_t* st_status;
   int32_t* st_done;
@@ -105,6 +112,8 @@ struct Dev {
   int32_t* st_nlim;
   int32_t* st_nswitch;
   int32_t* st_iters;
+  int32_t* st_nact;     // active contacts of the current step
+  unsigned long long* st_mx;  // largest node translation of the step (bits of a double >= 0)
   int64_t* st_rhs;      // right-hand sides solved since creation / the last state reset
   double* st_rn;        // residual norm at the last check
   double* st_rnprev;

@@ -752,21 +752,25 @@ __device__ bool lcp_parallel(LcpLds& S, const double* q, int m, bool warm, doubl
   const double tolw = 1e-12 * warp_max(fabs(qi));
   int np = 0;
   if (lane < LCPM) { S.In[lane] = 0; S.Yc[lane] = 0.0; }
-  // warm start
-  const unsigned long long wm = __ballot(warm && lane < m);
-  if (wm) {
+  // warm start: solve on the flagged set, drop the constraints whose y is not positive and
+  // solve again, until every y is positive (a feasible start) or the set is empty
+  unsigned long long wm = __ballot(warm && lane < m);
+  while (wm) {
     const int cnt = __popcll(wm);
-    if (warm && lane < m) S.P[__popcll(wm & ((1ull << lane) - 1ull))] = lane;
+    const bool mine = (wm >> lane) & 1ull;
+    const int pos = __popcll(wm & ((1ull << lane) - 1ull));
+    if (mine) S.P[pos] = lane;
     __syncthreads();
-    bool ok = lcp_factor(S, cnt);
-    if (ok) {
-      const double z = lcp_solve(S, cnt, lane < cnt ? -q[S.P[lane]] : 0.0);
-      ok = __ballot(lane < cnt && !(z > 0.0)) == 0ull;
-      if (ok) {
-        if (lane < cnt) { S.Yp[lane] = z; S.In[S.P[lane]] = 1; }
-        np = cnt;
-      }
+    if (!lcp_factor(S, cnt)) break;
+    const double z = lcp_solve(S, cnt, lane < cnt ? -q[S.P[lane]] : 0.0);
+    const unsigned long long bad = __ballot(lane < cnt && !(z > 0.0));
+    if (bad == 0ull) {
+      if (lane < cnt) { S.Yp[lane] = z; S.In[S.P[lane]] = 1; }
+      np = cnt;
+      __syncthreads();
+      break;
     }
+    wm = __ballot(mine && !((bad >> pos) & 1ull));
     __syncthreads();
   }
   bool done = false, failed = false;
@@ -858,50 +862,114 @@ __device__ void contact_q(const Dev& d, int64_t cb, int nc, const double* Zr, do
   }
 }
 
-// dx = dx_free + sum over active contacts of y_c Z_c (act/ya: the active contacts in index
-// order), then the step limit and the update of the state; the solved contacts become the
-// previous list.  Called by all NT threads of the robot's block.
-__device__ void take_step(const Dev& d, int r, int it, int nc, int nact, const int* act,
-                          const double* ya) {
+// After the LCP of robot r (one wavefront): the contacts with force > 0 in index order
+// (y by contact index in ct_y) into ac_idx / ac_y, their count into st_nact; clears st_mx.
+__device__ void store_active(const Dev& d, int r, int nc) {
   const int lane = threadIdx.x;
-  const int64_t o = d.off[r], n = d.off[r + 1] - o;
-  const int64_t N = d.Ntot;
-  const int64_t nf = n - 1;
   const int64_t cb = (int64_t)r * d.cap;
-  double* Zr = d.Z + d.zoff[r];
-  const int64_t ld = 6 * n;
   const double* y = d.ct_y + cb;
-  double dx0[3];
-  {
-    const double dep = d.depth_cur[r];
-    for (int k = 0; k < 3; ++k)
-      dx0[k] = d.base_pos[3 * r + k] + dep * d.base_dir[3 * r + k] - d.X[k * N + o];
+  int nact = 0;
+  for (int i0 = 0; i0 < nc; i0 += NT) {
+    const int i = i0 + lane;
+    const double yi = i < nc ? y[i] : 0.0;
+    const unsigned long long am = __ballot(yi > 0.0);
+    if (yi > 0.0) {
+      const int pos = nact + __popcll(am & ((1ull << lane) - 1ull));
+      d.ac_idx[cb + pos] = i;
+      d.ac_y[cb + pos] = yi;
+    }
+    nact += __popcll(am);
   }
-  for (int64_t j = lane; j < 6 * nf; j += NT) {
-    double v = Zr[j];
-    for (int k = 0; k < nact; ++k) v += ya[k] * Zr[(int64_t)(1 + act[k]) * ld + j];
-    Zr[j] = v;
+  if (lane == 0) {
+    d.st_nact[r] = nact;
+    d.st_mx[r] = 0ull;
   }
-  __syncthreads();
+}
 
-  double mx = 0.0;
-  for (int64_t f = lane; f < nf; f += NT) {
-    const double* z = Zr + 6 * f;
-    mx = fmax(mx, sqrt(z[0] * z[0] + z[1] * z[1] + z[2] * z[2]));
+// translation increment of the base node: to the clamped, inserted position (eq. 14)
+__device__ __forceinline__ void base_increment(const Dev& d, int r, int64_t o, double* dx0) {
+  const double dep = d.depth_cur[r];
+  for (int k = 0; k < 3; ++k)
+    dx0[k] = d.base_pos[3 * r + k] + dep * d.base_dir[3 * r + k] - d.X[k * d.Ntot + o];
+}
+
+// largest-translation reduction: a wavefront whose nodes all belong to robot r combines
+// its candidates first; v < 0 means no candidate (NaN translations are ignored, as fmax does)
+__device__ __forceinline__ void step_max(const Dev& d, int r, double v) {
+  const int rf = __shfl(r, 0);
+  const bool one = __ballot(r != rf) == 0ull;
+  if (one) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    if ((threadIdx.x & 63) == 0 && v >= 0.0)
+      atomicMax(d.st_mx + r, (unsigned long long)__double_as_longlong(v));
+  } else if (v >= 0.0) {
+    atomicMax(d.st_mx + r, (unsigned long long)__double_as_longlong(v));
   }
-  mx = warp_max(mx);
-  mx = fmax(mx, sqrt(dx0[0] * dx0[0] + dx0[1] * dx0[1] + dx0[2] * dx0[2]));
+}
+
+// phase 4b, one thread per node: dx = dx_free + sum over active contacts of y_c Z_c (in
+// place in Z's column 0, contacts in index order) and the robot's largest node translation
+__global__ void __launch_bounds__(256) step_dx_kernel(Dev d) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in = g < d.Ntot;
+  const int r = in ? d.robot_of[g] : d.robot_of[d.Ntot - 1];
+  const bool live = in && !d.st_done[r];
+  double v = -1.0;
+  if (live) {
+    const int64_t o = d.off[r];
+    const int64_t i = g - o;
+    if (i == 0) {
+      double dx0[3];
+      base_increment(d, r, o, dx0);
+      v = sqrt(dx0[0] * dx0[0] + dx0[1] * dx0[1] + dx0[2] * dx0[2]);
+    } else {
+      const int64_t n = d.off[r + 1] - o;
+      const int64_t ld = 6 * n;
+      const int64_t cb = (int64_t)r * d.cap;
+      double* z = d.Z + d.zoff[r] + 6 * (i - 1);
+      double dx[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) dx[k] = z[k];
+      const int nact = d.st_nact[r];
+      for (int a = 0; a < nact; ++a) {
+        const double ya = d.ac_y[cb + a];
+        const double* zc = z + (int64_t)(1 + d.ac_idx[cb + a]) * ld;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) dx[k] += ya * zc[k];
+      }
+#pragma unroll
+      for (int k = 0; k < 6; ++k) z[k] = dx[k];
+      v = sqrt(dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2]);
+      if (!(v >= 0.0)) v = -1.0;
+    }
+  }
+  step_max(d, r, v);
+}
+
+// phase 4c, one thread per node: the step-size limit (eq. 25-27: scale the step so that no
+// node moves more than beta, beta halved every 10 contact-set switches) and the state
+// update; the robot's contacts become the previous list (forces scaled with the step).
+__global__ void __launch_bounds__(256) step_apply_kernel(Dev d, int it) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= d.Ntot) return;
+  const int r = d.robot_of[g];
+  if (d.st_done[r]) return;
+  const int64_t N = d.Ntot;
+  const int64_t o = d.off[r], n = d.off[r + 1] - o;
+  const int64_t i = g - o;
+  const double mx = __longlong_as_double((long long)d.st_mx[r]);
   const int nsw = d.st_nswitch[r];
   const double beta = d.beta0 * fmax(1.0 / 64.0, ldexp(1.0, -(nsw / 10)));
   const bool limited = mx > beta;
   const double sc = limited ? beta / mx : 1.0;
-  // base node: translation only
-  if (lane == 0) {
+  if (i == 0) {
+    // base node: translation only
+    double dx0[3];
+    base_increment(d, r, o, dx0);
     for (int k = 0; k < 3; ++k) d.X[k * N + o] += sc * dx0[k];
-  }
-  for (int64_t f = lane; f < nf; f += NT) {
-    const int64_t g = o + f + 1;
-    const double* z = Zr + 6 * f;
+  } else {
+    const double* z = d.Z + d.zoff[r] + 6 * (i - 1);
     for (int k = 0; k < 3; ++k) d.X[k * N + g] += sc * z[k];
     const double wx = sc * z[3], wy = sc * z[4], wz = sc * z[5];
     const double th = sqrt(wx * wx + wy * wy + wz * wz);
@@ -922,16 +990,17 @@ __device__ void take_step(const Dev& d, int r, int it, int nc, int nact, const i
     const double inv = 1.0 / sqrt(nw * nw + nx * nx + ny * ny + nz * nz);
     d.X[3 * N + g] = nw * inv; d.X[4 * N + g] = nx * inv; d.X[5 * N + g] = ny * inv; d.X[6 * N + g] = nz * inv;
   }
-  // the solved contacts become the previous list (forces scaled with the step)
-  for (int c = lane; c < nc; c += NT) {
+  const int nc = d.st_nc[r];
+  const int64_t cb = (int64_t)r * d.cap;
+  for (int64_t c = i; c < nc; c += n) {
     d.cp_node[cb + c] = d.ct_node[cb + c];
     d.cp_tri[cb + c] = d.ct_tri[cb + c];
     d.cp_kind[cb + c] = d.ct_kind[cb + c];
     d.cp_gap[cb + c] = d.ct_gap[cb + c];
-    d.cp_y[cb + c] = sc * y[c];
+    d.cp_y[cb + c] = sc * d.ct_y[cb + c];
     for (int k = 0; k < 3; ++k) d.cp_n[3 * (cb + c) + k] = d.ct_n[3 * (cb + c) + k];
   }
-  if (lane == 0) {
+  if (i == 0) {
     d.st_ncp[r] = nc;
     d.st_limited[r] = limited ? 1 : 0;
     d.st_nlim[r] += limited ? 1 : 0;
@@ -946,14 +1015,12 @@ __global__ void __launch_bounds__(NT) update_kernel(Dev d, int it) {
   if (d.st_done[r]) return;
   const int nc = d.st_nc[r];
   if (nc > LCPM) return;               // update_wide_kernel
-  const int64_t o = d.off[r], n = d.off[r + 1] - o;
+  const int64_t n = d.off[r + 1] - d.off[r];
   const int64_t cb = (int64_t)r * d.cap;
   double* Zr = d.Z + d.zoff[r];
   const int64_t ld = 6 * n;
   __shared__ LcpLds S;
   __shared__ int s_lcp_ok;
-  __shared__ int sAct[LCPM];
-  __shared__ double sYa[LCPM];
   double* qv = d.q + cb;
   double* y = d.ct_y + cb;
   contact_q(d, cb, nc, Zr, qv);
@@ -963,6 +1030,7 @@ __global__ void __launch_bounds__(NT) update_kernel(Dev d, int it) {
     const int64_t f = d.ct_node[cb + lane] - 1;
     const double n0 = d.ct_n[3 * (cb + lane)], n1 = d.ct_n[3 * (cb + lane) + 1],
                  n2 = d.ct_n[3 * (cb + lane) + 2];
+#pragma unroll 4
     for (int b = 0; b <= lane; ++b) {
       const double* zb = Zr + (int64_t)(1 + b) * ld + 6 * f;
       S.W[pk(lane, b)] = n0 * zb[0] + n1 * zb[1] + n2 * zb[2];
@@ -974,20 +1042,13 @@ __global__ void __launch_bounds__(NT) update_kernel(Dev d, int it) {
   bool ok = true;
   if (nc > 0) ok = lcp_parallel(S, qv, nc, warm, yl);
   if (lane < nc) y[lane] = yl;
-  // active contacts for the step
-  const unsigned long long am = __ballot(lane < nc && yl > 0.0);
-  if (lane < nc && yl > 0.0) {
-    const int pos = __popcll(am & ((1ull << lane) - 1ull));
-    sAct[pos] = lane;
-    sYa[pos] = yl;
-  }
   if (lane == 0) s_lcp_ok = ok ? 1 : 0;
   __syncthreads();
   if (!s_lcp_ok) {
     finish(d, r, 2, it, d.st_rn[r]);
     return;
   }
-  take_step(d, r, it, nc, __popcll(am), sAct, sYa);
+  store_active(d, r, nc);
 }
 
 // ---------------------------------------------------------------- wide LCP (nc > LCPM)
@@ -1100,8 +1161,11 @@ __device__ bool wide_factor(const LcpWs& w, const double* Wc, int cap, int np) {
 #pragma unroll
   for (int s = 0; s < SP; ++s) {
     const int p = lane + NT * s;
-    if (p < np)
-      for (int b = 0; b <= p; ++b) w.L[pk(p, b)] = Wc[(int64_t)w.P[b] * cap + w.P[p]];
+    if (p < np) {
+      const int pp = w.P[p];
+#pragma unroll 8
+      for (int b = 0; b <= p; ++b) w.L[pk(p, b)] = Wc[(int64_t)w.P[b] * cap + pp];
+    }
   }
   __syncthreads();
   bool ok = true;
@@ -1156,31 +1220,48 @@ __device__ int lcp_wide(const Src& src, LcpWideLds& S, const LcpWs& w, double* W
       cnt += __popcll(wm);
     }
     __syncthreads();
-    if (cnt > 0 && cnt <= w.npmax) {
-      for (int a = 0; a < cnt; ++a) src.column(S, Wc, cap, m, w.P[a]);
-      bool ok = wide_factor<SP>(w, Wc, cap, cnt);
-      if (ok) {
-        double z[SP];
+    if (cnt > w.npmax) cnt = 0;
+    for (int a = 0; a < cnt; ++a) src.column(S, Wc, cap, m, w.P[a]);
+    // solve on the set, drop the constraints whose y is not positive, solve again
+    while (cnt > 0) {
+      if (!wide_factor<SP>(w, Wc, cap, cnt)) break;
+      double z[SP];
+#pragma unroll
+      for (int s = 0; s < SP; ++s) {
+        const int p = lane + NT * s;
+        z[s] = p < cnt ? -q[w.P[p]] : 0.0;
+      }
+      wide_fwd<SP>(w, cnt, z);
+      wide_bwd<SP>(w, cnt, z);
+      bool bad = false;
+#pragma unroll
+      for (int s = 0; s < SP; ++s) bad |= (lane + NT * s < cnt) && !(z[s] > 0.0);
+      if (__ballot(bad) == 0ull) {
 #pragma unroll
         for (int s = 0; s < SP; ++s) {
           const int p = lane + NT * s;
-          z[s] = p < cnt ? -q[w.P[p]] : 0.0;
+          if (p < cnt) { w.Yp[p] = z[s]; S.In[w.P[p]] = 1; }
         }
-        wide_fwd<SP>(w, cnt, z);
-        wide_bwd<SP>(w, cnt, z);
-        bool bad = false;
-#pragma unroll
-        for (int s = 0; s < SP; ++s) bad |= (lane + NT * s < cnt) && !(z[s] > 0.0);
-        ok = __ballot(bad) == 0ull;
-        if (ok) {
-#pragma unroll
-          for (int s = 0; s < SP; ++s) {
-            const int p = lane + NT * s;
-            if (p < cnt) { w.Yp[p] = z[s]; S.In[w.P[p]] = 1; }
-          }
-          np = cnt;
-        }
+        np = cnt;
+        __syncthreads();
+        break;
       }
+      int pidx[SP];
+      unsigned long long km[SP];
+#pragma unroll
+      for (int s = 0; s < SP; ++s) {
+        const int p = lane + NT * s;
+        pidx[s] = p < cnt ? w.P[p] : 0;
+        km[s] = __ballot(p < cnt && z[s] > 0.0);
+      }
+      __syncthreads();
+      int base = 0;
+#pragma unroll
+      for (int s = 0; s < SP; ++s) {
+        if ((km[s] >> (threadIdx.x & 63)) & 1ull) w.P[base + __popcll(km[s] & ((1ull << lane) - 1ull))] = pidx[s];
+        base += __popcll(km[s]);
+      }
+      cnt = base;
       __syncthreads();
     }
   }
@@ -1189,10 +1270,28 @@ __device__ int lcp_wide(const Src& src, LcpWideLds& S, const LcpWs& w, double* W
     // most violated inactive constraint: w_i = q_i + sum_a W(i, P_a) y_a
     double v = INFINITY;
     int t = 0x7fffffff;
-    for (int i = lane; i < m; i += NT) {
-      double wi = q[i];
-      for (int a = 0; a < np; ++a) wi += Wc[(int64_t)w.P[a] * cap + i] * w.Yp[a];
-      if (!S.In[i] && wi < -tolw && wi < v) { v = wi; t = i; }
+    for (int i0 = 0; i0 < m; i0 += 4 * NT) {   // 4 constraints per lane, loads in flight together
+      double wv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + lane + u * NT;
+        wv[u] = i < m ? q[i] : 0.0;
+      }
+#pragma unroll 2
+      for (int a = 0; a < np; ++a) {
+        const double ya = w.Yp[a];
+        const double* col = Wc + (int64_t)w.P[a] * cap;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = i0 + lane + u * NT;
+          if (i < m) wv[u] += col[i] * ya;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + lane + u * NT;
+        if (i < m && !S.In[i] && wv[u] < -tolw && wv[u] < v) { v = wv[u]; t = i; }
+      }
     }
     wave_argmin(v, t);
     if (!(v < INFINITY)) { done = true; break; }
@@ -1322,7 +1421,6 @@ __device__ int lcp_wide_any(const Src& src, LcpWideLds& S, double* Wc, int cap, 
 // phase 4 for robots with more than LCPM contacts
 __global__ void __launch_bounds__(NT) update_wide_kernel(Dev d, int it) {
   const int r = blockIdx.x;
-  const int lane = threadIdx.x;
   if (d.st_done[r]) return;
   const int nc = d.st_nc[r];
   if (nc <= LCPM) return;              // update_kernel
@@ -1335,7 +1433,7 @@ __global__ void __launch_bounds__(NT) update_wide_kernel(Dev d, int it) {
   double* qv = d.q + cb;
   double* y = d.ct_y + cb;
   double* Wc = d.W + (int64_t)r * cap * cap;
-  double* scratch = d.W + (int64_t)d.B * cap * cap + (int64_t)r * (cap * cap + 3 * cap);
+  double* scratch = d.W + (int64_t)d.B * cap * cap + (int64_t)r * lcp_ws_doubles(cap);
   contact_q(d, cb, nc, Zr, qv);
   __syncthreads();
   const RobotLcpSource src{&d, r, cb, Zr, ld};
@@ -1343,23 +1441,7 @@ __global__ void __launch_bounds__(NT) update_wide_kernel(Dev d, int it) {
     finish(d, r, 2, it, d.st_rn[r]);
     return;
   }
-  // active contacts in index order (the factor workspace is free again)
-  int* act = (int*)(scratch + nc);
-  double* ya = scratch;
-  int nact = 0;
-  for (int i0 = 0; i0 < nc; i0 += NT) {
-    const int i = i0 + lane;
-    const double yi = i < nc ? y[i] : 0.0;
-    const unsigned long long am = __ballot(yi > 0.0);
-    if (yi > 0.0) {
-      const int pos = nact + __popcll(am & ((1ull << lane) - 1ull));
-      act[pos] = i;
-      ya[pos] = yi;
-    }
-    nact += __popcll(am);
-  }
-  __syncthreads();
-  take_step(d, r, it, nc, nact, act, ya);
+  store_active(d, r, nc);
 }
 
 // fem_lcp: the LCP routines above on a given W (column-major, ld = m), one block
@@ -1423,6 +1505,8 @@ void launch_solve_phase(const Dev& d, int phase, int it, hipStream_t s) {
     default:
       hipLaunchKernelGGL(update_kernel, dim3(d.B), dim3(NT), 0, s, d, it);
       if (d.cap > LCPM) hipLaunchKernelGGL(update_wide_kernel, dim3(d.B), dim3(NT), 0, s, d, it);
+      hipLaunchKernelGGL(step_dx_kernel, dim3((unsigned)((d.Ntot + 255) / 256)), dim3(256), 0, s, d);
+      hipLaunchKernelGGL(step_apply_kernel, dim3((unsigned)((d.Ntot + 255) / 256)), dim3(256), 0, s, d, it);
       break;
   }
 }
