@@ -457,6 +457,8 @@ static fem_status create_impl(fem_ctx* c, const fem_params* p) {
   ALLOC(zoff_d, B);
   HIP_TRY(c, hipMemcpy(zoff_d, zoff.data(), B * sizeof(int64_t), hipMemcpyHostToDevice));
   d.zoff = zoff_d;
+  d.zp = ((int64_t)cap + 1 + 7) / 8 * 8;
+  ALLOC(d.Y, 6 * d.zp * N);
   ALLOC(d.Z, zt);
   ALLOC(d.W, (int64_t)B * cap * cap + (int64_t)B * lcp_ws_doubles(cap));
   ALLOC(d.q, BC);

@@ -96,9 +96,15 @@ struct Dev {
   double* cp_n;
   double* cp_gap;
   double* cp_y;
-  // solutions: robot r owns Z[zoff[r] .. zoff[r] + (1+cap)*6*N_r)
+  // solutions: robot r owns Z[zoff[r] .. zoff[r] + (1+cap)*6*N_r), column-major: column c
+  // (0 = the free increment, 1 + j = contact j) at zoff[r] + c*6*N_r, row 6 f + k of free node f
   const int64_t* zoff;
   double* Z;
+  // forward-swept values of every column, node-major: row 6 f + k of robot r is the zp
+  // doubles at Y + (6 off[r] + 6 f + k) * zp, one per column, so that a wavefront's columns
+  // are contiguous (column 0's right-hand side itself is written to Z's column 0)
+  double* Y;
+  int64_t zp;
   double* W;          // [B*cap*cap]
   double* q;          // [B*cap]
   int32_t* ac_idx;    // [B*cap] contacts with force > 0 after the LCP, in index order ...

@@ -29,7 +29,7 @@ constexpr int NT = SOLVE_THREADS;
 constexpr int CH = 16;                     // nodes per staged chunk
 constexpr int PF = (CH * 36 + NT - 1) / NT;  // prefetch registers per lane and array
 constexpr int CHF = 32;                    // nodes per staged chunk of the factorisation sweep
-constexpr int CHS = 8;                     // chunk of the substitution sweeps (register budget)
+constexpr int CHS = 6;                     // chunk of the substitution sweeps (register budget)
 constexpr int PFS = (CHS * 36 + NT - 1) / NT;
 
 __device__ __forceinline__ double warp_sum(double v) {
@@ -219,8 +219,6 @@ __global__ void __launch_bounds__(NT) check_rhs_kernel(Dev d, int it) {
 
   // ---------------------------------------------------------------- right-hand side
   double* Zr = d.Z + d.zoff[r];
-  const int64_t ld = 6 * n;             // column stride of Z
-  const int ncol = 1 + nc;
   const int64_t b0 = 0;                 // base node g = o
   const double bd[3] = {d.base_dir[3 * r], d.base_dir[3 * r + 1], d.base_dir[3 * r + 2]};
   double dx0[3];
@@ -228,8 +226,8 @@ __global__ void __launch_bounds__(NT) check_rhs_kernel(Dev d, int it) {
     const double dep = d.depth_cur[r];
     for (int k = 0; k < 3; ++k) dx0[k] = d.base_pos[3 * r + k] + dep * bd[k] - d.X[k * N + o + b0];
   }
-  // col 0 = -F over free DOFs.  The contact columns 1 + c (n_c at the contact node, zero
-  // elsewhere) are never stored: the forward sweeps generate them.
+  // col 0 = -F over free DOFs (Z's column 0).  The contact columns 1 + c (n_c at the contact
+  // node, zero elsewhere) are never stored: the forward sweeps generate them.
   for (int64_t f = lane; f < nf; f += NT) {
     const int64_t g = o + f + 1;
     for (int k = 0; k < 6; ++k) Zr[6 * f + k] = -d.F[k * N + g];
@@ -330,7 +328,9 @@ __global__ void __launch_bounds__(2 * NT) __attribute__((amdgpu_waves_per_eu(3))
   // wave 1: forward substitution of right-hand side `lane` (column c of Z)
   const int ncol = 1 + d.st_nc[r];
   const bool col = w == 1 && lane < ncol;
-  double* z = d.Z + d.zoff[r] + (int64_t)(col ? lane : 0) * (6 * n);
+  const int64_t zp = d.zp;
+  double* z = d.Y + 6 * o * zp + (col ? lane : 0);   // column `lane` of Y: row 6 j + q at z[(6j+q)*zp]
+  const double* z0 = d.Z + d.zoff[r];                // column 0's right-hand side (Z, contiguous)
   // column 0 is read from Z; contact column 1 + c is n_c at free node fc, zero elsewhere
   // (kept in LDS: registers live across the loop also count against wave 0's factorisation)
   __shared__ int32_t sFC[NT];
@@ -350,7 +350,7 @@ __global__ void __launch_bounds__(2 * NT) __attribute__((amdgpu_waves_per_eu(3))
   auto fwd_load = [&](int64_t j) {
     if (lane == 0) {
 #pragma unroll
-      for (int q = 0; q < 6; ++q) zn[q] = (col && j < nf) ? z[6 * j + q] : 0.0;
+      for (int q = 0; q < 6; ++q) zn[q] = (col && j < nf) ? z0[6 * j + q] : 0.0;
     } else {
       const bool here = j == (int64_t)sFC[lane];
       zn[0] = here ? sNC[lane] : 0.0; zn[1] = here ? sNC[NT + lane] : 0.0;
@@ -380,7 +380,7 @@ __global__ void __launch_bounds__(2 * NT) __attribute__((amdgpu_waves_per_eu(3))
     }
     if (col) {
 #pragma unroll
-      for (int q = 0; q < 6; ++q) z[6 * j + q] = yp[q];
+      for (int q = 0; q < 6; ++q) z[(6 * j + q) * zp] = yp[q];
     }
   };
   if (w == 1) fwd_load(0);
@@ -499,8 +499,11 @@ __global__ void __launch_bounds__(2 * NT) __attribute__((amdgpu_waves_per_eu(3))
 // those beyond the first NT, which phase 2 has already swept forward).
 // Block (r, p) takes columns p*NT .. p*NT + NT-1 of robot r's Z, one lane per column; every
 // lane sweeps the robot's nodes holding its column's whole 6-vector.  Per chunk of CHS nodes
-// the factor blocks (broadcast to all lanes) and the lanes' right-hand-side values are
-// staged through LDS, with the next chunk's loads in flight in registers meanwhile.
+// the factor blocks are staged through LDS (broadcast to all lanes), the next chunk's blocks
+// in flight in registers meanwhile; the lanes' own right-hand-side values are double-buffered
+// in registers (the block needs only the small LDS staging area, so many robots fit a CU).
+// The forward side lives in Y, node-major, so that the wavefront's loads of one row are one
+// contiguous segment; the backward solutions are written to Z column-major for the consumers.
 // Columns from NT on are contact columns (n_c at the contact node, zero elsewhere): their
 // forward sweep generates the right-hand side instead of reading it, and starts at the
 // chunk of the pass's first contact node (the solution is exactly zero above it).
@@ -517,79 +520,58 @@ __global__ void __launch_bounds__(NT) subst_kernel(Dev d) {
   double* Zr = d.Z + d.zoff[r];
   const int64_t ld = 6 * n;
   __shared__ double sKD[PFS * NT], sKS[PFS * NT];
-  __shared__ double sZ[CHS * 6 * NT];  // [u][k][lane]
-  {
-    const int c = c0 + lane;
-    const bool act = c < ncol;
-    double* z = Zr + (int64_t)(act ? c : 0) * ld;
-    const bool fwd_done = c0 == 0;       // the first NT columns were swept forward in phase 2
-    // contact of this lane's column (forward passes only): free node and normal
-    int64_t fcn = nf;
-    double cn0 = 0.0, cn1 = 0.0, cn2 = 0.0;
-    if (!fwd_done && act) {
-      const int64_t ci = (int64_t)r * d.cap + (c - 1);
-      fcn = d.ct_node[ci] - 1;
-      cn0 = d.ct_n[3 * ci]; cn1 = d.ct_n[3 * ci + 1]; cn2 = d.ct_n[3 * ci + 2];
+  const int c = c0 + lane;
+  const bool act = c < ncol;
+  double* z = Zr + (int64_t)(act ? c : 0) * ld;            // this column's solution (Z)
+  const int64_t zp = d.zp;
+  double* yv = d.Y + 6 * o * zp + (act ? c : 0);         // its forward side (Y, node-major)
+  const bool fwd_done = c0 == 0;         // the first NT columns were swept forward in phase 2
+  // contact of this lane's column (forward passes only): free node and normal
+  int64_t fcn = nf;
+  double cn0 = 0.0, cn1 = 0.0, cn2 = 0.0;
+  if (!fwd_done && act) {
+    const int64_t ci = (int64_t)r * d.cap + (c - 1);
+    fcn = d.ct_node[ci] - 1;
+    cn0 = d.ct_n[3 * ci]; cn1 = d.ct_n[3 * ci + 1]; cn2 = d.ct_n[3 * ci + 2];
+  }
+  double pd[PFS], ps[PFS];
+  auto stageK = [&]() {
+#pragma unroll
+    for (int u = 0; u < PFS; ++u) { sKD[lane + u * NT] = pd[u]; sKS[lane + u * NT] = ps[u]; }
+  };
+  // LD of nodes b0..b0+cnt-1 and LS of nodes s0..s0+cnt-1 (36 doubles each) into pd / ps
+  auto fetchK = [&](int64_t b0, int64_t s0, int64_t nodes) {
+    const int64_t cnt = nodes * 36;
+    const double* ldp = d.LD + (o + 1 + b0) * 36;
+    const double* lsp = d.LS + (o + 1 + s0) * 36;
+#pragma unroll
+    for (int u = 0; u < PFS; ++u) {
+      const int64_t idx = lane + (int64_t)u * NT;
+      pd[u] = idx < cnt ? ldp[idx] : 0.0;
+      ps[u] = idx < cnt ? lsp[idx] : 0.0;
     }
-    double pd[PFS], ps[PFS], pz[CHS * 6];
-    auto fetchZ = [&](int64_t f0, int64_t f1) {
-#pragma unroll
-      for (int u = 0; u < CHS; ++u)
-#pragma unroll
-        for (int k = 0; k < 6; ++k)
-          pz[u * 6 + k] = (act && f0 + u < f1 && f0 + u >= (fwd_done ? 0 : fcn)) ? z[6 * (f0 + u) + k] : 0.0;
-    };
-    auto genZ = [&](int64_t f0) {
-#pragma unroll
-      for (int u = 0; u < CHS; ++u) {
-        const bool here = f0 + u == fcn;
-        pz[u * 6 + 0] = here ? cn0 : 0.0;
-        pz[u * 6 + 1] = here ? cn1 : 0.0;
-        pz[u * 6 + 2] = here ? cn2 : 0.0;
-        pz[u * 6 + 3] = 0.0; pz[u * 6 + 4] = 0.0; pz[u * 6 + 5] = 0.0;
-      }
-    };
-    auto stage = [&]() {
-#pragma unroll
-      for (int u = 0; u < PFS; ++u) { sKD[lane + u * NT] = pd[u]; sKS[lane + u * NT] = ps[u]; }
-#pragma unroll
-      for (int q = 0; q < CHS * 6; ++q) sZ[q * NT + lane] = pz[q];
-    };
-    // forward sweep: chunk f0 needs LD of nodes f0..f1-1 and LS of nodes f0-1..f1-2
-    auto fetchF = [&](int64_t f0) {
-      const int64_t cnt = min((int64_t)CHS, nf - f0) * 36;
-      const double* ldp = d.LD + (o + 1 + f0) * 36;
-      const double* lsp = d.LS + (o + f0) * 36;          // node f0-1 (the base slot when f0 = 0)
-#pragma unroll
-      for (int u = 0; u < PFS; ++u) {
-        const int64_t idx = lane + (int64_t)u * NT;
-        pd[u] = idx < cnt ? ldp[idx] : 0.0;
-        ps[u] = idx < cnt ? lsp[idx] : 0.0;
-      }
-      genZ(f0);
-    };
+  };
+  // ---------------------------------------------------------------- forward (contact columns)
+  if (!fwd_done) {
     double yp[6] = {0, 0, 0, 0, 0, 0};   // previous block solution
-    int64_t fs = nf;
-    if (!fwd_done) {
-      int64_t m = fcn;
+    int64_t m = fcn;
 #pragma unroll
-      for (int sh = 32; sh > 0; sh >>= 1) m = min(m, (int64_t)__shfl_xor((long long)m, sh));
-      fs = (m / CHS) * CHS;
-      fetchF(fs);
-    }
-    for (int64_t f0 = fs; f0 < nf && !fwd_done; f0 += CHS) {
+    for (int sh = 32; sh > 0; sh >>= 1) m = min(m, (int64_t)__shfl_xor((long long)m, sh));
+    const int64_t fs = (m / CHS) * CHS;
+    // chunk f0 needs LD of nodes f0..f1-1 and LS of nodes f0-1..f1-2 (the base slot when f0 = 0)
+    fetchK(fs, fs - 1, min((int64_t)CHS, nf - fs));
+    for (int64_t f0 = fs; f0 < nf; f0 += CHS) {
       __syncthreads();
-      stage();
+      stageK();
       __syncthreads();
-      if (f0 + CHS < nf) fetchF(f0 + CHS);
+      if (f0 + CHS < nf) fetchK(f0 + CHS, f0 + CHS - 1, min((int64_t)CHS, nf - f0 - CHS));
       const int64_t f1 = min(nf, f0 + CHS);
 #pragma unroll
       for (int u = 0; u < CHS; ++u) {
         const int64_t f = f0 + u;
         if (f >= f1) break;
-        double bv[6];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) bv[k] = sZ[(u * 6 + k) * NT + lane];
+        const bool here = f == fcn;
+        double bv[6] = {here ? cn0 : 0.0, here ? cn1 : 0.0, here ? cn2 : 0.0, 0.0, 0.0, 0.0};
         if (f > 0) {
           const double* Ls = sKS + u * 36;                // L[f, f-1]
 #pragma unroll
@@ -607,60 +589,85 @@ __global__ void __launch_bounds__(NT) subst_kernel(Dev d) {
         }
         if (act && f >= fcn) {
 #pragma unroll
-          for (int k = 0; k < 6; ++k) z[6 * f + k] = yp[k];
+          for (int k = 0; k < 6; ++k) yv[(6 * f + k) * zp] = yp[k];
         }
       }
     }
-    // backward sweep over chunks from the tip: chunk [f0, f1) needs LD and LS of f0..f1-1
-    auto fetchB = [&](int64_t f0, int64_t f1) {
-      const int64_t cnt = (f1 - f0) * 36;
-      const double* ldp = d.LD + (o + 1 + f0) * 36;
-      const double* lsp = d.LS + (o + 1 + f0) * 36;
+  }
+  // ---------------------------------------------------------------- backward (all columns)
+  // chunk [f0, f1) needs LD and LS of nodes f0..f1-1; the column's values of the chunk come
+  // from Y (zero above the contact node of a forward-swept contact column); the solution
+  // goes to Z
+  const int64_t flo = fwd_done ? 0 : fcn;
+  double za[CHS * 6], zb[CHS * 6];
+  auto loadZ = [&](double (&zz)[CHS * 6], int64_t f0, int64_t f1) {
 #pragma unroll
-      for (int u = 0; u < PFS; ++u) {
-        const int64_t idx = lane + (int64_t)u * NT;
-        pd[u] = idx < cnt ? ldp[idx] : 0.0;
-        ps[u] = idx < cnt ? lsp[idx] : 0.0;
+    for (int u = 0; u < CHS; ++u)
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+        zz[u * 6 + k] = (act && f0 + u < f1 && f0 + u >= flo) ? yv[(6 * (f0 + u) + k) * zp] : 0.0;
+  };
+  double xn[6] = {0, 0, 0, 0, 0, 0};     // next block solution
+  auto bwd_chunk = [&](const double (&zz)[CHS * 6], int64_t f0, int64_t f1) {
+#pragma unroll
+    for (int u = CHS - 1; u >= 0; --u) {
+      const int64_t f = f0 + u;
+      if (f >= f1) continue;
+      double bv[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) bv[k] = zz[u * 6 + k];
+      if (f + 1 < nf) {
+        const double* Ls = sKS + u * 36;                  // L[f+1, f]; b -= L^T x_next
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+#pragma unroll
+          for (int p = 0; p < 6; ++p) bv[p] -= Ls[k * 6 + p] * xn[k];
       }
-      fetchZ(f0, f1);
-    };
-    double xn[6] = {0, 0, 0, 0, 0, 0};   // next block solution
-    const int64_t nch = (nf + CHS - 1) / CHS;
-    __syncthreads();                     // forward stores of this column precede the reloads
-    fetchB((nch - 1) * CHS, nf);
-    for (int64_t ch = nch - 1; ch >= 0; --ch) {
+      const double* Ld = sKD + u * 36;
+#pragma unroll
+      for (int k = 5; k >= 0; --k) {
+        const double x = bv[k] * Ld[k * 7];
+        xn[k] = x;
+#pragma unroll
+        for (int p = 0; p < k; ++p) bv[p] -= Ld[k * 6 + p] * x;
+      }
+      if (act) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) z[6 * f + k] = xn[k];
+      }
+    }
+  };
+  const int64_t nch = (nf + CHS - 1) / CHS;
+  __syncthreads();                       // forward stores of this column precede the reloads
+  {
+    const int64_t f0 = (nch - 1) * CHS;
+    fetchK(f0, f0, nf - f0);
+    loadZ(za, f0, nf);
+  }
+  // chunks from the tip, two per trip so that the two Z buffers keep fixed registers
+  for (int64_t ch = nch - 1; ch >= 0; ch -= 2) {
+    {
       const int64_t f0 = ch * CHS, f1 = min(nf, f0 + CHS);
       __syncthreads();
-      stage();
+      stageK();
       __syncthreads();
-      if (ch > 0) fetchB(f0 - CHS, f0);
-#pragma unroll
-      for (int u = CHS - 1; u >= 0; --u) {
-        const int64_t f = f0 + u;
-        if (f >= f1) continue;
-        double bv[6];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) bv[k] = sZ[(u * 6 + k) * NT + lane];
-        if (f + 1 < nf) {
-          const double* Ls = sKS + u * 36;                // L[f+1, f]; b -= L^T x_next
-#pragma unroll
-          for (int k = 0; k < 6; ++k)
-#pragma unroll
-            for (int p = 0; p < 6; ++p) bv[p] -= Ls[k * 6 + p] * xn[k];
-        }
-        const double* Ld = sKD + u * 36;
-#pragma unroll
-        for (int k = 5; k >= 0; --k) {
-          const double x = bv[k] * Ld[k * 7];
-          xn[k] = x;
-#pragma unroll
-          for (int p = 0; p < k; ++p) bv[p] -= Ld[k * 6 + p] * x;
-        }
-        if (act) {
-#pragma unroll
-          for (int k = 0; k < 6; ++k) z[6 * f + k] = xn[k];
-        }
+      if (ch > 0) {
+        fetchK(f0 - CHS, f0 - CHS, CHS);
+        loadZ(zb, f0 - CHS, f0);
       }
+      bwd_chunk(za, f0, f1);
+    }
+    if (ch == 0) break;
+    {
+      const int64_t f0 = (ch - 1) * CHS, f1 = f0 + CHS;
+      __syncthreads();
+      stageK();
+      __syncthreads();
+      if (ch > 1) {
+        fetchK(f0 - CHS, f0 - CHS, CHS);
+        loadZ(za, f0 - CHS, f0);
+      }
+      bwd_chunk(zb, f0, f1);
     }
   }
 }
