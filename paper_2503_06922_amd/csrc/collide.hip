@@ -104,19 +104,27 @@ __device__ __forceinline__ bool screen32(const Dev& d, int64_t t, P3<float> p, f
   return s >= -(float)d.r_c - slack && s <= band + slack;
 }
 
+// One group of CL lanes per node: lane j of the group takes entries j, j + CL, ... of the
+// node's cell list (consecutive entries to consecutive lanes), face contacts are appended
+// in ballot order, the fallback is the group's lexicographic minimum of (distance, triangle)
+// (the lowest triangle index among equally near ones, as a walk in list order finds), and
+// the group's first lane adds the persisting faces and orders the node's entries.
+constexpr int CL = 8;
+
 __global__ void __launch_bounds__(256) collide_kernel(Dev d) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t g = gt / CL;
+  const int j = (int)(gt % CL);
   if (g >= d.Ntot) return;
   const int r = d.robot_of[g];
   if (d.st_done[r]) return;
   const int64_t N = d.Ntot;
   const int64_t i = g - d.off[r];
-  int cnt = 0;
-  if (i == 0 || d.n_tris == 0) { d.CC[g] = 0; return; }
+  if (i == 0 || d.n_tris == 0) { if (j == 0) d.CC[g] = 0; return; }
   if (d.guide_axis[r] >= 0) {
     // reference arc length i*l0 + depth, without contraction (same decision as the solver)
     const double s = __dadd_rn(__dmul_rn((double)i, d.l0[r]), d.depth_cur[r]);
-    if (s < d.guide_len) { d.CC[g] = 0; return; }
+    if (s < d.guide_len) { if (j == 0) d.CC[g] = 0; return; }
   }
   P3<double> p{d.X[g], d.X[N + g], d.X[2 * N + g]};
   const double band = d.r_c + d.delta;
@@ -124,83 +132,90 @@ __global__ void __launch_bounds__(256) collide_kernel(Dev d) {
   int cy = (int)floor((p.y - d.g_org[1]) / d.g_h);
   int cz = (int)floor((p.z - d.g_org[2]) / d.g_h);
   if (cx < 0 || cy < 0 || cz < 0 || cx >= d.g_dim[0] || cy >= d.g_dim[1] || cz >= d.g_dim[2]) {
-    d.CC[g] = 0;
+    if (j == 0) d.CC[g] = 0;
     return;
   }
   const int64_t cell = ((int64_t)cz * d.g_dim[1] + cy) * d.g_dim[0] + cx;
   const int32_t b0 = d.cell_start[cell], b1 = d.cell_start[cell + 1];
+  const int gl = (int)(threadIdx.x & 63) & ~(CL - 1);      // first lane of the group
+  const unsigned long long gmask = ((1ull << CL) - 1ull) << gl;
+  const unsigned long long below = (1ull << (threadIdx.x & 63)) - 1ull;
+  int cnt = 0;
   int best_t = -1;
   double best_d = 0.0;
   P3<double> best_cp{0, 0, 0};
   P3<float> pf{(float)p.x, (float)p.y, (float)p.z};
   // FP32 screen allowance: coordinates ~1 m carry ~1e-7 m of rounding
   const float slack = 1e-5f;
-  // the cell list in batches of KB: the indices and the bounding spheres stored with them are
-  // loaded together (one memory round trip per batch), then tested in list order
-  constexpr int KB = 8;
-  for (int32_t k0 = b0; k0 < b1; k0 += KB) {
-    int32_t tk[KB];
-#pragma unroll
-    for (int j = 0; j < KB; ++j) tk[j] = (k0 + j < b1) ? d.cell_tris[k0 + j] : -1;
-    bool near[KB];
+  for (int32_t k0 = b0; k0 < b1; k0 += CL) {
+    const int32_t k = k0 + j;
+    const int32_t t = k < b1 ? d.cell_tris[k] : -1;
+    bool near;
     if (d.mixed) {
-      float4 S[KB];
-#pragma unroll
-      for (int j = 0; j < KB; ++j) S[j] = tk[j] >= 0 ? d.cell_sf[k0 + j] : make_float4(0.f, 0.f, 0.f, -1.f);
+      const float4 S = t >= 0 ? d.cell_sf[k] : make_float4(0.f, 0.f, 0.f, -1.f);
       const float bf = (float)band + slack;
-#pragma unroll
-      for (int j = 0; j < KB; ++j) {
-        const float sx = pf.x - S[j].x, sy = pf.y - S[j].y, sz = pf.z - S[j].z, rr = S[j].w + bf;
-        near[j] = tk[j] >= 0 && sx * sx + sy * sy + sz * sz <= rr * rr;
-      }
+      const float sx = pf.x - S.x, sy = pf.y - S.y, sz = pf.z - S.z, rr = S.w + bf;
+      near = t >= 0 && sx * sx + sy * sy + sz * sz <= rr * rr;
     } else {
-      double4 S[KB];
-#pragma unroll
-      for (int j = 0; j < KB; ++j) S[j] = tk[j] >= 0 ? d.cell_sd[k0 + j] : make_double4(0.0, 0.0, 0.0, -1.0);
-#pragma unroll
-      for (int j = 0; j < KB; ++j) {
-        const double sx = p.x - S[j].x, sy = p.y - S[j].y, sz = p.z - S[j].z;
-        const double rr = (S[j].w + band) * (1.0 + 1e-12);
-        near[j] = tk[j] >= 0 && sx * sx + sy * sy + sz * sz <= rr * rr;
-      }
+      const double4 S = t >= 0 ? d.cell_sd[k] : make_double4(0.0, 0.0, 0.0, -1.0);
+      const double sx = p.x - S.x, sy = p.y - S.y, sz = p.z - S.z;
+      const double rr = (S.w + band) * (1.0 + 1e-12);
+      near = t >= 0 && sx * sx + sy * sy + sz * sz <= rr * rr;
     }
-#pragma unroll
-    for (int j = 0; j < KB; ++j) {
-      if (!near[j]) continue;
-      const int64_t t = tk[j];
-      if (d.mixed && !screen32(d, t, pf, (float)band, slack)) continue;
-      TriTest tt = test_tri64(d, t, p);
+    if (near && d.mixed && !screen32(d, t, pf, (float)band, slack)) near = false;
+    bool face = false;
+    TriTest tt;
+    if (near) {
+      tt = test_tri64(d, t, p);
       if (tt.region == R_FACE) {
-        if (tt.s >= -d.r_c && tt.s <= band) {
-          if (cnt < MAXC) {
-            d.CT[cnt * N + g] = (int32_t)t;
-            d.CK[cnt * N + g] = 0;
-            d.CG[cnt * N + g] = tt.s - d.r_c;
-            d.CN[(3 * cnt + 0) * N + g] = tt.n.x;
-            d.CN[(3 * cnt + 1) * N + g] = tt.n.y;
-            d.CN[(3 * cnt + 2) * N + g] = tt.n.z;
-          }
-          ++cnt;
-        }
-      } else if (cnt == 0 && tt.s > 0.0 && tt.dist <= band) {
-        if (best_t < 0 || tt.dist < best_d) {  // cell lists are sorted: ties keep the lower index
+        face = tt.s >= -d.r_c && tt.s <= band;
+      } else if (tt.s > 0.0 && tt.dist <= band) {
+        if (best_t < 0 || tt.dist < best_d) {  // this lane's entries are in list order
           best_t = (int)t;
           best_d = tt.dist;
           best_cp = tt.cp;
         }
       }
     }
+    const unsigned long long fm = __ballot(face) & gmask;
+    if (face) {
+      const int pos = cnt + __popcll(fm & below);
+      if (pos < MAXC) {
+        d.CT[pos * N + g] = (int32_t)t;
+        d.CK[pos * N + g] = 0;
+        d.CG[pos * N + g] = tt.s - d.r_c;
+        d.CN[(3 * pos + 0) * N + g] = tt.n.x;
+        d.CN[(3 * pos + 1) * N + g] = tt.n.y;
+        d.CN[(3 * pos + 2) * N + g] = tt.n.z;
+      }
+    }
+    cnt += __popcll(fm);
   }
-  if (cnt == 0 && best_t >= 0) {
-    d.CT[g] = best_t;
-    d.CK[g] = 1;
-    d.CG[g] = best_d - d.r_c;
-    double inv = 1.0 / best_d;
-    d.CN[0 * N + g] = (p.x - best_cp.x) * inv;
-    d.CN[1 * N + g] = (p.y - best_cp.y) * inv;
-    d.CN[2 * N + g] = (p.z - best_cp.z) * inv;
-    cnt = 1;
+  if (cnt == 0) {
+    // the group's nearest edge/vertex candidate, ties to the lowest triangle index
+    double bd = best_t >= 0 ? best_d : INFINITY;
+    int bt = best_t >= 0 ? best_t : 0x7fffffff;
+#pragma unroll
+    for (int o = 1; o < CL; o <<= 1) {
+      const double od = __shfl_xor(bd, o);
+      const int ot = __shfl_xor(bt, o);
+      if (od < bd || (od == bd && ot < bt)) { bd = od; bt = ot; }
+    }
+    if (bt != 0x7fffffff) {
+      if (best_t == bt) {
+        d.CT[g] = bt;
+        d.CK[g] = 1;
+        d.CG[g] = best_d - d.r_c;
+        const double inv = 1.0 / best_d;
+        d.CN[0 * N + g] = (p.x - best_cp.x) * inv;
+        d.CN[1 * N + g] = (p.y - best_cp.y) * inv;
+        d.CN[2 * N + g] = (p.z - best_cp.z) * inv;
+      }
+      cnt = 1;
+    }
   }
+  __threadfence_block();                 // the group's entries precede the first lane's reads
+  if (j != 0) return;
   // persisting faces: the face contacts of this node that carried force in the previous
   // iterate and were not detected again stay as their plane while the node is within the
   // band of that triangle, unless a detected contact at the node lies on the same plane
@@ -303,7 +318,7 @@ __global__ void tri_setup_kernel(const double* V, const int32_t* tri, int64_t T,
 
 void launch_collide(const Dev& d, hipStream_t s) {
   const int T = 256;
-  const int64_t blocks = (d.Ntot + T - 1) / T;
+  const int64_t blocks = (d.Ntot * CL + T - 1) / T;
   hipLaunchKernelGGL(collide_kernel, dim3((unsigned)blocks), dim3(T), 0, s, d);
 }
 
