@@ -45,26 +45,31 @@ def algorithmic_bytes(info, n_nodes, sb, steps):
       factor_kernel per free node and Newton step: read the node's two elements (direction
                     3 x sb and 6 FP64 constants each; the left one is shared with the previous
                     node, so one element per node), write the Cholesky blocks L[i,i] (21 unique
-                    FP64) and L[i+1,i] (36 FP64); its second wavefront sweeps the right-hand
-                    sides forward: read b and write y, 2 x 6 FP64 per node and right-hand side
-      subst_kernel  per free node and Newton step: read L[i,i] and L[i+1,i] once for the
-                    backward sweep (57 FP64), and per right-hand side read y and write x
-                    (2 x 6 FP64); right-hand sides beyond the first 64 (more than 63 contacts,
-                    rare) also get their forward sweep here and are not counted
+                    FP64) and L[i+1,i] (36 FP64) and read column 0's right-hand side (6 FP64);
+                    its second wavefront sweeps the first 64 right-hand sides forward (the
+                    contact columns are generated, not read): write y, 6 FP64 per node and
+                    right-hand side
+      subst_kernel  per free node and pass of 64 right-hand sides: read L[i,i] and L[i+1,i]
+                    (57 FP64); per right-hand side read y and write x (2 x 6 FP64); those
+                    beyond the first 64 are also swept forward here (write y, 6 FP64)
     Returns {kernel: (bytes per unit, total bytes)}.
     """
     per = {"elem_kernel": 8 * (7 + 6) + 3 * sb,
-           "factor_kernel": (3 * sb + 8 * 6 + 8 * (21 + 36), 2 * 8 * 6),
-           "subst_kernel": (8 * 57, 2 * 8 * 6)}
+           "factor_kernel": (3 * sb + 8 * 6 + 8 * (21 + 36) + 8 * 6, 8 * 6),
+           "subst_kernel": (8 * 57, 2 * 8 * 6, 8 * 6)}
     elem_nodes = sum((i["iters_total"] + i["steps_total"]) * int(n_nodes[b]) for b, i in enumerate(info))
-    free_steps = sum(i["iters_total"] * (int(n_nodes[b]) - 1) for b, i in enumerate(info))
-    free_rhs = sum(i["rhs_total"] * (int(n_nodes[b]) - 1) for b, i in enumerate(info))
+    free = [int(n) - 1 for n in n_nodes]
+    free_steps = sum(i["iters_total"] * free[b] for b, i in enumerate(info))
+    free_rhs = sum(i["rhs_total"] * free[b] for b, i in enumerate(info))
+    free_fused = sum(i["rhs_fused"] * free[b] for b, i in enumerate(info))
+    free_passes = sum(i["sweep_passes"] * free[b] for b, i in enumerate(info))
     return {
         "elem_kernel": (per["elem_kernel"], per["elem_kernel"] * elem_nodes * steps),
         "factor_kernel": (per["factor_kernel"], (per["factor_kernel"][0] * free_steps
-                                                + per["factor_kernel"][1] * free_rhs) * steps),
-        "subst_kernel": (per["subst_kernel"], (per["subst_kernel"][0] * free_steps
-                                              + per["subst_kernel"][1] * free_rhs) * steps),
+                                                + per["factor_kernel"][1] * free_fused) * steps),
+        "subst_kernel": (per["subst_kernel"], (per["subst_kernel"][0] * free_passes
+                                              + per["subst_kernel"][1] * free_rhs
+                                              + per["subst_kernel"][2] * (free_rhs - free_fused)) * steps),
     }
 
 
@@ -174,6 +179,7 @@ def main():
 
     for _ in range(args.warmup):
         run_schedule(ctx, rb, args.load_steps, X0)
+        print("bench: warmup schedule done", file=sys.stderr, flush=True)
     # timed region: whole-batch insertions; each fem_solve returns after its stream synchronises
     ctx.fem_set_state(X0)  # resets the per-robot counters
     torch.cuda.synchronize()
@@ -182,6 +188,7 @@ def main():
         run_schedule(ctx, rb, args.load_steps, X0)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    print(f"bench: timed schedules done ({dt:.1f} s)", file=sys.stderr, flush=True)
     # counters cover the last schedule only (fem_set_state resets them): scale to all steps
     conv, total, iters, info = solves_of(ctx)
     solves = conv * args.steps
@@ -195,6 +202,7 @@ def main():
     cp.fem_set_lumen(V, T)
     cp.fem_set_actuation(0, np.zeros(3 * rb.n_robots), np.zeros(rb.n_robots))
     run_schedule(cp, rb, args.load_steps, X0)
+    print("bench: profiled schedule done", file=sys.stderr, flush=True)
     prof = [cp.fem_profile(k) for k in range(6)]
     _, _, _, info_p = solves_of(cp)
     cp.close()
@@ -243,6 +251,7 @@ def main():
         t1 = time.perf_counter()
         run_schedule(c64, rb, args.load_steps, X0)
         t64 = time.perf_counter() - t1
+        print(f"bench: FP64 schedule done ({t64:.1f} s)", file=sys.stderr, flush=True)
         conv64, _, _, info64 = solves_of(c64)
         Xm = ctx.fem_get_state()
         X64 = c64.fem_get_state()

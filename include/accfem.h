@@ -114,6 +114,9 @@ typedef struct {
   int32_t steps_total;      /* load steps since fem_create / fem_set_state */
   int64_t iters_total;      /* Newton iterations since fem_create / fem_set_state */
   int64_t rhs_total;        /* right-hand sides solved (1 + contacts per Newton step), same span */
+  int64_t rhs_fused;        /* of those, swept forward inside the factorisation (the first 64
+                               of each Newton step), same span */
+  int64_t sweep_passes;     /* substitution passes of 64 right-hand sides, same span */
 } fem_solve_info;
 
 typedef struct {

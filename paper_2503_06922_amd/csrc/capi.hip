@@ -465,7 +465,7 @@ static fem_status create_impl(fem_ctx* c, const fem_params* p) {
   ALLOC(d.ac_idx, BC); ALLOC(d.ac_y, BC);
   ALLOC(d.st_nact, B); ALLOC(d.st_mx, B);
   ALLOC(d.st_status, B); ALLOC(d.st_done, B); ALLOC(d.st_nc, B); ALLOC(d.st_ncp, B);
-  ALLOC(d.st_limited, B); ALLOC(d.st_nlim, B); ALLOC(d.st_nswitch, B); ALLOC(d.st_iters, B); ALLOC(d.st_rhs, B);
+  ALLOC(d.st_limited, B); ALLOC(d.st_nlim, B); ALLOC(d.st_nswitch, B); ALLOC(d.st_iters, B); ALLOC(d.st_rhs, 3 * B);
   ALLOC(d.st_rn, B); ALLOC(d.st_rnprev, B); ALLOC(d.n_done, 1);
   HIP_TRY(c, hipMemset(d.st_status, 0, B * sizeof(int32_t)));
   HIP_TRY(c, hipMemset(d.st_done, 0, B * sizeof(int32_t)));
@@ -473,7 +473,7 @@ static fem_status create_impl(fem_ctx* c, const fem_params* p) {
   HIP_TRY(c, hipMemset(d.st_ncp, 0, B * sizeof(int32_t)));
   HIP_TRY(c, hipMemset(d.st_nlim, 0, B * sizeof(int32_t)));
   HIP_TRY(c, hipMemset(d.st_iters, 0, B * sizeof(int32_t)));
-  HIP_TRY(c, hipMemset(d.st_rhs, 0, B * sizeof(int64_t)));
+  HIP_TRY(c, hipMemset(d.st_rhs, 0, 3 * B * sizeof(int64_t)));
   HIP_TRY(c, hipMemset(d.st_rn, 0, B * sizeof(double)));
   ALLOC(c->steps_conv, B); ALLOC(c->steps_tot, B); ALLOC(c->iters_tot, B);
   HIP_TRY(c, hipMemset(c->steps_conv, 0, B * sizeof(int32_t)));
@@ -668,7 +668,7 @@ fem_status fem_set_state(fem_ctx* c, const double* node_state) {
   HIP_TRY(c, hipMemsetAsync(c->steps_conv, 0, c->B * sizeof(int32_t), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->steps_tot, 0, c->B * sizeof(int32_t), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->iters_tot, 0, c->B * sizeof(int64_t), c->stream));
-  HIP_TRY(c, hipMemsetAsync(c->d.st_rhs, 0, c->B * sizeof(int64_t), c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d.st_rhs, 0, 3 * c->B * sizeof(int64_t), c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->solved = false;
   return FEM_OK;
@@ -727,14 +727,16 @@ fem_status fem_solve(fem_ctx* c, int32_t n_load_steps, double* node_state, fem_s
     HIP_TRY(c, hipMemcpy(sc.data(), c->steps_conv, B * sizeof(int32_t), hipMemcpyDeviceToHost));
     HIP_TRY(c, hipMemcpy(stt.data(), c->steps_tot, B * sizeof(int32_t), hipMemcpyDeviceToHost));
     HIP_TRY(c, hipMemcpy(itt.data(), c->iters_tot, B * sizeof(int64_t), hipMemcpyDeviceToHost));
-    std::vector<int64_t> rhs(B);
-    HIP_TRY(c, hipMemcpy(rhs.data(), d.st_rhs, B * sizeof(int64_t), hipMemcpyDeviceToHost));
+    std::vector<int64_t> rhs(3 * B);
+    HIP_TRY(c, hipMemcpy(rhs.data(), d.st_rhs, 3 * B * sizeof(int64_t), hipMemcpyDeviceToHost));
     std::vector<fem_solve_info> hi(B);
     for (int r = 0; r < B; ++r) {
       hi[r].status = st[r]; hi[r].iters = it[r]; hi[r].n_contacts = nc[r]; hi[r].n_limited = nl[r];
       hi[r].res_norm = rn[r]; hi[r].steps_converged = sc[r]; hi[r].steps_total = stt[r];
       hi[r].iters_total = itt[r];
-      hi[r].rhs_total = rhs[r];
+      hi[r].rhs_total = rhs[3 * r];
+      hi[r].rhs_fused = rhs[3 * r + 1];
+      hi[r].sweep_passes = rhs[3 * r + 2];
     }
     if (c->io_dev) {
       HIP_TRY(c, hipMemcpy(info, hi.data(), B * sizeof(fem_solve_info), hipMemcpyHostToDevice));

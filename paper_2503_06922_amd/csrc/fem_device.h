@@ -120,7 +120,8 @@ struct Dev {
   int32_t* st_iters;
   int32_t* st_nact;     // active contacts of the current step
   unsigned long long* st_mx;  // largest node translation of the step (bits of a double >= 0)
-  int64_t* st_rhs;      // right-hand sides solved since creation / the last state reset
+  int64_t* st_rhs;      // [3B] right-hand sides, those swept forward in the factorisation, and
+                        // substitution passes, since creation / the last state reset
   double* st_rn;        // residual norm at the last check
   double* st_rnprev;
   int32_t* n_done;      // [1] robots finished in this load step

@@ -215,7 +215,11 @@ __global__ void __launch_bounds__(NT) check_rhs_kernel(Dev d, int it) {
     }
   }
   __syncthreads();
-  if (lane == 0) d.st_rhs[r] += 1 + nc;
+  if (lane == 0) {
+    d.st_rhs[3 * r] += 1 + nc;                      // right-hand sides
+    d.st_rhs[3 * r + 1] += min(1 + nc, NT);         // forward-swept inside the factorisation
+    d.st_rhs[3 * r + 2] += (1 + nc + NT - 1) / NT;  // column passes of the substitution
+  }
 
   // ---------------------------------------------------------------- right-hand side
   double* Zr = d.Z + d.zoff[r];
