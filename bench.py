@@ -107,6 +107,42 @@ def solves_of(ctx):
             sum(i["iters_total"] for i in info), info)
 
 
+def config2(max_newton, capacity):
+    """The 1000-element robot inserted into the 200k-triangle lumen over 100 load steps, in
+    mixed precision and in FP64 (one context each): solves/s, converged load steps, Newton
+    iterations and the mixed path's relative tip error against the FP64 one per load step."""
+    from paper_2503_06922_amd import fem
+    from workloads import make_config, load_schedule
+    rb, V, T = make_config(2)
+    out = {"workload": "1 robot x %d load steps, %d elements, %dk-triangle branching lumen"
+                       % (rb.n_load_steps, int(rb.n_elem[0]), round(T.shape[0] / 1000))}
+    tips = {}
+    for name, prec in (("mixed", fem.FEM_MIXED), ("fp64", fem.FEM_FP64)):
+        ctx = fem.Context(fem.params_from_batch(rb, precision=prec, newton_tol=1e-10, stag_tol=1e-9,
+                                                max_newton=max_newton, contact_capacity=capacity))
+        ctx.fem_set_lumen(V, T)
+        ctx.fem_set_actuation(0, np.zeros(3), np.zeros(1))
+        tip, t_solve = [], 0.0
+        for k in range(1, rb.n_load_steps + 1):
+            d, t = load_schedule(rb, k)
+            ctx.fem_set_actuation(0, t.ravel(), d)
+            t0 = time.perf_counter()
+            o = ctx.fem_solve(1, state=True, info=True)
+            t_solve += time.perf_counter() - t0
+            tip.append((o["state"][-1, 0:3].copy(), o["info"][0]["status"]))
+        conv, total, iters, _ = solves_of(ctx)
+        ctx.close()
+        tips[name] = tip
+        out[name] = {"solves_per_s": conv / t_solve, "converged": conv, "load_steps": total,
+                     "newton_iters_per_solve": iters / max(total, 1)}
+    e = [np.linalg.norm(a[0] - b[0]) / rb.length[0]
+         for a, b in zip(tips["mixed"], tips["fp64"]) if a[1] == 0 and b[1] == 0]
+    out["tip_err_mixed_vs_fp64"] = {"max": float(max(e)) if e else None,
+                                    "median": float(np.median(e)) if e else None,
+                                    "load_steps_compared": len(e)}
+    return out
+
+
 def cpu_baseline(rb, V, T, n_robots, n_steps):
     """The FP64 oracle on a bounded sample: n_robots robots x n_steps load steps."""
     from oracle import solver, collision
@@ -147,6 +183,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-config2", action="store_true",
+                    help="skip the 1000-element robot on the 200k-triangle lumen")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
@@ -285,6 +323,9 @@ def main():
             c1.close()
         res["fp64_single_solves_per_s"] = conv_single / t_single
         res["ratio_vs_fp64_single"] = value / res["fp64_single_solves_per_s"]
+    if not args.no_config2:
+        res["config2"] = config2(args.max_newton, args.capacity)
+        print("bench: 1000-element robot done", file=sys.stderr, flush=True)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(rb, V, T, args.cpu_robots, args.cpu_steps)
     print(json.dumps(res), flush=True)
