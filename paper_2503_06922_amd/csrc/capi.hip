@@ -443,11 +443,11 @@ static fem_status create_impl(fem_ctx* c, const fem_params* p) {
   c->kc = kc;
   ALLOC(d.LD, 36 * N); ALLOC(d.LS, 36 * N);
   ALLOC(d.CC, N); ALLOC(d.CT, MAXC * N); ALLOC(d.CK, MAXC * N); ALLOC(d.CN, 3 * MAXC * N);
-  ALLOC(d.CG, MAXC * N);
+  ALLOC(d.CG, MAXC * N); ALLOC(d.CW, MAXC * N);
   HIP_TRY(c, hipMemset(d.CC, 0, N * sizeof(int32_t)));
   const int64_t BC = (int64_t)B * cap;
   ALLOC(d.ct_node, BC); ALLOC(d.ct_tri, BC); ALLOC(d.ct_kind, BC); ALLOC(d.ct_n, 3 * BC);
-  ALLOC(d.ct_gap, BC); ALLOC(d.ct_y, BC);
+  ALLOC(d.ct_gap, BC); ALLOC(d.ct_y, BC); ALLOC(d.ct_warm, BC);
   ALLOC(d.cp_node, BC); ALLOC(d.cp_tri, BC); ALLOC(d.cp_kind, BC); ALLOC(d.cp_n, 3 * BC);
   ALLOC(d.cp_gap, BC); ALLOC(d.cp_y, BC);
   std::vector<int64_t> zoff(B);

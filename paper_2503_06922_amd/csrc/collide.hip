@@ -13,6 +13,8 @@
 //                   not detected again stays as its plane while the node is within
 //                   r_c + delta of the triangle, unless a detected contact at the node
 //                   has the same plane (normals and gaps within PLANE_TOL)
+// Every entry also carries whether it had force > 0 at the previous iterate (detected
+// again with the same triangle and kind, or persisting): the LCP starts from those.
 // The base node and nodes held by the insertion guide are skipped.  Results are
 // written per node (up to MAXC, ordered by kind then triangle index) and compacted
 // per robot by the gather step of the solver.
@@ -183,6 +185,7 @@ __global__ void __launch_bounds__(256) collide_kernel(Dev d) {
       if (pos < MAXC) {
         d.CT[pos * N + g] = (int32_t)t;
         d.CK[pos * N + g] = 0;
+        d.CW[pos * N + g] = 0;
         d.CG[pos * N + g] = tt.s - d.r_c;
         d.CN[(3 * pos + 0) * N + g] = tt.n.x;
         d.CN[(3 * pos + 1) * N + g] = tt.n.y;
@@ -205,6 +208,7 @@ __global__ void __launch_bounds__(256) collide_kernel(Dev d) {
       if (best_t == bt) {
         d.CT[g] = bt;
         d.CK[g] = 1;
+        d.CW[g] = 0;
         d.CG[g] = best_d - d.r_c;
         const double inv = 1.0 / best_d;
         d.CN[0 * N + g] = (p.x - best_cp.x) * inv;
@@ -228,14 +232,18 @@ __global__ void __launch_bounds__(256) collide_kernel(Dev d) {
     if (d.cp_node[cb + mid] < i) lo = mid + 1; else hi = mid;
   }
   for (int c = lo; c < ncp && d.cp_node[cb + c] == i; ++c) {
-    if (!(d.cp_y[cb + c] > 0.0) || d.cp_kind[cb + c] != 0) continue;
+    if (!(d.cp_y[cb + c] > 0.0)) continue;
     const int32_t t = d.cp_tri[cb + c];
-    bool skip = false;
-    for (int q = 0; q < ndet; ++q) skip |= (d.CK[q * N + g] == 0 && d.CT[q * N + g] == t);
-    if (skip) continue;
+    const int32_t kc = d.cp_kind[cb + c];
+    // detected again: it starts the LCP's active set
+    bool found = false;
+    for (int q = 0; q < ndet; ++q)
+      if (d.CK[q * N + g] == kc && d.CT[q * N + g] == t) { d.CW[q * N + g] = 1; found = true; }
+    if (found || kc != 0) continue;
     const TriTest tt = test_tri64(d, t, p);
     if (!(tt.dist <= band)) continue;
     const double gap = tt.s - d.r_c;
+    bool skip = false;
     for (int q = 0; q < ndet; ++q) {
       const double nn = tt.n.x * d.CN[(3 * q) * N + g] + tt.n.y * d.CN[(3 * q + 1) * N + g] +
                         tt.n.z * d.CN[(3 * q + 2) * N + g];
@@ -245,6 +253,7 @@ __global__ void __launch_bounds__(256) collide_kernel(Dev d) {
     if (cnt < MAXC) {
       d.CT[cnt * N + g] = t;
       d.CK[cnt * N + g] = 0;
+      d.CW[cnt * N + g] = 1;
       d.CG[cnt * N + g] = gap;
       d.CN[(3 * cnt + 0) * N + g] = tt.n.x;
       d.CN[(3 * cnt + 1) * N + g] = tt.n.y;
@@ -255,19 +264,21 @@ __global__ void __launch_bounds__(256) collide_kernel(Dev d) {
   // order the node's entries by (kind, triangle): insertion sort of at most MAXC
   const int nst = min(cnt, MAXC);
   for (int a = 1; a < nst; ++a) {
-    const int32_t ta = d.CT[a * N + g], ka = d.CK[a * N + g];
+    const int32_t ta = d.CT[a * N + g], ka = d.CK[a * N + g], wa = d.CW[a * N + g];
     const double ga = d.CG[a * N + g], n0 = d.CN[(3 * a) * N + g], n1 = d.CN[(3 * a + 1) * N + g],
                  n2 = d.CN[(3 * a + 2) * N + g];
     int b = a - 1;
     while (b >= 0 && (d.CK[b * N + g] > ka || (d.CK[b * N + g] == ka && d.CT[b * N + g] > ta))) {
       d.CT[(b + 1) * N + g] = d.CT[b * N + g];
       d.CK[(b + 1) * N + g] = d.CK[b * N + g];
+      d.CW[(b + 1) * N + g] = d.CW[b * N + g];
       d.CG[(b + 1) * N + g] = d.CG[b * N + g];
       for (int k = 0; k < 3; ++k) d.CN[(3 * (b + 1) + k) * N + g] = d.CN[(3 * b + k) * N + g];
       --b;
     }
     d.CT[(b + 1) * N + g] = ta;
     d.CK[(b + 1) * N + g] = ka;
+    d.CW[(b + 1) * N + g] = wa;
     d.CG[(b + 1) * N + g] = ga;
     d.CN[(3 * (b + 1)) * N + g] = n0;
     d.CN[(3 * (b + 1) + 1) * N + g] = n1;

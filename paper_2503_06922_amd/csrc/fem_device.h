@@ -83,6 +83,7 @@ struct Dev {
   int32_t* CK;
   double* CN;
   double* CG;
+  int32_t* CW;          // entry carried force at the previous iterate (warm start of the LCP)
   // per robot contact lists (current and previous), capacity cap each
   int32_t* ct_node;   // [B*cap]
   int32_t* ct_tri;
@@ -90,6 +91,7 @@ struct Dev {
   double* ct_n;       // [B*cap*3]
   double* ct_gap;
   double* ct_y;
+  int32_t* ct_warm;     // contact carried force at the previous iterate
   int32_t* cp_node;
   int32_t* cp_tri;
   int32_t* cp_kind;

@@ -112,6 +112,7 @@ __device__ void gather_contacts(const Dev& d, int r, int* nc_out, bool* overflow
         d.ct_node[base + pos] = (int32_t)i;
         d.ct_tri[base + pos] = d.CT[s * N + g];
         d.ct_kind[base + pos] = d.CK[s * N + g];
+        d.ct_warm[base + pos] = d.CW[s * N + g];
         d.ct_gap[base + pos] = d.CG[s * N + g];
         d.ct_n[3 * (base + pos) + 0] = d.CN[(3 * s + 0) * N + g];
         d.ct_n[3 * (base + pos) + 1] = d.CN[(3 * s + 1) * N + g];
@@ -848,21 +849,6 @@ __device__ bool lcp_parallel(LcpLds& S, const double* q, int m, bool warm, doubl
   return true;
 }
 
-// true when contact i of robot r (node, triangle, kind) carried force at the previous iterate
-__device__ bool prev_active(const Dev& d, int r, int64_t cb, int i) {
-  const int ncp = d.st_ncp[r];
-  const int nd = d.ct_node[cb + i], tr = d.ct_tri[cb + i], kd = d.ct_kind[cb + i];
-  int lo = 0, hi = ncp;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (d.cp_node[cb + mid] < nd) lo = mid + 1; else hi = mid;
-  }
-  bool w = false;
-  for (int c = lo; c < ncp && d.cp_node[cb + c] == nd; ++c)
-    w |= (d.cp_tri[cb + c] == tr && d.cp_kind[cb + c] == kd && d.cp_y[cb + c] > 0.0);
-  return w;
-}
-
 // q_c = gap_c + n_c . dx_free(node of c) for the nc contacts of robot r
 __device__ void contact_q(const Dev& d, int64_t cb, int nc, const double* Zr, double* qv) {
   for (int a = threadIdx.x; a < nc; a += NT) {
@@ -1041,12 +1027,12 @@ __global__ void __launch_bounds__(NT) update_kernel(Dev d, int it) {
     const int64_t f = d.ct_node[cb + lane] - 1;
     const double n0 = d.ct_n[3 * (cb + lane)], n1 = d.ct_n[3 * (cb + lane) + 1],
                  n2 = d.ct_n[3 * (cb + lane) + 2];
-#pragma unroll 4
+#pragma unroll 8
     for (int b = 0; b <= lane; ++b) {
       const double* zb = Zr + (int64_t)(1 + b) * ld + 6 * f;
       S.W[pk(lane, b)] = n0 * zb[0] + n1 * zb[1] + n2 * zb[2];
     }
-    warm = prev_active(d, r, cb, lane);
+    warm = d.ct_warm[cb + lane] != 0;
   }
   __syncthreads();
   double yl = 0.0;
@@ -1114,12 +1100,31 @@ struct RobotLcpSource {
     if (threadIdx.x == 0) S.Val[t] = 1;
     __syncthreads();
   }
-  __device__ bool warm(int i) const { return prev_active(*d, r, cb, i); }
+  __device__ bool warm(int i) const { return d->ct_warm[cb + i] != 0; }
+  // the columns of the listed constraints, computed together (one barrier)
+  __device__ void columns(LcpWideLds& S, double* Wc, int cap, int m, const int* list, int cnt) const {
+#pragma unroll 2
+    for (int a = 0; a < cnt; ++a) {
+      const int t = list[a];
+      if (S.Val[t]) continue;
+      const double* zt = Zr + (int64_t)(1 + t) * ld;
+      double* wt = Wc + (int64_t)t * cap;
+      for (int i = threadIdx.x; i < m; i += NT) {
+        const int64_t f = d->ct_node[cb + i] - 1;
+        wt[i] = d->ct_n[3 * (cb + i)] * zt[6 * f] + d->ct_n[3 * (cb + i) + 1] * zt[6 * f + 1] +
+                d->ct_n[3 * (cb + i) + 2] * zt[6 * f + 2];
+      }
+    }
+    __syncthreads();
+    for (int a = threadIdx.x; a < cnt; a += NT) S.Val[list[a]] = 1;
+    __syncthreads();
+  }
 };
 
 // a given dense W (column-major, ld = cap), no warm start
 struct DenseLcpSource {
   __device__ void column(LcpWideLds&, double*, int, int, int) const {}
+  __device__ void columns(LcpWideLds&, double*, int, int, const int*, int) const {}
   __device__ bool warm(int) const { return false; }
 };
 
@@ -1232,7 +1237,7 @@ __device__ int lcp_wide(const Src& src, LcpWideLds& S, const LcpWs& w, double* W
     }
     __syncthreads();
     if (cnt > w.npmax) cnt = 0;
-    for (int a = 0; a < cnt; ++a) src.column(S, Wc, cap, m, w.P[a]);
+    src.columns(S, Wc, cap, m, w.P, cnt);
     // solve on the set, drop the constraints whose y is not positive, solve again
     while (cnt > 0) {
       if (!wide_factor<SP>(w, Wc, cap, cnt)) break;
