@@ -299,47 +299,69 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
   return y;
 }
 
-// phase 2: block-tridiagonal Cholesky of the QP tangent, with the forward substitution of
-// the first NT right-hand sides running one node behind it.
-// Wave 0 factors, serially over the robot's nodes; per node, lane L < 36 owns entry
-// (a, b) = (L / 6, L % 6):
-//   per chunk of CHF nodes, lane u generates node u's blocks D_i and S_i = K[i, i+1] from
-//   the chord directions and constants of its two elements (prefetched into registers
-//   during the previous chunk) and stages them in LDS;
-//   A = D_i - X_prev X_prev^T   (X_prev = L[f, f-1]; row a kept in registers, row b read from LDS)
+// phase 2: block-tridiagonal Cholesky of the QP tangent, eliminated from both ends, with the
+// forward substitution of the first NT right-hand sides running one node behind it.
+// The free nodes 0 .. m-1 are eliminated from the base and nf-1 .. m+1 from the tip
+// (m = nf / 2), the middle node m last: the Cholesky factorisation K = L L^T in the node
+// order 0, 1, .., m-1, nf-1, .., m+1, m, whose serial chain is half as long.
+// Four wavefronts per robot: per side, one factors and one sweeps forward.  The factoring
+// wave takes one node per step; per node, lane L < 36 owns entry (a, b) = (L / 6, L % 6):
+//   per chunk of CHF steps, lane u generates step u's blocks D_i and the coupling C = K[i, next]
+//   to the node eliminated next on its side (i+1 from the base, i-1 from the tip) from the
+//   chord directions and constants of the node's two elements (prefetched into registers during
+//   the previous chunk) and stages them in LDS;
+//   A = D_i - X_prev X_prev^T  (X_prev = the previous step's coupling block; row a kept in
+//   registers, row b read from LDS)
 //   every lane reads A's lower triangle from LDS and factors it in registers (right-looking,
-//   reciprocal square roots only), L[f, f] = chol(A);  row a of X = L[f+1, f] solves
-//   L x = S_i[:, a].
-// Rows/columns of prescribed DOFs are replaced by the identity.  L[f, f] is stored with the
-// reciprocal of its diagonal.  Wave 0 also puts L[f, f] and L[f+1, f] into small LDS rings;
-// between the same two barriers of node f, wave 1 (one lane per right-hand side) takes node
-// f-1 of the forward sweep, y = L[f-1, f-1]^-1 (b - L[f-1, f-2] y_prev), from the rings; it
-// reads b of column 0 from Z and generates the contact columns (n_c at the contact node).
-__global__ void __launch_bounds__(2 * NT) __attribute__((amdgpu_waves_per_eu(3))) factor_kernel(Dev d, int it) {
+//   reciprocal square roots only), L_ii = chol(A);  row a of X = L[next, i] solves L_ii x = C[:, a].
+// LD holds L_ii with the reciprocal of its diagonal, LS the block X of every node but the
+// middle one (its coupling towards the middle).  The middle node's pivot block takes both
+// sides' Schur complements, A_m = D_m - X_top X_top^T - X_bot X_bot^T.  Rows and columns of
+// prescribed DOFs are replaced by the identity.  Both sides take the same number of steps
+// (the shorter idles) so that the barriers match.
+// The factoring wave also puts L_ii and X into small LDS rings; between the same two barriers
+// of step k, its side's forward wave (one lane per right-hand side) takes step k-1,
+// y = L_ii^-1 (b - X_prev y_prev), from the rings, reading b of column 0 from Z and generating
+// the contact columns (n_c at the contact node), and writes y to Y.  At the middle node the
+// forward values of both sides meet: z_m = L_m^-1 (b_m - X_top y_top - X_bot y_bot), and the
+// middle node's solution x_m = L_m^-T z_m goes to Z, where the substitution starts both sides'
+// backward sweeps.
+__global__ void __launch_bounds__(4 * NT) __attribute__((amdgpu_waves_per_eu(3))) factor_kernel(Dev d, int it) {
   const int r = blockIdx.x;
   const int w = threadIdx.x / NT, lane = threadIdx.x % NT;
+  const int sd = w >> 1;                      // side: 0 from the base, 1 from the tip
+  const bool fw = (w & 1) != 0;               // the side's forward-substitution wave
   if (d.st_done[r]) return;
   const int64_t o = d.off[r], n = d.off[r + 1] - o;
   const int64_t nf = n - 1;
   const Guide G = make_guide(d, r, n);
-  __shared__ double sKD[CHF * 36], sKS[CHF * 36];
-  __shared__ double sA[36], sX[36];
-  __shared__ double rD[2][36], rS[3][36];     // L[f, f] by f % 2, L[f+1, f] by f % 3
+  const int64_t m = nf / 2;                   // the middle free node
+  const int64_t cnt = (sd == 0) ? m : nf - 1 - m;   // this side's eliminations before the middle
+  const int64_t K = m;                        // steps (the tip side has m or m - 1)
+  __shared__ double sKD[2][CHF * 36], sKS[2][CHF * 36];
+  __shared__ double sA[2][36], sX[2][36];
+  __shared__ double rD[2][2][36], rS[2][3][36];   // L_ii by step % 2, X by step % 3, per side
+  __shared__ int32_t sFC[NT];
+  __shared__ double sNC[3 * NT];
+  __shared__ double sYB[6 * NT];              // the tip side's last forward values
+  __shared__ double sLm[36];
+  __shared__ int s_fail;
   const int la = lane < 36 ? lane : 35;       // lanes 36..63 mirror lane 35 (results unused)
   const int a = la / 6, b = la % 6;
-  double Xa[6] = {0, 0, 0, 0, 0, 0};          // row a of L[f, f-1]
-  if (w == 0 && lane < 36) sX[lane] = 0.0;
+  double Xa[6] = {0, 0, 0, 0, 0, 0};          // row a of X_prev
+  if (!fw && lane < 36) sX[sd][lane] = 0.0;
+  if (threadIdx.x == 0) s_fail = 0;
   bool fail = false;
-  // wave 1: forward substitution of right-hand side `lane` (column c of Z)
+  // free index of this side's k-th elimination; node i = f + 1 has elements o+f and o+f+1
+  auto fidx = [&](int64_t k) { return sd == 0 ? k : nf - 1 - k; };
+  // forward waves: right-hand side `lane` (column c); column 0 is read from Z, contact column
+  // 1 + c is n_c at free node fc, zero elsewhere (kept in LDS: registers live across the loop
+  // also count against the factoring waves)
   const int ncol = 1 + d.st_nc[r];
-  const bool col = w == 1 && lane < ncol;
+  const bool col = fw && lane < ncol;
   const int64_t zp = d.zp;
   double* z = d.Y + 6 * o * zp + (col ? lane : 0);   // column `lane` of Y: row 6 j + q at z[(6j+q)*zp]
   const double* z0 = d.Z + d.zoff[r];                // column 0's right-hand side (Z, contiguous)
-  // column 0 is read from Z; contact column 1 + c is n_c at free node fc, zero elsewhere
-  // (kept in LDS: registers live across the loop also count against wave 0's factorisation)
-  __shared__ int32_t sFC[NT];
-  __shared__ double sNC[3 * NT];
   if (w == 1) {
     int32_t fc = -1;
     double n0 = 0.0, n1 = 0.0, n2 = 0.0;
@@ -351,31 +373,41 @@ __global__ void __launch_bounds__(2 * NT) __attribute__((amdgpu_waves_per_eu(3))
     sFC[lane] = fc;
     sNC[lane] = n0; sNC[NT + lane] = n1; sNC[2 * NT + lane] = n2;
   }
+  __syncthreads();
   double yp[6] = {0, 0, 0, 0, 0, 0}, zn[6] = {0, 0, 0, 0, 0, 0};
-  auto fwd_load = [&](int64_t j) {
+  auto rhs = [&](int64_t j, double* v) {      // b of free node j
     if (lane == 0) {
 #pragma unroll
-      for (int q = 0; q < 6; ++q) zn[q] = (col && j < nf) ? z0[6 * j + q] : 0.0;
+      for (int q = 0; q < 6; ++q) v[q] = col ? z0[6 * j + q] : 0.0;
     } else {
       const bool here = j == (int64_t)sFC[lane];
-      zn[0] = here ? sNC[lane] : 0.0; zn[1] = here ? sNC[NT + lane] : 0.0;
-      zn[2] = here ? sNC[2 * NT + lane] : 0.0;
-      zn[3] = 0.0; zn[4] = 0.0; zn[5] = 0.0;
+      v[0] = here ? sNC[lane] : 0.0; v[1] = here ? sNC[NT + lane] : 0.0;
+      v[2] = here ? sNC[2 * NT + lane] : 0.0;
+      v[3] = 0.0; v[4] = 0.0; v[5] = 0.0;
     }
   };
-  auto fwd_step = [&](int64_t j) {            // forward substitution at free node j
+  auto fwd_load = [&](int64_t k) {
+    if (k < cnt) {
+      rhs(fidx(k), zn);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) zn[q] = 0.0;
+    }
+  };
+  auto fwd_step = [&](int64_t k) {            // forward substitution at this side's step k
+    const int64_t j = fidx(k);
     double bv[6];
 #pragma unroll
     for (int q = 0; q < 6; ++q) bv[q] = zn[q];
-    fwd_load(j + 1);
-    if (j > 0) {
-      const double* Ls = rS[(j - 1) % 3];      // L[j, j-1]
+    fwd_load(k + 1);
+    if (k > 0) {
+      const double* Ls = rS[sd][(k - 1) % 3];  // the previous step's X
 #pragma unroll
       for (int p = 0; p < 6; ++p)
 #pragma unroll
         for (int q = 0; q < 6; ++q) bv[p] -= Ls[p * 6 + q] * yp[q];
     }
-    const double* Ld = rD[j % 2];
+    const double* Ld = rD[sd][k % 2];
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
       const double y = bv[q] * Ld[q * 7];
@@ -388,167 +420,242 @@ __global__ void __launch_bounds__(2 * NT) __attribute__((amdgpu_waves_per_eu(3))
       for (int q = 0; q < 6; ++q) z[(6 * j + q) * zp] = yp[q];
     }
   };
-  if (w == 1) fwd_load(0);
-  // lane u < CHF of wave 0 prefetches the two elements of free node f0 + u (node i = f0 + u + 1):
-  // element o + f0 + u on its left, o + f0 + u + 1 on its right (none at the tip)
+  if (fw) fwd_load(0);
+  // lane u < CHF of a factoring wave prefetches the two elements of its side's step k0 + u
   ElemK pL, pR;
   bool pr = false;
-  auto fetch = [&](int64_t f0) {
-    const int64_t f = f0 + lane;
-    if (w == 0 && lane < CHF && f < nf) {
+  auto fetch = [&](int64_t k0) {
+    const int64_t k = k0 + lane;
+    if (!fw && lane < CHF && k < cnt) {
+      const int64_t f = fidx(k);
       pL = load_elem(d, o + f);
       pr = f + 1 < nf;
       pR = load_elem(d, o + (pr ? f + 1 : f));
     }
   };
   fetch(0);
-  for (int64_t f0 = 0; f0 < nf; f0 += CHF) {
+  for (int64_t k0 = 0; k0 < K; k0 += CHF) {
     __syncthreads();
-    if (w == 0 && lane < CHF && f0 + lane < nf) {
+    if (!fw && lane < CHF && k0 + lane < cnt) {
+      double* D = sKD[sd] + lane * 36;
+      double* C = sKS[sd] + lane * 36;
 #pragma unroll
       for (int row = 0; row < 6; ++row)
 #pragma unroll
         for (int cl = 0; cl < 6; ++cl) {
-          sKD[lane * 36 + row * 6 + cl] = k_bb(pL, row, cl) + (pr ? k_aa(pR, row, cl) : 0.0);
-          sKS[lane * 36 + row * 6 + cl] = pr ? k_ab(pR, row, cl) : 0.0;
+          D[row * 6 + cl] = k_bb(pL, row, cl) + (pr ? k_aa(pR, row, cl) : 0.0);
+          // K[i, i+1] = K_ab of the right element; K[i, i-1] = K_ab of the left one, transposed
+          C[row * 6 + cl] = (sd == 0) ? k_ab(pR, row, cl) : k_ab(pL, cl, row);
         }
     }
     __syncthreads();
-    if (f0 + CHF < nf) fetch(f0 + CHF);
-    const int64_t f1 = min(nf, f0 + CHF);
-    for (int64_t f = f0; f < f1; ++f) {
-      const int64_t i = f + 1, g = o + i;
-      const int lf = (int)(f - f0) * 36;
-      const bool last = (f + 1 == nf);
+    if (k0 + CHF < K) fetch(k0 + CHF);
+    const int64_t k1 = min(K, k0 + CHF);
+    for (int64_t k = k0; k < k1; ++k) {
+      const bool act = k < cnt;
+      const int64_t f = fidx(k), i = f + 1, g = o + i;
+      const int64_t inext = (sd == 0) ? i + 1 : i - 1;
+      const int lf = (int)(k - k0) * 36;
       double sc[6];
-      if (w == 0) {
-        double dv = sKD[lf + la];
+      if (!fw && act) {
+        double dv = sKD[sd][lf + la];
         if (G.dof(i, a) || G.dof(i, b)) dv = (a == b) ? 1.0 : 0.0;
         // A(a, b) = D(a, b) - X_prev[a,:] . X_prev[b,:]
         double acc = dv;
 #pragma unroll
-        for (int k = 0; k < 6; ++k) acc -= Xa[k] * sX[b * 6 + k];
-        if (lane < 36) sA[lane] = acc;
-        // column a of S_i, prescribed rows and columns removed
+        for (int q = 0; q < 6; ++q) acc -= Xa[q] * sX[sd][b * 6 + q];
+        if (lane < 36) sA[sd][lane] = acc;
+        // column a of the coupling to the next node, prescribed rows and columns removed
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
-          double v = last ? 0.0 : sKS[lf + j * 6 + a];
-          if (!last && (G.dof(i, j) || G.dof(i + 1, a))) v = 0.0;
+          double v = sKS[sd][lf + j * 6 + a];
+          if (G.dof(i, j) || G.dof(inext, a)) v = 0.0;
           sc[j] = v;
         }
       }
       __syncthreads();
-      if (w == 0) {
-        double Lm[21];
+      if (!fw) {
+        if (act) {
+          double Lm[21];
 #pragma unroll
-        for (int p = 0, q = 0; p < 6; ++p)
+          for (int p = 0, q = 0; p < 6; ++p)
 #pragma unroll
-          for (int c = 0; c <= p; ++c, ++q) Lm[q] = sA[p * 6 + c];
-        // right-looking Cholesky: scale column k, update the trailing lower triangle
-        double rd[6];
+            for (int c = 0; c <= p; ++c, ++q) Lm[q] = sA[sd][p * 6 + c];
+          // right-looking Cholesky: scale column q, update the trailing lower triangle
+          double rd[6];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) {
-          const int kk = k * (k + 1) / 2;
-          double dk = Lm[kk + k];
-          if (!(dk > 0.0)) { fail = true; dk = 1.0; }
-          const double rk = rsqrt_nr(dk);
-          rd[k] = rk;
+          for (int q = 0; q < 6; ++q) {
+            double dq = Lm[q * (q + 1) / 2 + q];
+            if (!(dq > 0.0)) { fail = true; dq = 1.0; }
+            const double rq = rsqrt_nr(dq);
+            rd[q] = rq;
 #pragma unroll
-          for (int p = k + 1; p < 6; ++p) Lm[p * (p + 1) / 2 + k] *= rk;
+            for (int p = q + 1; p < 6; ++p) Lm[p * (p + 1) / 2 + q] *= rq;
 #pragma unroll
-          for (int p = k + 1; p < 6; ++p) {
-            const int pp = p * (p + 1) / 2;
+            for (int p = q + 1; p < 6; ++p) {
+              const int pp = p * (p + 1) / 2;
 #pragma unroll
-            for (int q = k + 1; q <= p; ++q) Lm[pp + q] -= Lm[pp + k] * Lm[q * (q + 1) / 2 + k];
+              for (int t = q + 1; t <= p; ++t) Lm[pp + t] -= Lm[pp + q] * Lm[t * (t + 1) / 2 + q];
+            }
+          }
+          // row a of X: forward substitution L x = C[:, a] (right-looking)
+#pragma unroll
+          for (int q = 0; q < 6; ++q) {
+            const double x = sc[q] * rd[q];
+            Xa[q] = x;
+#pragma unroll
+            for (int p = q + 1; p < 6; ++p) sc[p] -= Lm[p * (p + 1) / 2 + q] * x;
+          }
+          // select this lane's entries with compile-time indices (keeps the arrays in registers)
+          double lv = 0.0, xv = 0.0;
+#pragma unroll
+          for (int p = 0, q = 0; p < 6; ++p) {
+#pragma unroll
+            for (int c = 0; c <= p; ++c, ++q)
+              if (p == a && c == b) lv = (p == c) ? rd[p] : Lm[q];   // reciprocal on the diagonal
+            if (p == b) xv = Xa[p];
+          }
+          if (lane < 36) {
+            d.LD[g * 36 + lane] = lv;
+            d.LS[g * 36 + lane] = xv;
+            sX[sd][lane] = xv;                                       // X[a][b] for the next node
+            rD[sd][k % 2][lane] = lv;
+            rS[sd][k % 3][lane] = xv;
           }
         }
-        // row a of X: forward substitution L x = S[:, a] (right-looking)
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-          const double x = sc[k] * rd[k];
-          Xa[k] = last ? 0.0 : x;
-#pragma unroll
-          for (int p = k + 1; p < 6; ++p) sc[p] -= Lm[p * (p + 1) / 2 + k] * x;
-        }
-        // select this lane's entries with compile-time indices (keeps the arrays in registers)
-        double lv = 0.0, xv = 0.0;
-#pragma unroll
-        for (int p = 0, q = 0; p < 6; ++p) {
-#pragma unroll
-          for (int c = 0; c <= p; ++c, ++q)
-            if (p == a && c == b) lv = (p == c) ? rd[p] : Lm[q];   // reciprocal on the diagonal
-          if (p == b) xv = Xa[p];
-        }
-        if (lane < 36) {
-          d.LD[g * 36 + lane] = lv;
-          if (!last) d.LS[g * 36 + lane] = xv;
-          sX[lane] = xv;                                          // X[a][b] for the next node
-          rD[f % 2][lane] = lv;
-          rS[f % 3][lane] = xv;
-        }
-      } else if (f > 0) {
-        fwd_step(f - 1);
+      } else if (k > 0 && k - 1 < cnt) {
+        fwd_step(k - 1);
       }
       __syncthreads();
     }
   }
+  // the side whose last step was the loop's last still has its forward step pending
+  if (fw && cnt == K && K > 0) fwd_step(K - 1);
+  // ---------------------------------------------------------------- middle node
+  const int64_t im = m + 1, gm = o + im;
   if (w == 0) {
-    fail = __any(fail ? 1 : 0) != 0;
-    if (fail) finish(d, r, 3, it, d.st_rn[r]);
-  } else {
-    fwd_step(nf - 1);
+    // A_m = D_m - X_top X_top^T - X_bot X_bot^T (a zero X when a side is empty)
+    const bool rm = m + 1 < nf;
+    const ElemK KL = load_elem(d, o + m), KR = load_elem(d, o + (rm ? m + 1 : m));
+    double dv = k_bb(KL, a, b) + (rm ? k_aa(KR, a, b) : 0.0);
+    if (G.dof(im, a) || G.dof(im, b)) dv = (a == b) ? 1.0 : 0.0;
+    double acc = dv;
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+      acc -= sX[0][a * 6 + q] * sX[0][b * 6 + q] + sX[1][a * 6 + q] * sX[1][b * 6 + q];
+    if (lane < 36) sA[0][lane] = acc;
+  } else if (w == 3) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) sYB[q * NT + lane] = yp[q];
   }
+  __syncthreads();
+  if (w == 0) {
+    double Lm[21];
+#pragma unroll
+    for (int p = 0, q = 0; p < 6; ++p)
+#pragma unroll
+      for (int c = 0; c <= p; ++c, ++q) Lm[q] = sA[0][p * 6 + c];
+    double rd[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      double dq = Lm[q * (q + 1) / 2 + q];
+      if (!(dq > 0.0)) { fail = true; dq = 1.0; }
+      const double rq = rsqrt_nr(dq);
+      rd[q] = rq;
+#pragma unroll
+      for (int p = q + 1; p < 6; ++p) Lm[p * (p + 1) / 2 + q] *= rq;
+#pragma unroll
+      for (int p = q + 1; p < 6; ++p) {
+        const int pp = p * (p + 1) / 2;
+#pragma unroll
+        for (int t = q + 1; t <= p; ++t) Lm[pp + t] -= Lm[pp + q] * Lm[t * (t + 1) / 2 + q];
+      }
+    }
+    double lv = 0.0;
+#pragma unroll
+    for (int p = 0, q = 0; p < 6; ++p)
+#pragma unroll
+      for (int c = 0; c <= p; ++c, ++q)
+        if (p == a && c == b) lv = (p == c) ? rd[p] : Lm[q];
+    if (lane < 36) {
+      d.LD[gm * 36 + lane] = lv;
+      sLm[lane] = lv;
+    }
+  }
+  __syncthreads();
+  if (w == 1) {
+    // z_m = L_m^-1 (b_m - X_top y_top - X_bot y_bot), then x_m = L_m^-T z_m into Z
+    double bv[6];
+    rhs(m, bv);
+#pragma unroll
+    for (int p = 0; p < 6; ++p)
+#pragma unroll
+      for (int q = 0; q < 6; ++q)
+        bv[p] -= sX[0][p * 6 + q] * yp[q] + sX[1][p * 6 + q] * sYB[q * NT + lane];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const double y = bv[q] * sLm[q * 7];
+      bv[q] = y;
+#pragma unroll
+      for (int p = q + 1; p < 6; ++p) bv[p] -= sLm[p * 6 + q] * y;
+    }
+    double xm[6];
+#pragma unroll
+    for (int q = 5; q >= 0; --q) {
+      const double x = bv[q] * sLm[q * 7];
+      xm[q] = x;
+#pragma unroll
+      for (int p = 0; p < q; ++p) bv[p] -= sLm[q * 6 + p] * x;
+    }
+    if (col) {
+      double* zx = d.Z + d.zoff[r] + (int64_t)lane * (6 * n) + 6 * m;
+#pragma unroll
+      for (int q = 0; q < 6; ++q) zx[q] = xm[q];
+    }
+  }
+  if (fail) s_fail = 1;
+  __syncthreads();
+  if (s_fail) finish(d, r, 3, it, d.st_rn[r]);
 }
 
-// phase 3: backward substitution of all right-hand sides (and the forward substitution of
-// those beyond the first NT, which phase 2 has already swept forward).
-// Block (r, p) takes columns p*NT .. p*NT + NT-1 of robot r's Z, one lane per column; every
-// lane sweeps the robot's nodes holding its column's whole 6-vector.  Per chunk of CHS nodes
-// the factor blocks are staged through LDS (broadcast to all lanes), the next chunk's blocks
-// in flight in registers meanwhile; the lanes' own right-hand-side values are double-buffered
-// in registers (the block needs only the small LDS staging area, so many robots fit a CU).
-// The forward side lives in Y, node-major, so that the wavefront's loads of one row are one
-// contiguous segment; the backward solutions are written to Z column-major for the consumers.
-// Columns from NT on are contact columns (n_c at the contact node, zero elsewhere): their
-// forward sweep generates the right-hand side instead of reading it, and starts at the
-// chunk of the pass's first contact node (the solution is exactly zero above it).
-__global__ void __launch_bounds__(NT) subst_kernel(Dev d) {
-  const int r = blockIdx.x;
-  const int lane = threadIdx.x;
-  if (d.st_done[r]) return;
-  const int nc = d.st_nc[r];
-  const int ncol = 1 + nc;
-  const int c0 = blockIdx.y * NT;
-  if (c0 >= ncol) return;
-  const int64_t o = d.off[r], n = d.off[r + 1] - o;
-  const int64_t nf = n - 1;            // free nodes 1..n-1 -> f = 0..nf-1
-  double* Zr = d.Z + d.zoff[r];
-  const int64_t ld = 6 * n;
-  __shared__ double sKD[PFS * NT], sKS[PFS * NT];
-  const int c = c0 + lane;
-  const bool act = c < ncol;
-  double* z = Zr + (int64_t)(act ? c : 0) * ld;            // this column's solution (Z)
-  const int64_t zp = d.zp;
-  double* yv = d.Y + 6 * o * zp + (act ? c : 0);         // its forward side (Y, node-major)
-  const bool fwd_done = c0 == 0;         // the first NT columns were swept forward in phase 2
-  // contact of this lane's column (forward passes only): free node and normal
-  int64_t fcn = nf;
-  double cn0 = 0.0, cn1 = 0.0, cn2 = 0.0;
-  if (!fwd_done && act) {
-    const int64_t ci = (int64_t)r * d.cap + (c - 1);
-    fcn = d.ct_node[ci] - 1;
-    cn0 = d.ct_n[3 * ci]; cn1 = d.ct_n[3 * ci + 1]; cn2 = d.ct_n[3 * ci + 2];
-  }
+// phase 3: substitution of all right-hand sides with the two-ended factor of phase 2.
+// One lane per right-hand side (column c of Z), each lane holding its column's 6-vector.
+// Backward sweeps run from the middle node outwards: on the base side x_f = L_f^-T (y_f -
+// X_f^T x_{f+1}) for f = m-1 .. 0, on the tip side x_f = L_f^-T (y_f - X_f^T x_{f-1}) for
+// f = m+1 .. nf-1 (X_f, the block stored with node f, couples it towards the middle), starting
+// from the middle node's x_m.  Per chunk of CHS nodes (aligned at multiples of CHS) the factor
+// blocks are staged through LDS (broadcast to all lanes), the next chunk's blocks in flight in
+// registers meanwhile; the lanes' forward values (Y, node-major: one contiguous row segment per
+// wavefront load) are double-buffered in registers; the solutions go to Z (column-major).
+// One block per robot and pass of NT columns, one wavefront per side.  The first NT columns
+// were swept forward in phase 2, which also wrote x_m: their block only sweeps back.  Columns
+// from NT on are contact columns (n_c at the contact node, zero elsewhere): their block sweeps
+// them forward (generating the right-hand side, over the part of each side that the contact
+// node reaches), combines the two sides at the middle node, then sweeps back.
+
+// chunks of CHS nodes (aligned at multiples of CHS) that a side's sweep from f_begin visits
+__device__ __forceinline__ int64_t side_chunks(bool up, int64_t f_begin, int64_t nf) {
+  if (up) return f_begin >= nf ? 0 : (nf - 1) / CHS - f_begin / CHS + 1;
+  return f_begin < 0 ? 0 : f_begin / CHS + 1;
+}
+
+// backward sweep of one side; UP: f = f_begin .. nf-1 ascending (tip side), else f = f_begin
+// .. 0 descending (base side); ylo..yhi: nodes whose forward value is stored (zero elsewhere).
+// Every wavefront of the block must pass the same `trips` (>= this side's chunk count).
+template <bool UP>
+__device__ void bwd_side(const Dev& d, int64_t o, int64_t nf, int64_t f_begin, double* z,
+                         const double* yv, int64_t zp, bool act, int64_t ylo, int64_t yhi,
+                         double (&xn)[6], double* sKD, double* sKS, int64_t trips) {
+  const int lane = threadIdx.x % NT;
   double pd[PFS], ps[PFS];
   auto stageK = [&]() {
 #pragma unroll
     for (int u = 0; u < PFS; ++u) { sKD[lane + u * NT] = pd[u]; sKS[lane + u * NT] = ps[u]; }
   };
-  // LD of nodes b0..b0+cnt-1 and LS of nodes s0..s0+cnt-1 (36 doubles each) into pd / ps
-  auto fetchK = [&](int64_t b0, int64_t s0, int64_t nodes) {
-    const int64_t cnt = nodes * 36;
-    const double* ldp = d.LD + (o + 1 + b0) * 36;
-    const double* lsp = d.LS + (o + 1 + s0) * 36;
+  auto fetchK = [&](int64_t f0) {        // LD and LS of nodes f0 .. f0+CHS-1 (within the robot)
+    const int64_t cnt = min((int64_t)CHS, nf - f0) * 36;
+    const double* ldp = d.LD + (o + 1 + f0) * 36;
+    const double* lsp = d.LS + (o + 1 + f0) * 36;
 #pragma unroll
     for (int u = 0; u < PFS; ++u) {
       const int64_t idx = lane + (int64_t)u * NT;
@@ -556,125 +663,269 @@ __global__ void __launch_bounds__(NT) subst_kernel(Dev d) {
       ps[u] = idx < cnt ? lsp[idx] : 0.0;
     }
   };
-  // ---------------------------------------------------------------- forward (contact columns)
-  if (!fwd_done) {
-    double yp[6] = {0, 0, 0, 0, 0, 0};   // previous block solution
-    int64_t m = fcn;
-#pragma unroll
-    for (int sh = 32; sh > 0; sh >>= 1) m = min(m, (int64_t)__shfl_xor((long long)m, sh));
-    const int64_t fs = (m / CHS) * CHS;
-    // chunk f0 needs LD of nodes f0..f1-1 and LS of nodes f0-1..f1-2 (the base slot when f0 = 0)
-    fetchK(fs, fs - 1, min((int64_t)CHS, nf - fs));
-    for (int64_t f0 = fs; f0 < nf; f0 += CHS) {
-      __syncthreads();
-      stageK();
-      __syncthreads();
-      if (f0 + CHS < nf) fetchK(f0 + CHS, f0 + CHS - 1, min((int64_t)CHS, nf - f0 - CHS));
-      const int64_t f1 = min(nf, f0 + CHS);
-#pragma unroll
-      for (int u = 0; u < CHS; ++u) {
-        const int64_t f = f0 + u;
-        if (f >= f1) break;
-        const bool here = f == fcn;
-        double bv[6] = {here ? cn0 : 0.0, here ? cn1 : 0.0, here ? cn2 : 0.0, 0.0, 0.0, 0.0};
-        if (f > 0) {
-          const double* Ls = sKS + u * 36;                // L[f, f-1]
-#pragma unroll
-          for (int p = 0; p < 6; ++p)
-#pragma unroll
-            for (int k = 0; k < 6; ++k) bv[p] -= Ls[p * 6 + k] * yp[k];
-        }
-        const double* Ld = sKD + u * 36;                  // lower triangle, reciprocal diagonal
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-          const double y = bv[k] * Ld[k * 7];
-          yp[k] = y;
-#pragma unroll
-          for (int p = k + 1; p < 6; ++p) bv[p] -= Ld[p * 6 + k] * y;
-        }
-        if (act && f >= fcn) {
-#pragma unroll
-          for (int k = 0; k < 6; ++k) yv[(6 * f + k) * zp] = yp[k];
-        }
-      }
-    }
-  }
-  // ---------------------------------------------------------------- backward (all columns)
-  // chunk [f0, f1) needs LD and LS of nodes f0..f1-1; the column's values of the chunk come
-  // from Y (zero above the contact node of a forward-swept contact column); the solution
-  // goes to Z
-  const int64_t flo = fwd_done ? 0 : fcn;
-  double za[CHS * 6], zb[CHS * 6];
-  auto loadZ = [&](double (&zz)[CHS * 6], int64_t f0, int64_t f1) {
+  auto loadZ = [&](double (&zz)[CHS * 6], int64_t f0) {
 #pragma unroll
     for (int u = 0; u < CHS; ++u)
 #pragma unroll
-      for (int k = 0; k < 6; ++k)
-        zz[u * 6 + k] = (act && f0 + u < f1 && f0 + u >= flo) ? yv[(6 * (f0 + u) + k) * zp] : 0.0;
-  };
-  double xn[6] = {0, 0, 0, 0, 0, 0};     // next block solution
-  auto bwd_chunk = [&](const double (&zz)[CHS * 6], int64_t f0, int64_t f1) {
-#pragma unroll
-    for (int u = CHS - 1; u >= 0; --u) {
-      const int64_t f = f0 + u;
-      if (f >= f1) continue;
-      double bv[6];
-#pragma unroll
-      for (int k = 0; k < 6; ++k) bv[k] = zz[u * 6 + k];
-      if (f + 1 < nf) {
-        const double* Ls = sKS + u * 36;                  // L[f+1, f]; b -= L^T x_next
-#pragma unroll
-        for (int k = 0; k < 6; ++k)
-#pragma unroll
-          for (int p = 0; p < 6; ++p) bv[p] -= Ls[k * 6 + p] * xn[k];
+      for (int k = 0; k < 6; ++k) {
+        const int64_t f = f0 + u;
+        zz[u * 6 + k] = (act && f < nf && f >= ylo && f <= yhi) ? yv[(6 * f + k) * zp] : 0.0;
       }
-      const double* Ld = sKD + u * 36;
+  };
+  auto node = [&](const double (&zz)[CHS * 6], int u, int64_t f) {
+    double bv[6];
 #pragma unroll
-      for (int k = 5; k >= 0; --k) {
-        const double x = bv[k] * Ld[k * 7];
-        xn[k] = x;
+    for (int k = 0; k < 6; ++k) bv[k] = zz[u * 6 + k];
+    const double* Ls = sKS + u * 36;                      // X_f: b -= X_f^T x_neighbour
 #pragma unroll
-        for (int p = 0; p < k; ++p) bv[p] -= Ld[k * 6 + p] * x;
+    for (int k = 0; k < 6; ++k)
+#pragma unroll
+      for (int p = 0; p < 6; ++p) bv[p] -= Ls[k * 6 + p] * xn[k];
+    const double* Ld = sKD + u * 36;
+#pragma unroll
+    for (int k = 5; k >= 0; --k) {
+      const double x = bv[k] * Ld[k * 7];
+      xn[k] = x;
+#pragma unroll
+      for (int p = 0; p < k; ++p) bv[p] -= Ld[k * 6 + p] * x;
+    }
+    if (act) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) z[6 * f + k] = xn[k];
+    }
+  };
+  // chunk of CHS nodes with index ch covers f in [ch*CHS, ch*CHS + CHS) intersected with the side
+  auto chunk = [&](const double (&zz)[CHS * 6], int64_t ch) {
+    const int64_t f0 = ch * CHS;
+    if (UP) {
+#pragma unroll
+      for (int u = 0; u < CHS; ++u) {
+        const int64_t f = f0 + u;
+        if (f >= f_begin && f < nf) node(zz, u, f);
+      }
+    } else {
+#pragma unroll
+      for (int u = CHS - 1; u >= 0; --u) {
+        const int64_t f = f0 + u;
+        if (f <= f_begin && f >= 0) node(zz, u, f);
+      }
+    }
+  };
+  // chunk trips: this side's chunks (first = the one holding f_begin, towards the end), then idle
+  // trips up to `trips` (the other side's count in a two-wavefront block) with the same barriers
+  const int64_t mine = side_chunks(UP, f_begin, nf);
+  const int64_t ch_first = mine > 0 ? f_begin / CHS : 0;
+  const int64_t step = UP ? 1 : -1;
+  double za[CHS * 6], zb[CHS * 6];
+  if (mine > 0) {
+    fetchK(ch_first * CHS);
+    loadZ(za, ch_first * CHS);
+  }
+  // two trips per pass of the loop so that the two buffers keep fixed registers
+  for (int64_t t = 0; t < trips; t += 2) {
+    const int64_t ch = ch_first + t * step;
+    __syncthreads();
+    if (t < mine) stageK();
+    __syncthreads();
+    if (t + 1 < mine) {
+      fetchK((ch + step) * CHS);
+      loadZ(zb, (ch + step) * CHS);
+    }
+    if (t < mine) chunk(za, ch);
+    if (t + 1 >= trips) break;
+    __syncthreads();
+    if (t + 1 < mine) stageK();
+    __syncthreads();
+    if (t + 2 < mine) {
+      fetchK((ch + 2 * step) * CHS);
+      loadZ(za, (ch + 2 * step) * CHS);
+    }
+    if (t + 1 < mine) chunk(zb, ch + step);
+  }
+}
+
+// block (r, p) takes columns p*NT .. p*NT + NT-1: wave 0 the base side, wave 1 the tip side
+__global__ void __launch_bounds__(2 * NT) subst_kernel(Dev d) {
+  const int r = blockIdx.x;
+  const int w = threadIdx.x / NT, lane = threadIdx.x % NT;
+  if (d.st_done[r]) return;
+  const int nc = d.st_nc[r];
+  const int ncol = 1 + nc;
+  const int c0 = blockIdx.y * NT;
+  if (c0 >= ncol) return;
+  const int64_t o = d.off[r], n = d.off[r + 1] - o;
+  const int64_t nf = n - 1, m = nf / 2;
+  const int64_t ld = 6 * n;
+  const int c = c0 + lane;
+  const bool act = c < ncol;
+  double* z = d.Z + d.zoff[r] + (int64_t)(act ? c : 0) * ld;
+  const int64_t zp = d.zp;
+  double* yv = d.Y + 6 * o * zp + (act ? c : 0);
+  __shared__ double sKD[2][PFS * NT], sKS[2][PFS * NT];
+  __shared__ double sXT[6 * NT], sXM[6 * NT];
+  const int64_t trips = max(side_chunks(false, m - 1, nf), side_chunks(true, m + 1, nf));
+  const bool fwd = c0 > 0;                // the first NT columns were swept forward in phase 2
+  // this lane's contact: free node and normal (inactive lanes: no contact)
+  int64_t fcn = -1;
+  double cn0 = 0.0, cn1 = 0.0, cn2 = 0.0;
+  if (fwd && act) {
+    const int64_t ci = (int64_t)r * d.cap + (c - 1);
+    fcn = d.ct_node[ci] - 1;
+    cn0 = d.ct_n[3 * ci]; cn1 = d.ct_n[3 * ci + 1]; cn2 = d.ct_n[3 * ci + 2];
+  }
+  // ---------------------------------------------------------------- forward sweeps
+  // base side: f = fs .. m-1 ascending, b - X_{f-1} y_{f-1}; tip side: f = fe .. m+1
+  // descending, b - X_{f+1} y_{f+1}; a side's values are zero before the contact node
+  double yp[6] = {0, 0, 0, 0, 0, 0};
+  if (fwd) {
+    double* KD = sKD[w];
+    double* KS = sKS[w];
+    double pd[PFS], ps[PFS];
+    const bool up = w == 0;
+    int64_t lim;                          // first (base side) / last (tip side) contact node
+    {
+      long long v = act ? fcn : (up ? (long long)nf : -1ll);
+#pragma unroll
+      for (int sh = 32; sh > 0; sh >>= 1) {
+        const long long ov = __shfl_xor(v, sh);
+        v = up ? min(v, ov) : max(v, ov);
+      }
+      lim = v;
+    }
+    // chunk [f0, f0+CHS): LD of its nodes and, per node, X of the previous node in sweep order
+    auto fetchF = [&](int64_t f0) {
+      const int64_t cnt = min((int64_t)CHS, nf - f0) * 36;
+      const int64_t sh = up ? -1 : 1;
+      const double* ldp = d.LD + (o + 1 + f0) * 36;
+      const double* lsp = d.LS + (o + 1 + f0 + sh) * 36;
+#pragma unroll
+      for (int u = 0; u < PFS; ++u) {
+        const int64_t idx = lane + (int64_t)u * NT;
+        const int64_t fn = f0 + idx / 36 + sh;        // the neighbour whose block is read
+        pd[u] = idx < cnt ? ldp[idx] : 0.0;
+        ps[u] = (idx < cnt && fn >= 0 && fn < nf) ? lsp[idx] : 0.0;
+      }
+    };
+    auto fnode = [&](int u, int64_t f) {
+      const bool here = f == fcn;
+      double bv[6] = {here ? cn0 : 0.0, here ? cn1 : 0.0, here ? cn2 : 0.0, 0.0, 0.0, 0.0};
+      const double* Ls = KS + u * 36;
+#pragma unroll
+      for (int p = 0; p < 6; ++p)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) bv[p] -= Ls[p * 6 + k] * yp[k];
+      const double* Ldd = KD + u * 36;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        const double y = bv[k] * Ldd[k * 7];
+        yp[k] = y;
+#pragma unroll
+        for (int p = k + 1; p < 6; ++p) bv[p] -= Ldd[p * 6 + k] * y;
       }
       if (act) {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) z[6 * f + k] = xn[k];
+        for (int k = 0; k < 6; ++k) yv[(6 * f + k) * zp] = yp[k];
       }
-    }
-  };
-  const int64_t nch = (nf + CHS - 1) / CHS;
-  __syncthreads();                       // forward stores of this column precede the reloads
-  {
-    const int64_t f0 = (nch - 1) * CHS;
-    fetchK(f0, f0, nf - f0);
-    loadZ(za, f0, nf);
-  }
-  // chunks from the tip, two per trip so that the two Z buffers keep fixed registers
-  for (int64_t ch = nch - 1; ch >= 0; ch -= 2) {
+    };
+    // this side's nodes: base [max(lim, 0), m), tip (m, min(lim, nf-1)]
+    const int64_t lo = up ? lim : m + 1;
+    const int64_t hi = up ? m - 1 : lim;
+    const int64_t nch_lo = lo / CHS, nch_hi = hi >= 0 ? hi / CHS : -1;
+    // both waves take the same number of chunk trips so that their barriers match
+    const int64_t mine = (lo <= hi) ? nch_hi - nch_lo + 1 : 0;
+    int64_t other = 0;
     {
-      const int64_t f0 = ch * CHS, f1 = min(nf, f0 + CHS);
-      __syncthreads();
-      stageK();
-      __syncthreads();
-      if (ch > 0) {
-        fetchK(f0 - CHS, f0 - CHS, CHS);
-        loadZ(zb, f0 - CHS, f0);
+      // the other side's count, from the same quantities
+      long long v = act ? fcn : (!up ? (long long)nf : -1ll);
+#pragma unroll
+      for (int sh = 32; sh > 0; sh >>= 1) {
+        const long long ov = __shfl_xor(v, sh);
+        v = !up ? min(v, ov) : max(v, ov);
       }
-      bwd_chunk(za, f0, f1);
+      const int64_t olo = !up ? v : m + 1, ohi = !up ? m - 1 : v;
+      other = (olo <= ohi) ? (ohi / CHS) - (olo / CHS) + 1 : 0;
     }
-    if (ch == 0) break;
-    {
-      const int64_t f0 = (ch - 1) * CHS, f1 = f0 + CHS;
+    const int64_t trips = max(mine, other);
+    if (mine > 0) fetchF((up ? nch_lo : nch_hi) * CHS);
+    for (int64_t t = 0; t < trips; ++t) {
+      const int64_t ch = up ? nch_lo + t : nch_hi - t;
       __syncthreads();
-      stageK();
-      __syncthreads();
-      if (ch > 1) {
-        fetchK(f0 - CHS, f0 - CHS, CHS);
-        loadZ(za, f0 - CHS, f0);
+      if (t < mine) {
+#pragma unroll
+        for (int u = 0; u < PFS; ++u) { KD[lane + u * NT] = pd[u]; KS[lane + u * NT] = ps[u]; }
       }
-      bwd_chunk(zb, f0, f1);
+      __syncthreads();
+      if (t + 1 < mine) fetchF((up ? ch + 1 : ch - 1) * CHS);
+      if (t < mine) {
+        const int64_t f0 = ch * CHS;
+        if (up) {
+#pragma unroll
+          for (int u = 0; u < CHS; ++u) {
+            const int64_t f = f0 + u;
+            if (f >= lo && f <= hi) fnode(u, f);
+          }
+        } else {
+#pragma unroll
+          for (int u = CHS - 1; u >= 0; --u) {
+            const int64_t f = f0 + u;
+            if (f >= lo && f <= hi) fnode(u, f);
+          }
+        }
+      }
     }
   }
+  // ---------------------------------------------------------------- middle node
+  // z_m = L_m^-1 (b_m - X_{m-1} y_{m-1} - X_{m+1} y_{m+1}), x_m = L_m^-T z_m (phase 2 wrote
+  // it for the first NT columns)
+  if (!fwd) {
+    if (w == 0) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) sXM[k * NT + lane] = act ? z[6 * m + k] : 0.0;
+    }
+  } else if (w == 1) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) sXT[k * NT + lane] = yp[k];
+  }
+  __syncthreads();
+  if (fwd && w == 0) {
+    const bool here = m == fcn;
+    double bv[6] = {here ? cn0 : 0.0, here ? cn1 : 0.0, here ? cn2 : 0.0, 0.0, 0.0, 0.0};
+    const bool ht = m >= 1, hb = m + 1 < nf;
+    const double* Xt = d.LS + (o + 1 + (ht ? m - 1 : m)) * 36;   // X_{m-1} (base side), if any
+    const double* Xb = d.LS + (o + 1 + (hb ? m + 1 : m)) * 36;   // X_{m+1} (tip side), if any
+#pragma unroll
+    for (int p = 0; p < 6; ++p)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        if (ht) bv[p] -= Xt[p * 6 + k] * yp[k];
+        if (hb) bv[p] -= Xb[p * 6 + k] * sXT[k * NT + lane];
+      }
+    const double* Lm = d.LD + (o + 1 + m) * 36;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const double y = bv[k] * Lm[k * 7];
+      bv[k] = y;
+#pragma unroll
+      for (int p = k + 1; p < 6; ++p) bv[p] -= Lm[p * 6 + k] * y;
+    }
+#pragma unroll
+    for (int k = 5; k >= 0; --k) {
+      const double x = bv[k] * Lm[k * 7];
+      sXM[k * NT + lane] = x;
+      if (act) z[6 * m + k] = x;
+#pragma unroll
+      for (int p = 0; p < k; ++p) bv[p] -= Lm[k * 6 + p] * x;
+    }
+  }
+  __syncthreads();
+  // ---------------------------------------------------------------- backward sweeps
+  double xn[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) xn[k] = sXM[k * NT + lane];
+  // forward values are stored from the contact node on (base side) / up to it (tip side)
+  const int64_t ylo = fwd ? (act ? fcn : nf) : 0, yhi = fwd ? (act ? fcn : -1) : nf - 1;
+  if (w == 0) bwd_side<false>(d, o, nf, m - 1, z, yv, zp, act, ylo, nf - 1, xn, sKD[0], sKS[0], trips);
+  else bwd_side<true>(d, o, nf, m + 1, z, yv, zp, act, 0, yhi, xn, sKD[1], sKS[1], trips);
 }
 
 // phase 4: contact Schur complement, LCP, step limit and state update
@@ -1516,8 +1767,8 @@ __global__ void __launch_bounds__(NT) gather_kernel(Dev d) {
 void launch_solve_phase(const Dev& d, int phase, int it, hipStream_t s) {
   switch (phase) {
     case 0: hipLaunchKernelGGL(check_rhs_kernel, dim3(d.B), dim3(NT), 0, s, d, it); break;
-    case 1: hipLaunchKernelGGL(factor_kernel, dim3(d.B), dim3(2 * NT), 0, s, d, it); break;
-    case 2: hipLaunchKernelGGL(subst_kernel, dim3(d.B, (d.cap + NT) / NT), dim3(NT), 0, s, d); break;
+    case 1: hipLaunchKernelGGL(factor_kernel, dim3(d.B), dim3(4 * NT), 0, s, d, it); break;
+    case 2: hipLaunchKernelGGL(subst_kernel, dim3(d.B, (d.cap + NT) / NT), dim3(2 * NT), 0, s, d); break;
     default:
       hipLaunchKernelGGL(update_kernel, dim3(d.B), dim3(NT), 0, s, d, it);
       if (d.cap > LCPM) hipLaunchKernelGGL(update_wide_kernel, dim3(d.B), dim3(NT), 0, s, d, it);

@@ -6,8 +6,10 @@ are checked, at sampled load steps, against what the oracle computes at any size
     GPU's contact forces, vanishes over the free DOFs (to the Newton tolerance or the rounding
     floor of the stagnation test) and equals the residual the GPU reported;
   * detection (Sec. III-C): the oracle's brute-force (k-d-tree culled) detection at the GPU
-    state finds the GPU's contact set, outside nodes with near-threshold decisions; any other
-    GPU entry is a persisting face still within the band of its triangle;
+    state finds the GPU's contact set, outside nodes with near-threshold decisions (an
+    edge/vertex contact may carry another triangle whose nearest point is the same within
+    1e-9 m, with the same gap: the codes break such ties differently); any other GPU entry is
+    a persisting face still within the band of its triangle;
   * the contact conditions of eq. 12: forces >= 0, gaps >= 0 to the tolerance, force x gap = 0;
   * mixed precision against the FP64 GPU path: relative tip error <= 1e-5.
 """
@@ -80,8 +82,20 @@ def test_config2_equilibrium_detection_complementarity(config2_runs):
         amb = {c["node"] for c in det if c["ambiguous"]}
         orc = {(c["node"], c["tri"], c["kind"]) for c in det if c["tri"] >= 0 and c["node"] not in amb}
         gpu = {(c["node"], c["tri"], c["kind"]) for c in cts if c["node"] not in amb}
-        assert orc <= gpu, (s["k"], sorted(orc - gpu))
-        for (node, tri, kind) in sorted(gpu - orc):
+        # an oracle contact missing from the GPU set must be the same constraint under another
+        # triangle: the fallback's nearest point on an edge or vertex shared by two triangles is
+        # the same point, and which index wins the rounding-level tie differs between the codes
+        same_geom = set()
+        for (node, tri, kind) in sorted(orc - gpu):
+            oc = next(c for c in det if (c["node"], c["tri"], c["kind"]) == (node, tri, kind))
+            dist = oc["gap"] + rob.r_c               # contact point p - dist n, the same within 1e-9 m
+            alt = [c for c in cts if c["node"] == node and c["kind"] == kind
+                   and dist * np.linalg.norm(np.asarray(c["n"]) - oc["n"]) <= 1e-9
+                   and abs(c["gap"] - oc["gap"]) <= 1e-9]
+            assert alt, (s["k"], (node, tri, kind), oc["n"], oc["gap"],
+                         [(c["tri"], c["kind"], list(c["n"]), c["gap"]) for c in cts if c["node"] == node])
+            same_geom.add((node, alt[0]["tri"], kind))
+        for (node, tri, kind) in sorted(gpu - orc - same_geom):
             # a persisting face: the oracle's closest point of that triangle is within the band
             assert kind == 0, (s["k"], node, tri, kind)
             cpt, _, _ = collision.closest_points(P[node], rob.mesh, np.array([tri]))
