@@ -121,6 +121,7 @@ struct Dev {
   int32_t* st_nswitch;
   int32_t* st_iters;
   int32_t* st_nact;     // active contacts of the current step
+  int32_t* st_big;      // the wide LCP's active set outgrew its LDS factor this iteration
   unsigned long long* st_mx;  // largest node translation of the step (bits of a double >= 0)
   int64_t* st_rhs;      // [3B] right-hand sides, those swept forward in the factorisation, and
                         // substitution passes, since creation / the last state reset

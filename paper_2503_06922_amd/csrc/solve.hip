@@ -1674,17 +1674,6 @@ __device__ __forceinline__ LcpWs global_ws(double* g, int m) {
   return LcpWs{g, g + nl, g + nl + m, (int*)(g + nl + 2 * m), m};
 }
 
-// 0: solved with the factor in LDS, 1: solved with the factor in device memory, -1: failed
-template <class Src>
-__device__ int lcp_wide_any(const Src& src, LcpWideLds& S, double* Wc, int cap, const double* q,
-                            int m, double* y, double* gws) {
-  const LcpWs wl{S.L, S.Rd, S.Yp, S.P, NPW};
-  const int c = lcp_wide<SPL>(src, S, wl, Wc, cap, q, m, y, true);
-  if (c == 0) return 0;
-  if (c == 1) return -1;
-  return lcp_wide<SPG>(src, S, global_ws(gws, m), Wc, cap, q, m, y, false) == 0 ? 1 : -1;
-}
-
 // phase 4 for robots with more than LCPM contacts
 __global__ void __launch_bounds__(NT) update_wide_kernel(Dev d, int it) {
   const int r = blockIdx.x;
@@ -1704,7 +1693,36 @@ __global__ void __launch_bounds__(NT) update_wide_kernel(Dev d, int it) {
   contact_q(d, cb, nc, Zr, qv);
   __syncthreads();
   const RobotLcpSource src{&d, r, cb, Zr, ld};
-  if (lcp_wide_any(src, S, Wc, cap, qv, nc, y, scratch) < 0) {
+  const LcpWs wl{S.L, S.Rd, S.Yp, S.P, NPW};
+  const int code = lcp_wide<SPL>(src, S, wl, Wc, cap, qv, nc, y, true);
+  if (threadIdx.x == 0) d.st_big[r] = code == 2 ? 1 : 0;
+  if (code == 1) {
+    finish(d, r, 2, it, d.st_rn[r]);
+    return;
+  }
+  if (code == 0) store_active(d, r, nc);
+}
+
+// phase 4 for the robots whose wide LCP outgrew the LDS factor: the same method again with the
+// factor in the robot's device workspace (up to every constraint).  A kernel of its own, so
+// that the common path keeps its registers (this one holds 16 positions per lane).
+__global__ void __launch_bounds__(NT) update_big_kernel(Dev d, int it) {
+  const int r = blockIdx.x;
+  if (d.st_done[r]) return;
+  const int nc = d.st_nc[r];
+  if (nc <= LCPM || !d.st_big[r]) return;
+  const int64_t n = d.off[r + 1] - d.off[r];
+  const int cap = d.cap;
+  const int64_t cb = (int64_t)r * cap;
+  double* Zr = d.Z + d.zoff[r];
+  const int64_t ld = 6 * n;
+  __shared__ LcpWideLds S;
+  const double* qv = d.q + cb;                  // written by update_wide_kernel
+  double* y = d.ct_y + cb;
+  double* Wc = d.W + (int64_t)r * cap * cap;
+  double* scratch = d.W + (int64_t)d.B * cap * cap + (int64_t)r * lcp_ws_doubles(cap);
+  const RobotLcpSource src{&d, r, cb, Zr, ld};
+  if (lcp_wide<SPG>(src, S, global_ws(scratch, nc), Wc, cap, qv, nc, y, true) != 0) {
     finish(d, r, 2, it, d.st_rn[r]);
     return;
   }
@@ -1726,16 +1744,30 @@ __global__ void __launch_bounds__(NT) lcp_small_kernel(const double* W, const do
 }
 
 __global__ void __launch_bounds__(NT) lcp_wide_check_kernel(double* W, const double* q, int m,
-                                                            double* y, double* gws, int* code) {
+                                                            double* y, int* code) {
   __shared__ LcpWideLds S;
-  const int c = lcp_wide_any(DenseLcpSource{}, S, W, m, q, m, y, gws);
-  if (threadIdx.x == 0) *code = c < 0 ? -1 : 1 + c;
+  const LcpWs wl{S.L, S.Rd, S.Yp, S.P, NPW};
+  const int c = lcp_wide<SPL>(DenseLcpSource{}, S, wl, W, m, q, m, y, true);
+  if (threadIdx.x == 0) *code = c == 0 ? 1 : (c == 2 ? 2 : -1);
+}
+
+// the set outgrew the LDS factor (code 2): again with the factor in device memory
+__global__ void __launch_bounds__(NT) lcp_big_check_kernel(double* W, const double* q, int m,
+                                                           double* y, double* gws, int* code) {
+  if (*code != 2) return;
+  __shared__ LcpWideLds S;
+  const int c = lcp_wide<SPG>(DenseLcpSource{}, S, global_ws(gws, m), W, m, q, m, y, true);
+  __syncthreads();
+  if (threadIdx.x == 0) *code = c == 0 ? 2 : -1;
 }
 
 void launch_lcp_check(double* W, const double* q, int m, double* y, double* scratch, int* code,
                       hipStream_t s) {
   if (m <= LCPM) hipLaunchKernelGGL(lcp_small_kernel, dim3(1), dim3(NT), 0, s, W, q, m, y, code);
-  else hipLaunchKernelGGL(lcp_wide_check_kernel, dim3(1), dim3(NT), 0, s, W, q, m, y, scratch, code);
+  else {
+    hipLaunchKernelGGL(lcp_wide_check_kernel, dim3(1), dim3(NT), 0, s, W, q, m, y, code);
+    hipLaunchKernelGGL(lcp_big_check_kernel, dim3(1), dim3(NT), 0, s, W, q, m, y, scratch, code);
+  }
 }
 
 // detection-only path: compact the per-node contacts of every robot (no step)
@@ -1772,6 +1804,7 @@ void launch_solve_phase(const Dev& d, int phase, int it, hipStream_t s) {
     default:
       hipLaunchKernelGGL(update_kernel, dim3(d.B), dim3(NT), 0, s, d, it);
       if (d.cap > LCPM) hipLaunchKernelGGL(update_wide_kernel, dim3(d.B), dim3(NT), 0, s, d, it);
+      if (d.cap > NPW) hipLaunchKernelGGL(update_big_kernel, dim3(d.B), dim3(NT), 0, s, d, it);
       hipLaunchKernelGGL(step_dx_kernel, dim3((unsigned)((d.Ntot + 255) / 256)), dim3(256), 0, s, d);
       hipLaunchKernelGGL(step_apply_kernel, dim3((unsigned)((d.Ntot + 255) / 256)), dim3(256), 0, s, d, it);
       break;
