@@ -1331,40 +1331,65 @@ struct LcpWs {
   int npmax;
 };
 
-// W columns and warm-start flags of a robot's contact set: W(i, t) = n_i . Z_t(node of i)
+// W columns and warm-start flags of a robot's contact set: W(i, t) = n_i . Z_t(node of i),
+// computed from Z when t is first needed and cached in Wc (column-major, ld = cap).  Each lane
+// keeps the free node and normal of its constraints i = lane + NT s (s < CSL) in registers, so
+// that a column is one round of independent loads; larger sets read them per column.
+constexpr int CSL = 4;
 struct RobotLcpSource {
   const Dev* d;
   int r;
   int64_t cb;
   const double* Zr;
   int64_t ld;
-  __device__ void column(LcpWideLds& S, double* Wc, int cap, int m, int t) const {
-    if (S.Val[t]) return;
+  int m;
+  int64_t fs[CSL];
+  double nx[CSL], ny[CSL], nz[CSL];
+  __device__ RobotLcpSource(const Dev* d_, int r_, int64_t cb_, const double* Zr_, int64_t ld_, int m_)
+      : d(d_), r(r_), cb(cb_), Zr(Zr_), ld(ld_), m(m_) {
+#pragma unroll
+    for (int s = 0; s < CSL; ++s) {
+      const int i = (int)(threadIdx.x % NT) + NT * s;
+      const bool v = i < m;
+      const int64_t e = cb + (v ? i : 0);
+      fs[s] = v ? d->ct_node[e] - 1 : 0;
+      nx[s] = v ? d->ct_n[3 * e] : 0.0;
+      ny[s] = v ? d->ct_n[3 * e + 1] : 0.0;
+      nz[s] = v ? d->ct_n[3 * e + 2] : 0.0;
+    }
+  }
+  __device__ void fill(double* Wc, int cap, int t) const {   // column t into Wc
     const double* zt = Zr + (int64_t)(1 + t) * ld;
     double* wt = Wc + (int64_t)t * cap;
-    for (int i = threadIdx.x; i < m; i += NT) {
-      const int64_t f = d->ct_node[cb + i] - 1;
-      wt[i] = d->ct_n[3 * (cb + i)] * zt[6 * f] + d->ct_n[3 * (cb + i) + 1] * zt[6 * f + 1] +
-              d->ct_n[3 * (cb + i) + 2] * zt[6 * f + 2];
+    const int lane = threadIdx.x % NT;
+    if (m <= CSL * NT) {
+#pragma unroll
+      for (int s = 0; s < CSL; ++s) {
+        const int i = lane + NT * s;
+        if (i < m) wt[i] = nx[s] * zt[6 * fs[s]] + ny[s] * zt[6 * fs[s] + 1] + nz[s] * zt[6 * fs[s] + 2];
+      }
+    } else {
+      for (int i = lane; i < m; i += NT) {
+        const int64_t f = d->ct_node[cb + i] - 1;
+        wt[i] = d->ct_n[3 * (cb + i)] * zt[6 * f] + d->ct_n[3 * (cb + i) + 1] * zt[6 * f + 1] +
+                d->ct_n[3 * (cb + i) + 2] * zt[6 * f + 2];
+      }
     }
+  }
+  __device__ void column(LcpWideLds& S, double* Wc, int cap, int, int t) const {
+    if (S.Val[t]) return;
+    fill(Wc, cap, t);
     __syncthreads();
     if (threadIdx.x == 0) S.Val[t] = 1;
     __syncthreads();
   }
   __device__ bool warm(int i) const { return d->ct_warm[cb + i] != 0; }
   // the columns of the listed constraints, computed together (one barrier)
-  __device__ void columns(LcpWideLds& S, double* Wc, int cap, int m, const int* list, int cnt) const {
+  __device__ void columns(LcpWideLds& S, double* Wc, int cap, int, const int* list, int cnt) const {
 #pragma unroll 2
     for (int a = 0; a < cnt; ++a) {
       const int t = list[a];
-      if (S.Val[t]) continue;
-      const double* zt = Zr + (int64_t)(1 + t) * ld;
-      double* wt = Wc + (int64_t)t * cap;
-      for (int i = threadIdx.x; i < m; i += NT) {
-        const int64_t f = d->ct_node[cb + i] - 1;
-        wt[i] = d->ct_n[3 * (cb + i)] * zt[6 * f] + d->ct_n[3 * (cb + i) + 1] * zt[6 * f + 1] +
-                d->ct_n[3 * (cb + i) + 2] * zt[6 * f + 2];
-      }
+      if (!S.Val[t]) fill(Wc, cap, t);
     }
     __syncthreads();
     for (int a = threadIdx.x; a < cnt; a += NT) S.Val[list[a]] = 1;
@@ -1692,7 +1717,7 @@ __global__ void __launch_bounds__(NT) update_wide_kernel(Dev d, int it) {
   double* scratch = d.W + (int64_t)d.B * cap * cap + (int64_t)r * lcp_ws_doubles(cap);
   contact_q(d, cb, nc, Zr, qv);
   __syncthreads();
-  const RobotLcpSource src{&d, r, cb, Zr, ld};
+  const RobotLcpSource src(&d, r, cb, Zr, ld, nc);
   const LcpWs wl{S.L, S.Rd, S.Yp, S.P, NPW};
   const int code = lcp_wide<SPL>(src, S, wl, Wc, cap, qv, nc, y, true);
   if (threadIdx.x == 0) d.st_big[r] = code == 2 ? 1 : 0;
@@ -1721,7 +1746,7 @@ __global__ void __launch_bounds__(NT) update_big_kernel(Dev d, int it) {
   double* y = d.ct_y + cb;
   double* Wc = d.W + (int64_t)r * cap * cap;
   double* scratch = d.W + (int64_t)d.B * cap * cap + (int64_t)r * lcp_ws_doubles(cap);
-  const RobotLcpSource src{&d, r, cb, Zr, ld};
+  const RobotLcpSource src(&d, r, cb, Zr, ld, nc);
   if (lcp_wide<SPG>(src, S, global_ws(scratch, nc), Wc, cap, qv, nc, y, true) != 0) {
     finish(d, r, 2, it, d.st_rn[r]);
     return;
