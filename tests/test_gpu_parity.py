@@ -253,3 +253,39 @@ def test_invalid_calls_report_errors():
     assert e.value.status == fem.FEM_E_INVAL
     with pytest.raises(fem.FemError):
         ctx.fem_contacts(7)
+
+
+def test_short_robots_match_oracle():
+    """Robots of 2, 3, 4, 5 and 7 elements (the two-ended elimination with an empty tip side,
+    one node per side, ...) pushed into the straight tube by a dead lateral tip force sized to
+    deflect each free robot by 5 mm; every load step against the oracle per robot."""
+    from paper_2503_06922_amd import fem
+    rb0, V, T = make_config(0)
+    ne = [2, 3, 4, 5, 7]
+    rb = rb0.subset([0] * len(ne))
+    rb.n_elem[:] = ne
+    rb.length[:] = 0.015 * np.asarray(ne, float)
+    EI = np.pi / 4 * (rb.r_out**4 - rb.r_in**4) * rb.E
+    W = np.zeros((len(ne), 6))
+    W[:, 1] = -3 * EI * 5e-3 / rb.length**3
+    robs, mesh = oracle_robots(rb, V, T)
+    ctx = gpu_context(rb, V, T, newton_tol=1e-12, stag_tol=1e-9, max_newton=100)
+    n_steps = 5
+    trajs = []
+    for b, rob in enumerate(robs):
+        _, _, traj = solver.solve_robot(rob, lambda k, b=b: (0.0, W[b] * k / n_steps), n_steps,
+                                        act_kind=actuation.TIP_GLOBAL, tol=1e-12, stag_tol=1e-9)
+        trajs.append(traj)
+    n_active = 0
+    for k in range(1, n_steps + 1):
+        ctx.fem_set_actuation(fem.FEM_ACT_TIP_WRENCH_GLOBAL, (W * k / n_steps).ravel(), None)
+        out = ctx.fem_solve(1)
+        for b, (sl, rob) in enumerate(zip(robot_slices(rb), robs)):
+            o = trajs[b][k - 1]
+            assert out["info"][b]["status"] == 0 and o["info"]["status"] == solver.OK, (b, k)
+            Pref = rob.reference()[0]
+            assert displacement_error(out["state"][sl, 0:3], o["P"], Pref) <= 1e-9, (b, k)
+            n_cmp, _ = compare_contact_keys(ctx.fem_contacts(b), list(zip(o["contacts"], o["y"])),
+                                            o["P"], rob)
+            n_active += n_cmp
+    assert n_active > 0
