@@ -73,21 +73,29 @@ def algorithmic_bytes(info, n_nodes, sb, steps):
     }
 
 
-def measured_traffic(kernel):
-    """Per-launch HBM bytes of `kernel` from the committed rocprofv3 counter summary, if the
-    kernel's source is unchanged since the counters were taken (else None)."""
+def traffic_key(kernel, capacity):
+    """What the counters of `kernel` depend on: its source, the shared device header and the
+    contact capacity of the run (hashed together)."""
     import hashlib
+    h = hashlib.sha256()
+    for name in (KERNEL_SOURCE[kernel], "fem_device.h"):
+        with open(os.path.join(ROOT, "paper_2503_06922_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    h.update(b"capacity=%d" % capacity)
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, capacity):
+    """Per-launch HBM bytes of `kernel` from the committed rocprofv3 counter summary, if the
+    kernel's source, the device header and the contact capacity are those the counters were
+    taken with (else None)."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f).get(kernel)
-    if not rec:
+    if not rec or traffic_key(kernel, capacity) != rec.get("key_sha256"):
         return None
-    src = os.path.join(ROOT, "paper_2503_06922_amd", "csrc", KERNEL_SOURCE[kernel])
-    with open(src, "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != rec.get("source_sha256"):
-            return None
     return rec.get("bytes_per_launch")
 
 
@@ -176,7 +184,7 @@ def main():
     ap.add_argument("--load-steps", type=int, default=100)
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--max-newton", type=int, default=60)
-    ap.add_argument("--capacity", type=int, default=256)
+    ap.add_argument("--capacity", type=int, default=512)
     ap.add_argument("--cpu-robots", type=int, default=2)
     ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--single-robots", type=int, default=4)
@@ -257,7 +265,7 @@ def main():
         launches = max(prof[k][1], 1)
         avg_s = prof[k][0] / 1e3 / launches
         gbs = total_bytes / launches / avg_s / 1e9
-        tr = measured_traffic(name)
+        tr = measured_traffic(name, args.capacity)
         roofs[name] = dict(bound="hbm", kernel=name, achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s",
                            frac=gbs / HBM_PEAK_GBS, traffic=tr, bytes_per_unit=per_unit,
                            bytes_per_launch=total_bytes / launches, avg_launch_us=avg_s * 1e6)
@@ -273,6 +281,7 @@ def main():
                                "50k-triangle branching lumen" % (rb.n_robots, args.load_steps),
                    "robots": int(rb.n_robots), "load_steps": args.load_steps,
                    "precision": args.precision, "max_newton": args.max_newton,
+                   "contact_capacity": args.capacity,
                    "nodes": int(ctx.n_nodes)},
         "converged_fraction": conv / max(total, 1),
         "newton_iters_per_solve": iters / max(total, 1),

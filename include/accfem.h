@@ -72,7 +72,7 @@ enum {
   FEM_ROBOT_NOCONV = 1,    /* max_newton iterations without convergence */
   FEM_ROBOT_LCPFAIL = 2,   /* the contact active-set method did not terminate */
   FEM_ROBOT_NONSPD = 3,    /* a Cholesky pivot was not positive */
-  FEM_ROBOT_OVERFLOW = 4   /* more contacts than contact_capacity */
+  FEM_ROBOT_OVERFLOW = 4   /* more contacts than contact_capacity, or more than 48 at a node */
 };
 
 typedef struct {

@@ -22,7 +22,8 @@ namespace accfem {
 __host__ __device__ inline int64_t lcp_ws_doubles(int cap) {
   return (int64_t)cap * (cap + 1) / 2 + 3 * (int64_t)cap;
 }
-constexpr int MAXC = 8;          // contact candidates kept per node
+constexpr int MAXC = 48;         // contact candidates kept per node (a node in a branch
+                                 // narrower than the band meets a ring of facets)
 constexpr int SOLVE_THREADS = 64;  // one wavefront per robot in the solve kernel
 
 struct Dev {
