@@ -112,9 +112,10 @@ def out_of_balance(robot, P, R, act_kind, act_values):
 
 def detect(robot, P, guided=None, prev=None):
     """Contacts of the current iterate.  With prev = (contacts, y) of the previous Newton
-    iterate, its active face contacts that were not detected again persist as the same
-    plane constraint while the node stays within the detection band of that triangle and
-    no detected contact at the node lies on the same plane (see persist_faces)."""
+    iterate, its active contacts that were not detected again persist (a face as its plane,
+    an edge/vertex contact as the direction from the triangle's nearest point) while the
+    node stays within the detection band of that triangle and no detected contact at the
+    node lies on the same plane (see persist_faces)."""
     if robot.mesh is None:
         return []
     det = collision.active(collision.detect(P, robot.mesh, robot.r_c, robot.delta, skip=guided))
@@ -127,15 +128,21 @@ PLANE_TOL = 1e-9
 
 
 def persist_faces(robot, P, det, cont_prev, y_prev):
-    """Detected contacts plus the persisting faces, ordered by (node, kind, triangle).
+    """Detected contacts plus the persisting ones, ordered by (node, kind, triangle).
 
     Within a Newton loop the iterate can cross from one triangle's face region into the
     neighbouring edge or vertex region and back on every step, so that the detected set
-    never settles (a 2-cycle between a face contact and the edge/vertex fallback).  A face
-    contact that carried force (y > 0) in the previous iterate therefore stays, with its
-    plane n_t . (p - v0_t) - r_c as the gap, as long as the node's distance to the
-    triangle is at most r_c + delta; it is dropped when a detected contact at the node has
-    the same plane (normals and gaps equal within PLANE_TOL: coplanar neighbours).
+    never settles (a 2-cycle between a face contact and the edge/vertex fallback, which is
+    only detected while the node has no detected face contact).  A contact that carried
+    force (y > 0) in the previous iterate and is not detected again with the same triangle
+    and kind therefore stays, as long as the node's distance to the triangle is at most
+    r_c + delta:
+      * a face contact as its plane, gap n_t . (p - v0_t) - r_c;
+      * an edge/vertex contact as the direction from the triangle's nearest point q,
+        n = (p - q) / |p - q|, gap |p - q| - r_c, while the node is on the triangle's inner
+        side (n_t . (p - v0_t) > 0, the fallback's own condition).
+    It is dropped when a detected contact at the node has the same plane (normals and gaps
+    equal within PLANE_TOL: coplanar neighbours).
     """
     mesh = robot.mesh
     band = robot.r_c + robot.delta
@@ -145,19 +152,27 @@ def persist_faces(robot, P, det, cont_prev, y_prev):
         by_node.setdefault(c["node"], []).append(c)
     extra = []
     for c, y in zip(cont_prev, y_prev):
-        if not (y > 0.0) or c["kind"] != 0 or (c["node"], c["tri"], 0) in keys:
+        key = (c["node"], c["tri"], c["kind"])
+        if not (y > 0.0) or key in keys:
             continue
         i, t = c["node"], c["tri"]
         p = P[i]
         cpt, _, _ = collision.closest_points(p, mesh, np.array([t]))
-        if not (np.linalg.norm(p - cpt[0]) <= band):
+        dist = float(np.linalg.norm(p - cpt[0]))
+        if not (dist <= band):
             continue
-        gap = float(mesh.n[t] @ (p - mesh.v0[t])) - robot.r_c
-        if any(abs(float(mesh.n[t] @ o["n"]) - 1.0) <= PLANE_TOL and abs(o["gap"] - gap) <= PLANE_TOL
+        s_t = float(mesh.n[t] @ (p - mesh.v0[t]))
+        if c["kind"] == collision.FACE:
+            n, gap = mesh.n[t].copy(), s_t - robot.r_c
+        else:
+            if not (s_t > 0.0) or dist == 0.0:
+                continue
+            n, gap = (p - cpt[0]) / dist, dist - robot.r_c
+        if any(abs(float(n @ o["n"]) - 1.0) <= PLANE_TOL and abs(o["gap"] - gap) <= PLANE_TOL
                for o in by_node.get(i, [])):
             continue
         amb = any(o.get("ambiguous", False) for o in by_node.get(i, []))
-        extra.append(dict(node=i, tri=t, kind=0, n=mesh.n[t].copy(), gap=gap, ambiguous=amb))
+        extra.append(dict(node=i, tri=t, kind=c["kind"], n=n, gap=gap, ambiguous=amb))
     return sorted(det + extra, key=lambda c: (c["node"], c["kind"], c["tri"]))
 
 

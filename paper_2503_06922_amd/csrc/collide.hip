@@ -9,10 +9,12 @@
 //   face contacts : region = face and -r_c <= s <= r_c + delta      (all of them)
 //   fallback      : if a node has no face contact, the nearest edge/vertex point
 //                   with s > 0 within r_c + delta (ties to the lowest triangle)
-//   persisting    : a face contact of the previous Newton iterate with force > 0 that is
-//                   not detected again stays as its plane while the node is within
-//                   r_c + delta of the triangle, unless a detected contact at the node
-//                   has the same plane (normals and gaps within PLANE_TOL)
+//   persisting    : a contact of the previous Newton iterate with force > 0 that is not
+//                   detected again (same triangle and kind) stays while the node is within
+//                   r_c + delta of the triangle: a face as its plane, an edge/vertex contact
+//                   as the direction from the triangle's nearest point (while s > 0), unless
+//                   a detected contact at the node has the same plane (normals and gaps
+//                   within PLANE_TOL)
 // Every entry also carries whether it had force > 0 at the previous iterate (detected
 // again with the same triangle and kind, or persisting): the LCP starts from those.
 // The base node and nodes held by the insertion guide are skipped.  Results are
@@ -110,7 +112,7 @@ __device__ __forceinline__ bool screen32(const Dev& d, int64_t t, P3<float> p, f
 // node's cell list (consecutive entries to consecutive lanes), face contacts are appended
 // in ballot order, the fallback is the group's lexicographic minimum of (distance, triangle)
 // (the lowest triangle index among equally near ones, as a walk in list order finds), and
-// the group's first lane adds the persisting faces and orders the node's entries.
+// the group's first lane adds the persisting contacts and orders the node's entries.
 constexpr int CL = 8;
 
 __global__ void __launch_bounds__(256) collide_kernel(Dev d) {
@@ -220,9 +222,9 @@ __global__ void __launch_bounds__(256) collide_kernel(Dev d) {
   }
   __threadfence_block();                 // the group's entries precede the first lane's reads
   if (j != 0) return;
-  // persisting faces: the face contacts of this node that carried force in the previous
-  // iterate and were not detected again stay as their plane while the node is within the
-  // band of that triangle, unless a detected contact at the node lies on the same plane
+  // persisting contacts: those of this node that carried force in the previous iterate and
+  // were not detected again stay while the node is within the band of their triangle,
+  // unless a detected contact at the node lies on the same plane
   const int ndet = min(cnt, MAXC);
   const int64_t cb = (int64_t)r * d.cap;
   const int ncp = d.st_ncp[r];
@@ -239,25 +241,37 @@ __global__ void __launch_bounds__(256) collide_kernel(Dev d) {
     bool found = false;
     for (int q = 0; q < ndet; ++q)
       if (d.CK[q * N + g] == kc && d.CT[q * N + g] == t) { d.CW[q * N + g] = 1; found = true; }
-    if (found || kc != 0) continue;
+    if (found) continue;
     const TriTest tt = test_tri64(d, t, p);
     if (!(tt.dist <= band)) continue;
-    const double gap = tt.s - d.r_c;
+    // a face keeps its plane; an edge/vertex contact keeps the direction from the triangle's
+    // nearest point while the node stays on the triangle's inner side
+    double gap;
+    P3<double> nc;
+    if (kc == 0) {
+      gap = tt.s - d.r_c;
+      nc = tt.n;
+    } else {
+      if (!(tt.s > 0.0) || tt.dist == 0.0) continue;
+      const double inv = 1.0 / tt.dist;
+      gap = tt.dist - d.r_c;
+      nc = P3<double>{(p.x - tt.cp.x) * inv, (p.y - tt.cp.y) * inv, (p.z - tt.cp.z) * inv};
+    }
     bool skip = false;
     for (int q = 0; q < ndet; ++q) {
-      const double nn = tt.n.x * d.CN[(3 * q) * N + g] + tt.n.y * d.CN[(3 * q + 1) * N + g] +
-                        tt.n.z * d.CN[(3 * q + 2) * N + g];
+      const double nn = nc.x * d.CN[(3 * q) * N + g] + nc.y * d.CN[(3 * q + 1) * N + g] +
+                        nc.z * d.CN[(3 * q + 2) * N + g];
       skip |= fabs(nn - 1.0) <= PLANE_TOL && fabs(d.CG[q * N + g] - gap) <= PLANE_TOL;
     }
     if (skip) continue;
     if (cnt < MAXC) {
       d.CT[cnt * N + g] = t;
-      d.CK[cnt * N + g] = 0;
+      d.CK[cnt * N + g] = kc;
       d.CW[cnt * N + g] = 1;
       d.CG[cnt * N + g] = gap;
-      d.CN[(3 * cnt + 0) * N + g] = tt.n.x;
-      d.CN[(3 * cnt + 1) * N + g] = tt.n.y;
-      d.CN[(3 * cnt + 2) * N + g] = tt.n.z;
+      d.CN[(3 * cnt + 0) * N + g] = nc.x;
+      d.CN[(3 * cnt + 1) * N + g] = nc.y;
+      d.CN[(3 * cnt + 2) * N + g] = nc.z;
     }
     ++cnt;
   }

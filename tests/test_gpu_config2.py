@@ -9,7 +9,7 @@ are checked, at sampled load steps, against what the oracle computes at any size
     state finds the GPU's contact set, outside nodes with near-threshold decisions (an
     edge/vertex contact may carry another triangle whose nearest point is the same within
     1e-9 m, with the same gap: the codes break such ties differently); any other GPU entry is
-    a persisting face still within the band of its triangle;
+    a persisting contact still within the band of its triangle;
   * the contact conditions of eq. 12: forces >= 0, gaps >= 0 to the tolerance, force x gap = 0;
   * mixed precision against the FP64 GPU path: relative tip error <= 1e-5.
 """
@@ -96,10 +96,12 @@ def test_config2_equilibrium_detection_complementarity(config2_runs):
                          [(c["tri"], c["kind"], list(c["n"]), c["gap"]) for c in cts if c["node"] == node])
             same_geom.add((node, alt[0]["tri"], kind))
         for (node, tri, kind) in sorted(gpu - orc - same_geom):
-            # a persisting face: the oracle's closest point of that triangle is within the band
-            assert kind == 0, (s["k"], node, tri, kind)
+            # a persisting contact: the oracle's closest point of that triangle is within the
+            # band; an edge/vertex one also has the node on the triangle's inner side
             cpt, _, _ = collision.closest_points(P[node], rob.mesh, np.array([tri]))
             assert np.linalg.norm(P[node] - cpt[0]) <= band + 1e-12, (s["k"], node, tri)
+            if kind != 0:
+                assert rob.mesh.n[tri] @ (P[node] - rob.mesh.v0[tri]) > 0.0, (s["k"], node, tri, kind)
         # contact conditions
         for c in cts:
             assert c["force"] >= 0.0

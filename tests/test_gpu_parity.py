@@ -289,3 +289,29 @@ def test_short_robots_match_oracle():
                                             o["P"], rob)
             n_active += n_cmp
     assert n_active > 0
+
+
+def test_persisting_edge_contact_converges_like_oracle():
+    """A robot of the batched workload (116 elements) whose tip node, at load step 24, used to
+    alternate between a detected face and an edge fallback on every iteration (60 iterations,
+    not converged): with force-carrying edge/vertex contacts persisting, the GPU and the oracle
+    converge on every load step to the same state and active set."""
+    rb, V, T = make_config(3)
+    sub = rb.subset([2950])
+    assert int(sub.n_elem[0]) == 116
+    robs, mesh = oracle_robots(sub, V, T)
+    rob = robs[0]
+    ctx = gpu_context(sub, V, T, newton_tol=1e-10, stag_tol=1e-9, max_newton=60)
+    P, R = rob.reference()
+    Pref = P.copy()
+    for k in range(1, 25):
+        d, t = load_schedule(sub, k)
+        ctx.fem_set_actuation(0, t.ravel(), d)
+        out = ctx.fem_solve(1)
+        P, R, cont, y, info = solver.solve_load_step(rob, P, R, rob.base_target(d[0]), 0, t[0],
+                                                     tol=1e-10, stag_tol=1e-9, max_iter=60,
+                                                     guided=rob.guided(d[0]))
+        assert info["status"] == solver.OK and out["info"][0]["status"] == 0, k
+        assert displacement_error(out["state"][:, 0:3], P, Pref) <= 1e-9, k
+        compare_contact_keys(ctx.fem_contacts(0), list(zip(cont, y)), P, rob)
+    ctx.close()

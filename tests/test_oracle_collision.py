@@ -136,3 +136,41 @@ def test_persisting_face_skips_coplanar_duplicate():
     prev = [dict(node=1, tri=0, kind=0, n=mesh.n[0].copy(), gap=0.0)]
     assert collision.contact_set(solver.detect(rob, P, prev=(prev, np.array([0.2])))) == \
         collision.contact_set(det)
+
+
+def test_persisting_edge_contact_rules_by_hand():
+    """The same convex ridge along x = 0 (shared by triangles 0 and 3).  A node that was pressed
+    on the ridge through an edge contact of triangle 3 and is now back over face 0 (face 0
+    detected, so no fallback) keeps that contact as the direction from the ridge:
+    n = (p - q) / |p - q| with q the foot of p on the ridge line, gap |p - q| - r_c.  The same
+    contact taken on triangle 0, whose nearest point is now the foot on face 0, lies on face
+    0's plane and is dropped; below the plane of triangle 3 it is not kept."""
+    from oracle import solver
+    s = np.sin(np.radians(20.0)); c = np.cos(np.radians(20.0))
+    V = np.array([[-0.01, -0.01, 0.0], [0.0, -0.01, 0.0], [0.0, 0.01, 0.0], [-0.01, 0.01, 0.0],
+                  [0.01 * c, -0.01, -0.01 * s], [0.01 * c, 0.01, -0.01 * s]])
+    T = np.array([[0, 1, 2], [0, 2, 3], [1, 4, 5], [1, 5, 2]])
+    mesh = collision.Mesh(V, T)
+    rob = _persist_robot(mesh)
+    r_c = rob.r_c
+    P = np.array([[-0.015, 0.0, 0.01], [-0.0005, -0.002, 0.0016], [0.015, 0.0, 0.01]])
+    det = solver.detect(rob, P)
+    assert [(c_["node"], c_["tri"], c_["kind"]) for c_ in det] == [(1, 0, 0)]
+    prev = [dict(node=1, tri=3, kind=1, n=np.array([0.0, 0.0, 1.0]), gap=0.0)]
+    got = solver.detect(rob, P, prev=(prev, np.array([0.4])))
+    assert [(c_["node"], c_["tri"], c_["kind"]) for c_ in got] == [(1, 0, 0), (1, 3, 1)]
+    q = np.array([0.0, -0.002, 0.0])
+    dq = P[1] - q
+    assert np.allclose(got[1]["n"], dq / np.linalg.norm(dq), rtol=0, atol=1e-14)
+    assert got[1]["gap"] == pytest.approx(np.linalg.norm(dq) - r_c, abs=1e-15)
+    # the same contact on triangle 0: its nearest point is the foot on face 0 -> same plane
+    prev0 = [dict(node=1, tri=0, kind=1, n=np.array([0.0, 0.0, 1.0]), gap=0.0)]
+    assert collision.contact_set(solver.detect(rob, P, prev=(prev0, np.array([0.4])))) == \
+        collision.contact_set(det)
+    # within the band of triangle 3 but below its plane: not kept
+    P3 = P.copy()
+    P3[1] = [-0.002, -0.002, 0.0006]
+    assert mesh.n[3][2] > 0 and float(mesh.n[3] @ (P3[1] - V[1])) < 0
+    assert np.linalg.norm(P3[1] - np.array([0.0, -0.002, 0.0])) <= r_c + rob.delta
+    assert collision.contact_set(solver.detect(rob, P3, prev=(prev, np.array([0.4])))) == \
+        collision.contact_set(solver.detect(rob, P3))
