@@ -215,14 +215,15 @@ fem_status fem_profile(fem_ctx* c, int32_t kernel, double* total_ms, int64_t* la
  * (the contact conditions of eq. 12 for the contact forces y, with W = A_c K^-1 A_c^T
  * the contact-space Schur complement) with the device routines that fem_solve applies
  * to a robot's contact set; no context.  Intended for verification of those routines.
- *   W [m*m] symmetric positive definite, column-major; q [m]; y [m] output; host memory
+ *   W [m*m] symmetric positive semidefinite, column-major; q [m]; y [m] output; host memory
  *   *path: the routine taken, 0 = active set with W packed in LDS (m <= 64),
  *          1 = wavefront active set with W columns in device memory and the Cholesky
  *          factor of the active block in LDS (m > 64), 2 = that routine's single-lane
  *          fallback once the active set outgrows 128 positions
  * Runs on the null stream of the current device and allocates and frees its own device
  * buffers.  FEM_E_INVAL: NULL pointers or m outside 1..1024.  FEM_E_NOCONV: a
- * non-positive pivot or the iteration limit (y not written).  FEM_E_NOMEM, FEM_E_HIP. */
+ * non-positive pivot, a dependent constraint that no active one can give way to (no
+ * solution), or the iteration limit (y not written).  FEM_E_NOMEM, FEM_E_HIP. */
 fem_status fem_lcp(const double* W, const double* q, int32_t m, double* y, int32_t* path);
 
 /* Total number of nodes over the batch (sum of n_elem + 1), or -1 for NULL. */

@@ -950,17 +950,20 @@ __device__ __forceinline__ void wave_argmin(double& v, int& idx) {
 }
 
 // Primal active-set method for the LCP  w = W y + q >= 0, y >= 0, y.w = 0  with W symmetric
-// positive definite, i.e. the convex QP  min 1/2 y.W y + q.y  over y >= 0 (the Lawson-Hanson
+// positive semidefinite, i.e. the convex QP  min 1/2 y.W y + q.y  over y >= 0 (the Lawson-Hanson
 // scheme): add the most violated inactive constraint (most negative w), solve
 // W_PP z = -q_P; if z > 0 take it, else move from y toward z until the first active y
 // reaches zero, drop those and solve again.  This version runs on one wavefront for
 // m <= LCPM with everything in LDS.  Lane i owns constraint i.  sW holds W packed (lower, constraint
 // order); sL the Cholesky factor of W_PP packed with rows in active-set order and sRd its
 // reciprocal diagonal; sP the active set in order of entry; sYp the active y by position.
-// Adding the most violated constraint appends one row to the factor; dropping constraints
-// refactors.  `warm` flags a starting active set (the contacts active at the previous
+// Adding the most violated constraint appends one row to the factor; one that depends
+// linearly on the active set (W only semidefinite: more contacts at a node than it has
+// directions) is exchanged for an active one along a null direction of W; dropping
+// constraints refactors.  `warm` flags a starting active set (the contacts active at the previous
 // iteration); it is used when its own solution is positive, else the start is empty.
-// Returns false on a non-positive pivot or when the iteration limits are reached.
+// Returns false on a non-positive pivot, a dependent constraint that no active one can
+// give way to, or when the iteration limits are reached.
 struct LcpLds {
   double W[LCPM * (LCPM + 1) / 2];
   double L[LCPM * (LCPM + 1) / 2];
@@ -1054,17 +1057,36 @@ __device__ bool lcp_parallel(LcpLds& S, const double* q, int m, bool warm, doubl
     }
     const double dtt = S.W[pk(t, t)] - warp_sum(lane < np ? bv * bv : 0.0);
     __syncthreads();
-    if (!(dtt > 0.0)) { failed = true; break; }
-    if (lane < np) S.L[pk(np, lane)] = bv;
-    if (lane == 0) {
-      S.L[pk(np, np)] = 1.0;
-      S.Rd[np] = rsqrt_nr(dtt);
-      S.P[np] = t;
-      S.Yp[np] = 0.0;
-      S.In[t] = 1;
+    if (dtt > 0.0) {
+      if (lane < np) S.L[pk(np, lane)] = bv;
+      if (lane == 0) {
+        S.L[pk(np, np)] = 1.0;
+        S.Rd[np] = rsqrt_nr(dtt);
+        S.P[np] = t;
+        S.Yp[np] = 0.0;
+        S.In[t] = 1;
+      }
+      ++np;
+      __syncthreads();
+    } else {
+      // t depends linearly on the active set (several contacts at one node): W(P, t) =
+      // W_PP c.  Raising y_t by s and lowering y_P by s c leaves every w unchanged; the
+      // first active y to reach zero (smallest y_a / c_a over c_a > 0) leaves and t takes
+      // its position, which keeps the set independent.  No c_a > 0: no solution.
+      const double c = lcp_solve(S, np, lane < np ? S.W[pks(S.P[lane], t)] : 0.0);
+      const double cmax = warp_max(lane < np ? fabs(c) : 0.0);
+      double rat = (lane < np && c > 1e-12 * cmax) ? S.Yp[lane] / c : INFINITY;
+      int jp = lane;
+      wave_argmin(rat, jp);
+      if (!(rat < INFINITY)) { failed = true; break; }
+      const double yv = lane < np ? (lane == jp ? rat : fmax(S.Yp[lane] - rat * c, 0.0)) : 0.0;
+      const int oldj = S.P[jp];
+      __syncthreads();
+      if (lane < np) S.Yp[lane] = yv;
+      if (lane == 0) { S.In[oldj] = 0; S.P[jp] = t; S.In[t] = 1; }
+      __syncthreads();
+      if (!lcp_factor(S, np)) { failed = true; break; }
     }
-    ++np;
-    __syncthreads();
     for (int inner = 0; inner < 4 * m + 8; ++inner) {
       const double z = lcp_solve(S, np, lane < np ? -q[S.P[lane]] : 0.0);
       if (__ballot(lane < np && !(z > 0.0)) == 0ull) {
@@ -1602,21 +1624,58 @@ __device__ int lcp_wide(const Src& src, LcpWideLds& S, const LcpWs& w, double* W
     for (int s = 0; s < SP; ++s) ss += (lane + NT * s < np) ? bv[s] * bv[s] : 0.0;
     const double dtt = Wc[(int64_t)t * cap + t] - warp_sum(ss);
     __syncthreads();
-    if (!(dtt > 0.0)) { failed = true; break; }
+    if (dtt > 0.0) {
 #pragma unroll
-    for (int s = 0; s < SP; ++s) {
-      const int p = lane + NT * s;
-      if (p < np) w.L[pk(np, p)] = bv[s];
+      for (int s = 0; s < SP; ++s) {
+        const int p = lane + NT * s;
+        if (p < np) w.L[pk(np, p)] = bv[s];
+      }
+      if (lane == 0) {
+        w.L[pk(np, np)] = 1.0;
+        w.Rd[np] = rsqrt_nr(dtt);
+        w.P[np] = t;
+        w.Yp[np] = 0.0;
+        S.In[t] = 1;
+      }
+      ++np;
+      __syncthreads();
+    } else {
+      // t depends linearly on the active set: exchange it for the first active constraint
+      // whose y reaches zero along y_P - s c, c = W_PP^-1 W(P, t) (every w unchanged)
+      wide_bwd<SP>(w, np, bv);
+      double cmax = 0.0;
+#pragma unroll
+      for (int s = 0; s < SP; ++s) cmax = fmax(cmax, (lane + NT * s < np) ? fabs(bv[s]) : 0.0);
+      cmax = warp_max(cmax);
+      double rat = INFINITY;
+      int jp = 0x7fffffff;
+#pragma unroll
+      for (int s = 0; s < SP; ++s) {
+        const int p = lane + NT * s;
+        if (p < np && bv[s] > 1e-12 * cmax) {
+          const double r = w.Yp[p] / bv[s];
+          if (r < rat) { rat = r; jp = p; }
+        }
+      }
+      wave_argmin(rat, jp);
+      if (!(rat < INFINITY)) { failed = true; break; }
+      double yv[SP];
+#pragma unroll
+      for (int s = 0; s < SP; ++s) {
+        const int p = lane + NT * s;
+        yv[s] = p < np ? (p == jp ? rat : fmax(w.Yp[p] - rat * bv[s], 0.0)) : 0.0;
+      }
+      const int oldj = w.P[jp];
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < SP; ++s) {
+        const int p = lane + NT * s;
+        if (p < np) w.Yp[p] = yv[s];
+      }
+      if (lane == 0) { S.In[oldj] = 0; w.P[jp] = t; S.In[t] = 1; }
+      __syncthreads();
+      if (!wide_factor<SP>(w, Wc, cap, np)) { failed = true; break; }
     }
-    if (lane == 0) {
-      w.L[pk(np, np)] = 1.0;
-      w.Rd[np] = rsqrt_nr(dtt);
-      w.P[np] = t;
-      w.Yp[np] = 0.0;
-      S.In[t] = 1;
-    }
-    ++np;
-    __syncthreads();
     for (int inner = 0; inner < 4 * m + 8; ++inner) {
       double z[SP];
 #pragma unroll

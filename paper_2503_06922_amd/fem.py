@@ -300,7 +300,7 @@ def state_to_PR(X):
 
 def fem_lcp(W, q):
     """LCP w = W y + q >= 0, y >= 0, y.w = 0 solved by the library's device routines
-    (W symmetric positive definite).  Returns (y, path) with path 0 (LDS active set,
+    (W symmetric positive semidefinite).  Returns (y, path) with path 0 (LDS active set,
     m <= 64), 1 (wavefront active set) or 2 (its single-lane fallback)."""
     W = np.asarray(W, dtype=np.float64)
     m = W.shape[0]

@@ -94,3 +94,36 @@ def test_wide_contact_set_trajectory_matches_oracle():
         fo = node_forces([dict(c, force=y) for c, y in zip(o["contacts"], o["y"])], Pg.shape[0])
         assert np.abs(fg - fo).max() <= 1e-7 * max(np.abs(fo).max(), 1e-12) + 1e-13
     assert wide == rb.n_load_steps
+
+
+def _singular_problem(m, r, seed):
+    """W = B B^T / r of rank r < m (more constraints than independent directions, as when
+    several contacts share a node) and q = w* - W y* from a complementary pair with y* > 0 on
+    r + 3 constraints: solvable, and no solution's active set is independent of the rest."""
+    rng = np.random.default_rng([m, r, seed])
+    B = rng.normal(size=(m, r))
+    W = B @ B.T / r
+    S = rng.permutation(m)[: r + 3]
+    y = np.zeros(m)
+    y[S] = rng.uniform(0.2, 1.0, size=len(S))
+    w = rng.uniform(0.1, 1.0, size=m)
+    w[S] = 0.0
+    return W, w - W @ y
+
+
+@pytest.mark.parametrize("m,r,path", [(9, 4, 0), (40, 12, 0), (100, 30, 1), (700, 200, 2)])
+def test_lcp_routines_semidefinite_W(m, r, path):
+    """Singular W: y is not unique, but w = W y + q is (a convex QP's gradient is constant on
+    its optimal set); the routines must exchange dependent constraints instead of failing."""
+    from paper_2503_06922_amd import fem
+    for seed in range(2):
+        W, q = _singular_problem(m, r, seed)
+        y, p = fem.fem_lcp(W, q)
+        yo = lcp.lemke(W, q)
+        assert p == path, (m, p)
+        scale = max(np.abs(q).max(), 1.0)
+        w, wo = W @ y + q, W @ yo + q
+        assert np.all(y >= 0.0)
+        assert w.min() >= -1e-10 * scale, (m, seed, w.min())
+        assert np.max(y * np.abs(w)) <= 1e-10 * scale * max(y.max(), 1.0), (m, seed)
+        assert np.abs(w - wo).max() <= 1e-9 * scale, (m, seed, np.abs(w - wo).max())

@@ -291,20 +291,23 @@ def test_short_robots_match_oracle():
     assert n_active > 0
 
 
-def test_persisting_edge_contact_converges_like_oracle():
-    """A robot of the batched workload (116 elements) whose tip node, at load step 24, used to
+@pytest.mark.parametrize("robot,n_elem,n_steps", [(2950, 116, 24), (1509, 240, 27)])
+def test_contact_cycles_and_dependent_contacts_converge_like_oracle(robot, n_elem, n_steps):
+    """Two robots of the batched workload: robot 2950, whose tip node at load step 24 used to
     alternate between a detected face and an edge fallback on every iteration (60 iterations,
-    not converged): with force-carrying edge/vertex contacts persisting, the GPU and the oracle
-    converge on every load step to the same state and active set."""
+    not converged; fixed by persisting edge/vertex contacts), and robot 1509, whose LCP at
+    load step 27 meets a contact that depends linearly on the active ones (the active-set
+    method used to give up; fixed by the exchange along a null direction of W).  The GPU and
+    the oracle converge on every load step to the same state and active set."""
     rb, V, T = make_config(3)
-    sub = rb.subset([2950])
-    assert int(sub.n_elem[0]) == 116
+    sub = rb.subset([robot])
+    assert int(sub.n_elem[0]) == n_elem
     robs, mesh = oracle_robots(sub, V, T)
     rob = robs[0]
     ctx = gpu_context(sub, V, T, newton_tol=1e-10, stag_tol=1e-9, max_newton=60)
     P, R = rob.reference()
     Pref = P.copy()
-    for k in range(1, 25):
+    for k in range(1, n_steps + 1):
         d, t = load_schedule(sub, k)
         ctx.fem_set_actuation(0, t.ravel(), d)
         out = ctx.fem_solve(1)
