@@ -312,6 +312,15 @@ def main():
                                         "p99": float(np.percentile(e, 99)) if both.any() else None,
                                         "within_1e-5": int(np.sum(e <= 1e-5)),
                                         "robots_compared": int(both.sum())}
+        # robots that converged on every load step in both precisions (no diverging restart
+        # from a failed load step's last iterate on either side)
+        every = np.array([i["steps_converged"] == i["steps_total"] and
+                          j["steps_converged"] == j["steps_total"] for i, j in zip(info, info64)])
+        ea = err[every]
+        res["tip_err_mixed_vs_fp64"]["every_step_converged"] = {
+            "robots": int(every.sum()), "within_1e-5": int(np.sum(ea <= 1e-5)),
+            "p99": float(np.percentile(ea, 99)) if every.any() else None,
+            "max": float(ea.max()) if every.any() else None}
         c64.close()
     if not args.no_single:
         # plain FP64 path of configuration 0: one robot per context, run one after another
