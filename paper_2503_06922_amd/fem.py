@@ -274,7 +274,9 @@ class Context:
 
 def params_from_batch(rb, precision=FEM_FP64, newton_tol=1e-10, stag_tol=1e-9, max_newton=100,
                       contact_capacity=64, **extra):
-    """fem_params of a workloads.RobotBatch (field mapping only)."""
+    """fem_params of a workloads.RobotBatch (field mapping only).  contact_capacity is the
+    length of each robot's contact list; a robot with more candidates ends its load step
+    with FEM_ROBOT_OVERFLOW (the batched insertion into the branching lumen needs 512)."""
     p = dict(n_robots=rb.n_robots, n_elem=rb.n_elem, length=rb.length, base_pos=rb.base_pos,
              base_dir=rb.base_dir, base_up=rb.base_up, r_out=rb.r_out, r_in=rb.r_in, E=rb.E,
              nu=rb.nu, tip_len=rb.tip_len, shaft_E=rb.shaft_E, shaft_A=rb.shaft_A,
