@@ -318,3 +318,40 @@ def test_contact_cycles_and_dependent_contacts_converge_like_oracle(robot, n_ele
         assert displacement_error(out["state"][:, 0:3], P, Pref) <= 1e-9, k
         compare_contact_keys(ctx.fem_contacts(0), list(zip(cont, y)), P, rob)
     ctx.close()
+
+
+def test_full_batch_in_bench_configuration_sampled_robots():
+    """All 4096 robots of the batched insertion in the launch configuration of the benchmark
+    (mixed precision, contact capacity 512, at most 60 Newton iterations) through its first 12
+    load steps, where the first contacts appear; six seeded robots against their own oracle
+    solves at every load step: same status, displacement within 1e-7 and tip within 1e-5 of
+    the robot length (the mixed-precision bar), identical active sets."""
+    from paper_2503_06922_amd import fem
+    rb, V, T = make_config(3)
+    assert rb.n_robots == 4096
+    pick = sorted(np.random.default_rng(2025).choice(rb.n_robots, size=6, replace=False).tolist())
+    sub = rb.subset(pick)
+    robs, mesh = oracle_robots(sub, V, T)
+    ctx = gpu_context(rb, V, T, precision=fem.FEM_MIXED, newton_tol=1e-10, stag_tol=1e-9,
+                      max_newton=60, contact_capacity=512)
+    states = [r.reference() for r in robs]
+    slices = robot_slices(rb)
+    n_active = 0
+    for k in range(1, 13):
+        d, t = load_schedule(rb, k)
+        ctx.fem_set_actuation(0, t.ravel(), d)
+        out = ctx.fem_solve(1)
+        for j, (b, rob) in enumerate(zip(pick, robs)):
+            P, R = states[j]
+            P, R, cont, y, info = solver.solve_load_step(rob, P, R, rob.base_target(d[b]), 0, t[b],
+                                                         tol=1e-10, stag_tol=1e-9, max_iter=60,
+                                                         guided=rob.guided(d[b]))
+            states[j] = (P, R)
+            assert out["info"][b]["status"] == (0 if info["status"] == solver.OK else 1), (k, b)
+            Pg = out["state"][slices[b], 0:3]
+            assert displacement_error(Pg, P, rob.reference()[0]) <= 1e-7, (k, b)
+            assert np.linalg.norm(Pg[-1] - P[-1]) / rob.length <= 1e-5, (k, b)
+            n_cmp, _ = compare_contact_keys(ctx.fem_contacts(b), list(zip(cont, y)), P, rob)
+            n_active += n_cmp
+    ctx.close()
+    assert n_active > 0
