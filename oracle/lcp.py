@@ -50,6 +50,15 @@ def lemke(W, q, max_pivots=None):
                 rhs[i] -= f * rhs[r]
         basis[r] = col
 
+    def lex_less(u, v):
+        # lexicographic u < v where components closer than the rounding level count as
+        # equal: ties of the ratio test are exact in exact arithmetic (a degenerate basis
+        # with zero right-hand sides) and must be broken by the B^-1 rows, not by noise
+        for a, b in zip(u, v):
+            if abs(a - b) > 1e-12 * (1.0 + max(abs(a), abs(b))):
+                return a < b
+        return False
+
     def lex_ratio(col, rows):
         # lexicographic minimum of (rhs_i, B^-1 row i) / a_i among rows with a_i > 0;
         # B^-1 is the tableau block under the initial basis (the w columns)
@@ -58,7 +67,7 @@ def lemke(W, q, max_pivots=None):
         for i in rows:
             a = Tab[i, col]
             key = np.concatenate([[rhs[i]], Tab[i, :n]]) / a
-            if best is None or tuple(key) < tuple(best_key):
+            if best is None or lex_less(key, best_key):
                 best, best_key = i, key
         return best
 

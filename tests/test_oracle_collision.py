@@ -174,3 +174,54 @@ def test_persisting_edge_contact_rules_by_hand():
     assert np.linalg.norm(P3[1] - np.array([0.0, -0.002, 0.0])) <= r_c + rob.delta
     assert collision.contact_set(solver.detect(rob, P3, prev=(prev, np.array([0.4])))) == \
         collision.contact_set(solver.detect(rob, P3))
+
+
+def test_ambiguity_flag_marks_decisions_within_1e9_of_a_threshold():
+    """Nodes whose detection decisions lie within AMBIG_TOL (1e-9 m) of a threshold are
+    flagged - the parity tests exclude exactly those from the exact set comparison - and
+    clear decisions are not."""
+    m = one_triangle()
+    rc, dl = 1.5e-3, 1e-3
+    band = rc + dl
+    base = np.array([0, 0, -1.0])
+
+    def det(p):
+        return collision.detect(np.array([base, p]), m, rc, dl)
+
+    # clear face contact, well inside the face region and the band
+    c = det(np.array([0.002, 0.003, band - 1e-6]))
+    assert len(c) == 1 and c[0]["kind"] == 0 and not c[0]["ambiguous"]
+    # just inside the band edge: a contact, flagged
+    c = det(np.array([0.002, 0.003, band - 4e-10]))
+    assert len(c) == 1 and c[0]["kind"] == 0 and c[0]["ambiguous"]
+    # just outside the band edge: no contact, but a flagged placeholder (tri = -1)
+    c = det(np.array([0.002, 0.003, band + 4e-10]))
+    assert len(c) == 1 and c[0]["tri"] == -1 and c[0]["ambiguous"]
+    assert collision.active(c) == [] and collision.contact_set(c) == ()
+    # just behind the plane's lower threshold s = -r_c
+    c = det(np.array([0.002, 0.003, -rc + 4e-10]))
+    assert len(c) == 1 and c[0]["ambiguous"]
+    # projection 4e-10 m inside edge AB (y = 0): face-region decision is near its boundary
+    c = det(np.array([0.004, 4e-10, 2e-3]))
+    assert len(c) == 1 and c[0]["kind"] == 0 and c[0]["ambiguous"]
+    # and 1e-6 m inside: clear
+    c = det(np.array([0.004, 1e-6, 2e-3]))
+    assert len(c) == 1 and not c[0]["ambiguous"]
+
+
+def test_ambiguity_flag_on_edge_fallback_ties():
+    """Two triangles whose nearest edge points are equally far from the node (within
+    1e-9 m) but distinct: the fallback's choice between them is flagged."""
+    # two coplanar triangles (normal +z) with parallel edges at x = -a and x = +a
+    a = 2e-3
+    V = np.array([[-a, -0.01, 0], [-0.012, 0.0, 0], [-a, 0.01, 0],
+                  [a, -0.01, 0], [a, 0.01, 0], [0.012, 0.0, 0]], float)
+    T = np.array([[0, 2, 1], [3, 5, 4]])
+    m = collision.Mesh(V, T)
+    assert m.n[0][2] > 0 and m.n[1][2] > 0
+    rc, dl = 1.5e-3, 1e-3
+    z = 1.2e-3                     # distance to both edges sqrt(a^2 + z^2) = 2.33 mm < band
+    c = collision.detect(np.array([[0, 0, -1.0], [0.0, 0.0, z]]), m, rc, dl)
+    assert len(c) == 1 and c[0]["kind"] == 1 and c[0]["tri"] == 0 and c[0]["ambiguous"]
+    c = collision.detect(np.array([[0, 0, -1.0], [1e-6, 0.0, z]]), m, rc, dl)
+    assert len(c) == 1 and c[0]["kind"] == 1 and c[0]["tri"] == 1 and not c[0]["ambiguous"]

@@ -1,6 +1,7 @@
 """Pins of the oracle's Newton/QP iteration: KKT of each linear step, the step limit,
 and equilibrium conditions (complementarity, global balance) on the straight-tube workload."""
 import numpy as np
+import scipy.spatial.transform
 import pytest
 
 from oracle import solver, collision, beam, actuation, lcp
@@ -149,3 +150,110 @@ def test_convex_ridge_fallback_keeps_node_constrained():
     c = collision.detect(np.array([[0, 0, -1.0], p]), m, 1.5e-3, 1e-3)
     assert len(c) == 1 and c[0]["kind"] == 1
     assert np.allclose(c[0]["n"], [0, 0, 1]) and c[0]["gap"] == pytest.approx(0.1e-3, abs=1e-15)
+
+
+def _scripted_loop(monkeypatch, rob, contact_sets, residuals, limited=None, tol=1e-14):
+    """Run solve_load_step with detection, residual and linear step replaced by scripts:
+    iterate k detects contact_sets[k], sees residual norm residuals[k] and takes a zero
+    step (limited[k]).  Returns (betas passed to the linear step, info)."""
+    betas = []
+    k = {"det": 0, "res": 0, "lin": 0}
+    N = rob.n_elem + 1
+
+    def fake_detect(robot, P, guided=None, prev=None):
+        i = min(k["det"], len(contact_sets) - 1)
+        k["det"] += 1
+        return [dict(node=n, tri=t, kind=0, n=np.array([0.0, 0.0, 1.0]), gap=1e-3)
+                for n, t in contact_sets[i]]
+
+    def fake_residual(F, contacts, y, robot=None, guided=None):
+        i = min(k["res"], len(residuals) - 1)
+        k["res"] += 1
+        r = np.zeros((N - 1, 6))
+        r[0, 0] = residuals[i]
+        return r
+
+    def fake_step(robot, P, R, F, ab, base_target, contacts, guided=None, beta=None):
+        betas.append(beta)
+        i = k["lin"]
+        k["lin"] += 1
+        lim = bool(limited[i]) if limited is not None and i < len(limited) else False
+        return np.zeros((N, 6)), np.zeros(len(contacts)), lim
+
+    monkeypatch.setattr(solver, "detect", fake_detect)
+    monkeypatch.setattr(solver, "contact_residual", fake_residual)
+    monkeypatch.setattr(solver, "linear_step", fake_step)
+    P, R = rob.reference()
+    *_, info = solver.solve_load_step(rob, P, R, rob.base_target(0.0), actuation.CABLES,
+                                      np.zeros(3), tol=tol, stag_tol=1e-9, max_iter=75)
+    return betas, info
+
+
+def _plain_robot():
+    rb, _, _ = make_config(0)
+    return solver.robots_from_batch(rb, None)[0]
+
+
+def test_step_limit_halves_every_ten_contact_set_changes(monkeypatch):
+    """The step limit is beta0 until the detected contact set has changed 10 times within
+    the load step, then beta0/2 until 20 changes, ... and never below beta0/64 (reading of
+    the unstated beta of eq. 25-26)."""
+    rob = _plain_robot()
+    sets = [[(5, 0)] if k % 2 == 0 else [(6, 1)] for k in range(80)]   # a change every iterate
+    betas, info = _scripted_loop(monkeypatch, rob, sets, [1.0])
+    assert info["status"] == solver.NOCONV and len(betas) == 75
+    b0 = rob.beta0
+    expected = ([b0] * 10 + [b0 / 2] * 10 + [b0 / 4] * 10 + [b0 / 8] * 10 + [b0 / 16] * 10
+                + [b0 / 32] * 10 + [b0 / 64] * 15)
+    assert betas == expected
+    # a fixed contact set never halves
+    betas, _ = _scripted_loop(monkeypatch, rob, [[(5, 0)]], [1.0])
+    assert betas == [b0] * 75
+
+
+def test_stagnation_acceptance(monkeypatch):
+    """A residual below the stagnation level is accepted once it stops halving; while it
+    still halves, or above the level, the iteration goes on; below tol it stops at once;
+    a limited last step is never accepted."""
+    rob = _plain_robot()
+    stag = solver.stagnation_tol(rob, 1e-9)
+    assert stag >= 1e-9
+    same = [[(5, 0)]]
+    # the first residual is seen at iterate 1 (iterate 0 has no previous step)
+    seq = [None, 1e-3, 1e-6, 0.4 * stag, 0.3 * stag]            # accepted at the 4th
+    _, info = _scripted_loop(monkeypatch, rob, same, seq[1:])
+    assert info["status"] == solver.OK and info["iters"] == 4
+    seq = [1e-3, 0.9 * stag, 0.4 * stag, 0.15 * stag, 0.07 * stag, 0.06 * stag]
+    _, info = _scripted_loop(monkeypatch, rob, same, seq)     # halving until the last
+    assert info["status"] == solver.OK and info["iters"] == 6
+    _, info = _scripted_loop(monkeypatch, rob, same, [1e-3, 2.0 * stag])   # never below
+    assert info["status"] == solver.NOCONV
+    _, info = _scripted_loop(monkeypatch, rob, same, [1e-3, 5e-11], tol=1e-10)  # below tol
+    assert info["status"] == solver.OK and info["iters"] == 2
+    _, info = _scripted_loop(monkeypatch, rob, same, [1e-3, 5e-11, 5e-11], tol=1e-10,
+                             limited=[False, True, False])
+    assert info["status"] == solver.OK and info["iters"] == 3
+    # a changing contact set is never accepted, whatever the residual
+    _, info = _scripted_loop(monkeypatch, rob, [[(5, 0)], [(6, 0)]], [1e-12], tol=1e-10)
+    assert info["status"] == solver.OK and info["iters"] == 2
+
+
+def test_stagnation_level_lies_above_the_rounding_floor():
+    """The out-of-balance force of a stress-free robot moved rigidly to coordinates of
+    order 1 m is pure rounding; the stagnation level must exceed it (or a stagnating
+    iteration at that floor would never be accepted) without being loose by more than
+    about three orders of magnitude."""
+    rb, _, _ = make_config(3, n_robots=8)
+    rng = np.random.default_rng(3)
+    for rob in solver.robots_from_batch(rb, None):
+        P, R = rob.reference()
+        for _ in range(3):
+            Q = scipy.spatial.transform.Rotation.random(random_state=rng).as_matrix()
+            t = rng.uniform(-1.0, 1.0, 3)
+            P2 = P @ Q.T + t
+            R2 = np.einsum("ij,njk->nik", Q, R)
+            F = beam.internal_forces(P2, R2, rob.l0, rob.K7)
+            floor = float(np.linalg.norm(F[1:]))
+            level = solver.stagnation_tol(rob, 0.0)
+            assert floor < level, (floor, level)
+            assert level < 3e3 * max(floor, 1e-300) or floor == 0.0
