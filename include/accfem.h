@@ -54,16 +54,24 @@ typedef enum {
  * to the same equilibrium. */
 typedef enum { FEM_FP64 = 0, FEM_MIXED = 1 } fem_precision;
 
-/* Actuation kinds (eq. 16-18).  CABLES: values[b*n_cables + j] = tension T_j (N)
- * of cable j, attached at radius cable_radius and angle cable_angle[j] in the
- * tip section; the tip node receives the follower moment sum_j d_j x F_j with
- * F_j = -T_j e_x (the pull is carried inside the cable-tube pair, so it adds no
- * net axial force).  TIP_WRENCH_LOCAL: values[b*6..] = (F, M) in the tip frame
- * (follower).  TIP_WRENCH_GLOBAL: values[b*6..] = (F, M) in global axes. */
+/* Actuation kinds (Sec. II-E, eq. 16-18).  Cable j is attached at radius
+ * cable_radius and angle cable_angle[j] in the tip section,
+ * d_j = r (0, cos a_j, sin a_j), and pulls toward the base, F_j = -T_j e_x, both in
+ * the tip frame T_M, which turns them into global axes (a follower load).
+ *   CABLES: values[b*n_cables + j] = tension T_j (N); the tip node receives the
+ *     moments sum_j d_j x F_j of eq. 16 only (the pull is carried inside the
+ *     cable-tube pair, so it adds no net axial force).  Default of the workloads.
+ *   CABLE_WRENCH: values as CABLES; the tip node receives eq. 17 as printed, the
+ *     summed cable force sum_j F_j and the moments sum_j d_j x F_j.  The axial
+ *     follower compression makes the QP-tangent iteration of eq. 20-23 converge only
+ *     at small tensions (a few Euler loads of the robot).
+ *   TIP_WRENCH_LOCAL: values[b*6..] = (F, M) in the tip frame (follower).
+ *   TIP_WRENCH_GLOBAL: values[b*6..] = (F, M) in global axes (dead load). */
 typedef enum {
   FEM_ACT_CABLES = 0,
   FEM_ACT_TIP_WRENCH_LOCAL = 1,
-  FEM_ACT_TIP_WRENCH_GLOBAL = 2
+  FEM_ACT_TIP_WRENCH_GLOBAL = 2,
+  FEM_ACT_CABLE_WRENCH = 3
 } fem_act_kind;
 
 /* Per-robot status in fem_solve_info.status */
@@ -127,29 +135,51 @@ typedef struct {
   double force;             /* contact force magnitude y >= 0 (N) of the last linear step */
 } fem_contact;
 
-/* Create a context for a batch of robots; allocates device memory for all of
- * them and places every robot in its straight reference configuration (S_0). */
+/* Create a context for a batch of robots (Sec. II-B: each robot is split into
+ * n_elem equal beam elements of length l0 = length / n_elem along its centreline,
+ * six DOF per node; section and material as in Table I).  Allocates device memory
+ * for all of them and places every robot in its straight reference configuration
+ * S_0 of eq. 3 (node i at base_pos + i l0 base_dir, triads [base_dir, base_up, x]).
+ * p and its arrays are host memory, read during the call.  *out receives the
+ * context (the caller frees it with fem_destroy), or NULL on error; FEM_E_INVAL for
+ * out-of-range sizes or material (message from fem_last_error(NULL)), FEM_E_NOMEM,
+ * FEM_E_HIP. */
 fem_status fem_create(const fem_params* p, fem_ctx** out);
 
-/* Free the context and all its device memory.  NULL is ignored. */
+/* Free the context and all its device memory (library bookkeeping, no passage of
+ * the method).  Waits for the context's stream first.  NULL is ignored. */
 void fem_destroy(fem_ctx* c);
 
-/* Message of the last error on this context (static storage while c lives). */
+/* Message of the last error on this context, or of the last failed fem_create for
+ * NULL (library bookkeeping, no passage of the method).  The string is owned by the
+ * library and valid until the next call on c. */
 const char* fem_last_error(const fem_ctx* c);
 
-/* Upload the lumen mesh (Sec. II-C): verts [n_verts*3], tris [n_tris*3] with
- * winding (v1-v0)x(v2-v0) pointing into the lumen.  Builds the triangle planes
- * and the uniform grid used by contact detection.  n_tris may be 0 (no wall). */
+/* Upload the lumen mesh, the triangulated cavity wall whose planes bound the nodes
+ * in the contact constraint of eq. 3 (Sec. II-C) and that detection matches nodes
+ * against (Sec. III-C): verts [n_verts*3] (x y z per vertex), tris [n_tris*3] vertex
+ * indices with winding (v1-v0)x(v2-v0) pointing into the lumen.  Both follow
+ * io_on_device and are copied.  Builds the triangle planes and the uniform grid used
+ * by contact detection.  n_tris may be 0 (no wall).  FEM_E_INVAL: negative sizes,
+ * NULL arrays, an index out of range or a degenerate triangle (the previous mesh is
+ * then dropped). */
 fem_status fem_set_lumen(fem_ctx* c, const double* verts, int64_t n_verts,
                          const int32_t* tris, int64_t n_tris);
 
-/* Set the actuation and insertion depth reached at the end of the next
- * fem_solve call.  values: [B*n_cables] (CABLES) or [B*6] (tip wrench kinds);
- * insertion_depth: [B] or NULL (= 0).  The kind must not change between calls. */
+/* Set the actuation (Sec. II-E, eq. 16-18) and the insertion depth reached at the
+ * end of the next fem_solve call.  The depth moves the clamped base node along
+ * base_dir: the prescribed displacement b_fn of the fixed-node constraint (Sec. II-D,
+ * eq. 14-15), the insertion of Sec. IV-B.  values: [B*n_cables] (CABLES,
+ * CABLE_WRENCH) or [B*6] (tip wrench kinds); insertion_depth: [B] or NULL (= 0); both
+ * follow io_on_device and are copied.  The kind must not change between calls
+ * (FEM_E_INVAL). */
 fem_status fem_set_actuation(fem_ctx* c, fem_act_kind kind, const double* values,
                              const double* insertion_depth);
 
-/* Run n_load_steps quasi-static load steps.  Load step j applies
+/* Run n_load_steps quasi-static load steps, each solved to the equilibrium of the
+ * complementarity problem of eq. 19 by a Newton iteration whose linear steps are
+ * the quadratic programs of eq. 23 (Sec. III-A, III-B) with the step-size limit of
+ * eq. 25-27 (Sec. III-D).  Load step j applies
  * prev + (target - prev) * j / n_load_steps of the actuation and depth, where
  * prev is what the previous call reached (0 initially) and target the values
  * of fem_set_actuation.  Each load step starts from the previous state.
@@ -160,17 +190,21 @@ fem_status fem_set_actuation(fem_ctx* c, fem_act_kind kind, const double* values
 fem_status fem_solve(fem_ctx* c, int32_t n_load_steps, double* node_state,
                      fem_solve_info* info);
 
-/* Contacts of the last iterate of robot `robot` (-1 = all robots, in order).
- * Writes min(total, capacity) entries; *n_out = total even if larger. */
+/* Contacts of the last iterate of robot `robot` (-1 = all robots, in order): the
+ * rows of A_c (normal n_i, eq. 9), the gaps b_c (eq. 10) and the contact forces y_c
+ * (eq. 11), i.e. the collision positions that detection returns (Sec. III-C).
+ * out [capacity] follows io_on_device.  Writes min(total, capacity) entries;
+ * *n_out (host) = total even if larger.  FEM_E_INVAL: robot out of range, NULL
+ * n_out, or capacity > 0 with NULL out. */
 fem_status fem_contacts(const fem_ctx* c, int32_t robot, fem_contact* out,
                         int32_t capacity, int32_t* n_out);
 
 /* Adjoint gradient at the converged state of the last load step (equilibrium of
- * eq. 19 with the contact conditions of eq. 14-16; the adjoint is an addition to
- * the method).  For a loss L on node positions, given dL/dp of n_sensors sensor
+ * eq. 19 with the contact conditions of eq. 12-13 and the fixed-node constraints of
+ * eq. 14-15; the adjoint is an addition to the method).  For a loss L on node positions, given dL/dp of n_sensors sensor
  * nodes per robot, writes dL/du for the actuation values u of the last
- * fem_set_actuation kind: the cable tensions [B*n_cables] for FEM_ACT_CABLES,
- * else the tip wrench [B*6].  It solves J^T lam + A_act^T mu = dL/dx,
+ * fem_set_actuation kind: the cable tensions [B*n_cables] for FEM_ACT_CABLES and
+ * FEM_ACT_CABLE_WRENCH, else the tip wrench [B*6].  It solves J^T lam + A_act^T mu = dL/dx,
  * A_act lam = 0 with the exact Jacobian J of the out-of-balance force (element
  * material and geometric stiffness plus the follower-load stiffness), the active
  * contacts (force > 0) held as planes at their normals and the base and guided
@@ -188,12 +222,15 @@ fem_status fem_contacts(const fem_ctx* c, int32_t robot, fem_contact* out,
 fem_status fem_grad(fem_ctx* c, const int32_t* sensor_nodes, int32_t n_sensors,
                     const double* dL_dp, double* dL_du);
 
-/* Copy the node state [total_nodes*7] out of / into the context.  fem_set_state
- * also resets the per-robot statistics; quaternions are renormalised. */
+/* Copy the nodal configuration x_t of eq. 1 (Sec. II-B), node state
+ * [total_nodes*7] in the layout above, out of / into the context; node_state
+ * follows io_on_device.  fem_set_state also resets the per-robot statistics;
+ * quaternions are renormalised.  FEM_E_INVAL for NULL. */
 fem_status fem_get_state(const fem_ctx* c, double* node_state);
 fem_status fem_set_state(fem_ctx* c, const double* node_state);
 
-/* Evaluate the element update and contact detection at the current state under
+/* Evaluate the out-of-balance force F(x) - F_a of eq. 1 and 18, the tangent
+ * K(x) of eq. 20 and contact detection (Sec. III-C) at the current state under
  * the actuation and depth set by the last fem_set_actuation (no Newton step):
  * F [total_nodes*6] = internal force minus actuation per node, KD and KS
  * [total_nodes*36] = row-major 6x6 diagonal block of each node and its
@@ -202,7 +239,8 @@ fem_status fem_set_state(fem_ctx* c, const double* node_state);
  * Intended for verification of the element and detection kernels. */
 fem_status fem_eval(fem_ctx* c, double* F, double* KD, double* KS);
 
-/* Kernel timing of a context created with profile = 1: for kernel class k
+/* Measurement, not part of the method.  Kernel timing of a context created with
+ * profile = 1: for kernel class k
  * (0 = element update, 1 = contact detection, 2..5 = the Newton step's phases:
  * convergence test + right-hand sides, block Cholesky, substitutions, contact
  * Schur complement + LCP + update) the
@@ -226,7 +264,8 @@ fem_status fem_profile(fem_ctx* c, int32_t kernel, double* total_ms, int64_t* la
  * solution), or the iteration limit (y not written).  FEM_E_NOMEM, FEM_E_HIP. */
 fem_status fem_lcp(const double* W, const double* q, int32_t m, double* y, int32_t* path);
 
-/* Total number of nodes over the batch (sum of n_elem + 1), or -1 for NULL. */
+/* Total number of nodes over the batch (Sec. II-B: n_elem + 1 per robot, summed),
+ * or -1 for NULL. */
 int64_t fem_total_nodes(const fem_ctx* c);
 
 #ifdef __cplusplus

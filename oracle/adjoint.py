@@ -90,8 +90,8 @@ def tension_gradient(robot, P, R, contacts, y, act_values, sensor_nodes, dL_dp, 
 
 def load_gradient(robot, R_tip, act_kind):
     """dF_a/du [6, n_values] of the tip load (eq. 18) for the actuation values u."""
-    if act_kind == actuation.CABLES:
-        return actuation.tension_gradient(R_tip, robot.cable_radius, robot.cable_angle)
+    if act_kind in (actuation.CABLES, actuation.CABLE_WRENCH):
+        return actuation.tension_gradient(R_tip, robot.cable_radius, robot.cable_angle, act_kind)
     if act_kind == actuation.TIP_LOCAL:
         G = np.zeros((6, 6))
         G[0:3, 0:3] = R_tip

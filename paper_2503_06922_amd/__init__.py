@@ -6,5 +6,5 @@ torch.autograd wrapper (FEMEquilibrium) around its solve and adjoint.
 """
 from .fem import (Context, FemError, params_from_batch, state_to_PR, lib,  # noqa: F401
                   FEM_FP64, FEM_MIXED, FEM_ACT_CABLES, FEM_ACT_TIP_WRENCH_LOCAL,
-                  FEM_ACT_TIP_WRENCH_GLOBAL)
+                  FEM_ACT_TIP_WRENCH_GLOBAL, FEM_ACT_CABLE_WRENCH)
 

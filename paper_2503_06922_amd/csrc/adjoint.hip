@@ -1,6 +1,7 @@
 // Adjoint gradient of a loss on node positions with respect to the actuation values,
 // at a converged equilibrium of a load step (the equilibrium of eq. 19 with the
-// contact conditions of eq. 14-16; the adjoint itself is an addition to the method).
+// contact conditions of eq. 12-13 and the fixed-node constraints of eq. 14-15; the
+// adjoint itself is an addition to the method).
 //
 // At equilibrium  F(x) - F_a(x, u) - A^T y = 0  with the active contacts held
 // (A_act dx = 0), base node and guided lateral DOFs fixed.  For a loss L(x) with
@@ -102,11 +103,12 @@ __global__ void __launch_bounds__(256) adj_jac_kernel(Dev d, double* JL, double*
     // follower load at the tip: F_a = (R f, R m) turns with the tip triad
     const double* v = d.act_cur + (int64_t)r * d.act_nv;
     double fl[3] = {0, 0, 0}, ml[3] = {0, 0, 0};
-    if (d.act_kind == 0) {
+    if (d.act_kind == 0 || d.act_kind == 3) {
       for (int j = 0; j < d.n_cables; ++j) {
         const double T = v[j] * d.cable_radius;
         ml[1] -= T * d.cable_sin[j];
         ml[2] += T * d.cable_cos[j];
+        if (d.act_kind == 3) fl[0] -= v[j];
       }
     } else {
       fl[0] = v[0]; fl[1] = v[1]; fl[2] = v[2];
@@ -362,13 +364,15 @@ __global__ void __launch_bounds__(64) adj_sweep_kernel(Dev d, const double* JL, 
     node_pR(d, gt, p, R);
     const bool ok = !bad && d.st_status[r] == 0;
     double* y = out + (int64_t)r * nv;
-    if (d.act_kind == 0) {
+    if (d.act_kind == 0 || d.act_kind == 3) {
       for (int j = 0; j < d.n_cables; ++j) {
-        // dF_a/dT_j = (0, R m_j), m_j = rc (0, -sin, cos)
+        // dF_a/dT_j = (0, R m_j), m_j = rc (0, -sin, cos); with the cable force of eq. 17
+        // also (-R e_x, .)
         const double m1 = -d.cable_radius * d.cable_sin[j], m2 = d.cable_radius * d.cable_cos[j];
         double s = 0.0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) s += lam[3 + a] * (R[a * 3 + 1] * m1 + R[a * 3 + 2] * m2);
+        if (d.act_kind == 3) s -= lam[0] * R[0] + lam[1] * R[3] + lam[2] * R[6];
         y[j] = ok ? s : NAN;
       }
     } else if (d.act_kind == 1) {

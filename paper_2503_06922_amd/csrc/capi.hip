@@ -621,9 +621,9 @@ fem_status fem_set_lumen(fem_ctx* c, const double* verts, int64_t n_verts, const
 fem_status fem_set_actuation(fem_ctx* c, fem_act_kind kind, const double* values,
                              const double* insertion_depth) {
   if (!c) return FEM_E_INVAL;
-  if (kind < FEM_ACT_CABLES || kind > FEM_ACT_TIP_WRENCH_GLOBAL || !values)
+  if (kind < FEM_ACT_CABLES || kind > FEM_ACT_CABLE_WRENCH || !values)
     return fail(c, FEM_E_INVAL, "bad actuation kind or NULL values");
-  const int nv = (kind == FEM_ACT_CABLES) ? c->p.n_cables : 6;
+  const int nv = (kind == FEM_ACT_CABLES || kind == FEM_ACT_CABLE_WRENCH) ? c->p.n_cables : 6;
   if (c->act_kind >= 0 && c->act_kind != (int)kind)
     return fail(c, FEM_E_INVAL, "actuation kind cannot change");
   hipSetDevice(c->device);

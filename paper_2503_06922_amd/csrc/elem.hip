@@ -73,11 +73,12 @@ __global__ void __launch_bounds__(256) elem_kernel(Dev d) {
   } else {  // tip node: subtract the actuation load (eq. 18)
     const double* v = d.act_cur + (int64_t)r * d.act_nv;
     V3 Fl = v3(0, 0, 0), Ml = v3(0, 0, 0);
-    if (d.act_kind == 0) {
+    if (d.act_kind == 0 || d.act_kind == 3) {
       for (int j = 0; j < d.n_cables; ++j) {
-        // M_j = d_j x F_j with d_j = rc (0, cos, sin), F_j = -T_j e_x
+        // M_j = d_j x F_j with d_j = rc (0, cos, sin), F_j = -T_j e_x (eq. 16)
         double T = v[j];
         Ml = Ml + (T * d.cable_radius) * v3(0.0, -d.cable_sin[j], d.cable_cos[j]);
+        if (d.act_kind == 3) Fl.x -= T;  // eq. 17: the cable force itself acts on the tip
       }
     } else {
       Fl = v3(v[0], v[1], v[2]);

@@ -15,7 +15,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libaccfem.
 
 FEM_OK, FEM_E_INVAL, FEM_E_NOMEM, FEM_E_HIP, FEM_E_STATE, FEM_E_NOCONV = 0, -1, -2, -3, -4, -5
 FEM_FP64, FEM_MIXED = 0, 1
-FEM_ACT_CABLES, FEM_ACT_TIP_WRENCH_LOCAL, FEM_ACT_TIP_WRENCH_GLOBAL = 0, 1, 2
+FEM_ACT_CABLES, FEM_ACT_TIP_WRENCH_LOCAL, FEM_ACT_TIP_WRENCH_GLOBAL, FEM_ACT_CABLE_WRENCH = 0, 1, 2, 3
 ROBOT_OK, ROBOT_NOCONV, ROBOT_LCPFAIL, ROBOT_NONSPD, ROBOT_OVERFLOW = 0, 1, 2, 3, 4
 
 
@@ -200,7 +200,7 @@ class Context:
         self.act_kind = int(kind)
         if self.io_on_device:
             return self._check(lib().fem_set_actuation(self._h, int(kind), _ptr(values), _ptr(depth)))
-        nv = self.n_cables if kind == FEM_ACT_CABLES else 6
+        nv = self.n_cables if kind in (FEM_ACT_CABLES, FEM_ACT_CABLE_WRENCH) else 6
         v = _f64(values, self.B * nv)
         d = None if depth is None else _f64(depth, self.B)
         return self._check(lib().fem_set_actuation(self._h, int(kind), _ptr(v), _ptr(d)))
@@ -250,7 +250,7 @@ class Context:
 
         Returns (gradient, status) with status FEM_OK or FEM_E_NOCONV."""
         s = np.ascontiguousarray(np.asarray(sensor_nodes, np.int32)).ravel()
-        nv = self.n_cables if self.act_kind == FEM_ACT_CABLES else 6
+        nv = self.n_cables if self.act_kind in (FEM_ACT_CABLES, FEM_ACT_CABLE_WRENCH) else 6
         g = _f64(dL_dp, self.B * s.size * 3)
         out = np.empty((self.B, nv))
         st = lib().fem_grad(self._h, _ptr(s), int(s.size), _ptr(g), _ptr(out))

@@ -50,7 +50,9 @@ def test_adjoint_cable_gradient_closed_form():
     # cable j's moment in the tip frame is rc (0, -sin, cos); about z its arm is rc cos(angle)
     # when the tip triad is the reference one (R = [e_x, e_y, e_z])
     Rt = R[-1]
-    m = np.array([Rt @ (rob.cable_radius * np.array([0.0, -np.sin(t), np.cos(t)]))
+    # eq. 16: M_j = d_j x F_j with the attachment d_j and the pull F_j = -e_x per unit tension
+    m = np.array([Rt @ np.cross(rob.cable_radius * np.array([0.0, np.cos(t), np.sin(t)]),
+                                [-1.0, 0.0, 0.0])
                   for t in rob.cable_angle])
     flex_M = np.array([0.0, 0.0, 0.0])  # tip y under M = (Mx, My, Mz): only Mz acts
     flex_M[2] = rob.length ** 2 / (2 * EI)
@@ -85,3 +87,40 @@ def test_adjoint_matches_finite_difference_resolves():
         fd[j] = (adjoint.sensor_loss(run(Tp)[0], sens, targets)[0]
                  - adjoint.sensor_loss(run(Tm)[0], sens, targets)[0]) / (2 * h)
     assert np.abs(g - fd).max() <= 1e-6 * np.abs(fd).max()
+
+
+def test_adjoint_cable_wrench_matches_finite_difference_resolves():
+    """Eq. 17 as printed (CABLE_WRENCH): the follower cable force adds a load stiffness and
+    a force column to dF_a/dT; the adjoint must still match central differences of complete
+    re-solves (a narrow tube, so that contacts are active, at tensions where the iteration
+    of eq. 20-23 converges)."""
+    from workloads.lumen import straight_cylinder_mesh
+    rb, _, _ = make_config(0)
+    V, T = straight_cylinder_mesh(radius=2.2e-3, axis_xy=(0.0, 0.2e-3))
+    rob = solver.robots_from_batch(rb, collision.Mesh(V, T))[0]
+    Tf = rb.tensions[0] * 0.01
+    n_steps = 20
+
+    def run(Tv):
+        sched = lambda k: (0.0, Tv * k / n_steps)
+        P, R, traj = solver.solve_robot(rob, sched, n_steps, act_kind=actuation.CABLE_WRENCH,
+                                        tol=1e-13, stag_tol=1e-9, max_iter=300)
+        assert all(t["info"]["status"] == solver.OK for t in traj)
+        return P, R, traj[-1]
+
+    P, R, last = run(Tf)
+    assert int(np.sum(last["y"] > 0)) >= 1
+    sens = [rob.n_elem - 4, rob.n_elem]
+    targets = P[sens] + np.array([[1e-3, -2e-3, 0.5e-3], [-1e-3, 1e-3, 2e-3]])
+    _, dLdp = adjoint.sensor_loss(P, sens, targets)
+    g = adjoint.tension_gradient(rob, P, R, last["contacts"], last["y"], Tf, sens, dLdp,
+                                 act_kind=actuation.CABLE_WRENCH)
+    h = 1e-7
+    fd = np.zeros(3)
+    for j in range(3):
+        Tp, Tm = Tf.copy(), Tf.copy()
+        Tp[j] += h
+        Tm[j] -= h
+        fd[j] = (adjoint.sensor_loss(run(Tp)[0], sens, targets)[0]
+                 - adjoint.sensor_loss(run(Tm)[0], sens, targets)[0]) / (2 * h)
+    assert np.abs(g - fd).max() <= 1e-5 * np.abs(fd).max()

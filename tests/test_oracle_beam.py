@@ -172,3 +172,80 @@ def test_axial_follower_force_uniform_shortening():
     P, R = _tip_solve(rob, [F, 0, 0, 0, 0, 0], actuation.TIP_LOCAL)
     assert np.abs(P[:, 0:2]).max() < 1e-15
     assert P[-1, 2] == pytest.approx(rob.length * (1 + F / rob.EA[0]), rel=1e-14)
+
+
+def test_cable_moments_of_equal_tensions_cancel():
+    """Eq. 16 with three cables at 120 degrees: equal tensions give no moment, a single
+    cable's moment is T r about the section axis normal to its attachment direction."""
+    rb = robots_for_config(0)
+    rob = solver.robots_from_batch(rb)[0]
+    r = rob.cable_radius
+    F, M = actuation.cable_wrench_local([0.7, 0.7, 0.7], r, rob.cable_angle)
+    assert np.abs(M).max() <= 1e-16 and F == pytest.approx([-2.1, 0, 0], abs=1e-15)
+    for j, phi in enumerate(rob.cable_angle):
+        T = np.zeros(3)
+        T[j] = 1.3
+        _, M = actuation.cable_wrench_local(T, r, rob.cable_angle)
+        d = r * np.array([0.0, np.cos(phi), np.sin(phi)])       # attachment point
+        assert np.linalg.norm(M) == pytest.approx(1.3 * r, rel=1e-15)
+        assert abs(M @ d) <= 1e-18 and M[0] == 0.0             # normal to d and the axis
+        # pulling toward the base at d turns the section toward d: M = d x (-T e_x)
+        assert np.allclose(M, np.cross(d, [-1.3, 0, 0]), rtol=0, atol=1e-18)
+
+
+@pytest.mark.parametrize("phi,tol", [(0.0, 1e-11), (np.pi / 2, 1e-11), (2 * np.pi / 3, 1e-7)])
+def test_single_cable_bends_toward_it_on_a_circle(phi, tol):
+    """One tensioned cable at angle phi (the moment-only CABLES kind): a follower end moment
+    T r, so the nodes lie on the discrete circle of turn alpha = T r l0 / EI, curving toward
+    the side of the section the cable is attached to (Sec. II-E, Fig. 1c).  Exact in the
+    planes of the section axes; in an oblique plane the element frame (built from the
+    nodes' section y-axes) couples bending and torsion at second order, which leaves a
+    relative twist of ~2e-8 per element here, hence the looser bound there."""
+    rb = robots_for_config(0)
+    rob = solver.robots_from_batch(rb)[0]
+    rob.cable_angle = np.array([phi, phi + 2 * np.pi / 3, phi + 4 * np.pi / 3])
+    EI, L, r = rob.EI[0], rob.length, rob.cable_radius
+    Tn = EI * (np.pi / 2) / (L * r)        # a quarter circle
+    P, R = _tip_solve(rob, [Tn, 0.0, 0.0], actuation.CABLES, n_steps=4)
+    alpha = Tn * r * rob.l0 / EI
+    rho_h = rob.l0 / (2 * np.sin(alpha / 2))
+    k = np.arange(P.shape[0])
+    t = np.asarray(rob.base_dir, float)
+    u = np.asarray(rob.base_up, float)
+    b = np.cross(t, u)
+    side = np.cos(phi) * u + np.sin(phi) * b        # the cable's side of the section
+    exp = (np.asarray(rob.base_pos, float) + (rho_h * np.sin(k * alpha))[:, None] * t
+           + (rho_h * (1 - np.cos(k * alpha)))[:, None] * side)
+    assert np.abs(P - exp).max() <= tol * L
+
+
+def test_cable_wrench_equal_tensions_shorten_the_straight_robot():
+    """Eq. 17 as printed (CABLE_WRENCH): equal tensions give no moment and the summed cable
+    force compresses the robot along its axis, so it stays straight and every element
+    shortens by sum(T) l0 / EA (exact for the l - l0 strain measure)."""
+    rb = robots_for_config(0)
+    rob = solver.robots_from_batch(rb)[0]
+    T = np.full(3, 0.3)
+    P, R = _tip_solve(rob, T, actuation.CABLE_WRENCH)
+    # the cable moments cancel to rounding (~1e-19 N m), which the axial follower
+    # compression (about 200 Euler loads) amplifies into ~1e-13 m of lateral offset
+    assert np.abs(P[:, 0:2] - np.asarray(rob.base_pos)[0:2]).max() <= 1e-12
+    dz = np.diff(P[:, 2])
+    assert np.allclose(dz, rob.l0 * (1 - T.sum() / rob.EA[0]), rtol=1e-14, atol=0)
+    # the moment-only kind leaves the robot untouched
+    P2, _ = _tip_solve(rob, T, actuation.CABLES)
+    assert np.abs(P2 - rob.reference()[0]).max() <= 1e-15
+
+
+def test_cable_wrench_single_cable_load_reaches_the_base():
+    """Eq. 17 with one cable: at equilibrium (no wall) the clamp carries the cable's pull,
+    i.e. the internal force at the base node is -sum_j F_j turned by the tip triad, T e1_tip,
+    and the robot bends toward the cable."""
+    rb = robots_for_config(0)
+    rob = solver.robots_from_batch(rb)[0]
+    T = np.array([4e-3, 0.0, 0.0])          # about one Euler load pi^2 EI / 4 L^2
+    P, R = _tip_solve(rob, T, actuation.CABLE_WRENCH, n_steps=4)
+    fint = beam.internal_forces(P, R, rob.l0, rob.K7)
+    assert np.allclose(fint[0, 0:3], T.sum() * R[-1][:, 0], rtol=0, atol=1e-12)
+    side = np.asarray(rob.base_up, float)    # cable 0 at angle 0: the section y-axis
+    assert (P[-1] - P[0]) @ side > 0.0
