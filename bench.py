@@ -5,13 +5,20 @@ Workload (the batched configuration): 4096 robots with 50..400 elements
 load steps and insertion depths U(0.1,0.5) m over 100 load steps, sharing one
 50k-triangle branching lumen.  One bench step = the whole quasi-static
 insertion (all load steps) of the whole batch from the straight reference
-state, inputs resident on the GPU.  A solve = one converged load step of one
-robot; value = converged solves / wall time of the timed steps.
+state, run as one explicit schedule in which every robot advances through its
+load steps on its own; inputs (state, schedule tables, lumen) are resident on
+the GPU.
 
-Prints one JSON line (see --help).  Extra fields: per-kernel HIP-event times,
-the roofline of the dominant kernel, the FP64 oracle timed on the host on a
-bounded sample, and the plain FP64 single-robot GPU path on a sample of the
-same robots (the configuration-0 design run one robot at a time).
+value = solves per second that meet the metric: a solve is one load step of one
+robot that converged in mixed precision AND in plain FP64 with the mixed-precision
+tip within 1e-5 of the robot length of the FP64 tip at that load step.  The raw
+rate of converged mixed-precision solves is reported beside it.
+
+Prints one JSON line.  Extra fields: per-kernel HIP-event times, the roofline of
+the dominant kernel (the step's algorithmic bytes of the scope table, plus this
+design's own byte model), per-load-step tip error percentiles, the FP64 oracle
+timed on the host's cores on a bounded sample, and the plain FP64 single-robot
+GPU path on a sample of the same robots.
 """
 from __future__ import annotations
 
@@ -28,7 +35,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "contact-FEM solves/sec, batched+mixed vs plain FP64 at 1e-5 rel tip error"
 HBM_PEAK_GBS = 8000.0
-
+TIP_TOL = 1e-5
 
 KERNELS = ["elem_kernel", "collide_kernel", "check_rhs_kernel", "factor_kernel", "subst_kernel",
            "update_kernel"]
@@ -36,40 +43,50 @@ KERNEL_SOURCE = {"elem_kernel": "elem.hip", "collide_kernel": "collide.hip", "ch
                  "factor_kernel": "solve.hip", "subst_kernel": "solve.hip", "update_kernel": "solve.hip"}
 
 
-def algorithmic_bytes(info, n_nodes, sb, steps):
-    """HBM bytes the kernels with a fixed per-node byte count must move over one schedule.
-
-    sb = bytes of a stored chord-direction component (4 in mixed precision, 8 in FP64).
-      elem_kernel   per active node: read the state (7 FP64), write F (6 FP64) and the chord
-                    direction of its element (3 x sb)
-      factor_kernel per free node and Newton step: read the node's two elements (direction
-                    3 x sb and 6 FP64 constants each; the left one is shared with the previous
-                    node, so one element per node), write the Cholesky blocks L[i,i] (21 unique
-                    FP64) and L[i+1,i] (36 FP64) and read column 0's right-hand side (6 FP64);
-                    its second wavefront sweeps the first 64 right-hand sides forward (the
-                    contact columns are generated, not read): write y, 6 FP64 per node and
-                    right-hand side
-      subst_kernel  per free node and pass of 64 right-hand sides: read L[i,i] and L[i+1,i]
-                    (57 FP64); per right-hand side read y and write x (2 x 6 FP64); those
-                    beyond the first 64 are also swept forward here (write y, 6 FP64)
-    Returns {kernel: (bytes per unit, total bytes)}.
-    """
-    per = {"elem_kernel": 8 * (7 + 6) + 3 * sb,
-           "factor_kernel": (3 * sb + 8 * 6 + 8 * (21 + 36) + 8 * 6, 8 * 6),
-           "subst_kernel": (8 * 57, 2 * 8 * 6, 8 * 6)}
-    elem_nodes = sum((i["iters_total"] + i["steps_total"]) * int(n_nodes[b]) for b, i in enumerate(info))
+def launch_units(info, n_nodes):
+    """Work units of one schedule, summed over robots: node-iterations of the element update
+    (every pass of a load step, the final check included), free node-steps of the Newton step
+    (one per Newton iteration and free node), free-node right-hand sides, those swept forward
+    inside the factorisation, and free-node substitution passes."""
     free = [int(n) - 1 for n in n_nodes]
-    free_steps = sum(i["iters_total"] * free[b] for b, i in enumerate(info))
-    free_rhs = sum(i["rhs_total"] * free[b] for b, i in enumerate(info))
-    free_fused = sum(i["rhs_fused"] * free[b] for b, i in enumerate(info))
-    free_passes = sum(i["sweep_passes"] * free[b] for b, i in enumerate(info))
+    return dict(
+        elem_node_iters=sum((i["iters_total"] + i["steps_total"]) * int(n_nodes[b]) for b, i in enumerate(info)),
+        free_node_steps=sum(i["iters_total"] * free[b] for b, i in enumerate(info)),
+        free_node_rhs=sum(i["rhs_total"] * free[b] for b, i in enumerate(info)),
+        free_node_rhs_fused=sum(i["rhs_fused"] * free[b] for b, i in enumerate(info)),
+        free_node_passes=sum(i["sweep_passes"] * free[b] for b, i in enumerate(info)),
+    )
+
+
+def byte_models(u, sb):
+    """Algorithmic HBM bytes per schedule of the kernels with a per-node byte count.
+
+    "scope": the minimum of the step itself (the hot-path scope table): the element update
+    reads the node state (7 FP64) and writes its out-of-balance force (6 FP64) and tangent
+    blocks D (21) and S (36) in the element precision, 560 B (FP64) / 280 B (FP32) per node;
+    the block Cholesky reads and writes the 57 unique block values per free node (912 B);
+    the multi-right-hand-side solve reads L twice per free node, shared by all right-hand
+    sides of the step (912 B).
+    "design": what this design's kernels must move: the element update writes the chord
+    direction (3 x sb) instead of D and S; the factorisation reads the element (3 x sb + 6
+    FP64 constants) and column 0's right-hand side and writes L[i,i] and the coupling block,
+    plus 6 FP64 of forward values per node for each of the first 64 right-hand sides; the
+    substitution reads L per pass of 64 right-hand sides and reads y / writes x per node and
+    right-hand side (plus the forward values of those beyond the first 64).
+    Returns {kernel: {"scope": (bytes_per_unit, unit, total), "design": (...)}}."""
+    el_scope = 8 * (7 + 6) + (21 + 36) * (8 if sb == 8 else 4)
+    el_design = 8 * (7 + 6) + 3 * sb
+    fa_design = 3 * sb + 8 * 6 + 8 * (21 + 36) + 8 * 6
     return {
-        "elem_kernel": (per["elem_kernel"], per["elem_kernel"] * elem_nodes * steps),
-        "factor_kernel": (per["factor_kernel"], (per["factor_kernel"][0] * free_steps
-                                                + per["factor_kernel"][1] * free_fused) * steps),
-        "subst_kernel": (per["subst_kernel"], (per["subst_kernel"][0] * free_passes
-                                              + per["subst_kernel"][1] * free_rhs
-                                              + per["subst_kernel"][2] * (free_rhs - free_fused)) * steps),
+        "elem_kernel": {"scope": (el_scope, "node-iteration", el_scope * u["elem_node_iters"]),
+                        "design": (el_design, "node-iteration", el_design * u["elem_node_iters"])},
+        "factor_kernel": {"scope": (912, "free node-step", 912 * u["free_node_steps"]),
+                          "design": ([fa_design, 48], "free node-step, fused rhs",
+                                     fa_design * u["free_node_steps"] + 48 * u["free_node_rhs_fused"])},
+        "subst_kernel": {"scope": (912, "free node-step", 912 * u["free_node_steps"]),
+                         "design": ([456, 96, 48], "free node-pass, node-rhs, node-rhs beyond 64",
+                                    456 * u["free_node_passes"] + 96 * u["free_node_rhs"]
+                                    + 48 * (u["free_node_rhs"] - u["free_node_rhs_fused"]))},
     }
 
 
@@ -99,80 +116,102 @@ def measured_traffic(kernel, capacity):
     return rec.get("bytes_per_launch")
 
 
-def run_schedule(ctx, rb, n_load_steps, X0):
-    from workloads import load_schedule
+def make_context(fem, rb, prec, args, V, T, **kw):
+    import torch
+    ctx = fem.Context(fem.params_from_batch(rb, precision=prec, newton_tol=1e-10, stag_tol=1e-9,
+                                            max_newton=args.max_newton,
+                                            contact_capacity=args.capacity, io_on_device=1, **kw))
+    ctx.fem_set_lumen(torch.tensor(V, device="cuda"), torch.tensor(T, dtype=torch.int32, device="cuda"))
+    return ctx
+
+
+def run_schedule(ctx, X0, vals, deps, records=False):
+    """One insertion of the batch from X0: one explicit schedule, every robot on its own."""
     ctx.fem_set_state(X0)
-    for k in range(1, n_load_steps + 1):
-        d, t = load_schedule(rb, k)
-        ctx.fem_set_actuation(0, t.ravel(), d)
-        ctx.fem_solve(1, state=False, info=False)
+    return ctx.fem_solve_schedule(0, vals, deps, state=False, info=True, records=records)
 
 
-def solves_of(ctx):
-    out = ctx.fem_solve(0, state=False, info=True)
-    info = out["info"]
-    return (sum(i["steps_converged"] for i in info), sum(i["steps_total"] for i in info),
-            sum(i["iters_total"] for i in info), info)
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
-def config2(max_newton, capacity):
-    """The 1000-element robot inserted into the 200k-triangle lumen over 100 load steps, in
-    mixed precision and in FP64 (one context each): solves/s, converged load steps, Newton
-    iterations and the mixed path's relative tip error against the FP64 one per load step."""
-    from paper_2503_06922_amd import fem
+def _cpu_worker(args):
+    """One robot of the batched workload through all load steps with the FP64 oracle
+    (a process of its own, one BLAS thread)."""
+    b, n_steps = args
+    os.environ["OMP_NUM_THREADS"] = "1"
+    from oracle import solver, collision
     from workloads import make_config, load_schedule
+    rb, V, T = make_config(3)
+    sub = rb.subset([b])
+    rob = solver.robots_from_batch(sub, collision.Mesh(V, T))[0]
+    sched = lambda k: (lambda d, t: (d[0], t[0]))(*load_schedule(sub, k))
+    t0 = time.perf_counter()
+    _, _, traj = solver.solve_robot(rob, sched, n_steps, tol=1e-10, stag_tol=1e-9, max_iter=60)
+    return sum(1 for s in traj if s["info"]["status"] == solver.OK), time.perf_counter() - t0
+
+
+def cpu_baseline(n_robots, n_steps, workers, total_solves_gpu):
+    """The FP64 oracle on the host cores: a seeded sample of the batch's robots, each through
+    n_steps load steps in a process of its own (pool of `workers`)."""
+    import multiprocessing as mp
+    rng = np.random.default_rng([3, 7])
+    pick = sorted(rng.choice(4096, size=n_robots, replace=False).tolist())
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        res = pool.map(_cpu_worker, [(b, n_steps) for b in pick], chunksize=1)
+    wall = time.perf_counter() - t0
+    conv = sum(r[0] for r in res)
+    rate = conv / wall
+    return dict(value=rate, unit="solves/s", cores=workers, kind="oracle",
+                cpu=cpu_model(),
+                sample=f"{n_robots} seeded robots of the batched workload x {n_steps} load steps, "
+                       f"one process per robot on {workers} cores ({conv} converged solves in "
+                       f"{wall:.1f} s wall, {sum(r[1] for r in res):.0f} s CPU)",
+                extrapolated_batch_s=total_solves_gpu / rate if rate > 0 else None,
+                extrapolation="time the oracle would take for the batch's converged solves "
+                              "at the sample's rate (extrapolated, not measured)")
+
+
+def config2(args):
+    """The 1000-element robot inserted into the 200k-triangle lumen over 100 load steps, in
+    mixed precision and in FP64: solves/s, converged load steps, Newton iterations and the
+    mixed path's relative tip error against the FP64 one per load step."""
+    from paper_2503_06922_amd import fem
+    from workloads import make_config, schedule_table
     rb, V, T = make_config(2)
     out = {"workload": "1 robot x %d load steps, %d elements, %dk-triangle branching lumen"
                        % (rb.n_load_steps, int(rb.n_elem[0]), round(T.shape[0] / 1000))}
-    tips = {}
+    vals, deps = schedule_table(rb)
+    rec = {}
     for name, prec in (("mixed", fem.FEM_MIXED), ("fp64", fem.FEM_FP64)):
         ctx = fem.Context(fem.params_from_batch(rb, precision=prec, newton_tol=1e-10, stag_tol=1e-9,
-                                                max_newton=max_newton, contact_capacity=capacity))
+                                                max_newton=args.max_newton,
+                                                contact_capacity=args.capacity))
         ctx.fem_set_lumen(V, T)
-        ctx.fem_set_actuation(0, np.zeros(3), np.zeros(1))
-        tip, t_solve = [], 0.0
-        for k in range(1, rb.n_load_steps + 1):
-            d, t = load_schedule(rb, k)
-            ctx.fem_set_actuation(0, t.ravel(), d)
-            t0 = time.perf_counter()
-            o = ctx.fem_solve(1, state=True, info=True)
-            t_solve += time.perf_counter() - t0
-            tip.append((o["state"][-1, 0:3].copy(), o["info"][0]["status"]))
-        conv, total, iters, _ = solves_of(ctx)
+        t0 = time.perf_counter()
+        o = ctx.fem_solve_schedule(0, vals, deps, state=False, info=True, records=True)
+        t_solve = time.perf_counter() - t0
+        i = o["info"][0]
         ctx.close()
-        tips[name] = tip
-        out[name] = {"solves_per_s": conv / t_solve, "converged": conv, "load_steps": total,
-                     "newton_iters_per_solve": iters / max(total, 1)}
-    e = [np.linalg.norm(a[0] - b[0]) / rb.length[0]
-         for a, b in zip(tips["mixed"], tips["fp64"]) if a[1] == 0 and b[1] == 0]
-    out["tip_err_mixed_vs_fp64"] = {"max": float(max(e)) if e else None,
-                                    "median": float(np.median(e)) if e else None,
-                                    "load_steps_compared": len(e)}
+        rec[name] = o
+        out[name] = {"solves_per_s": i["steps_converged"] / t_solve, "converged": i["steps_converged"],
+                     "load_steps": i["steps_total"],
+                     "newton_iters_per_solve": i["iters_total"] / max(i["steps_total"], 1)}
+    ok = (rec["mixed"]["rec_status"][:, 0] == 0) & (rec["fp64"]["rec_status"][:, 0] == 0)
+    e = np.linalg.norm(rec["mixed"]["rec_tip"][:, 0] - rec["fp64"]["rec_tip"][:, 0], axis=1) / rb.length[0]
+    out["tip_err_mixed_vs_fp64"] = {"max": float(e[ok].max()) if ok.any() else None,
+                                    "median": float(np.median(e[ok])) if ok.any() else None,
+                                    "load_steps_compared": int(ok.sum())}
     return out
-
-
-def cpu_baseline(rb, V, T, n_robots, n_steps):
-    """The FP64 oracle on a bounded sample: n_robots robots x n_steps load steps."""
-    from oracle import solver, collision
-    from workloads import load_schedule
-    try:
-        from threadpoolctl import threadpool_limits
-        lim = threadpool_limits(1)
-    except Exception:
-        lim = None
-    mesh = collision.Mesh(V, T)
-    sub = rb.subset(np.arange(n_robots))
-    robs = solver.robots_from_batch(sub, mesh)
-    t0 = time.perf_counter()
-    conv = 0
-    for b, rob in enumerate(robs):
-        sched = lambda k, b=b: (lambda d, t: (d[b], t[b]))(*load_schedule(sub, k))
-        _, _, traj = solver.solve_robot(rob, sched, n_steps, tol=1e-10, stag_tol=1e-9, max_iter=100)
-        conv += sum(1 for s in traj if s["info"]["status"] == solver.OK)
-    dt = time.perf_counter() - t0
-    return dict(value=conv / dt, unit="solves/s", cores=1, kind="oracle",
-                sample=f"{n_robots} robots x {n_steps} load steps of the batched workload "
-                       f"({conv} converged solves in {dt:.1f} s, 1 BLAS thread)")
 
 
 def main():
@@ -182,15 +221,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--robots", type=int, default=4096)
     ap.add_argument("--load-steps", type=int, default=100)
-    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--max-newton", type=int, default=60)
     ap.add_argument("--capacity", type=int, default=512)
-    ap.add_argument("--cpu-robots", type=int, default=2)
-    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--cpu-robots", type=int, default=0, help="oracle sample size (0 = one per core)")
+    ap.add_argument("--cpu-steps", type=int, default=100)
+    ap.add_argument("--cpu-workers", type=int, default=0, help="0 = the host's cores, at most 16")
     ap.add_argument("--single-robots", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-single", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel timing schedule")
     ap.add_argument("--no-config2", action="store_true",
                     help="skip the 1000-element robot on the 200k-triangle lumen")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -201,10 +240,10 @@ def main():
               "independent: a multi-GPU run would shard the batch, see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
 
-    from paper_2503_06922_amd import fem
-    from workloads import make_config
-
     import torch
+    from paper_2503_06922_amd import fem
+    from workloads import make_config, schedule_table
+
     torch.cuda.init()
     if args.copy_calib_mib > 0:
         n = args.copy_calib_mib * (1 << 20) // 8
@@ -215,137 +254,147 @@ def main():
         del src, dst
     rb_all, V, T = make_config(3)
     rb = rb_all.subset(np.arange(args.robots)) if args.robots < rb_all.n_robots else rb_all
-    prec = fem.FEM_MIXED if args.precision == "mixed" else fem.FEM_FP64
-    ctx = fem.Context(fem.params_from_batch(rb, precision=prec, newton_tol=1e-10, stag_tol=1e-9,
-                                            max_newton=args.max_newton,
-                                            contact_capacity=args.capacity))
-    ctx.fem_set_lumen(V, T)
-    ctx.fem_set_actuation(0, np.zeros(3 * rb.n_robots), np.zeros(rb.n_robots))
-    X0 = ctx.fem_get_state()
+    nls = args.load_steps
+    vals_h, deps_h = schedule_table(rb, nls)
+    vals = torch.tensor(vals_h, device="cuda")
+    deps = torch.tensor(deps_h, device="cuda")
 
+    ctx = make_context(fem, rb, fem.FEM_MIXED, args, V, T)
+    X0 = ctx.fem_get_state()
     for _ in range(args.warmup):
-        run_schedule(ctx, rb, args.load_steps, X0)
+        run_schedule(ctx, X0, vals, deps)
         print("bench: warmup schedule done", file=sys.stderr, flush=True)
-    # timed region: whole-batch insertions; each fem_solve returns after its stream synchronises
-    ctx.fem_set_state(X0)  # resets the per-robot counters
+    # timed region: whole-batch insertions; each call returns after its stream synchronises
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        run_schedule(ctx, rb, args.load_steps, X0)
+    for s in range(args.steps):
+        out = run_schedule(ctx, X0, vals, deps, records=(s == args.steps - 1))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     print(f"bench: timed schedules done ({dt:.1f} s)", file=sys.stderr, flush=True)
-    # counters cover the last schedule only (fem_set_state resets them): scale to all steps
-    conv, total, iters, info = solves_of(ctx)
-    solves = conv * args.steps
-    value = solves / dt
+    info = out["info"]                      # counters of the last schedule (fem_set_state resets)
+    conv = sum(i["steps_converged"] for i in info)
+    total = sum(i["steps_total"] for i in info)
+    iters = sum(i["iters_total"] for i in info)
+    st_m = out["rec_status"].cpu().numpy()
+    tip_m = out["rec_tip"].cpu().numpy()
 
-    # kernel times: one more schedule on a context that brackets every launch with HIP events
-    # on its stream (outside the timed region: the event synchronisation slows the loop)
-    cp = fem.Context(fem.params_from_batch(rb, precision=prec, newton_tol=1e-10, stag_tol=1e-9,
-                                           max_newton=args.max_newton,
-                                           contact_capacity=args.capacity, profile=1))
-    cp.fem_set_lumen(V, T)
-    cp.fem_set_actuation(0, np.zeros(3 * rb.n_robots), np.zeros(rb.n_robots))
-    run_schedule(cp, rb, args.load_steps, X0)
-    print("bench: profiled schedule done", file=sys.stderr, flush=True)
-    prof = [cp.fem_profile(k) for k in range(6)]
-    _, _, _, info_p = solves_of(cp)
-    cp.close()
-    kern = {KERNELS[k]: dict(total_ms=prof[k][0], launches=prof[k][1],
-                             avg_us=1e3 * prof[k][0] / max(prof[k][1], 1)) for k in range(6)}
-    dom = KERNELS[max(range(6), key=lambda k: prof[k][0])]
-    # rooflines: algorithmic bytes per launch / average launch time
-    sb = 4 if prec == fem.FEM_MIXED else 8
-    n_nodes = np.asarray(rb.n_elem, np.int64) + 1
-    alg = algorithmic_bytes(info_p, n_nodes, sb, 1)
-    roofs = {}
-    for name, (per_unit, total_bytes) in alg.items():
-        k = KERNELS.index(name)
-        launches = max(prof[k][1], 1)
-        avg_s = prof[k][0] / 1e3 / launches
-        gbs = total_bytes / launches / avg_s / 1e9
-        tr = measured_traffic(name, args.capacity)
-        roofs[name] = dict(bound="hbm", kernel=name, achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s",
-                           frac=gbs / HBM_PEAK_GBS, traffic=tr, bytes_per_unit=per_unit,
-                           bytes_per_launch=total_bytes / launches, avg_launch_us=avg_s * 1e6)
-    roof = roofs.get(dom) or max(roofs.values(), key=lambda r: r["avg_launch_us"])
+    # the same schedule in plain FP64 (batched): throughput and the per-step reference tips
+    c64 = make_context(fem, rb, fem.FEM_FP64, args, V, T)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    o64 = run_schedule(c64, X0, vals, deps, records=True)
+    t64 = time.perf_counter() - t1
+    print(f"bench: FP64 schedule done ({t64:.1f} s)", file=sys.stderr, flush=True)
+    conv64 = sum(i["steps_converged"] for i in o64["info"])
+    st_64 = o64["rec_status"].cpu().numpy()
+    tip_64 = o64["rec_tip"].cpu().numpy()
+    c64.close()
+    err = np.linalg.norm(tip_m - tip_64, axis=2) / rb.length[None, :]      # [steps, robots]
+    both = (st_m == 0) & (st_64 == 0)
+    valid = both & (err <= TIP_TOL)
+    value = int(valid.sum()) * args.steps / dt
+    p50, p99, pmax = [], [], []
+    for k in range(nls):
+        e = err[k][both[k]]
+        p50.append(float(np.median(e)) if e.size else None)
+        p99.append(float(np.percentile(e, 99)) if e.size else None)
+        pmax.append(float(e.max()) if e.size else None)
+    apart = np.any(both & (err > TIP_TOL), axis=0)
+    first_apart = [int(np.argmax(both[:, b] & (err[:, b] > TIP_TOL))) + 1 for b in np.nonzero(apart)[0]]
+    tip_err = {
+        "per_step_p50": [float("%.2g" % v) if v is not None else None for v in p50],
+        "per_step_p99": [float("%.2g" % v) if v is not None else None for v in p99],
+        "per_step_max": [float("%.2g" % v) if v is not None else None for v in pmax],
+        "solves_compared": int(both.sum()), "solves_within_1e-5": int(valid.sum()),
+        "robots_ever_apart": int(apart.sum()),
+        "first_step_apart_quartiles": (np.percentile(first_apart, [25, 50, 75]).tolist()
+                                       if first_apart else None),
+    }
 
     res = {
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 tangent+screen / f64" if prec == fem.FEM_MIXED else "f64",
+        "dtype": "f64 (f32 tangent storage + f32 detection screen)",
         "data": "synthetic",
-        "config": {"workload": "batched insertion: %d robots x %d load steps, 50-400 elements, "
-                               "50k-triangle branching lumen" % (rb.n_robots, args.load_steps),
-                   "robots": int(rb.n_robots), "load_steps": args.load_steps,
-                   "precision": args.precision, "max_newton": args.max_newton,
-                   "contact_capacity": args.capacity,
+        "config": {"workload": "batched insertion: %d robots x %d load steps, 50-400 elements "
+                               "(Table I shaft + 70 mm tube tip), moment-only cable load (eq. 16), "
+                               "rigid insertion guide, 50k-triangle branching lumen, mixed "
+                               "precision" % (rb.n_robots, nls),
+                   "robots": int(rb.n_robots), "load_steps": nls, "precision": "mixed",
+                   "max_newton": args.max_newton, "contact_capacity": args.capacity,
                    "nodes": int(ctx.n_nodes)},
+        "solves_converged_per_s": conv * args.steps / dt,
         "converged_fraction": conv / max(total, 1),
         "newton_iters_per_solve": iters / max(total, 1),
-        "kernels": kern, "dominant_kernel": dom,
-        "roofline": roof, "rooflines": roofs,
+        "fp64_batched_solves_per_s": conv64 / t64,
+        "mixed_vs_fp64_batched": (conv * args.steps / dt) / (conv64 / t64),
+        "tip_err_mixed_vs_fp64": tip_err,
     }
-    if prec == fem.FEM_MIXED and not args.no_fp64:
-        # the same batch in plain FP64 (batched): throughput and the mixed path's tip error
-        c64 = fem.Context(fem.params_from_batch(rb, precision=fem.FEM_FP64, newton_tol=1e-10,
-                                                stag_tol=1e-9, max_newton=args.max_newton,
-                                                contact_capacity=args.capacity))
-        c64.fem_set_lumen(V, T)
-        c64.fem_set_actuation(0, np.zeros(3 * rb.n_robots), np.zeros(rb.n_robots))
-        t1 = time.perf_counter()
-        run_schedule(c64, rb, args.load_steps, X0)
-        t64 = time.perf_counter() - t1
-        print(f"bench: FP64 schedule done ({t64:.1f} s)", file=sys.stderr, flush=True)
-        conv64, _, _, info64 = solves_of(c64)
-        Xm = ctx.fem_get_state()
-        X64 = c64.fem_get_state()
-        tips = np.asarray(rb.node_offset[1:]) - 1
-        both = np.array([i["status"] == 0 and j["status"] == 0 for i, j in zip(info, info64)])
-        err = np.linalg.norm(Xm[tips, 0:3] - X64[tips, 0:3], axis=1) / rb.length
-        res["fp64_batched_solves_per_s"] = conv64 / t64
-        e = err[both]
-        res["tip_err_mixed_vs_fp64"] = {"max": float(e.max()) if both.any() else None,
-                                        "median": float(np.median(e)) if both.any() else None,
-                                        "p99": float(np.percentile(e, 99)) if both.any() else None,
-                                        "within_1e-5": int(np.sum(e <= 1e-5)),
-                                        "robots_compared": int(both.sum())}
-        # robots that converged on every load step in both precisions (no diverging restart
-        # from a failed load step's last iterate on either side)
-        every = np.array([i["steps_converged"] == i["steps_total"] and
-                          j["steps_converged"] == j["steps_total"] for i, j in zip(info, info64)])
-        ea = err[every]
-        res["tip_err_mixed_vs_fp64"]["every_step_converged"] = {
-            "robots": int(every.sum()), "within_1e-5": int(np.sum(ea <= 1e-5)),
-            "p99": float(np.percentile(ea, 99)) if every.any() else None,
-            "max": float(ea.max()) if every.any() else None}
-        c64.close()
+
+    if not args.no_profile:
+        # kernel times: one more schedule on a context that brackets every kernel class with
+        # HIP events on its stream (outside the timed region: it synchronises every pass)
+        cp = make_context(fem, rb, fem.FEM_MIXED, args, V, T, profile=1)
+        op = run_schedule(cp, X0, vals, deps)
+        print("bench: profiled schedule done", file=sys.stderr, flush=True)
+        prof = [cp.fem_profile(k) for k in range(6)]
+        cp.close()
+        kern = {KERNELS[k]: dict(total_ms=prof[k][0], launches=prof[k][1],
+                                 avg_us=1e3 * prof[k][0] / max(prof[k][1], 1)) for k in range(6)}
+        dom = KERNELS[max(range(6), key=lambda k: prof[k][0])]
+        n_nodes = np.asarray(rb.n_elem, np.int64) + 1
+        units = launch_units(op["info"], n_nodes)
+        models = byte_models(units, 4)
+        roofs = {}
+        for name, m in models.items():
+            k = KERNELS.index(name)
+            launches = max(prof[k][1], 1)
+            avg_s = prof[k][0] / 1e3 / launches
+            r = {"bound": "hbm", "kernel": name, "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                 "avg_launch_us": avg_s * 1e6, "launches": launches,
+                 "traffic": measured_traffic(name, args.capacity)}
+            for key in ("scope", "design"):
+                per, unit, tot = m[key]
+                gbs = tot / launches / avg_s / 1e9
+                r[key] = dict(bytes_per_unit=per, unit_name=unit, bytes_per_launch=tot / launches,
+                              achieved=gbs, frac=gbs / HBM_PEAK_GBS)
+            r["achieved"] = r["scope"]["achieved"]
+            r["frac"] = r["scope"]["frac"]
+            roofs[name] = r
+        res["units_per_schedule"] = units
+        res["kernels"] = kern
+        res["dominant_kernel"] = dom
+        roof = roofs.get(dom) or max(roofs.values(), key=lambda r: r["avg_launch_us"])
+        res["roofline"] = roof
+        res["rooflines"] = roofs
     if not args.no_single:
         # plain FP64 path of configuration 0: one robot per context, run one after another
-        t_single = 0.0
-        conv_single = 0
+        t_single, conv_single = 0.0, 0
         for b in range(args.single_robots):
             sub = rb.subset([b])
+            v1, d1 = schedule_table(sub, nls)
             c1 = fem.Context(fem.params_from_batch(sub, precision=fem.FEM_FP64, newton_tol=1e-10,
                                                    stag_tol=1e-9, max_newton=args.max_newton,
                                                    contact_capacity=args.capacity))
             c1.fem_set_lumen(V, T)
-            c1.fem_set_actuation(0, np.zeros(3), np.zeros(1))
-            X1 = c1.fem_get_state()
             t1 = time.perf_counter()
-            run_schedule(c1, sub, args.load_steps, X1)
+            o1 = c1.fem_solve_schedule(0, v1, d1, state=False, info=True, records=False)
             t_single += time.perf_counter() - t1
-            conv_single += solves_of(c1)[0]
+            conv_single += o1["info"][0]["steps_converged"]
             c1.close()
         res["fp64_single_solves_per_s"] = conv_single / t_single
         res["ratio_vs_fp64_single"] = value / res["fp64_single_solves_per_s"]
+    ctx.close()
     if not args.no_config2:
-        res["config2"] = config2(args.max_newton, args.capacity)
+        res["config2"] = config2(args)
         print("bench: 1000-element robot done", file=sys.stderr, flush=True)
     if not args.no_cpu:
-        res["cpu_baseline"] = cpu_baseline(rb, V, T, args.cpu_robots, args.cpu_steps)
+        workers = args.cpu_workers or min(16, os.cpu_count() or 1)
+        n_cpu = args.cpu_robots or workers
+        res["cpu_baseline"] = cpu_baseline(n_cpu, min(args.cpu_steps, nls), workers, conv)
+        print("bench: oracle sample done", file=sys.stderr, flush=True)
     print(json.dumps(res), flush=True)
 
 

@@ -107,7 +107,8 @@ typedef struct {
   int32_t contact_capacity;   /* max contacts per robot (<= 1024) */
   double grid_cell;           /* uniform-grid cell size for the lumen, 0 = automatic */
   fem_precision precision;    /* FEM_FP64 or FEM_MIXED */
-  void* hip_stream;           /* hipStream_t to run on, or NULL for the null stream */
+  void* hip_stream;           /* hipStream_t to run on, or NULL: the null stream for copies
+                                 and a stream of the context's own for the load-step loop */
   int32_t io_on_device;       /* 1: array arguments of later calls are device pointers */
   int32_t profile;            /* 1: time every kernel launch with HIP events (fem_profile) */
 } fem_params;
@@ -184,11 +185,34 @@ fem_status fem_set_actuation(fem_ctx* c, fem_act_kind kind, const double* values
  * prev is what the previous call reached (0 initially) and target the values
  * of fem_set_actuation.  Each load step starts from the previous state.
  * n_load_steps = 0 solves nothing and takes the target as reached, so that it
- * starts the next ramp (e.g. after fem_set_state with a state at that load).
+ * starts the next ramp (e.g. after fem_set_state with a state at that load).  Every robot
+ * advances through the load steps on its own (see fem_solve_schedule).
  * node_state [total_nodes*7] and info [B] may be NULL.  Returns FEM_E_NOCONV
  * if any robot's last load step did not converge (outputs still written). */
 fem_status fem_solve(fem_ctx* c, int32_t n_load_steps, double* node_state,
                      fem_solve_info* info);
+
+/* Run an explicit schedule of quasi-static load steps (Sec. III-A: each time step of the
+ * insertion solves the equilibrium of eq. 19 with the QP of eq. 23 and the step-size
+ * limit of eq. 25-27), e.g. tensions ramped over the first load steps and the insertion
+ * depth over all of them.  Step k (1-based) of robot b applies the actuation values
+ * values[((k-1)*B + b)*n_values ..] of `kind` (n_values = n_cables for the cable kinds,
+ * 6 for the tip wrenches) and the insertion depth insertion_depth[(k-1)*B + b] (NULL:
+ * the depth stays where the previous call left it).  Every robot advances through the
+ * steps on its own: a robot whose load step has ended starts its next one while other
+ * robots are still iterating, so the results equal those of n_load_steps calls of
+ * fem_set_actuation + fem_solve(1) with the same values.  The last step's values become
+ * the target reached (a later fem_solve ramps from them).  Optional per-step records
+ * (NULL to skip): rec_tip [n_load_steps*B*3] tip-node position at the end of each load
+ * step, rec_status [n_load_steps*B] its FEM_ROBOT_* status, rec_iters [n_load_steps*B]
+ * its Newton iterations, step-major like the inputs.  values, insertion_depth and the
+ * records follow io_on_device; node_state and info as in fem_solve.  FEM_E_INVAL:
+ * n_load_steps < 1, NULL values or a kind different from the context's.  FEM_E_STATE: no
+ * lumen set.  Returns FEM_E_NOCONV if any robot's last load step did not converge. */
+fem_status fem_solve_schedule(fem_ctx* c, fem_act_kind kind, int32_t n_load_steps,
+                              const double* values, const double* insertion_depth,
+                              double* node_state, fem_solve_info* info, double* rec_tip,
+                              int32_t* rec_status, int32_t* rec_iters);
 
 /* Contacts of the last iterate of robot `robot` (-1 = all robots, in order): the
  * rows of A_c (normal n_i, eq. 9), the gaps b_c (eq. 10) and the contact forces y_c

@@ -15,7 +15,7 @@
 namespace accfem {
 void launch_elem(const Dev& d, hipStream_t s);
 void launch_collide(const Dev& d, hipStream_t s);
-void launch_solve_phase(const Dev& d, int phase, int it, hipStream_t s);
+void launch_solve_phase(const Dev& d, int phase, hipStream_t s);
 void launch_gather(const Dev& d, hipStream_t s);
 void launch_adjoint(const Dev& d, const int32_t* sens, int n_s, const double* dLdp, double* JL,
                     double* JD, double* JU, double* QB, int32_t* KF, double* GP, double* out,
@@ -130,16 +130,72 @@ __global__ void set_load_kernel(Dev d, const double* act_prev, const double* act
   d.st_rn[r] = INFINITY;
 }
 
-__global__ void finalize_kernel(Dev d, int32_t* steps_conv, int32_t* steps_tot, int64_t* iters_tot) {
+// Every robot runs through the load steps of a call on its own: when its Newton iteration of a
+// load step has ended (converged or failed), the next pass of the loop books that load step
+// and starts the robot's next one, while other robots are still iterating.
+__global__ void init_steps_kernel(Dev d) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= d.B) return;
-  if (!d.st_done[r]) {  // loop ended without a final test (cannot happen with max_newton + 1 passes)
-    d.st_status[r] = 1;
-    d.st_done[r] = 1;
+  d.st_step[r] = 0;
+  d.st_it[r] = 0;
+  d.st_done[r] = 1;
+  d.st_fin[r] = 0;
+}
+
+// load step j of robot r (1-based): actuation and depth of the step, a fresh Newton state
+__device__ void begin_load_step(const Dev& d, int r, int j) {
+  const int n = d.n_steps;
+  const double f = (double)j / (double)n;
+  for (int k = 0; k < d.act_nv; ++k) {
+    const int64_t q = (int64_t)r * d.act_nv + k;
+    if (d.sched_act)
+      d.act_cur[q] = d.sched_act[((int64_t)(j - 1) * d.B + r) * d.act_nv + k];
+    else
+      d.act_cur[q] = (j == n) ? d.act_tgt[q] : d.act_prev[q] + (d.act_tgt[q] - d.act_prev[q]) * f;
   }
-  steps_tot[r] += 1;
-  steps_conv[r] += (d.st_status[r] == 0) ? 1 : 0;
-  iters_tot[r] += d.st_iters[r];
+  if (d.sched_dep)
+    d.depth_cur[r] = d.sched_dep[(int64_t)(j - 1) * d.B + r];
+  else
+    d.depth_cur[r] = (j == n) ? d.dep_tgt[r] : d.dep_prev[r] + (d.dep_tgt[r] - d.dep_prev[r]) * f;
+  d.st_step[r] = j;
+  d.st_it[r] = 0;
+  d.st_status[r] = 1;
+  d.st_done[r] = 0;
+  d.st_ncp[r] = 0;
+  d.st_nc[r] = 0;
+  d.st_limited[r] = 1;
+  d.st_nlim[r] = 0;
+  d.st_nswitch[r] = 0;
+  d.st_iters[r] = 0;
+  d.st_rnprev[r] = INFINITY;
+  d.st_rn[r] = INFINITY;
+}
+
+// first kernel of every pass of the loop: a robot whose load step has ended books it (counters
+// and the optional per-step records) and begins its next load step, or is finished
+__global__ void advance_kernel(Dev d) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= d.B) return;
+  if (d.st_fin[r] || !d.st_done[r]) return;
+  const int j = d.st_step[r];
+  if (j > 0) {
+    d.steps_tot[r] += 1;
+    d.steps_conv[r] += (d.st_status[r] == 0) ? 1 : 0;
+    d.iters_tot[r] += d.st_iters[r];
+    const int64_t q = (int64_t)(j - 1) * d.B + r;
+    if (d.rec_status) d.rec_status[q] = d.st_status[r];
+    if (d.rec_iters) d.rec_iters[q] = d.st_iters[r];
+    if (d.rec_tip) {
+      const int64_t t = d.off[r + 1] - 1, N = d.Ntot;
+      for (int k = 0; k < 3; ++k) d.rec_tip[3 * q + k] = d.X[k * N + t];
+    }
+  }
+  if (j >= d.n_steps) {
+    d.st_fin[r] = 1;
+    atomicAdd(d.n_done, 1);
+    return;
+  }
+  begin_load_step(d, r, j + 1);
 }
 
 __global__ void renorm_kernel(Dev d) {
@@ -210,6 +266,19 @@ struct fem_ctx {
   int32_t a_ns_cap = 0;
   // lumen buffers (reallocated by fem_set_lumen)
   std::vector<void*> mesh_allocs;
+  // load-stepping loop: the stream it runs on when the caller gave none, the captured graph
+  // of `graph_iters` passes and the Dev it was captured with
+  hipStream_t own_stream = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  Dev graph_dev{};
+  int graph_iters = 0;
+  int iters_per_graph = 8;  // passes per replay between host checks of the finished count
+  int32_t* h_done = nullptr;  // pinned host copy of the finished count
+  // device copies of an explicit schedule and per-step records (grown as needed)
+  double* sched_buf = nullptr;
+  int64_t sched_cap = 0;
+  double* rec_buf = nullptr;
+  int64_t rec_cap = 0;
   // per-kernel event timing
   bool profile = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -268,19 +337,95 @@ inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 // launch with optional HIP-event timing of kernel class k
 template <typename Fn>
-fem_status timed(fem_ctx* c, int k, Fn&& launch) {
+fem_status timed(fem_ctx* c, hipStream_t s, int k, Fn&& launch) {
   if (!c->profile) {
     launch();
     return FEM_OK;
   }
-  HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
+  HIP_TRY(c, hipEventRecord(c->ev0, s));
   launch();
-  HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
+  HIP_TRY(c, hipEventRecord(c->ev1, s));
   HIP_TRY(c, hipEventSynchronize(c->ev1));
   float ms = 0.f;
   HIP_TRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
   c->prof_ms[k] += ms;
   c->prof_n[k] += 1;
+  return FEM_OK;
+}
+
+// one pass of the loop over every robot: load-step advance, element update, detection and
+// the Newton step's phases
+void launch_pass(const Dev& d, hipStream_t s) {
+  hipLaunchKernelGGL(advance_kernel, dim3(nblk(d.B, 256)), dim3(256), 0, s, d);
+  launch_elem(d, s);
+  launch_collide(d, s);
+  for (int ph = 0; ph < 4; ++ph) launch_solve_phase(d, ph, s);
+}
+
+// Run the n load steps of a call: every robot advances through them on its own (a robot whose
+// load step has ended starts its next one in the following pass while the others iterate).
+// Passes are replayed from a captured graph of iters_per_graph passes; the host reads the
+// count of finished robots between replays.  A context with profile = 1 launches every pass
+// directly with HIP events around each kernel class.
+fem_status run_load_steps(fem_ctx* c, int n) {
+  Dev& d = c->d;
+  d.n_steps = n;
+  hipStream_t xs = c->stream ? c->stream : c->own_stream;
+  if (!c->stream) HIP_TRY(c, hipStreamSynchronize(nullptr));
+  hipLaunchKernelGGL(init_steps_kernel, dim3(nblk(d.B, 256)), dim3(256), 0, xs, d);
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipMemsetAsync(d.n_done, 0, sizeof(int32_t), xs));
+  // each load step takes at most max_newton + 1 passes, and one more books the last
+  const int64_t max_pass = (int64_t)n * (c->p.max_newton + 1) + 1;
+  int64_t pass = 0;
+  if (c->profile) {
+    for (;;) {
+      fem_status s;
+      if ((s = timed(c, xs, 2, [&] {
+             hipLaunchKernelGGL(advance_kernel, dim3(nblk(d.B, 256)), dim3(256), 0, xs, d);
+           })) != FEM_OK)
+        return s;
+      if ((s = timed(c, xs, 0, [&] { launch_elem(d, xs); })) != FEM_OK) return s;
+      if ((s = timed(c, xs, 1, [&] { launch_collide(d, xs); })) != FEM_OK) return s;
+      for (int ph = 0; ph < 4; ++ph)
+        if ((s = timed(c, xs, 2 + ph, [&] { launch_solve_phase(d, ph, xs); })) != FEM_OK) return s;
+      HIP_TRY(c, hipGetLastError());
+      ++pass;
+      HIP_TRY(c, hipMemcpyAsync(c->h_done, d.n_done, sizeof(int32_t), hipMemcpyDeviceToHost, xs));
+      HIP_TRY(c, hipStreamSynchronize(xs));
+      if (*c->h_done >= d.B) break;
+      if (pass > max_pass) return fail(c, FEM_E_HIP, "load stepping did not terminate");
+    }
+    return FEM_OK;
+  }
+  const int K = c->iters_per_graph;
+  if (!c->graph_exec || c->graph_iters != K || std::memcmp(&c->graph_dev, &d, sizeof(Dev)) != 0) {
+    if (c->graph_exec) {
+      HIP_TRY(c, hipGraphExecDestroy(c->graph_exec));
+      c->graph_exec = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    HIP_TRY(c, hipStreamBeginCapture(xs, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < K; ++k) launch_pass(d, xs);
+    hipError_t e = hipStreamEndCapture(xs, &g);
+    if (e != hipSuccess) return fail(c, FEM_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      c->graph_exec = nullptr;
+      return fail(c, FEM_E_HIP, std::string("graph instantiation: ") + hipGetErrorString(e));
+    }
+    std::memcpy(&c->graph_dev, &d, sizeof(Dev));
+    c->graph_iters = K;
+  }
+  for (;;) {
+    HIP_TRY(c, hipGraphLaunch(c->graph_exec, xs));
+    pass += K;
+    HIP_TRY(c, hipMemcpyAsync(c->h_done, d.n_done, sizeof(int32_t), hipMemcpyDeviceToHost, xs));
+    HIP_TRY(c, hipStreamSynchronize(xs));
+    if (*c->h_done >= d.B) break;
+    if (pass > max_pass + K) return fail(c, FEM_E_HIP, "load stepping did not terminate");
+  }
   return FEM_OK;
 }
 
@@ -298,6 +443,12 @@ void fem_destroy(fem_ctx* c) {
   if (c->stream) hipStreamSynchronize(c->stream);
   for (void* p : c->mesh_allocs) hipFree(p);
   for (void* p : c->allocs) hipFree(p);
+  if (c->own_stream) hipStreamSynchronize(c->own_stream);
+  if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
+  if (c->own_stream) hipStreamDestroy(c->own_stream);
+  if (c->h_done) hipHostFree(c->h_done);
+  if (c->sched_buf) hipFree(c->sched_buf);
+  if (c->rec_buf) hipFree(c->rec_buf);
   if (c->ev0) hipEventDestroy(c->ev0);
   if (c->ev1) hipEventDestroy(c->ev1);
   delete c;
@@ -468,6 +619,14 @@ static fem_status create_impl(fem_ctx* c, const fem_params* p) {
   ALLOC(d.st_status, B); ALLOC(d.st_done, B); ALLOC(d.st_nc, B); ALLOC(d.st_ncp, B);
   ALLOC(d.st_limited, B); ALLOC(d.st_nlim, B); ALLOC(d.st_nswitch, B); ALLOC(d.st_iters, B); ALLOC(d.st_rhs, 3 * B);
   ALLOC(d.st_rn, B); ALLOC(d.st_rnprev, B); ALLOC(d.n_done, 1);
+  ALLOC(d.st_step, B); ALLOC(d.st_it, B); ALLOC(d.st_fin, B);
+  HIP_TRY(c, hipMemset(d.st_step, 0, B * sizeof(int32_t)));
+  HIP_TRY(c, hipMemset(d.st_it, 0, B * sizeof(int32_t)));
+  HIP_TRY(c, hipMemset(d.st_fin, 0, B * sizeof(int32_t)));
+  d.act_prev = c->act_prev; d.act_tgt = c->act_tgt; d.dep_prev = c->dep_prev; d.dep_tgt = c->dep_tgt;
+  d.sched_act = nullptr; d.sched_dep = nullptr;
+  d.rec_tip = nullptr; d.rec_status = nullptr; d.rec_iters = nullptr;
+  d.n_steps = 1;
   HIP_TRY(c, hipMemset(d.st_status, 0, B * sizeof(int32_t)));
   HIP_TRY(c, hipMemset(d.st_done, 0, B * sizeof(int32_t)));
   HIP_TRY(c, hipMemset(d.st_nc, 0, B * sizeof(int32_t)));
@@ -477,6 +636,7 @@ static fem_status create_impl(fem_ctx* c, const fem_params* p) {
   HIP_TRY(c, hipMemset(d.st_rhs, 0, 3 * B * sizeof(int64_t)));
   HIP_TRY(c, hipMemset(d.st_rn, 0, B * sizeof(double)));
   ALLOC(c->steps_conv, B); ALLOC(c->steps_tot, B); ALLOC(c->iters_tot, B);
+  d.steps_conv = c->steps_conv; d.steps_tot = c->steps_tot; d.iters_tot = c->iters_tot;
   HIP_TRY(c, hipMemset(c->steps_conv, 0, B * sizeof(int32_t)));
   HIP_TRY(c, hipMemset(c->steps_tot, 0, B * sizeof(int32_t)));
   HIP_TRY(c, hipMemset(c->iters_tot, 0, B * sizeof(int64_t)));
@@ -492,6 +652,8 @@ static fem_status create_impl(fem_ctx* c, const fem_params* p) {
     HIP_TRY(c, hipEventCreate(&c->ev0));
     HIP_TRY(c, hipEventCreate(&c->ev1));
   }
+  HIP_TRY(c, hipHostMalloc((void**)&c->h_done, sizeof(int32_t), hipHostMallocDefault));
+  if (!c->stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking));
   hipLaunchKernelGGL(init_state_kernel, dim3(nblk(N, 256)), dim3(256), 0, c->stream, d, p->r_out,
                      p->r_in, p->E, p->nu, p->tip_len, p->shaft_E, p->shaft_A, p->shaft_I,
                      (const double*)c->length_d, c->kc);
@@ -675,39 +837,11 @@ fem_status fem_set_state(fem_ctx* c, const double* node_state) {
   return FEM_OK;
 }
 
-fem_status fem_solve(fem_ctx* c, int32_t n_load_steps, double* node_state, fem_solve_info* info) {
-  if (!c) return FEM_E_INVAL;
-  if (n_load_steps < 0) return fail(c, FEM_E_INVAL, "n_load_steps < 0");
-  if (!c->lumen_set) return fail(c, FEM_E_STATE, "fem_set_lumen was not called");
-  if (!c->act_set) return fail(c, FEM_E_STATE, "fem_set_actuation was not called");
-  hipSetDevice(c->device);
-  Dev& d = c->d;
+// after the load steps of a call: the target is reached (the start of the next ramp, also
+// for zero load steps); per-robot records and the state are written out
+static fem_status solve_epilogue(fem_ctx* c, double* node_state, fem_solve_info* info) {
   const int B = c->B;
-  const int max_it = c->p.max_newton;
-  for (int j = 1; j <= n_load_steps; ++j) {
-    hipLaunchKernelGGL(set_load_kernel, dim3(nblk(B, 256)), dim3(256), 0, c->stream, d,
-                       (const double*)c->act_prev, (const double*)c->act_tgt, c->act_cur,
-                       (const double*)c->dep_prev, (const double*)c->dep_tgt, c->dep_cur, j,
-                       n_load_steps);
-    HIP_TRY(c, hipMemsetAsync(d.n_done, 0, sizeof(int32_t), c->stream));
-    for (int it = 0; it <= max_it; ++it) {
-      fem_status s;
-      if ((s = timed(c, 0, [&] { launch_elem(d, c->stream); })) != FEM_OK) return s;
-      if ((s = timed(c, 1, [&] { launch_collide(d, c->stream); })) != FEM_OK) return s;
-      for (int ph = 0; ph < 4; ++ph)
-        if ((s = timed(c, 2 + ph, [&] { launch_solve_phase(d, ph, it, c->stream); })) != FEM_OK) return s;
-      HIP_TRY(c, hipGetLastError());
-      int32_t nd = 0;
-      HIP_TRY(c, hipMemcpyAsync(&nd, d.n_done, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-      HIP_TRY(c, hipStreamSynchronize(c->stream));
-      if (nd >= B) break;
-    }
-    hipLaunchKernelGGL(finalize_kernel, dim3(nblk(B, 256)), dim3(256), 0, c->stream, d,
-                       c->steps_conv, c->steps_tot, c->iters_tot);
-    HIP_TRY(c, hipGetLastError());
-  }
-  // the target is reached: it is the start of the next ramp (also for n_load_steps = 0)
-  if (n_load_steps > 0) c->solved = true;
+  Dev& d = c->d;
   HIP_TRY(c, hipMemcpyAsync(c->act_prev, c->act_tgt, (size_t)B * 8 * sizeof(double),
                             hipMemcpyDeviceToDevice, c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->dep_prev, c->dep_tgt, (size_t)B * sizeof(double),
@@ -750,6 +884,108 @@ fem_status fem_solve(fem_ctx* c, int32_t n_load_steps, double* node_state, fem_s
     if (s != FEM_OK) return s;
   }
   return any_fail ? FEM_E_NOCONV : FEM_OK;
+}
+
+fem_status fem_solve(fem_ctx* c, int32_t n_load_steps, double* node_state, fem_solve_info* info) {
+  if (!c) return FEM_E_INVAL;
+  if (n_load_steps < 0) return fail(c, FEM_E_INVAL, "n_load_steps < 0");
+  if (!c->lumen_set) return fail(c, FEM_E_STATE, "fem_set_lumen was not called");
+  if (!c->act_set) return fail(c, FEM_E_STATE, "fem_set_actuation was not called");
+  hipSetDevice(c->device);
+  Dev& d = c->d;
+  d.sched_act = nullptr; d.sched_dep = nullptr;
+  d.rec_tip = nullptr; d.rec_status = nullptr; d.rec_iters = nullptr;
+  if (n_load_steps > 0) {
+    fem_status s = run_load_steps(c, n_load_steps);
+    if (s != FEM_OK) return s;
+    c->solved = true;
+  }
+  return solve_epilogue(c, node_state, info);
+}
+
+fem_status fem_solve_schedule(fem_ctx* c, fem_act_kind kind, int32_t n_load_steps,
+                              const double* values, const double* insertion_depth,
+                              double* node_state, fem_solve_info* info, double* rec_tip,
+                              int32_t* rec_status, int32_t* rec_iters) {
+  if (!c) return FEM_E_INVAL;
+  if (n_load_steps < 1) return fail(c, FEM_E_INVAL, "n_load_steps < 1");
+  if (kind < FEM_ACT_CABLES || kind > FEM_ACT_CABLE_WRENCH || !values)
+    return fail(c, FEM_E_INVAL, "bad actuation kind or NULL values");
+  if (c->act_kind >= 0 && c->act_kind != (int)kind)
+    return fail(c, FEM_E_INVAL, "actuation kind cannot change");
+  if (!c->lumen_set) return fail(c, FEM_E_STATE, "fem_set_lumen was not called");
+  hipSetDevice(c->device);
+  const int B = c->B;
+  const int nv = (kind == FEM_ACT_CABLES || kind == FEM_ACT_CABLE_WRENCH) ? c->p.n_cables : 6;
+  const int64_t nsb = (int64_t)n_load_steps * B;
+  Dev& d = c->d;
+  c->act_kind = kind;
+  c->act_nv = nv;
+  d.act_kind = kind;
+  d.act_nv = nv;
+  // the schedule in device memory
+  const double* sa = values;
+  const double* sd = insertion_depth;
+  if (!c->io_dev) {
+    const int64_t need = nsb * (nv + 1);
+    if (need > c->sched_cap) {
+      if (c->sched_buf) (void)hipFree(c->sched_buf);
+      c->sched_buf = nullptr;
+      c->sched_cap = 0;
+      if (hipMalloc(&c->sched_buf, need * sizeof(double)) != hipSuccess)
+        return fail(c, FEM_E_NOMEM, "hipMalloc of the schedule failed");
+      c->sched_cap = need;
+    }
+    HIP_TRY(c, hipMemcpy(c->sched_buf, values, nsb * nv * sizeof(double), hipMemcpyHostToDevice));
+    sa = c->sched_buf;
+    if (insertion_depth) {
+      HIP_TRY(c, hipMemcpy(c->sched_buf + nsb * nv, insertion_depth, nsb * sizeof(double),
+                           hipMemcpyHostToDevice));
+      sd = c->sched_buf + nsb * nv;
+    }
+  } else {
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
+  // per-step records in device memory: tips (doubles), then status and iterations (int32)
+  double* rt = rec_tip;
+  int32_t* rs = rec_status;
+  int32_t* ri = rec_iters;
+  if (!c->io_dev && (rec_tip || rec_status || rec_iters)) {
+    const int64_t need = nsb * 4;
+    if (need > c->rec_cap) {
+      if (c->rec_buf) (void)hipFree(c->rec_buf);
+      c->rec_buf = nullptr;
+      c->rec_cap = 0;
+      if (hipMalloc(&c->rec_buf, need * sizeof(double)) != hipSuccess)
+        return fail(c, FEM_E_NOMEM, "hipMalloc of the per-step records failed");
+      c->rec_cap = need;
+    }
+    rt = rec_tip ? c->rec_buf : nullptr;
+    rs = rec_status ? (int32_t*)(c->rec_buf + 3 * nsb) : nullptr;
+    ri = rec_iters ? (int32_t*)(c->rec_buf + 3 * nsb) + nsb : nullptr;
+  }
+  // without depths the depth stays where the previous call left it
+  if (!sd)
+    HIP_TRY(c, hipMemcpy(c->dep_tgt, c->dep_prev, (size_t)B * sizeof(double), hipMemcpyDeviceToDevice));
+  d.sched_act = sa; d.sched_dep = sd;
+  d.rec_tip = rt; d.rec_status = rs; d.rec_iters = ri;
+  c->act_set = true;
+  fem_status s = run_load_steps(c, n_load_steps);
+  d.sched_act = nullptr; d.sched_dep = nullptr;
+  d.rec_tip = nullptr; d.rec_status = nullptr; d.rec_iters = nullptr;
+  if (s != FEM_OK) return s;
+  c->solved = true;
+  // the last step's values are the target reached (the start of a later ramp)
+  HIP_TRY(c, hipMemcpy(c->act_tgt, sa + (nsb - B) * nv, (size_t)B * nv * sizeof(double),
+                       hipMemcpyDeviceToDevice));
+  if (sd)
+    HIP_TRY(c, hipMemcpy(c->dep_tgt, sd + (nsb - B), (size_t)B * sizeof(double), hipMemcpyDeviceToDevice));
+  if (!c->io_dev) {
+    if (rec_tip) HIP_TRY(c, hipMemcpy(rec_tip, rt, nsb * 3 * sizeof(double), hipMemcpyDeviceToHost));
+    if (rec_status) HIP_TRY(c, hipMemcpy(rec_status, rs, nsb * sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (rec_iters) HIP_TRY(c, hipMemcpy(rec_iters, ri, nsb * sizeof(int32_t), hipMemcpyDeviceToHost));
+  }
+  return solve_epilogue(c, node_state, info);
 }
 
 fem_status fem_grad(fem_ctx* c, const int32_t* sensor_nodes, int32_t n_sensors,

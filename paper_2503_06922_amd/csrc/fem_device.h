@@ -47,9 +47,9 @@ struct Dev {
   double cable_radius;
   const double* cable_cos;  // [n_cables]
   const double* cable_sin;
-  const double* act_cur;    // [B*nv] values of the current load step
+  double* act_cur;          // [B*nv] values of each robot's current load step
   int act_nv;
-  const double* depth_cur;  // [B]
+  double* depth_cur;        // [B]
   double guide_len;
   // contact rule
   double r_c, delta, beta0;
@@ -128,8 +128,25 @@ struct Dev {
                         // substitution passes, since creation / the last state reset
   double* st_rn;        // residual norm at the last check
   double* st_rnprev;
-  int32_t* n_done;      // [1] robots finished in this load step
+  int32_t* n_done;      // [1] robots that finished every load step of the current call
   int mixed;
+  // load stepping: every robot advances through the load steps of a call on its own
+  int n_steps;              // load steps of the current call
+  int32_t* st_step;         // [B] current load step (1-based; 0 before the first)
+  int32_t* st_it;           // [B] Newton iteration within the current load step
+  int32_t* st_fin;          // [B] every load step of the call is done
+  const double* act_prev;   // [B*8] ramp start (values reached by the previous call) ...
+  const double* act_tgt;    // [B*8] ... and end (the call's target)
+  const double* dep_prev;   // [B]
+  const double* dep_tgt;    // [B]
+  const double* sched_act;  // [n_steps*B*act_nv] explicit per-step values, or NULL (ramp)
+  const double* sched_dep;  // [n_steps*B] explicit per-step depths, or NULL (ramp)
+  double* rec_tip;          // [n_steps*B*3] tip position at the end of each load step, or NULL
+  int32_t* rec_status;      // [n_steps*B] status of each load step, or NULL
+  int32_t* rec_iters;       // [n_steps*B] Newton iterations of each load step, or NULL
+  int32_t* steps_conv;      // [B] statistics since creation / the last state reset
+  int32_t* steps_tot;
+  int64_t* iters_tot;
 };
 
 // ------------------------------------------------------------------ vectors

@@ -130,15 +130,15 @@ __device__ __forceinline__ void finish(const Dev& d, int r, int status, int iter
     d.st_done[r] = 1;
     d.st_iters[r] = iters;
     d.st_rn[r] = rn;
-    atomicAdd(d.n_done, 1);
   }
 }
 
 // phase 1: contact gather, convergence test, right-hand sides (col 0 = -r, contact columns)
-__global__ void __launch_bounds__(NT) check_rhs_kernel(Dev d, int it) {
+__global__ void __launch_bounds__(NT) check_rhs_kernel(Dev d) {
   const int r = blockIdx.x;
   const int lane = threadIdx.x;
   if (d.st_done[r]) return;
+  const int it = d.st_it[r];
   const int64_t o = d.off[r], n = d.off[r + 1] - o;
   const int64_t N = d.Ntot;
   const int64_t nf = n - 1;            // free nodes 1..n-1 -> f = 0..nf-1
@@ -326,7 +326,7 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 // forward values of both sides meet: z_m = L_m^-1 (b_m - X_top y_top - X_bot y_bot), and the
 // middle node's solution x_m = L_m^-T z_m goes to Z, where the substitution starts both sides'
 // backward sweeps.
-__global__ void __launch_bounds__(4 * NT) __attribute__((amdgpu_waves_per_eu(3))) factor_kernel(Dev d, int it) {
+__global__ void __launch_bounds__(4 * NT) __attribute__((amdgpu_waves_per_eu(3))) factor_kernel(Dev d) {
   const int r = blockIdx.x;
   const int w = threadIdx.x / NT, lane = threadIdx.x % NT;
   const int sd = w >> 1;                      // side: 0 from the base, 1 from the tip
@@ -615,7 +615,7 @@ __global__ void __launch_bounds__(4 * NT) __attribute__((amdgpu_waves_per_eu(3))
   }
   if (fail) s_fail = 1;
   __syncthreads();
-  if (s_fail) finish(d, r, 3, it, d.st_rn[r]);
+  if (s_fail) finish(d, r, 3, d.st_it[r], d.st_rn[r]);
 }
 
 // phase 3: substitution of all right-hand sides with the two-ended factor of phase 2.
@@ -1220,7 +1220,7 @@ __global__ void __launch_bounds__(256) step_dx_kernel(Dev d) {
 // phase 4c, one thread per node: the step-size limit (eq. 25-27: scale the step so that no
 // node moves more than beta, beta halved every 10 contact-set switches) and the state
 // update; the robot's contacts become the previous list (forces scaled with the step).
-__global__ void __launch_bounds__(256) step_apply_kernel(Dev d, int it) {
+__global__ void __launch_bounds__(256) step_apply_kernel(Dev d) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= d.Ntot) return;
   const int r = d.robot_of[g];
@@ -1274,12 +1274,14 @@ __global__ void __launch_bounds__(256) step_apply_kernel(Dev d, int it) {
     d.st_ncp[r] = nc;
     d.st_limited[r] = limited ? 1 : 0;
     d.st_nlim[r] += limited ? 1 : 0;
+    const int it = d.st_it[r];
     d.st_iters[r] = it + 1;
+    d.st_it[r] = it + 1;
   }
 }
 
 // phase 4 for robots with at most LCPM contacts: W packed in LDS, the wavefront LCP
-__global__ void __launch_bounds__(NT) update_kernel(Dev d, int it) {
+__global__ void __launch_bounds__(NT) update_kernel(Dev d) {
   const int r = blockIdx.x;
   const int lane = threadIdx.x;
   if (d.st_done[r]) return;
@@ -1315,7 +1317,7 @@ __global__ void __launch_bounds__(NT) update_kernel(Dev d, int it) {
   if (lane == 0) s_lcp_ok = ok ? 1 : 0;
   __syncthreads();
   if (!s_lcp_ok) {
-    finish(d, r, 2, it, d.st_rn[r]);
+    finish(d, r, 2, d.st_it[r], d.st_rn[r]);
     return;
   }
   store_active(d, r, nc);
@@ -1759,7 +1761,7 @@ __device__ __forceinline__ LcpWs global_ws(double* g, int m) {
 }
 
 // phase 4 for robots with more than LCPM contacts
-__global__ void __launch_bounds__(NT) update_wide_kernel(Dev d, int it) {
+__global__ void __launch_bounds__(NT) update_wide_kernel(Dev d) {
   const int r = blockIdx.x;
   if (d.st_done[r]) return;
   const int nc = d.st_nc[r];
@@ -1781,7 +1783,7 @@ __global__ void __launch_bounds__(NT) update_wide_kernel(Dev d, int it) {
   const int code = lcp_wide<SPL>(src, S, wl, Wc, cap, qv, nc, y, true);
   if (threadIdx.x == 0) d.st_big[r] = code == 2 ? 1 : 0;
   if (code == 1) {
-    finish(d, r, 2, it, d.st_rn[r]);
+    finish(d, r, 2, d.st_it[r], d.st_rn[r]);
     return;
   }
   if (code == 0) store_active(d, r, nc);
@@ -1790,7 +1792,7 @@ __global__ void __launch_bounds__(NT) update_wide_kernel(Dev d, int it) {
 // phase 4 for the robots whose wide LCP outgrew the LDS factor: the same method again with the
 // factor in the robot's device workspace (up to every constraint).  A kernel of its own, so
 // that the common path keeps its registers (this one holds 16 positions per lane).
-__global__ void __launch_bounds__(NT) update_big_kernel(Dev d, int it) {
+__global__ void __launch_bounds__(NT) update_big_kernel(Dev d) {
   const int r = blockIdx.x;
   if (d.st_done[r]) return;
   const int nc = d.st_nc[r];
@@ -1807,7 +1809,7 @@ __global__ void __launch_bounds__(NT) update_big_kernel(Dev d, int it) {
   double* scratch = d.W + (int64_t)d.B * cap * cap + (int64_t)r * lcp_ws_doubles(cap);
   const RobotLcpSource src(&d, r, cb, Zr, ld, nc);
   if (lcp_wide<SPG>(src, S, global_ws(scratch, nc), Wc, cap, qv, nc, y, true) != 0) {
-    finish(d, r, 2, it, d.st_rn[r]);
+    finish(d, r, 2, d.st_it[r], d.st_rn[r]);
     return;
   }
   store_active(d, r, nc);
@@ -1880,17 +1882,17 @@ __global__ void __launch_bounds__(NT) gather_kernel(Dev d) {
 }
 
 // phases of one Newton step: 0 check + right-hand sides, 1 factor, 2 substitute, 3 update
-void launch_solve_phase(const Dev& d, int phase, int it, hipStream_t s) {
+void launch_solve_phase(const Dev& d, int phase, hipStream_t s) {
   switch (phase) {
-    case 0: hipLaunchKernelGGL(check_rhs_kernel, dim3(d.B), dim3(NT), 0, s, d, it); break;
-    case 1: hipLaunchKernelGGL(factor_kernel, dim3(d.B), dim3(4 * NT), 0, s, d, it); break;
+    case 0: hipLaunchKernelGGL(check_rhs_kernel, dim3(d.B), dim3(NT), 0, s, d); break;
+    case 1: hipLaunchKernelGGL(factor_kernel, dim3(d.B), dim3(4 * NT), 0, s, d); break;
     case 2: hipLaunchKernelGGL(subst_kernel, dim3(d.B, (d.cap + NT) / NT), dim3(2 * NT), 0, s, d); break;
     default:
-      hipLaunchKernelGGL(update_kernel, dim3(d.B), dim3(NT), 0, s, d, it);
-      if (d.cap > LCPM) hipLaunchKernelGGL(update_wide_kernel, dim3(d.B), dim3(NT), 0, s, d, it);
-      if (d.cap > NPW) hipLaunchKernelGGL(update_big_kernel, dim3(d.B), dim3(NT), 0, s, d, it);
+      hipLaunchKernelGGL(update_kernel, dim3(d.B), dim3(NT), 0, s, d);
+      if (d.cap > LCPM) hipLaunchKernelGGL(update_wide_kernel, dim3(d.B), dim3(NT), 0, s, d);
+      if (d.cap > NPW) hipLaunchKernelGGL(update_big_kernel, dim3(d.B), dim3(NT), 0, s, d);
       hipLaunchKernelGGL(step_dx_kernel, dim3((unsigned)((d.Ntot + 255) / 256)), dim3(256), 0, s, d);
-      hipLaunchKernelGGL(step_apply_kernel, dim3((unsigned)((d.Ntot + 255) / 256)), dim3(256), 0, s, d, it);
+      hipLaunchKernelGGL(step_apply_kernel, dim3((unsigned)((d.Ntot + 255) / 256)), dim3(256), 0, s, d);
       break;
   }
 }

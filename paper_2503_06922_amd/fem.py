@@ -73,6 +73,13 @@ def lib():
         if not os.path.exists(_LIB_PATH):
             raise RuntimeError(f"{_LIB_PATH} is missing: build it with "
                                "`python -m paper_2503_06922_amd.build`")
+        try:
+            # torch ships a HIP runtime of its own under the same soname as the system one:
+            # loading torch first makes the library bind to that runtime, so that one HIP
+            # runtime serves both and torch's device memory and streams are valid here
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(_LIB_PATH)
         P = C.c_void_p
         L.fem_create.argtypes = [C.POINTER(fem_params), C.POINTER(P)]
@@ -83,6 +90,7 @@ def lib():
         L.fem_set_lumen.argtypes = [P, P, C.c_int64, P, C.c_int64]
         L.fem_set_actuation.argtypes = [P, C.c_int, P, P]
         L.fem_solve.argtypes = [P, C.c_int32, P, P]
+        L.fem_solve_schedule.argtypes = [P, C.c_int, C.c_int32, P, P, P, P, P, P, P]
         L.fem_contacts.argtypes = [P, C.c_int32, P, C.c_int32, C.POINTER(C.c_int32)]
         L.fem_get_state.argtypes = [P, P]
         L.fem_set_state.argtypes = [P, P]
@@ -93,7 +101,8 @@ def lib():
         L.fem_total_nodes.argtypes = [P]
         L.fem_total_nodes.restype = C.c_int64
         L.fem_lcp.argtypes = [P, P, C.c_int32, P, C.POINTER(C.c_int32)]
-        for f in ("fem_create", "fem_set_lumen", "fem_set_actuation", "fem_solve", "fem_contacts",
+        for f in ("fem_create", "fem_set_lumen", "fem_set_actuation", "fem_solve",
+                  "fem_solve_schedule", "fem_contacts",
                   "fem_get_state", "fem_set_state", "fem_eval", "fem_profile", "fem_grad", "fem_lcp"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -101,7 +110,7 @@ def lib():
 
 
 EXPORTED = ("fem_create", "fem_destroy", "fem_last_error", "fem_set_lumen", "fem_set_actuation",
-            "fem_solve", "fem_contacts", "fem_get_state", "fem_set_state", "fem_eval",
+            "fem_solve", "fem_solve_schedule", "fem_contacts", "fem_get_state", "fem_set_state", "fem_eval",
             "fem_profile", "fem_grad", "fem_total_nodes", "fem_lcp")
 
 
@@ -205,12 +214,29 @@ class Context:
         d = None if depth is None else _f64(depth, self.B)
         return self._check(lib().fem_set_actuation(self._h, int(kind), _ptr(v), _ptr(d)))
 
+    def _dev_empty(self, shape, dtype):
+        """Output buffer of a context with io_on_device = 1: a torch tensor on the current
+        device (the library writes it on the context's stream)."""
+        import torch
+        return torch.empty(shape, dtype=dtype, device="cuda")
+
     def fem_solve(self, n_load_steps, state=True, info=True):
+        """With io_on_device = 1 the state is returned as a torch device tensor [N, 7] and
+        the info records are read back from the device buffer the library wrote."""
         self.generation += 1
-        X = np.empty((self.n_nodes, 7)) if state else None
-        I = (fem_solve_info * self.B)() if info else None
-        st = lib().fem_solve(self._h, int(n_load_steps), _ptr(X),
-                             C.cast(I, C.c_void_p) if info else None)
+        if self.io_on_device:
+            import torch
+            X = self._dev_empty((self.n_nodes, 7), torch.float64) if state else None
+            Ib = self._dev_empty((self.B * C.sizeof(fem_solve_info),), torch.uint8) if info else None
+            st = lib().fem_solve(self._h, int(n_load_steps), _ptr(X), _ptr(Ib))
+            I = None
+            if info:
+                I = (fem_solve_info * self.B).from_buffer_copy(Ib.cpu().numpy().tobytes())
+        else:
+            X = np.empty((self.n_nodes, 7)) if state else None
+            I = (fem_solve_info * self.B)() if info else None
+            st = lib().fem_solve(self._h, int(n_load_steps), _ptr(X),
+                                 C.cast(I, C.c_void_p) if info else None)
         self._check(st, ok=(FEM_OK, FEM_E_NOCONV))
         out = {"status": st}
         if state:
@@ -220,23 +246,78 @@ class Context:
                            for b in range(self.B)]
         return out
 
+    def fem_solve_schedule(self, kind, values, depth=None, state=True, info=True, records=True):
+        """Explicit load-step schedule: values [n_steps, B, n_values], depth [n_steps, B] or
+        None (numpy arrays, or torch device tensors with io_on_device = 1).  Returns the
+        fem_solve outputs plus, with records, per-step "rec_tip" [n_steps, B, 3],
+        "rec_status" and "rec_iters" [n_steps, B]."""
+        self.generation += 1
+        self.act_kind = int(kind)
+        nv = self.n_cables if kind in (FEM_ACT_CABLES, FEM_ACT_CABLE_WRENCH) else 6
+        n = int(values.shape[0])
+        if self.io_on_device:
+            import torch
+            v, d = values, depth
+            X = self._dev_empty((self.n_nodes, 7), torch.float64) if state else None
+            Ib = self._dev_empty((self.B * C.sizeof(fem_solve_info),), torch.uint8) if info else None
+            rt = self._dev_empty((n, self.B, 3), torch.float64) if records else None
+            rs = self._dev_empty((n, self.B), torch.int32) if records else None
+            ri = self._dev_empty((n, self.B), torch.int32) if records else None
+            st = lib().fem_solve_schedule(self._h, int(kind), n, _ptr(v), _ptr(d), _ptr(X), _ptr(Ib),
+                                          _ptr(rt), _ptr(rs), _ptr(ri))
+            I = None
+            if info:
+                I = (fem_solve_info * self.B).from_buffer_copy(Ib.cpu().numpy().tobytes())
+        else:
+            v = _f64(values, n * self.B * nv)
+            d = None if depth is None else _f64(depth, n * self.B)
+            X = np.empty((self.n_nodes, 7)) if state else None
+            I = (fem_solve_info * self.B)() if info else None
+            rt = np.empty((n, self.B, 3)) if records else None
+            rs = np.empty((n, self.B), np.int32) if records else None
+            ri = np.empty((n, self.B), np.int32) if records else None
+            st = lib().fem_solve_schedule(self._h, int(kind), n, _ptr(v), _ptr(d), _ptr(X),
+                                          C.cast(I, C.c_void_p) if info else None,
+                                          _ptr(rt), _ptr(rs), _ptr(ri))
+        self._check(st, ok=(FEM_OK, FEM_E_NOCONV))
+        out = {"status": st}
+        if state:
+            out["state"] = X
+        if info:
+            out["info"] = [{f: getattr(I[b], f) for f, _ in fem_solve_info._fields_}
+                           for b in range(self.B)]
+        if records:
+            out.update(rec_tip=rt, rec_status=rs, rec_iters=ri)
+        return out
+
     def fem_contacts(self, robot=-1):
         n = C.c_int32(0)
         self._check(lib().fem_contacts(self._h, int(robot), None, 0, C.byref(n)))
-        buf = (fem_contact * max(1, n.value))()
-        self._check(lib().fem_contacts(self._h, int(robot), C.cast(buf, C.c_void_p), n.value,
-                                       C.byref(n)))
+        if self.io_on_device:
+            import torch
+            dbuf = self._dev_empty((max(1, n.value) * C.sizeof(fem_contact),), torch.uint8)
+            self._check(lib().fem_contacts(self._h, int(robot), _ptr(dbuf), n.value, C.byref(n)))
+            buf = (fem_contact * max(1, n.value)).from_buffer_copy(dbuf.cpu().numpy().tobytes())
+        else:
+            buf = (fem_contact * max(1, n.value))()
+            self._check(lib().fem_contacts(self._h, int(robot), C.cast(buf, C.c_void_p), n.value,
+                                           C.byref(n)))
         return [dict(robot=c.robot, node=c.node, tri=c.tri, kind=c.kind, n=np.array(c.n[:]),
                      gap=c.gap, force=c.force) for c in buf[:n.value]]
 
     def fem_get_state(self):
-        X = np.empty((self.n_nodes, 7))
+        if self.io_on_device:
+            import torch
+            X = self._dev_empty((self.n_nodes, 7), torch.float64)
+        else:
+            X = np.empty((self.n_nodes, 7))
         self._check(lib().fem_get_state(self._h, _ptr(X)))
         return X
 
     def fem_set_state(self, X):
         self.generation += 1
-        X = _f64(X, self.n_nodes * 7)
+        if not self.io_on_device:
+            X = _f64(X, self.n_nodes * 7)
         return self._check(lib().fem_set_state(self._h, _ptr(X)))
 
     def fem_profile(self, kernel, reset=False):
@@ -251,8 +332,13 @@ class Context:
         Returns (gradient, status) with status FEM_OK or FEM_E_NOCONV."""
         s = np.ascontiguousarray(np.asarray(sensor_nodes, np.int32)).ravel()
         nv = self.n_cables if self.act_kind in (FEM_ACT_CABLES, FEM_ACT_CABLE_WRENCH) else 6
-        g = _f64(dL_dp, self.B * s.size * 3)
-        out = np.empty((self.B, nv))
+        if self.io_on_device:
+            import torch
+            g = dL_dp
+            out = self._dev_empty((self.B, nv), torch.float64)
+        else:
+            g = _f64(dL_dp, self.B * s.size * 3)
+            out = np.empty((self.B, nv))
         st = lib().fem_grad(self._h, _ptr(s), int(s.size), _ptr(g), _ptr(out))
         self._check(st, ok=(FEM_OK, FEM_E_NOCONV))
         return out, st

@@ -48,3 +48,15 @@ def compare_contact_keys(gpu_contacts, orc_contacts, P_orc, rob):
     o = {(c["node"], c["tri"], c["kind"]) for c, y in orc_contacts if y > 0 and c["node"] not in amb}
     assert g == o, (sorted(g ^ o), sorted(amb))
     return len(o), len(amb)
+
+
+def same_contacts(a, b):
+    """Two fem_contacts lists are identical, field by field (bitwise)."""
+    if len(a) != len(b):
+        return False
+    for x, y in zip(a, b):
+        if {k: x[k] for k in x if k != "n"} != {k: y[k] for k in y if k != "n"}:
+            return False
+        if not np.array_equal(x["n"], y["n"]):
+            return False
+    return True

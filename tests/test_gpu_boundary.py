@@ -1,0 +1,120 @@
+"""GPU tests of the C ABI's hand-offs and of the eq. 17 cable wrench, through the library."""
+import numpy as np
+import pytest
+
+from oracle import solver, actuation
+from workloads import make_config, load_schedule
+from tests.gpu_helpers import (gpu_context, robot_slices, oracle_robots, displacement_error,
+                               node_forces, compare_contact_keys, same_contacts)
+
+pytestmark = pytest.mark.gpu
+
+
+def test_cable_wrench_trajectory_matches_oracle():
+    """Eq. 17 as printed (FEM_ACT_CABLE_WRENCH: summed cable force and cable moments, both
+    following the tip) in the straight tube: three robots in one batch, each pulling one of
+    the three cables to 0.03 N over 10 load steps (about 7 Euler loads of axial follower
+    compression, inside the range where the QP-tangent iteration converges); the bending
+    presses the tip region into the wall.  Every load step against the oracle: status,
+    identical active sets, displacements and per-node contact forces within 1e-9 of their
+    largest value over the trajectory (the compressive follower load softens the robot, so
+    the residual tolerance of 1e-12 N fixes the early, small displacements only to ~1e-12 m
+    in absolute terms)."""
+    from paper_2503_06922_amd import fem
+    rb0, V, T = make_config(0)
+    rb = rb0.subset([0, 0, 0])
+    Tfin = 0.03 * np.eye(3)
+    n_steps = 10
+    robs, mesh = oracle_robots(rb, V, T)
+    trajs = []
+    for b, rob in enumerate(robs):
+        _, _, traj = solver.solve_robot(rob, lambda k, b=b: (0.0, Tfin[b] * k / n_steps), n_steps,
+                                        act_kind=actuation.CABLE_WRENCH, tol=1e-12, stag_tol=1e-9,
+                                        max_iter=200)
+        trajs.append(traj)
+    ctx = gpu_context(rb, V, T, newton_tol=1e-12, stag_tol=1e-9, max_newton=200)
+    n_active = 0
+    du = np.zeros((3, n_steps))          # max node position difference per robot and step
+    fe = np.zeros((3, n_steps))          # max per-node contact force difference
+    for k in range(1, n_steps + 1):
+        ctx.fem_set_actuation(fem.FEM_ACT_CABLE_WRENCH, (Tfin * k / n_steps).ravel(), None)
+        out = ctx.fem_solve(1)
+        for b, (sl, rob) in enumerate(zip(robot_slices(rb), robs)):
+            o = trajs[b][k - 1]
+            assert out["info"][b]["status"] == 0 and o["info"]["status"] == solver.OK, (b, k)
+            P = out["state"][sl, 0:3]
+            du[b, k - 1] = np.linalg.norm(P - o["P"], axis=1).max()
+            gc = ctx.fem_contacts(b)
+            n_cmp, n_amb = compare_contact_keys(gc, list(zip(o["contacts"], o["y"])), o["P"], rob)
+            assert n_amb == 0
+            n_active += n_cmp
+            fg = node_forces(gc, P.shape[0])
+            fo = node_forces([dict(c, force=y) for c, y in zip(o["contacts"], o["y"])], P.shape[0])
+            fe[b, k - 1] = np.abs(fg - fo).max()
+    for b, rob in enumerate(robs):
+        u_scale = max(np.linalg.norm(t["P"] - rob.reference()[0], axis=1).max() for t in trajs[b])
+        f_scale = max(np.abs(node_forces([dict(c, force=y) for c, y in zip(t["contacts"], t["y"])],
+                                         rob.n_elem + 1)).max() for t in trajs[b])
+        print("robot", b, "displacement error", du[b].max() / u_scale, "force error",
+              fe[b].max() / f_scale)
+        assert du[b].max() <= 1e-9 * u_scale, (b, du[b] / u_scale)
+        assert fe[b].max() <= 1e-9 * f_scale, (b, fe[b] / f_scale)
+    print("cable wrench: active contacts compared", n_active)
+    assert n_active >= 10
+
+
+def test_io_on_device_and_torch_stream_match_host_io():
+    """fem_params.io_on_device = 1 with torch device tensors for every array argument and a
+    torch side stream as hip_stream: the same batch solved through host arrays on the null
+    stream gives bit-identical states, solve records, contacts and gradients."""
+    import torch
+    from paper_2503_06922_amd import fem
+    rb0, V, T = make_config(0)
+    rb = rb0.subset([0, 0])
+    tens = np.array([[0.6, 0.0, 0.2], [0.0, 1.1, 0.3]])
+    host = gpu_context(rb, V, T, newton_tol=1e-12, stag_tol=1e-9, max_newton=100)
+    stream = torch.cuda.Stream()
+    dev = fem.Context(fem.params_from_batch(rb, newton_tol=1e-12, stag_tol=1e-9, max_newton=100,
+                                            io_on_device=1, hip_stream=stream.cuda_stream))
+    with torch.cuda.stream(stream):
+        Vd = torch.tensor(V, dtype=torch.float64, device="cuda")
+        Td = torch.tensor(T, dtype=torch.int32, device="cuda")
+        dev.fem_set_lumen(Vd, Td)
+    host.fem_set_lumen(V, T)
+    X0 = host.fem_get_state()
+    with torch.cuda.stream(stream):
+        X0d = dev.fem_get_state()
+    stream.synchronize()
+    assert isinstance(X0d, torch.Tensor) and X0d.is_cuda
+    assert np.array_equal(X0d.cpu().numpy(), X0)
+    sens = np.array([-1, -4], np.int32)
+    rng = np.random.default_rng(5)
+    dLdp = rng.normal(size=(rb.n_robots, 2, 3))
+    for k in range(1, 6):
+        t = tens * k / 5
+        host.fem_set_actuation(fem.FEM_ACT_CABLES, t.ravel(), None)
+        oh = host.fem_solve(1)
+        with torch.cuda.stream(stream):
+            td = torch.tensor(t.ravel(), dtype=torch.float64, device="cuda")
+            dd = torch.zeros(rb.n_robots, dtype=torch.float64, device="cuda")
+            dev.fem_set_actuation(fem.FEM_ACT_CABLES, td, dd)
+            od = dev.fem_solve(1)
+        assert od["state"].is_cuda
+        assert np.array_equal(od["state"].cpu().numpy(), oh["state"]), k
+        assert od["info"] == oh["info"], k
+        assert same_contacts(host.fem_contacts(-1), dev.fem_contacts(-1)), k
+    assert sum(c["force"] > 0 for c in host.fem_contacts(-1)) > 0
+    gh, sh = host.fem_grad(sens, dLdp)
+    with torch.cuda.stream(stream):
+        gd, sd = dev.fem_grad(sens, torch.tensor(dLdp.ravel(), device="cuda"))
+    assert sh == sd == fem.FEM_OK
+    assert np.array_equal(gd.cpu().numpy(), gh)
+    # a state written from device memory is what the host context holds
+    with torch.cuda.stream(stream):
+        dev.fem_set_state(torch.tensor(oh["state"], device="cuda"))
+        Xd = dev.fem_get_state()
+    stream.synchronize()
+    host.fem_set_state(oh["state"])
+    assert np.array_equal(Xd.cpu().numpy(), host.fem_get_state())
+    host.close()
+    dev.close()

@@ -72,6 +72,15 @@ def load_schedule(rb: RobotBatch, k: int):
     return rb.depth * fd, rb.tensions * ft
 
 
+def schedule_table(rb: RobotBatch, n_steps: int | None = None):
+    """The load steps 1..n_steps of load_schedule as tables: tensions [n, B, n_cables]
+    and depths [n, B] (the layout of an explicit load-step schedule)."""
+    n = rb.n_load_steps if n_steps is None else n_steps
+    steps = [load_schedule(rb, k) for k in range(1, n + 1)]
+    return (np.ascontiguousarray(np.stack([t for _, t in steps])),
+            np.ascontiguousarray(np.stack([d for d, _ in steps])))
+
+
 def _frames(B, rng=None, roll=False):
     d = np.tile(np.array([0.0, 0.0, 1.0]), (B, 1))
     if roll and rng is not None:
