@@ -17,9 +17,16 @@ def test_cable_wrench_trajectory_matches_oracle():
     compression, inside the range where the QP-tangent iteration converges); the bending
     presses the tip region into the wall.  Every load step against the oracle: status,
     identical active sets, displacements and per-node contact forces within 1e-9 of their
-    largest value over the trajectory (the compressive follower load softens the robot, so
-    the residual tolerance of 1e-12 N fixes the early, small displacements only to ~1e-12 m
-    in absolute terms)."""
+    largest value over the trajectory, or within 1e-11 m where that is larger; the oracle's
+    own FP64 out-of-balance force at the GPU state, with the GPU's contact forces, is the
+    residual the GPU reported and is below the stagnation level.  Both sides iterate to
+    1e-13 N, but under this compressive follower load the modified Newton iteration
+    contracts slowly, and either side may accept a stagnating residual anywhere below the
+    stagnation level (10 times the rounding floor eps EA/l0 (1 m) sqrt(DOF), 3.2e-10 N
+    here, or stag_tol = 1e-9 N), which is where the two stopping points part: up to 7.8e-10
+    N of residual and 4e-12 m of displacement (2.4e-9 of the 1.6 mm displacement scale on
+    one robot).  The equilibrium is fixed only to that level, so that is the floor the
+    comparison allows (forces: 1e-9 N)."""
     from paper_2503_06922_amd import fem
     rb0, V, T = make_config(0)
     rb = rb0.subset([0, 0, 0])
@@ -29,10 +36,10 @@ def test_cable_wrench_trajectory_matches_oracle():
     trajs = []
     for b, rob in enumerate(robs):
         _, _, traj = solver.solve_robot(rob, lambda k, b=b: (0.0, Tfin[b] * k / n_steps), n_steps,
-                                        act_kind=actuation.CABLE_WRENCH, tol=1e-12, stag_tol=1e-9,
+                                        act_kind=actuation.CABLE_WRENCH, tol=1e-13, stag_tol=1e-9,
                                         max_iter=200)
         trajs.append(traj)
-    ctx = gpu_context(rb, V, T, newton_tol=1e-12, stag_tol=1e-9, max_newton=200)
+    ctx = gpu_context(rb, V, T, newton_tol=1e-13, stag_tol=1e-9, max_newton=200)
     n_active = 0
     du = np.zeros((3, n_steps))          # max node position difference per robot and step
     fe = np.zeros((3, n_steps))          # max per-node contact force difference
@@ -51,14 +58,20 @@ def test_cable_wrench_trajectory_matches_oracle():
             fg = node_forces(gc, P.shape[0])
             fo = node_forces([dict(c, force=y) for c, y in zip(o["contacts"], o["y"])], P.shape[0])
             fe[b, k - 1] = np.abs(fg - fo).max()
+            # equilibrium of the GPU state by the oracle's own force evaluation
+            Pg, Rg = fem.state_to_PR(out["state"][sl])
+            F = solver.out_of_balance(rob, Pg, Rg, actuation.CABLE_WRENCH, Tfin[b] * k / n_steps)
+            rn = np.linalg.norm(solver.contact_residual(F, gc, np.array([c["force"] for c in gc])))
+            assert rn <= solver.stagnation_tol(rob, 1e-9) * 1.001, (b, k, rn)
+            assert abs(rn - out["info"][b]["res_norm"]) <= 1e-10, (b, k, rn, out["info"][b]["res_norm"])
     for b, rob in enumerate(robs):
         u_scale = max(np.linalg.norm(t["P"] - rob.reference()[0], axis=1).max() for t in trajs[b])
         f_scale = max(np.abs(node_forces([dict(c, force=y) for c, y in zip(t["contacts"], t["y"])],
                                          rob.n_elem + 1)).max() for t in trajs[b])
         print("robot", b, "displacement error", du[b].max() / u_scale, "force error",
               fe[b].max() / f_scale)
-        assert du[b].max() <= 1e-9 * u_scale, (b, du[b] / u_scale)
-        assert fe[b].max() <= 1e-9 * f_scale, (b, fe[b] / f_scale)
+        assert du[b].max() <= max(1e-9 * u_scale, 1e-11), (b, du[b] / u_scale)
+        assert fe[b].max() <= max(1e-9 * f_scale, 1e-9), (b, fe[b] / f_scale)
     print("cable wrench: active contacts compared", n_active)
     assert n_active >= 10
 
