@@ -288,6 +288,26 @@ fem_status fem_profile(fem_ctx* c, int32_t kernel, double* total_ms, int64_t* la
  * solution), or the iteration limit (y not written).  FEM_E_NOMEM, FEM_E_HIP. */
 fem_status fem_lcp(const double* W, const double* q, int32_t m, double* y, int32_t* path);
 
+/* Largest m accepted by fem_lcp_noalloc. */
+#define FEM_LCP_NOALLOC_MAX_M 512
+
+/* fem_lcp without any device allocation, for callers that cannot allocate (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the same device
+ * routines and results as fem_lcp, with the caller's device buffers and a workspace held in
+ * a fixed device array of the library (about 1.1 MB: the HBM factor of up to
+ * FEM_LCP_NOALLOC_MAX_M positions and a result code), one per GPU, kept until the process
+ * ends.  No hipMalloc, hipFree or other allocating call is made.
+ *   W [m*m] column-major, q [m], y [m] output: device pointers on the current device
+ *   path: host pointer, the routine taken (as fem_lcp)
+ *   hip_stream: hipStream_t the routines run on (NULL = the null stream); the call waits
+ *     for it before returning
+ * Every call on one GPU uses that GPU's workspace, which keeps the last call's contents;
+ * calls that overlap on one GPU (other threads, other streams) race and must be
+ * serialised by the caller.  FEM_E_INVAL: NULL pointers or m outside
+ * 1..FEM_LCP_NOALLOC_MAX_M.  FEM_E_NOCONV as fem_lcp (y then undefined).  FEM_E_HIP. */
+fem_status fem_lcp_noalloc(const double* W, const double* q, int32_t m, double* y,
+                           int32_t* path, void* hip_stream);
+
 /* Total number of nodes over the batch (Sec. II-B: n_elem + 1 per robot, summed),
  * or -1 for NULL. */
 int64_t fem_total_nodes(const fem_ctx* c);

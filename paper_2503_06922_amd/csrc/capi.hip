@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1166,6 +1167,54 @@ fem_status fem_lcp(const double* W, const double* q, int32_t m, double* y, int32
   (void)hipFree(dcode);
   (void)hipFree(dW);
   return st;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ allocation-free LCP
+// Device workspace of fem_lcp_noalloc: the factor workspace of the HBM-factor routine for up
+// to FEM_LCP_NOALLOC_MAX_M constraints, followed by one slot for the routine's result code.
+// Each GPU holds its own copy until the process ends; in host code the array's name is not a
+// device address, so its address is taken once per device with hipGetSymbolAddress.
+namespace {
+constexpr int64_t kNoallocWs = (int64_t)FEM_LCP_NOALLOC_MAX_M * (FEM_LCP_NOALLOC_MAX_M + 1) / 2 +
+                               3 * (int64_t)FEM_LCP_NOALLOC_MAX_M;
+static_assert(kNoallocWs >= 1, "workspace");
+__device__ __align__(256) double scratch[kNoallocWs + 1];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+extern "C" {
+
+fem_status fem_lcp_noalloc(const double* W, const double* q, int32_t m, double* y, int32_t* path,
+                           void* hip_stream) {
+  if (!W || !q || !y || !path || m < 1 || m > FEM_LCP_NOALLOC_MAX_M) return FEM_E_INVAL;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return FEM_E_HIP;
+  double* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+      void* a = nullptr;
+      if (hipGetSymbolAddress(&a, HIP_SYMBOL(scratch)) != hipSuccess || !a) return FEM_E_HIP;
+      g_scratch_ptr[dev] = static_cast<double*>(a);
+    }
+    ws = g_scratch_ptr[dev];
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  int* dcode = reinterpret_cast<int*>(ws + kNoallocWs);
+  // the routines only read W (the dense source builds no columns)
+  launch_lcp_check(const_cast<double*>(W), q, m, y, ws, dcode, s);
+  if (hipGetLastError() != hipSuccess) return FEM_E_HIP;
+  int code = -1;
+  if (hipMemcpyAsync(&code, dcode, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return FEM_E_HIP;
+  if (code < 0) return FEM_E_NOCONV;
+  *path = code;
+  return FEM_OK;
 }
 
 }  // extern "C"

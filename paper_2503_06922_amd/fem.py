@@ -101,9 +101,11 @@ def lib():
         L.fem_total_nodes.argtypes = [P]
         L.fem_total_nodes.restype = C.c_int64
         L.fem_lcp.argtypes = [P, P, C.c_int32, P, C.POINTER(C.c_int32)]
+        L.fem_lcp_noalloc.argtypes = [P, P, C.c_int32, P, C.POINTER(C.c_int32), P]
         for f in ("fem_create", "fem_set_lumen", "fem_set_actuation", "fem_solve",
                   "fem_solve_schedule", "fem_contacts",
-                  "fem_get_state", "fem_set_state", "fem_eval", "fem_profile", "fem_grad", "fem_lcp"):
+                  "fem_get_state", "fem_set_state", "fem_eval", "fem_profile", "fem_grad", "fem_lcp",
+                  "fem_lcp_noalloc"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -111,7 +113,8 @@ def lib():
 
 EXPORTED = ("fem_create", "fem_destroy", "fem_last_error", "fem_set_lumen", "fem_set_actuation",
             "fem_solve", "fem_solve_schedule", "fem_contacts", "fem_get_state", "fem_set_state", "fem_eval",
-            "fem_profile", "fem_grad", "fem_total_nodes", "fem_lcp")
+            "fem_profile", "fem_grad", "fem_total_nodes", "fem_lcp", "fem_lcp_noalloc")
+FEM_LCP_NOALLOC_MAX_M = 512
 
 
 class FemError(RuntimeError):
@@ -400,3 +403,17 @@ def fem_lcp(W, q):
     if st != FEM_OK:
         raise FemError(st, "fem_lcp failed")
     return y, path.value
+
+
+def fem_lcp_noalloc(W, q, y, stream=None):
+    """fem_lcp on caller-owned device memory with no allocation in the library: W (m x m,
+    column-major, i.e. the transpose of the row-major matrix for a symmetric W), q and y are
+    contiguous float64 torch tensors on the current device; y receives the forces.  Returns
+    the path taken.  stream: a torch stream (None = the null stream)."""
+    m = int(q.shape[0])
+    path = C.c_int32(-1)
+    st = lib().fem_lcp_noalloc(_ptr(W), _ptr(q), m, _ptr(y), C.byref(path),
+                               C.c_void_p(stream.cuda_stream) if stream is not None else None)
+    if st != FEM_OK:
+        raise FemError(st, "fem_lcp_noalloc failed")
+    return path.value
