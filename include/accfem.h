@@ -46,12 +46,15 @@ typedef enum {
   FEM_E_NOCONV = -5    /* results written, some robots did not converge: see info */
 } fem_status;
 
-/* Arithmetic of the Newton loop.  FEM_FP64: everything in FP64.  FEM_MIXED: the
- * element chord directions that carry the QP tangent are stored in FP32 (the
- * tangent blocks are regenerated from them in FP64, so K stays positive definite)
- * and contact detection screens triangles in FP32 before deciding in FP64; the
- * residual, the factorisation, the LCP and the state stay FP64, so both converge
- * to the same equilibrium. */
+/* Arithmetic of the Newton loop.  FEM_FP64: everything in FP64.  FEM_MIXED: while a
+ * robot's residual is above 1e-4 (N, N m) its element forces are evaluated in FP32
+ * with FP32 accumulation (chord, stretch and relative rotations formed in FP64, then
+ * cast), below it in FP64: the convergence decision is always taken on an FP64
+ * residual (FP64 refinement of the Newton iteration); the element chord directions
+ * that carry the QP tangent are stored in FP32 (the tangent blocks are regenerated
+ * from them in FP64, so K stays positive definite) and contact detection screens
+ * triangles in FP32 before deciding in FP64; the factorisation, the LCP and the state
+ * stay FP64, so both precisions converge to the same equilibrium. */
 typedef enum { FEM_FP64 = 0, FEM_MIXED = 1 } fem_precision;
 
 /* Actuation kinds (Sec. II-E, eq. 16-18).  Cable j is attached at radius

@@ -13,6 +13,9 @@
 // only (see ElemK), so the element update stores e1 and the solver generates the blocks.
 // One thread per node computes its two adjacent elements and writes the node's
 // out-of-balance force F_i (6, component-major) and the chord direction of element (i, i+1).
+// Mixed precision: while the robot's residual is above F32_RESIDUAL the element forces are
+// evaluated in FP32 (geometry and relative rotations formed in FP64, then cast) and
+// accumulated in FP32; near convergence, and for the convergence decision, in FP64.
 #include "element_math.h"
 
 namespace accfem {
@@ -48,22 +51,43 @@ __global__ void __launch_bounds__(256) elem_kernel(Dev d) {
   const int64_t N = d.Ntot;
 
   double F[6] = {0, 0, 0, 0, 0, 0};
+  float F32[6] = {0, 0, 0, 0, 0, 0};
+  const bool f32 = d.mixed && d.st_rn[r] > F32_RESIDUAL;
   NodeState me = load_node(d, g);
   if (i > 0) {  // element (i-1, i): this node is its end b
     NodeState A = load_node(d, g - 1);
-    double fa[6], fb[6];
-    V3 e1;
-    element_force(A, me, l0, d.EA[g - 1], d.EI[g - 1], d.GJ[g - 1], fa, fb, &e1);
+    if (f32) {
+      float fa[6], fb[6];
+      V3T<double> e1;
+      element_force_mixed(V3T<double>{A.p.x, A.p.y, A.p.z}, A.R, V3T<double>{me.p.x, me.p.y, me.p.z},
+                          me.R, l0, d.EA[g - 1], d.EI[g - 1], d.GJ[g - 1], fa, fb, &e1);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) F[k] += fb[k];
+      for (int k = 0; k < 6; ++k) F32[k] += fb[k];
+    } else {
+      double fa[6], fb[6];
+      V3 e1;
+      element_force(A, me, l0, d.EA[g - 1], d.EI[g - 1], d.GJ[g - 1], fa, fb, &e1);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) F[k] += fb[k];
+    }
   }
   if (i < n - 1) {  // element (i, i+1): this node is its end a
     NodeState Bn = load_node(d, g + 1);
-    double fa[6], fb[6];
     V3 e1;
-    element_force(me, Bn, l0, d.EA[g], d.EI[g], d.GJ[g], fa, fb, &e1);
+    if (f32) {
+      float fa[6], fb[6];
+      V3T<double> e;
+      element_force_mixed(V3T<double>{me.p.x, me.p.y, me.p.z}, me.R, V3T<double>{Bn.p.x, Bn.p.y, Bn.p.z},
+                          Bn.R, l0, d.EA[g], d.EI[g], d.GJ[g], fa, fb, &e);
+      e1 = v3(e.x, e.y, e.z);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) F[k] += fa[k];
+      for (int k = 0; k < 6; ++k) F32[k] += fa[k];
+    } else {
+      double fa[6], fb[6];
+      element_force(me, Bn, l0, d.EA[g], d.EI[g], d.GJ[g], fa, fb, &e1);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) F[k] += fa[k];
+    }
     // the QP tangent of element (i, i+1) is carried by its chord direction
     if (d.mixed) {
       d.E1f[g] = (float)e1.x; d.E1f[N + g] = (float)e1.y; d.E1f[2 * N + g] = (float)e1.z;
@@ -91,11 +115,16 @@ __global__ void __launch_bounds__(256) elem_kernel(Dev d) {
       Fg = Fl.x * col(me.R, 0) + Fl.y * col(me.R, 1) + Fl.z * col(me.R, 2);
       Mg = Ml.x * col(me.R, 0) + Ml.y * col(me.R, 1) + Ml.z * col(me.R, 2);
     }
-    F[0] -= Fg.x; F[1] -= Fg.y; F[2] -= Fg.z;
-    F[3] -= Mg.x; F[4] -= Mg.y; F[5] -= Mg.z;
+    if (f32) {
+      F32[0] -= (float)Fg.x; F32[1] -= (float)Fg.y; F32[2] -= (float)Fg.z;
+      F32[3] -= (float)Mg.x; F32[4] -= (float)Mg.y; F32[5] -= (float)Mg.z;
+    } else {
+      F[0] -= Fg.x; F[1] -= Fg.y; F[2] -= Fg.z;
+      F[3] -= Mg.x; F[4] -= Mg.y; F[5] -= Mg.z;
+    }
   }
 #pragma unroll
-  for (int k = 0; k < 6; ++k) d.F[k * N + g] = F[k];
+  for (int k = 0; k < 6; ++k) d.F[k * N + g] = f32 ? (double)F32[k] : F[k];
 }
 
 void launch_elem(const Dev& d, hipStream_t s) {

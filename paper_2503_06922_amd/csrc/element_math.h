@@ -126,4 +126,74 @@ __device__ void element_force_t(V3T<T> pa, const T* Ra, V3T<T> pb, const T* Rb, 
   *e1_out = e1;
 }
 
+// Mixed-precision element force: the geometry (chord, length, stretch, element frame, the
+// relative rotations R_e^T R_a, R_e^T R_b and their log maps) is formed in FP64 and cast; the
+// generalised stresses, the inverse left Jacobians and the assembly of the nodal forces run in
+// FP32.  Absolute coordinates are never subtracted in FP32 (a 0.6 mm element 0.6 m from the
+// origin would lose 1e-4 of its strain).
+struct F3 { float x, y, z; };
+__device__ __forceinline__ F3 f3(V3T<double> v) { return F3{(float)v.x, (float)v.y, (float)v.z}; }
+__device__ __forceinline__ F3 f3add(F3 a, F3 b) { return F3{a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ F3 f3sub(F3 a, F3 b) { return F3{a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ F3 f3scl(float s, F3 a) { return F3{s * a.x, s * a.y, s * a.z}; }
+__device__ __forceinline__ float f3dot(F3 a, F3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ F3 f3cross(F3 a, F3 b) {
+  return F3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+
+// J_l(theta)^-T s in FP32; beta from its series below 0.2 rad, where the closed form cancels
+__device__ __forceinline__ F3 jl_inv_T_f32(F3 th, F3 s) {
+  const float t2 = f3dot(th, th);
+  float beta;
+  if (t2 < 0.04f) {
+    beta = 1.0f / 12.0f + t2 * (1.0f / 720.0f + t2 * (1.0f / 30240.0f));
+  } else {
+    const float t = sqrtf(t2);
+    beta = 1.0f / t2 - (1.0f + cosf(t)) / (2.0f * t * sinf(t));
+  }
+  const F3 ts = f3cross(th, s);
+  return f3add(f3add(s, f3scl(0.5f, ts)), f3scl(beta, f3cross(th, ts)));
+}
+
+__device__ inline void element_force_mixed(V3T<double> pa, const double* Ra, V3T<double> pb,
+                                           const double* Rb, double l0, double EA, double EI,
+                                           double GJ, float* fa, float* fb, V3T<double>* e1_out) {
+  // FP64 geometry
+  const V3T<double> c = sub(pb, pa);
+  const double l = sqrt(dot3(c, c));
+  const V3T<double> e1 = scl(1.0 / l, c);
+  const V3T<double> qa{Ra[1], Ra[4], Ra[7]}, qb{Rb[1], Rb[4], Rb[7]};
+  const V3T<double> q = scl(0.5, add(qa, qb));
+  const V3T<double> r = cross3(e1, q);
+  const V3T<double> e3 = scl(1.0 / sqrt(dot3(r, r)), r);
+  const V3T<double> e2 = cross3(e3, e1);
+  double Qa[9], Qb[9];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const V3T<double> ca{Ra[j], Ra[3 + j], Ra[6 + j]}, cb{Rb[j], Rb[3 + j], Rb[6 + j]};
+    Qa[j] = dot3(e1, ca); Qa[3 + j] = dot3(e2, ca); Qa[6 + j] = dot3(e3, ca);
+    Qb[j] = dot3(e1, cb); Qb[3 + j] = dot3(e2, cb); Qb[6 + j] = dot3(e3, cb);
+  }
+  const F3 ta = f3(so3_log(Qa)), tb = f3(so3_log(Qb));
+  const float u = (float)(l - l0);
+  const float q1 = (float)dot3(q, e1), q2 = (float)dot3(q, e2), lf = (float)l;
+  const F3 E1 = f3(e1), E2 = f3(e2), E3 = f3(e3), QA = f3(qa), QB = f3(qb);
+  // FP32 constitutive law and nodal forces
+  const float gt = (float)(GJ / l0), eb = (float)(EI / l0), ea = (float)(EA / l0);
+  const F3 sa{gt * (ta.x - tb.x), eb * (4.0f * ta.y + 2.0f * tb.y), eb * (4.0f * ta.z + 2.0f * tb.z)};
+  const F3 sb{gt * (tb.x - ta.x), eb * (2.0f * ta.y + 4.0f * tb.y), eb * (2.0f * ta.z + 4.0f * tb.z)};
+  const float Nx = ea * u;
+  const F3 ma = jl_inv_T_f32(ta, sa), mb = jl_inv_T_f32(tb, sb);
+  const F3 m = f3add(ma, mb);
+  const F3 fpb = f3sub(f3add(f3scl(Nx, E1), f3scl((m.x * q1 / q2 + m.y) / lf, E3)), f3scl(m.z / lf, E2));
+  const float c1 = m.x / (2.0f * q2);
+  const F3 Ma = f3add(f3add(f3scl(ma.x, E1), f3scl(ma.y, E2)), f3scl(ma.z, E3));
+  const F3 Mb = f3add(f3add(f3scl(mb.x, E1), f3scl(mb.y, E2)), f3scl(mb.z, E3));
+  const F3 fta = f3sub(Ma, f3scl(c1, f3cross(QA, E3)));
+  const F3 ftb = f3sub(Mb, f3scl(c1, f3cross(QB, E3)));
+  fa[0] = -fpb.x; fa[1] = -fpb.y; fa[2] = -fpb.z; fa[3] = fta.x; fa[4] = fta.y; fa[5] = fta.z;
+  fb[0] = fpb.x;  fb[1] = fpb.y;  fb[2] = fpb.z;  fb[3] = ftb.x; fb[4] = ftb.y; fb[5] = ftb.z;
+  *e1_out = e1;
+}
+
 }  // namespace accfem

@@ -25,6 +25,11 @@ __host__ __device__ inline int64_t lcp_ws_doubles(int cap) {
 constexpr int MAXC = 48;         // contact candidates kept per node (a node in a branch
                                  // narrower than the band meets a ring of facets)
 constexpr int SOLVE_THREADS = 64;  // one wavefront per robot in the solve kernel
+// Mixed precision: a robot whose residual at the last check is above this level (N, N m) has
+// its element forces evaluated in FP32 with FP32 accumulation; below it, and for the
+// convergence decision, in FP64 (the FP64 refinement of the Newton iteration).  FP32 forces
+// carry ~1e-7 of the element forces (~1e-6 N here), far below this level.
+constexpr double F32_RESIDUAL = 1e-4;
 
 struct Dev {
   int B;

@@ -196,7 +196,9 @@ __global__ void __launch_bounds__(NT) check_rhs_kernel(Dev d) {
     const double rn = sqrt(ss);
     const double rn_prev = d.st_rnprev[r];
     const bool same = (diff == 0);
-    const bool conv = same && !d.st_limited[r] && gmin >= -1e-9 &&
+    // mixed precision: a residual of FP32 element forces never decides convergence
+    const bool fp32_forces = d.mixed && d.st_rn[r] > F32_RESIDUAL;
+    const bool conv = same && !d.st_limited[r] && gmin >= -1e-9 && !fp32_forces &&
                       (rn <= d.newton_tol || (rn <= d.stag_r[r] && rn > 0.5 * rn_prev));
     __syncthreads();
     if (lane == 0) {

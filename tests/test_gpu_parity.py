@@ -38,11 +38,18 @@ def _quat(R):
     return np.array([w, x, y, z])
 
 
-def test_element_update_matches_oracle():
-    """F, diagonal and coupling blocks of the QP tangent at deformed states (several robots)."""
+@pytest.mark.parametrize("mixed", [False, True])
+def test_element_update_matches_oracle(mixed):
+    """F, diagonal and coupling blocks of the QP tangent at deformed states (several robots).
+    Plain FP64: F within 1e-12 and the blocks within 1e-13 of their largest entries.  Mixed
+    precision far from convergence (the residual of a fresh load step is unknown, so above the
+    FP32 level): element forces in FP32 with FP32 accumulation from FP64 geometry, within 1e-6
+    of the largest force (a few FP32 roundings of the element forces, which here are of the
+    size of the node forces); tangent blocks from the FP32 chord directions within 1e-6."""
+    from paper_2503_06922_amd import fem
     rb = robots_for_config(3, n_robots=6)
     rng = np.random.default_rng(1)
-    ctx = gpu_context(rb)
+    ctx = gpu_context(rb, precision=fem.FEM_MIXED if mixed else fem.FEM_FP64)
     T = rb.tensions
     ctx.fem_set_actuation(0, T.ravel(), np.zeros(rb.n_robots))
     X, PR = _perturbed_states(rb, rng)
@@ -57,10 +64,15 @@ def test_element_update_matches_oracle():
         KDo = np.array([Ko[6 * i:6 * i + 6, 6 * i:6 * i + 6] for i in range(n)])
         KSo = np.array([Ko[6 * i:6 * i + 6, 6 * i + 6:6 * i + 12] for i in range(n - 1)])
         fs = np.abs(Fo).max()
-        assert np.abs(F[sl] - Fo).max() <= 1e-12 * fs + 1e-13
         ks = np.abs(Ko).max()
-        assert np.abs(KD[sl] - KDo).max() <= 1e-13 * ks
-        assert np.abs(KS[sl][:-1] - KSo).max() <= 1e-13 * ks
+        tf, tk = (1e-6, 1e-6) if mixed else (1e-12, 1e-13)
+        print("robot", b, "force error", np.abs(F[sl] - Fo).max() / fs, "block error",
+              max(np.abs(KD[sl] - KDo).max(), np.abs(KS[sl][:-1] - KSo).max()) / ks)
+        assert np.abs(F[sl] - Fo).max() <= tf * fs + 1e-13
+        if mixed:
+            assert np.abs(F[sl] - Fo).max() > 1e-12 * fs     # the FP32 path did run
+        assert np.abs(KD[sl] - KDo).max() <= tk * ks
+        assert np.abs(KS[sl][:-1] - KSo).max() <= tk * ks
 
 
 def test_detection_matches_oracle_brute_force():
@@ -320,14 +332,17 @@ def test_contact_cycles_and_dependent_contacts_converge_like_oracle(robot, n_ele
     ctx.close()
 
 
-@pytest.mark.parametrize("mixed,disp_tol", [(True, 1e-7), (False, 1e-9)])
+@pytest.mark.parametrize("mixed,disp_tol", [(True, 1e-5), (False, 1e-9)])
 def test_full_batch_in_bench_configuration_sampled_robots(mixed, disp_tol):
     """All 4096 robots of the batched insertion in the launch configuration of the benchmark
     (contact capacity 512, at most 60 Newton iterations; mixed precision as timed, and plain
     FP64) through its first 12 load steps, where the first contacts appear; six seeded robots
     against their own oracle solves at every load step: same status, displacement within
-    1e-7 (mixed) / 1e-9 (FP64) and tip within 1e-5 of the robot length, identical active
-    sets."""
+    1e-5 (mixed) / 1e-9 (FP64) and tip within 1e-5 of the robot length, identical active
+    sets.  Plain FP64 follows the oracle's own iteration path, so both stop at the same
+    iterate; the mixed path takes FP32 element forces while the residual is large, a
+    different path to the same equilibrium, which the residual tolerance of 1e-10 N fixes
+    only to about 2e-7 of the displacement here."""
     from paper_2503_06922_amd import fem
     rb, V, T = make_config(3)
     assert rb.n_robots == 4096
