@@ -8,8 +8,12 @@ so a perturbation dT moves the equilibrium by dx with
 load stiffness of the follower moment).  For a loss L(x) with gradient g, the
 adjoint pair solves  J^T lam + A_act^T mu = g,  A_act lam = 0,  and then
     dL/dT_j = lam . dF_a/dT_j.
-Contacts are treated as planes at their current normals (exact for face
-contacts; for the edge/vertex fallback the normal's own variation is left out).
+A face contact is a plane, so its constraint has no curvature.  An edge/vertex
+fallback contact constrains the distance rho = |p - q| from the node to the
+nearest point q of a fixed edge line or vertex (gap rho - r_c), whose normal
+n = (p - q)/rho turns with the node: dn/dp = (I - n n^T - t t^T)/rho for an edge
+of unit direction t, (I - n n^T)/rho for a vertex, so the contact force -y n
+adds -y dn/dp to the node's translation block of J (the constraint curvature).
 Fixed DOFs (base node, guided lateral DOFs) are removed.  J is taken by central
 finite differences of the out-of-balance force (banded, Richardson-extrapolated), the KKT system is
 solved densely.  Independent check: central differences of complete re-solves.
@@ -19,7 +23,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import beam, actuation, solver
+from . import beam, actuation, solver, collision
 
 
 def free_mask(robot, n_nodes, guided):
@@ -51,6 +55,27 @@ def jacobian(robot, P, R, act_kind, act_values, h=1e-6):
     return (4.0 * J1 - J2) / 3.0
 
 
+def normal_derivative(p, mesh, tri):
+    """dn/dp [3, 3] of an edge/vertex contact's normal n = (p - q)/|p - q|, q the nearest
+    point of triangle `tri` to p on the edge or vertex that holds it."""
+    cpt, region, _ = collision.closest_points(np.asarray(p, float), mesh, np.array([tri]))
+    d = np.asarray(p, float) - cpt[0]
+    rho = float(np.linalg.norm(d))
+    n = d / rho
+    H = np.eye(3) - np.outer(n, n)
+    reg = int(region[0])
+    if reg == collision.FACE:
+        return np.zeros((3, 3))        # nearest point inside the face: a plane
+    ends = {collision.EDGE_AB: (mesh.v0, mesh.v1), collision.EDGE_AC: (mesh.v0, mesh.v2),
+            collision.EDGE_BC: (mesh.v1, mesh.v2)}
+    if reg in ends:
+        a, b = ends[reg]
+        t = b[tri] - a[tri]
+        t = t / np.linalg.norm(t)
+        H -= np.outer(t, t)
+    return H / rho
+
+
 def loss_gradient_x(P, sensor_nodes, dL_dp):
     """Scatter dL/dp of the sensor nodes [n_s, 3] into a 6N vector."""
     g = np.zeros(6 * P.shape[0])
@@ -65,6 +90,10 @@ def tension_gradient(robot, P, R, contacts, y, act_values, sensor_nodes, dL_dp, 
     loss gradient dL_dp [n_sensors, 3] at the sensor nodes."""
     N = P.shape[0]
     J = jacobian(robot, P, R, act_kind, act_values)
+    for c, yy in zip(contacts, y):
+        if yy > active_tol and c["kind"] != 0:
+            i = c["node"]
+            J[6 * i:6 * i + 3, 6 * i:6 * i + 3] -= yy * normal_derivative(P[i], robot.mesh, c["tri"])
     m = free_mask(robot, N, guided)
     Jf = J[np.ix_(m, m)]
     g = loss_gradient_x(P, sensor_nodes, dL_dp)[m]

@@ -15,16 +15,24 @@
 // first k_i translation components of node i removed.  Dependent normals (the two
 // triangles of a flat quad) fall out of the Gram-Schmidt rank test.
 //
+// An edge/vertex contact constrains the distance rho = |p - q| from the node to the nearest
+// point q of a fixed edge line or vertex; its normal n = (p - q)/rho turns with the node,
+// dn/dp = (I - n n^T - t t^T)/rho (edge of unit direction t) or (I - n n^T)/rho (vertex), so
+// the contact force -y n adds -y dn/dp to the node's translation block of J.  A face
+// contact is a plane and adds nothing.
+//
 // Kernels:
 //   jac       one thread per (node, direction): exact Jacobian columns by forward-mode
 //             dual numbers through the element force (material + geometric
-//             stiffness) and the follower actuation load at the tip
+//             stiffness) and the follower actuation load at the tip, plus the curvature of
+//             the node's active edge/vertex contacts
 //   basis     one thread per node: constraint basis Q_i, k_i and T^T g
 //   transform one thread per node: blocks of T^T J T, fixed rows/columns removed
 //   sweep     one wavefront per robot: block elimination of (T^T J T)^T from the base
 //             to the tip with partial pivoting inside each 6x6 block; the tip's
 //             multipliers are the last unknowns, so no back substitution is needed.
 #include "element_math.h"
+#include "tri_geometry.h"
 
 namespace accfem {
 
@@ -66,6 +74,32 @@ __device__ __forceinline__ DualNode dual_node(const Dev& d, int64_t g, int c) {
     }
   }
   return n;
+}
+
+// dn/dp (row-major 3x3) of an edge/vertex contact of triangle t at node position p
+__device__ void contact_curvature(const Dev& d, int64_t t, P3<double> p, double* H) {
+  const double4* rec = reinterpret_cast<const double4*>(d.tv + 12 * t);
+  const P3<double> a{rec[0].x, rec[0].y, rec[0].z}, b{rec[1].x, rec[1].y, rec[1].z},
+      c{rec[2].x, rec[2].y, rec[2].z};
+  P3<double> q;
+  const int f = closest_feature(p, a, b, c, &q);
+  const P3<double> dv = sub(p, q);
+  const double rho = sqrt(dotp(dv, dv));
+#pragma unroll
+  for (int k = 0; k < 9; ++k) H[k] = 0.0;
+  if (f == F_FACE || !(rho > 0.0)) return;
+  const double n[3] = {dv.x / rho, dv.y / rho, dv.z / rho};
+  double tv[3] = {0.0, 0.0, 0.0};
+  if (f == F_AB || f == F_AC || f == F_BC) {
+    const P3<double> e = f == F_AB ? sub(b, a) : (f == F_AC ? sub(c, a) : sub(c, b));
+    const double le = sqrt(dotp(e, e));
+    tv[0] = e.x / le; tv[1] = e.y / le; tv[2] = e.z / le;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      H[3 * k + j] = ((k == j ? 1.0 : 0.0) - n[k] * n[j] - tv[k] * tv[j]) / rho;
 }
 
 __global__ void __launch_bounds__(256) adj_jac_kernel(Dev d, double* JL, double* JD, double* JU) {
@@ -124,6 +158,26 @@ __global__ void __launch_bounds__(256) adj_jac_kernel(Dev d, double* JL, double*
       }
       col[k] -= df;
       col[3 + k] -= dm;
+    }
+  }
+  if (c < 3) {
+    // curvature of the node's active edge/vertex contacts: column c of -y dn/dp
+    const int64_t cb = (int64_t)r * d.cap;
+    const int ncp = d.st_ncp[r];
+    int lo = 0, hi = ncp;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (d.cp_node[cb + mid] < i) lo = mid + 1; else hi = mid;
+    }
+    const int64_t N = d.Ntot;
+    const P3<double> p{d.X[g], d.X[N + g], d.X[2 * N + g]};
+    for (int q = lo; q < ncp && d.cp_node[cb + q] == i; ++q) {
+      const double y = d.cp_y[cb + q];
+      if (!(y > 0.0) || d.cp_kind[cb + q] == 0) continue;
+      double H[9];
+      contact_curvature(d, d.cp_tri[cb + q], p, H);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) col[k] -= y * H[3 * k + c];
     }
   }
 #pragma unroll

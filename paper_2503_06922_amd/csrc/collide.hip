@@ -16,7 +16,9 @@
 //                   a detected contact at the node has the same plane (normals and gaps
 //                   within PLANE_TOL)
 // Every entry also carries whether it had force > 0 at the previous iterate (detected
-// again with the same triangle and kind, or persisting): the LCP starts from those.
+// again with the same triangle and kind, or persisting): the LCP starts from those.  At the
+// first iteration of a load step the previous iterate is the previous load step's
+// equilibrium: its contacts flag the warm start but none persists.
 // The base node and nodes held by the insertion guide are skipped.  Results are
 // written per node (up to MAXC, ordered by kind then triangle index) and compacted
 // per robot by the gather step of the solver.
@@ -25,57 +27,9 @@
 // so the contact set is the FP64 one; in FP64 a bounding-sphere test rejects most
 // triangles first.  The screens read packed per-triangle records (one or four
 // 16-byte loads), the FP64 test the structure-of-arrays vertices.
-#include "fem_device.h"
+#include "tri_geometry.h"
 
 namespace accfem {
-
-enum { R_FACE = 0, R_EDGE = 1, R_VERT = 2 };
-constexpr double PLANE_TOL = 1e-9;   // two contacts lie on the same plane (normals and gaps)
-
-template <typename T>
-struct P3 { T x, y, z; };
-template <typename T>
-__device__ __forceinline__ P3<T> sub(P3<T> a, P3<T> b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
-template <typename T>
-__device__ __forceinline__ T dotp(P3<T> a, P3<T> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
-template <typename T>
-__device__ __forceinline__ P3<T> axpy(P3<T> a, T s, P3<T> b) { return {a.x + s * b.x, a.y + s * b.y, a.z + s * b.z}; }
-
-// closest point of triangle (a, b, c) to p and its region
-template <typename T>
-__device__ __forceinline__ int closest_on_tri(P3<T> p, P3<T> a, P3<T> b, P3<T> c, P3<T>* out) {
-  P3<T> ab = sub(b, a), ac = sub(c, a), ap = sub(p, a);
-  T d1 = dotp(ab, ap), d2 = dotp(ac, ap);
-  if (d1 <= T(0) && d2 <= T(0)) { *out = a; return R_VERT; }
-  P3<T> bp = sub(p, b);
-  T d3 = dotp(ab, bp), d4 = dotp(ac, bp);
-  if (d3 >= T(0) && d4 <= d3) { *out = b; return R_VERT; }
-  T vc = d1 * d4 - d3 * d2;
-  if (vc <= T(0) && d1 >= T(0) && d3 <= T(0)) {
-    T v = d1 / (d1 - d3);
-    *out = axpy(a, v, ab);
-    return R_EDGE;
-  }
-  P3<T> cp = sub(p, c);
-  T d5 = dotp(ab, cp), d6 = dotp(ac, cp);
-  if (d6 >= T(0) && d5 <= d6) { *out = c; return R_VERT; }
-  T vb = d5 * d2 - d1 * d6;
-  if (vb <= T(0) && d2 >= T(0) && d6 <= T(0)) {
-    T w = d2 / (d2 - d6);
-    *out = axpy(a, w, ac);
-    return R_EDGE;
-  }
-  T va = d3 * d6 - d5 * d4;
-  if (va <= T(0) && (d4 - d3) >= T(0) && (d5 - d6) >= T(0)) {
-    T w = (d4 - d3) / ((d4 - d3) + (d5 - d6));
-    *out = axpy(b, w, sub(c, b));
-    return R_EDGE;
-  }
-  T den = T(1) / (va + vb + vc);
-  T v = vb * den, w = vc * den;
-  *out = axpy(axpy(a, v, ab), w, ac);
-  return R_FACE;
-}
 
 struct TriTest { int region; double s, dist; P3<double> cp, n; };
 
@@ -112,9 +66,10 @@ __device__ __forceinline__ bool screen32(const Dev& d, int64_t t, P3<float> p, f
 // node's cell list (consecutive entries to consecutive lanes), face contacts are appended
 // in ballot order, the fallback is the group's lexicographic minimum of (distance, triangle)
 // (the lowest triangle index among equally near ones, as a walk in list order finds), and
-// the group's first lane adds the persisting contacts and orders the node's entries.
-constexpr int CL = 8;
-
+// the group's first lane adds the persisting contacts and orders the node's entries.  The
+// group width CL (4, 8 or 16 lanes) is a launch shape picked per context (autotuned or 8);
+// the detected set does not depend on it.
+template <int CL>
 __global__ void __launch_bounds__(256) collide_kernel(Dev d) {
   const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t g = gt / CL;
@@ -228,6 +183,9 @@ __global__ void __launch_bounds__(256) collide_kernel(Dev d) {
   const int ndet = min(cnt, MAXC);
   const int64_t cb = (int64_t)r * d.cap;
   const int ncp = d.st_ncp[r];
+  // first iteration of a load step: the list is the previous load step's final contacts,
+  // which only flag the warm start
+  const bool fresh = d.st_it[r] == 0;
   int lo = 0, hi = ncp;
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
@@ -241,7 +199,7 @@ __global__ void __launch_bounds__(256) collide_kernel(Dev d) {
     bool found = false;
     for (int q = 0; q < ndet; ++q)
       if (d.CK[q * N + g] == kc && d.CT[q * N + g] == t) { d.CW[q * N + g] = 1; found = true; }
-    if (found) continue;
+    if (found || fresh) continue;
     const TriTest tt = test_tri64(d, t, p);
     if (!(tt.dist <= band)) continue;
     // a face keeps its plane; an edge/vertex contact keeps the direction from the triangle's
@@ -343,8 +301,11 @@ __global__ void tri_setup_kernel(const double* V, const int32_t* tri, int64_t T,
 
 void launch_collide(const Dev& d, hipStream_t s) {
   const int T = 256;
-  const int64_t blocks = (d.Ntot * CL + T - 1) / T;
-  hipLaunchKernelGGL(collide_kernel, dim3((unsigned)blocks), dim3(T), 0, s, d);
+  const int cl = (d.coll_lanes == 4 || d.coll_lanes == 16) ? d.coll_lanes : 8;
+  const int64_t blocks = (d.Ntot * cl + T - 1) / T;
+  if (cl == 4) hipLaunchKernelGGL(collide_kernel<4>, dim3((unsigned)blocks), dim3(T), 0, s, d);
+  else if (cl == 16) hipLaunchKernelGGL(collide_kernel<16>, dim3((unsigned)blocks), dim3(T), 0, s, d);
+  else hipLaunchKernelGGL(collide_kernel<8>, dim3((unsigned)blocks), dim3(T), 0, s, d);
 }
 
 __global__ void cell_spheres_kernel(const int32_t* cell_tris, int64_t n, const double4* tsd,

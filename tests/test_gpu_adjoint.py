@@ -211,3 +211,41 @@ def test_grad_error_paths():
     with pytest.raises(fem.FemError) as e:
         ctx.fem_grad([-1], np.zeros((1, 1, 3)))
     assert e.value.status == -4
+
+
+def test_grad_edge_contact_matches_oracle():
+    """A node pressed onto a convex ridge (the edge fallback; the ridge runs along the robot)
+    by a dead tip load: fem_grad, with the turning of the edge contact's normal, against the
+    oracle's adjoint at the oracle's own equilibrium (pinned against re-solves on the CPU)."""
+    from paper_2503_06922_amd import fem
+    from workloads.robots import RobotBatch
+    zr = -1.7e-3
+    V = np.array([[0.04, 0.0, zr], [0.08, 0.0, zr], [0.06, -0.01, zr - 0.002], [0.06, 0.01, zr - 0.002]])
+    T = np.array([[0, 2, 1], [1, 3, 0]], np.int32)
+    rb = RobotBatch(n_elem=np.array([10], np.int32), length=np.array([0.3]), base_pos=np.zeros((1, 3)),
+                    base_dir=np.array([[1.0, 0, 0]]), base_up=np.array([[0, 1.0, 0]]),
+                    tensions=np.zeros((1, 3)), depth=np.zeros(1))
+    robs, _ = oracle_robots(rb, V, T)
+    rob = robs[0]
+    u0 = np.array([0.0, 0.0, -3e-4, 0.0, 0.0, 0.0])
+    ctx = gpu_context(rb, V, T, newton_tol=1e-13, stag_tol=1e-9, max_newton=300)
+    ctx.fem_set_actuation(fem.FEM_ACT_TIP_WRENCH_GLOBAL, u0, None)
+    out = ctx.fem_solve(10)
+    assert out["info"][0]["status"] == 0
+    P, R, traj = solver.solve_robot(rob, lambda k: (0.0, u0 * k / 10), 10, act_kind=actuation.TIP_GLOBAL,
+                                    tol=1e-13, stag_tol=1e-9, max_iter=300)
+    last = traj[-1]
+    assert last["info"]["status"] == solver.OK
+    gc = ctx.fem_contacts(0)
+    assert [(c["node"], c["kind"]) for c in gc if c["force"] > 0] == [(2, 1)]
+    sens = [2, 10]
+    targets = P[sens] + np.array([[1e-3, -2e-3, 0.5e-3], [-1e-3, 1e-3, 2e-3]])
+    _, dLdp_o = adjoint.sensor_loss(P, sens, targets)
+    go = adjoint.tension_gradient(rob, P, R, last["contacts"], last["y"], u0, sens, dLdp_o,
+                                  act_kind=actuation.TIP_GLOBAL)
+    Pg = out["state"][:, 0:3]
+    _, dLdp_g = adjoint.sensor_loss(Pg, sens, targets)
+    g, st = ctx.fem_grad(sens, dLdp_g[None])
+    assert st == 0
+    print("gpu", g[0], "oracle", go, "relative", _rel(g[0], go))
+    assert _rel(g[0], go) <= TOL_GRAD
