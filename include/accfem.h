@@ -77,6 +77,17 @@ typedef enum {
   FEM_ACT_CABLE_WRENCH = 3
 } fem_act_kind;
 
+/* QP method of the Newton iteration's linear step (eq. 23, Sec. III-B).
+ *   FEM_QP_EXACT: block-tridiagonal Cholesky, contact-space Schur complement and a finite
+ *     active-set LCP method (the exact QP solution).
+ *   FEM_QP_ADMM: the operator-splitting iteration of OSQP, the solver the paper uses
+ *     (Stellato et al. 2020, Algorithm 1, without problem scaling, fixed penalty admm_rho,
+ *     sigma 1e-6, relaxation 1.6) on the same QP, with the block-tridiagonal factor of
+ *     K + sigma I + rho A^T A (every contact row lies on one node) and one forward and
+ *     backward sweep per iteration, until the primal and dual residuals are below
+ *     admm_eps (absolute and relative) or admm_max_iter iterations. */
+typedef enum { FEM_QP_EXACT = 0, FEM_QP_ADMM = 1 } fem_qp_solver;
+
 /* Per-robot status in fem_solve_info.status */
 enum {
   FEM_ROBOT_OK = 0,        /* last load step converged */
@@ -114,6 +125,13 @@ typedef struct {
                                  and a stream of the context's own for the load-step loop */
   int32_t io_on_device;       /* 1: array arguments of later calls are device pointers */
   int32_t profile;            /* 1: time every kernel launch with HIP events (fem_profile) */
+  int32_t autotune;           /* 1: the launch shapes of the element update and contact
+                                 detection are picked by timing during the first solve
+                                 (fem_tuning) */
+  int32_t qp_solver;          /* fem_qp_solver; FEM_QP_EXACT = 0 */
+  double admm_rho;            /* FEM_QP_ADMM penalty (N/m); 0 = 1 */
+  double admm_eps;            /* FEM_QP_ADMM tolerance; 0 = 1e-11 */
+  int32_t admm_max_iter;      /* FEM_QP_ADMM iteration limit per linear step; 0 = 20000 */
 } fem_params;
 
 typedef struct {
@@ -129,6 +147,7 @@ typedef struct {
   int64_t rhs_fused;        /* of those, swept forward inside the factorisation (the first 64
                                of each Newton step), same span */
   int64_t sweep_passes;     /* substitution passes of 64 right-hand sides, same span */
+  int64_t qp_iters_total;   /* FEM_QP_ADMM iterations, same span (0 for FEM_QP_EXACT) */
 } fem_solve_info;
 
 typedef struct {
@@ -310,6 +329,17 @@ fem_status fem_lcp(const double* W, const double* q, int32_t m, double* y, int32
  * 1..FEM_LCP_NOALLOC_MAX_M.  FEM_E_NOCONV as fem_lcp (y then undefined).  FEM_E_HIP. */
 fem_status fem_lcp_noalloc(const double* W, const double* q, int32_t m, double* y,
                            int32_t* path, void* hip_stream);
+
+/* Launch shapes of the context (a measurement aid, no passage of the method): threads per
+ * block of the element update and lanes per node of contact detection, as picked by the
+ * autotuner of a context created with autotune = 1, once, after 512 Newton passes of its
+ * first fem_solve / fem_solve_schedule call (or at the end of that call if it is shorter),
+ * each candidate timed with HIP events on the state reached (64, 128, 256 threads; 4, 8, 16
+ * lanes); else the defaults 256 and 8.  times_us [6] (or NULL) receives
+ * the measured median launch times in that order (NaN before tuning).  The results of the
+ * method do not depend on the shapes.  Any output may be NULL. */
+fem_status fem_tuning(const fem_ctx* c, int32_t* elem_block, int32_t* detect_lanes,
+                      double* times_us);
 
 /* Total number of nodes over the batch (Sec. II-B: n_elem + 1 per robot, summed),
  * or -1 for NULL. */

@@ -21,10 +21,13 @@ scipy (LAPACK banded LU, scipy.spatial.transform) and plain Python loops:
                   step-size limit (eq. 20-23, 25-27) and quasi-static load
                   stepping.
 * ``adjoint``   - gradient of a tip-sensor loss with respect to the cable tensions
-                  at a converged equilibrium.
+                  at a converged equilibrium (with the curvature of edge/vertex
+                  contact constraints).
+* ``admm``      - the operator-splitting (OSQP) iteration on the linear step's QP,
+                  the solver Sec. III-B uses, as an alternative linear step.
 
 Parity pins: every function is checked in tests/test_oracle_*.py against closed
 forms (cantilever tip deflection, exact circular arc under a pure tip moment,
 uniform axial shortening), invariances, finite differences and brute force.
 """
-from . import beam, actuation, collision, lcp, solver, adjoint  # noqa: F401
+from . import beam, actuation, collision, lcp, solver, adjoint, admm  # noqa: F401

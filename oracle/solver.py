@@ -294,10 +294,13 @@ def stagnation_tol(robot, stag_tol):
 
 
 def solve_load_step(robot, P, R, base_target, act_kind, act_values, tol=1e-10,
-                    stag_tol=1e-9, max_iter=200, guided=None):
+                    stag_tol=1e-9, max_iter=200, guided=None, qp=None):
     """Newton iteration of one quasi-static load step from (P, R).
 
-    Returns (P, R, contacts, y, info) with info = dict(status, iters, n_limited, res_norm).
+    qp = None solves each QP of eq. 23 exactly; qp = dict(rho=..., eps=..., max_iter=...)
+    solves it with the ADMM iteration of oracle.admm (the paper's OSQP variant).
+    Returns (P, R, contacts, y, info) with info = dict(status, iters, n_limited, res_norm)
+    (plus qp_iters, the ADMM iterations summed over the load step, with qp).
     """
     stag_tol = stagnation_tol(robot, stag_tol)
     resid = lambda P_, R_: out_of_balance(robot, P_, R_, act_kind, act_values)
@@ -306,6 +309,7 @@ def solve_load_step(robot, P, R, base_target, act_kind, act_values, tol=1e-10,
     n_lim = 0
     n_switch = 0
     rn = np.inf
+    qp_iters = 0
     for it in range(max_iter + 1):
         F = resid(P, R)
         contacts = detect(robot, P, guided, None if prev is None else (prev[1], prev[0]))
@@ -317,22 +321,34 @@ def solve_load_step(robot, P, R, base_target, act_kind, act_values, tol=1e-10,
             gmin = min([ct["gap"] for ct in contacts], default=np.inf)
             if (same and not lim_p and gmin >= -1e-9
                     and (rn <= tol or (rn <= stag_tol and rn > 0.5 * rn_prev))):
-                return P, R, cont_p, y_p, dict(status=OK, iters=it, n_limited=n_lim, res_norm=rn)
+                info = dict(status=OK, iters=it, n_limited=n_lim, res_norm=rn)
+                if qp is not None:
+                    info["qp_iters"] = qp_iters
+                return P, R, cont_p, y_p, info
             rn_prev = rn
         if it == max_iter:
             break
         ab = beam.tangent_qp_upper_banded(P, R, robot.K12)
-        try:
-            dX, y, limited = linear_step(robot, P, R, F, ab, base_target, contacts, guided,
-                                         step_limit(robot.beta0, n_switch))
-        except lcp.LCPFailure:
-            return P, R, contacts, np.zeros(len(contacts)), dict(
-                status=LCPFAIL, iters=it, n_limited=n_lim, res_norm=rn)
+        if qp is not None:
+            from . import admm
+            dX, y, limited, qit = admm.linear_step_admm(robot, P, R, F, ab, base_target, contacts,
+                                                        guided, step_limit(robot.beta0, n_switch), **qp)
+            qp_iters += qit
+        else:
+            try:
+                dX, y, limited = linear_step(robot, P, R, F, ab, base_target, contacts, guided,
+                                             step_limit(robot.beta0, n_switch))
+            except lcp.LCPFailure:
+                return P, R, contacts, np.zeros(len(contacts)), dict(
+                    status=LCPFAIL, iters=it, n_limited=n_lim, res_norm=rn)
         n_lim += int(limited)
         P, R = beam.apply_increment(P, R, dX)
         prev = (y, contacts, limited)
     y_p, cont_p, _ = prev
-    return P, R, cont_p, y_p, dict(status=NOCONV, iters=max_iter, n_limited=n_lim, res_norm=rn)
+    info = dict(status=NOCONV, iters=max_iter, n_limited=n_lim, res_norm=rn)
+    if qp is not None:
+        info["qp_iters"] = qp_iters
+    return P, R, cont_p, y_p, info
 
 
 def solve_robot(robot, schedule, n_steps, act_kind=actuation.CABLES, state=None,

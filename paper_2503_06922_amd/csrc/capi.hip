@@ -162,7 +162,8 @@ __device__ void begin_load_step(const Dev& d, int r, int j) {
   d.st_it[r] = 0;
   d.st_status[r] = 1;
   d.st_done[r] = 0;
-  d.st_ncp[r] = 0;
+  // the previous load step's final contacts stay listed: at iteration 0 detection uses them
+  // only to flag the LCP's warm start (no contact persists across load steps)
   d.st_nc[r] = 0;
   d.st_limited[r] = 1;
   d.st_nlim[r] = 0;
@@ -280,6 +281,12 @@ struct fem_ctx {
   int64_t sched_cap = 0;
   double* rec_buf = nullptr;
   int64_t rec_cap = 0;
+  // autotuned launch shapes: measured once, at the first solve of a context created with
+  // autotune = 1 (times in us: element update at 64/128/256 threads per block, detection at
+  // 4/8/16 lanes per node)
+  bool tuned = false;
+  double tune_us[6] = {NAN, NAN, NAN, NAN, NAN, NAN};
+  int32_t* tune_save = nullptr;  // [B] the done flags while the autotuner runs every robot
   // per-kernel event timing
   bool profile = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -354,6 +361,63 @@ fem_status timed(fem_ctx* c, hipStream_t s, int k, Fn&& launch) {
   return FEM_OK;
 }
 
+// Autotuner of the launch shapes of the element update (threads per block) and of contact
+// detection (lanes per node): on the context's current state, with every robot active, each
+// candidate is launched once to warm up, then timed three times with HIP events on the
+// loop's stream; the median decides.  Both kernels only read the state and write per-node
+// outputs that the next pass recomputes, and neither result depends on the shape.  It runs
+// once per context, after kTunePass passes of its first long enough call (robots inserted
+// and in contact: the straight reference state would favour shapes that suit no contacts),
+// or at the end of the first call if that is shorter.
+constexpr int64_t kTunePass = 512;
+fem_status autotune(fem_ctx* c, hipStream_t s) {
+  Dev& d = c->d;
+  const int B = c->B;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(c, hipEventCreate(&e0));
+  HIP_TRY(c, hipEventCreate(&e1));
+  int32_t* saved = c->tune_save;
+  HIP_TRY(c, hipMemcpyAsync(saved, d.st_done, B * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(c, hipMemsetAsync(d.st_done, 0, B * sizeof(int32_t), s));
+  auto median_us = [&](auto&& launch, double* out) -> fem_status {
+    launch();
+    float t[3];
+    for (int k = 0; k < 3; ++k) {
+      HIP_TRY(c, hipEventRecord(e0, s));
+      launch();
+      HIP_TRY(c, hipEventRecord(e1, s));
+      HIP_TRY(c, hipEventSynchronize(e1));
+      HIP_TRY(c, hipEventElapsedTime(&t[k], e0, e1));
+    }
+    HIP_TRY(c, hipGetLastError());
+    std::sort(t, t + 3);
+    *out = 1e3 * t[1];
+    return FEM_OK;
+  };
+  const int blocks[3] = {64, 128, 256}, lanes[3] = {4, 8, 16};
+  int best_b = 256, best_l = 8;
+  double tb = INFINITY, tl = INFINITY;
+  fem_status st = FEM_OK;
+  for (int k = 0; k < 3 && st == FEM_OK; ++k) {
+    d.elem_block = blocks[k];
+    st = median_us([&] { launch_elem(d, s); }, &c->tune_us[k]);
+    if (st == FEM_OK && c->tune_us[k] < tb) { tb = c->tune_us[k]; best_b = blocks[k]; }
+  }
+  for (int k = 0; k < 3 && st == FEM_OK; ++k) {
+    d.coll_lanes = lanes[k];
+    st = median_us([&] { launch_collide(d, s); }, &c->tune_us[3 + k]);
+    if (st == FEM_OK && c->tune_us[3 + k] < tl) { tl = c->tune_us[3 + k]; best_l = lanes[k]; }
+  }
+  d.elem_block = best_b;
+  d.coll_lanes = best_l;
+  HIP_TRY(c, hipMemcpyAsync(d.st_done, saved, B * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st == FEM_OK) c->tuned = true;
+  return st;
+}
+
 // one pass of the loop over every robot: load-step advance, element update, detection and
 // the Newton step's phases
 void launch_pass(const Dev& d, hipStream_t s) {
@@ -394,36 +458,45 @@ fem_status run_load_steps(fem_ctx* c, int n) {
       ++pass;
       HIP_TRY(c, hipMemcpyAsync(c->h_done, d.n_done, sizeof(int32_t), hipMemcpyDeviceToHost, xs));
       HIP_TRY(c, hipStreamSynchronize(xs));
+      if (c->p.autotune && !c->tuned && (pass == kTunePass || *c->h_done >= d.B)) {
+        fem_status s = autotune(c, xs);
+        if (s != FEM_OK) return s;
+      }
       if (*c->h_done >= d.B) break;
       if (pass > max_pass) return fail(c, FEM_E_HIP, "load stepping did not terminate");
     }
     return FEM_OK;
   }
   const int K = c->iters_per_graph;
-  if (!c->graph_exec || c->graph_iters != K || std::memcmp(&c->graph_dev, &d, sizeof(Dev)) != 0) {
-    if (c->graph_exec) {
-      HIP_TRY(c, hipGraphExecDestroy(c->graph_exec));
-      c->graph_exec = nullptr;
-    }
-    hipGraph_t g = nullptr;
-    HIP_TRY(c, hipStreamBeginCapture(xs, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < K; ++k) launch_pass(d, xs);
-    hipError_t e = hipStreamEndCapture(xs, &g);
-    if (e != hipSuccess) return fail(c, FEM_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
-    e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) {
-      c->graph_exec = nullptr;
-      return fail(c, FEM_E_HIP, std::string("graph instantiation: ") + hipGetErrorString(e));
-    }
-    std::memcpy(&c->graph_dev, &d, sizeof(Dev));
-    c->graph_iters = K;
-  }
   for (;;) {
+    // (re)capture when the launch parameters changed (first call, new schedule, tuned shapes)
+    if (!c->graph_exec || c->graph_iters != K || std::memcmp(&c->graph_dev, &d, sizeof(Dev)) != 0) {
+      if (c->graph_exec) {
+        HIP_TRY(c, hipGraphExecDestroy(c->graph_exec));
+        c->graph_exec = nullptr;
+      }
+      hipGraph_t g = nullptr;
+      HIP_TRY(c, hipStreamBeginCapture(xs, hipStreamCaptureModeThreadLocal));
+      for (int k = 0; k < K; ++k) launch_pass(d, xs);
+      hipError_t e = hipStreamEndCapture(xs, &g);
+      if (e != hipSuccess) return fail(c, FEM_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+      e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        c->graph_exec = nullptr;
+        return fail(c, FEM_E_HIP, std::string("graph instantiation: ") + hipGetErrorString(e));
+      }
+      std::memcpy(&c->graph_dev, &d, sizeof(Dev));
+      c->graph_iters = K;
+    }
     HIP_TRY(c, hipGraphLaunch(c->graph_exec, xs));
     pass += K;
     HIP_TRY(c, hipMemcpyAsync(c->h_done, d.n_done, sizeof(int32_t), hipMemcpyDeviceToHost, xs));
     HIP_TRY(c, hipStreamSynchronize(xs));
+    if (c->p.autotune && !c->tuned && (pass >= kTunePass || *c->h_done >= d.B)) {
+      fem_status s = autotune(c, xs);
+      if (s != FEM_OK) return s;
+    }
     if (*c->h_done >= d.B) break;
     if (pass > max_pass + K) return fail(c, FEM_E_HIP, "load stepping did not terminate");
   }
@@ -437,6 +510,15 @@ extern "C" {
 const char* fem_last_error(const fem_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
 
 int64_t fem_total_nodes(const fem_ctx* c) { return c ? c->Ntot : -1; }
+
+fem_status fem_tuning(const fem_ctx* c, int32_t* elem_block, int32_t* detect_lanes, double* times_us) {
+  if (!c) return FEM_E_INVAL;
+  if (elem_block) *elem_block = c->d.elem_block;
+  if (detect_lanes) *detect_lanes = c->d.coll_lanes;
+  if (times_us)
+    for (int k = 0; k < 6; ++k) times_us[k] = c->tune_us[k];
+  return FEM_OK;
+}
 
 void fem_destroy(fem_ctx* c) {
   if (!c) return;
@@ -486,6 +568,9 @@ static fem_status create_impl(fem_ctx* c, const fem_params* p) {
   if (p->max_newton < 1 || p->contact_capacity < 1 || p->contact_capacity > 1024)
     return bad("max_newton or contact_capacity out of range");
   if (!(p->newton_tol > 0.0) || !(p->stag_tol >= 0.0)) return bad("tolerances out of range");
+  if (p->qp_solver != FEM_QP_EXACT && p->qp_solver != FEM_QP_ADMM) return bad("unknown qp_solver");
+  if (p->admm_rho < 0.0 || p->admm_eps < 0.0 || p->admm_max_iter < 0)
+    return bad("ADMM parameters out of range");
   c->p = *p;
   c->B = p->n_robots;
   c->io_dev = p->io_on_device ? 1 : 0;
@@ -628,6 +713,15 @@ static fem_status create_impl(fem_ctx* c, const fem_params* p) {
   d.sched_act = nullptr; d.sched_dep = nullptr;
   d.rec_tip = nullptr; d.rec_status = nullptr; d.rec_iters = nullptr;
   d.n_steps = 1;
+  d.coll_lanes = 8;
+  d.elem_block = 256;
+  d.qp_admm = p->qp_solver == FEM_QP_ADMM ? 1 : 0;
+  d.admm_rho = p->admm_rho > 0.0 ? p->admm_rho : 1.0;
+  d.admm_eps = p->admm_eps > 0.0 ? p->admm_eps : 1e-11;
+  d.admm_max_iter = p->admm_max_iter > 0 ? p->admm_max_iter : 20000;
+  ALLOC(d.st_qpit, B);
+  ALLOC(c->tune_save, B);
+  HIP_TRY(c, hipMemset(d.st_qpit, 0, B * sizeof(int64_t)));
   HIP_TRY(c, hipMemset(d.st_status, 0, B * sizeof(int32_t)));
   HIP_TRY(c, hipMemset(d.st_done, 0, B * sizeof(int32_t)));
   HIP_TRY(c, hipMemset(d.st_nc, 0, B * sizeof(int32_t)));
@@ -833,6 +927,7 @@ fem_status fem_set_state(fem_ctx* c, const double* node_state) {
   HIP_TRY(c, hipMemsetAsync(c->steps_tot, 0, c->B * sizeof(int32_t), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->iters_tot, 0, c->B * sizeof(int64_t), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->d.st_rhs, 0, 3 * c->B * sizeof(int64_t), c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d.st_qpit, 0, c->B * sizeof(int64_t), c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->solved = false;
   return FEM_OK;
@@ -863,8 +958,9 @@ static fem_status solve_epilogue(fem_ctx* c, double* node_state, fem_solve_info*
     HIP_TRY(c, hipMemcpy(sc.data(), c->steps_conv, B * sizeof(int32_t), hipMemcpyDeviceToHost));
     HIP_TRY(c, hipMemcpy(stt.data(), c->steps_tot, B * sizeof(int32_t), hipMemcpyDeviceToHost));
     HIP_TRY(c, hipMemcpy(itt.data(), c->iters_tot, B * sizeof(int64_t), hipMemcpyDeviceToHost));
-    std::vector<int64_t> rhs(3 * B);
+    std::vector<int64_t> rhs(3 * B), qpit(B);
     HIP_TRY(c, hipMemcpy(rhs.data(), d.st_rhs, 3 * B * sizeof(int64_t), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(qpit.data(), d.st_qpit, B * sizeof(int64_t), hipMemcpyDeviceToHost));
     std::vector<fem_solve_info> hi(B);
     for (int r = 0; r < B; ++r) {
       hi[r].status = st[r]; hi[r].iters = it[r]; hi[r].n_contacts = nc[r]; hi[r].n_limited = nl[r];
@@ -873,6 +969,7 @@ static fem_status solve_epilogue(fem_ctx* c, double* node_state, fem_solve_info*
       hi[r].rhs_total = rhs[3 * r];
       hi[r].rhs_fused = rhs[3 * r + 1];
       hi[r].sweep_passes = rhs[3 * r + 2];
+      hi[r].qp_iters_total = qpit[r];
     }
     if (c->io_dev) {
       HIP_TRY(c, hipMemcpy(info, hi.data(), B * sizeof(fem_solve_info), hipMemcpyHostToDevice));

@@ -128,7 +128,8 @@ __global__ void __launch_bounds__(256) elem_kernel(Dev d) {
 }
 
 void launch_elem(const Dev& d, hipStream_t s) {
-  const int T = 256;
+  // block size: a launch shape picked per context (autotuned or 256)
+  const int T = (d.elem_block == 64 || d.elem_block == 128) ? d.elem_block : 256;
   const int64_t blocks = (d.Ntot + T - 1) / T;
   hipLaunchKernelGGL(elem_kernel, dim3((unsigned)blocks), dim3(T), 0, s, d);
 }

@@ -152,6 +152,14 @@ struct Dev {
   int32_t* steps_conv;      // [B] statistics since creation / the last state reset
   int32_t* steps_tot;
   int64_t* iters_tot;
+  // QP method of the linear step: 0 exact (Schur complement + LCP), 1 ADMM (OSQP iteration)
+  int qp_admm;
+  double admm_rho, admm_eps;
+  int admm_max_iter;
+  int64_t* st_qpit;         // [B] ADMM iterations since creation / the last state reset
+  // launch shapes (picked per context by the autotuner, or the defaults 8 and 256)
+  int coll_lanes;           // lanes per node in contact detection: 4, 8 or 16
+  int elem_block;           // threads per block of the element update: 64, 128 or 256
 };
 
 // ------------------------------------------------------------------ vectors

@@ -1883,16 +1883,270 @@ __global__ void __launch_bounds__(NT) gather_kernel(Dev d) {
   }
 }
 
+// ------------------------------------------------------------------ ADMM variant
+// The QP of eq. 23 solved by the operator-splitting iteration of OSQP (the solver Sec. III-B
+// uses; Stellato et al. 2020, Algorithm 1, without problem scaling, fixed penalty rho) instead
+// of the exact Schur complement + LCP.  The QP over the free DOFs is
+//     min 1/2 x^T K x - b^T x   subject to   A x + g >= 0
+// (b = column 0 of Z as written by check_rhs_kernel: minus the out-of-balance force with the
+// base coupling and prescribed increments moved over, prescribed DOFs as identity rows), and
+// OSQP's multiplier y_o of l <= A x with l = -g is minus the contact force.  Per iteration
+//     (K + sigma I + rho A^T A) xt = sigma x + b + A^T (rho z - y_o)
+//     x <- alpha xt + (1 - alpha) x,  zr = alpha A xt + (1 - alpha) z
+//     z <- max(zr + y_o / rho, -g),   y_o <- y_o + rho (zr - z)
+// until |A x - z| and |K x - b + A^T y_o| (infinity norms over free DOFs) are below
+// eps (1 + the scale OSQP uses).  Every contact row lies on one node, so K + sigma I +
+// rho A^T A stays block tridiagonal: it is factored once per Newton iteration (one-ended
+// block Cholesky, 6x6 blocks) and each iteration is one forward and one backward sweep.
+// One wavefront per robot: the factorisation and the sweeps run serially in lane 0 (the
+// variant exists for comparison with the exact method, which parallelises over the
+// right-hand sides), the contact updates over lanes.  The result x goes to Z's column 0
+// and the forces to the contact list, so the step kernels apply it like an exact step.
+constexpr double ADMM_SIGMA = 1e-6, ADMM_ALPHA = 1.6;
+
+// the node's 6x6 block of M = K + sigma I + rho A^T A, prescribed rows and columns -> identity
+__device__ void admm_diag_block(const Dev& d, int r, int64_t o, int64_t n, int64_t i, const Guide& G,
+                                int c0, int c1, int64_t cb, double* A) {
+  const bool right = i < n - 1;
+  const ElemK KL = load_elem(d, o + i - 1), KR = load_elem(d, o + (right ? i : i - 1));
+  for (int a = 0; a < 6; ++a)
+    for (int b = 0; b < 6; ++b) A[a * 6 + b] = k_bb(KL, a, b) + (right ? k_aa(KR, a, b) : 0.0);
+  for (int a = 0; a < 6; ++a) A[a * 7] += ADMM_SIGMA;
+  for (int c = c0; c < c1; ++c) {
+    const double* nc = d.ct_n + 3 * (cb + c);
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) A[a * 6 + b] += d.admm_rho * nc[a] * nc[b];
+  }
+  for (int a = 0; a < 6; ++a)
+    for (int b = 0; b < 6; ++b)
+      if (G.dof(i, a) || G.dof(i, b)) A[a * 6 + b] = (a == b) ? 1.0 : 0.0;
+}
+
+__global__ void __launch_bounds__(NT) admm_kernel(Dev d) {
+  const int r = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (d.st_done[r]) return;
+  const int64_t o = d.off[r], n = d.off[r + 1] - o, nf = n - 1;
+  const Guide G = make_guide(d, r, n);
+  const int nc = d.st_nc[r];
+  const int cap = d.cap;
+  const int64_t cb = (int64_t)r * cap;
+  const int64_t zp = d.zp;
+  double* Yr = d.Y + 6 * o * zp;                 // per free DOF row: x, xt, v, K x in columns 0..3
+  double* b0 = d.Z + d.zoff[r];                  // b (free DOF rows), then the result x
+  double* ws = d.W + (int64_t)d.B * cap * cap + (int64_t)r * lcp_ws_doubles(cap);
+  double* zc = ws;                               // z, y_o per contact
+  double* yo = ws + cap;
+  const double rho = d.admm_rho, eps = d.admm_eps;
+  __shared__ int s_fail, s_stop;
+  if (lane == 0) { s_fail = 0; s_stop = 0; }
+  // ---------------------------------------------------------------- factorisation (lane 0)
+  if (lane == 0) {
+    double Xp[36];
+    for (int k = 0; k < 36; ++k) Xp[k] = 0.0;
+    int cp = 0;
+    for (int64_t f = 0; f < nf; ++f) {
+      const int64_t i = f + 1, g = o + i;
+      while (cp < nc && d.ct_node[cb + cp] < i) ++cp;
+      int c1 = cp;
+      while (c1 < nc && d.ct_node[cb + c1] == i) ++c1;
+      double A[36];
+      admm_diag_block(d, r, o, n, i, G, cp, c1, cb, A);
+      cp = c1;
+      for (int a = 0; a < 6; ++a)
+        for (int b = 0; b < 6; ++b) {
+          double s = 0.0;
+          for (int q = 0; q < 6; ++q) s += Xp[a * 6 + q] * Xp[b * 6 + q];
+          A[a * 6 + b] -= s;
+        }
+      // lower Cholesky in place, reciprocal diagonal
+      for (int q = 0; q < 6; ++q) {
+        double dq = A[q * 7];
+        for (int t = 0; t < q; ++t) dq -= A[q * 6 + t] * A[q * 6 + t];
+        if (!(dq > 0.0)) { s_fail = 1; dq = 1.0; }
+        const double rq = 1.0 / sqrt(dq);
+        A[q * 7] = rq;
+        for (int p = q + 1; p < 6; ++p) {
+          double v = A[p * 6 + q];
+          for (int t = 0; t < q; ++t) v -= A[p * 6 + t] * A[q * 6 + t];
+          A[p * 6 + q] = v * rq;
+        }
+      }
+      for (int k = 0; k < 36; ++k) d.LD[g * 36 + k] = A[k];
+      // X = L_{i+1,i}: row a solves L x = C[:, a], C = K[i, i+1] without prescribed rows/columns
+      double X[36];
+      if (i < n - 1) {
+        const ElemK KR = load_elem(d, o + i);
+        for (int a = 0; a < 6; ++a) {
+          double x[6];
+          for (int q = 0; q < 6; ++q) {
+            double v = (G.dof(i, q) || G.dof(i + 1, a)) ? 0.0 : k_ab(KR, q, a);
+            for (int t = 0; t < q; ++t) v -= A[q * 6 + t] * x[t];
+            x[q] = v * A[q * 7];
+          }
+          for (int q = 0; q < 6; ++q) X[a * 6 + q] = x[q];
+        }
+      } else {
+        for (int k = 0; k < 36; ++k) X[k] = 0.0;
+      }
+      for (int k = 0; k < 36; ++k) { d.LS[g * 36 + k] = X[k]; Xp[k] = X[k]; }
+    }
+  }
+  for (int64_t k = lane; k < 6 * nf; k += NT) {
+    const int64_t f = k / 6;
+    const int q = (int)(k % 6);
+    Yr[k * zp + 0] = G.dof(f + 1, q) ? b0[k] : 0.0;   // x: prescribed rows at their increments
+  }
+  for (int c = lane; c < nc; c += NT) { zc[c] = 0.0; yo[c] = 0.0; }
+  __syncthreads();
+  if (s_fail) {
+    finish(d, r, 3, d.st_it[r], d.st_rn[r]);
+    return;
+  }
+  int it = 0;
+  for (; it < d.admm_max_iter; ++it) {
+    // ------------------------------------------------ x-update: one solve with M (lane 0)
+    if (lane == 0) {
+      double vp[6] = {0, 0, 0, 0, 0, 0};
+      int cp = 0;
+      for (int64_t f = 0; f < nf; ++f) {
+        const int64_t i = f + 1, g = o + i;
+        double v[6];
+        for (int q = 0; q < 6; ++q) {
+          const int64_t row = 6 * f + q;
+          v[q] = G.dof(i, q) ? b0[row] : ADMM_SIGMA * Yr[row * zp] + b0[row];
+        }
+        while (cp < nc && d.ct_node[cb + cp] < i) ++cp;
+        for (; cp < nc && d.ct_node[cb + cp] == i; ++cp) {
+          const double w = rho * zc[cp] - yo[cp];
+          for (int a = 0; a < 3; ++a)
+            if (!G.dof(i, a)) v[a] += w * d.ct_n[3 * (cb + cp) + a];
+        }
+        if (f > 0) {
+          const double* Xl = d.LS + (g - 1) * 36;     // L_{i,i-1}
+          for (int p = 0; p < 6; ++p)
+            for (int q = 0; q < 6; ++q) v[p] -= Xl[p * 6 + q] * vp[q];
+        }
+        const double* L = d.LD + g * 36;
+        for (int q = 0; q < 6; ++q) {
+          double s = v[q];
+          for (int t = 0; t < q; ++t) s -= L[q * 6 + t] * vp[t];
+          vp[q] = s * L[q * 7];
+        }
+        for (int q = 0; q < 6; ++q) Yr[(6 * f + q) * zp + 2] = vp[q];
+      }
+      double xn[6] = {0, 0, 0, 0, 0, 0};
+      for (int64_t f = nf - 1; f >= 0; --f) {
+        const int64_t i = f + 1, g = o + i;
+        double v[6];
+        for (int q = 0; q < 6; ++q) v[q] = Yr[(6 * f + q) * zp + 2];
+        if (f < nf - 1) {
+          const double* X = d.LS + g * 36;           // L_{i+1,i}
+          for (int q = 0; q < 6; ++q)
+            for (int p = 0; p < 6; ++p) v[q] -= X[p * 6 + q] * xn[p];
+        }
+        const double* L = d.LD + g * 36;
+        double x[6];
+        for (int q = 5; q >= 0; --q) {
+          double s = v[q];
+          for (int t = q + 1; t < 6; ++t) s -= L[t * 6 + q] * x[t];
+          x[q] = s * L[q * 7];
+        }
+        for (int q = 0; q < 6; ++q) {
+          xn[q] = x[q];
+          const int64_t row = 6 * f + q;
+          Yr[row * zp + 1] = x[q];
+          Yr[row * zp + 0] = ADMM_ALPHA * x[q] + (1.0 - ADMM_ALPHA) * Yr[row * zp + 0];
+        }
+      }
+    }
+    __syncthreads();
+    // ------------------------------------------------ z and y_o updates (lanes over contacts)
+    double rp = 0.0, sAx = 0.0, sz = 0.0;
+    for (int c = lane; c < nc; c += NT) {
+      const int64_t f = d.ct_node[cb + c] - 1;
+      const double* nv = d.ct_n + 3 * (cb + c);
+      double zt = 0.0, ax = 0.0;
+      for (int a = 0; a < 3; ++a) {
+        zt += nv[a] * Yr[(6 * f + a) * zp + 1];
+        ax += nv[a] * Yr[(6 * f + a) * zp + 0];
+      }
+      const double zr = ADMM_ALPHA * zt + (1.0 - ADMM_ALPHA) * zc[c];
+      const double zn = fmax(zr + yo[c] / rho, -d.ct_gap[cb + c]);
+      yo[c] += rho * (zr - zn);
+      zc[c] = zn;
+      rp = fmax(rp, fabs(ax - zn));
+      sAx = fmax(sAx, fabs(ax));
+      sz = fmax(sz, fabs(zn));
+    }
+    rp = warp_max(rp); sAx = warp_max(sAx); sz = warp_max(sz);
+    __syncthreads();
+    // ------------------------------------------------ dual residual K x - b + A^T y_o (lanes over nodes)
+    double rd = 0.0, sKx = 0.0, sAy = 0.0, sq = 0.0;
+    for (int64_t f = lane; f < nf; f += NT) {
+      const int64_t i = f + 1;
+      const bool right = i < n - 1;
+      const ElemK KL = load_elem(d, o + i - 1), KR = load_elem(d, o + (right ? i : i - 1));
+      double kx[6] = {0, 0, 0, 0, 0, 0};
+      for (int a = 0; a < 6; ++a) {
+        if (G.dof(i, a)) continue;
+        double s = 0.0;
+        for (int b = 0; b < 6; ++b) {
+          if (!G.dof(i, b)) s += (k_bb(KL, a, b) + (right ? k_aa(KR, a, b) : 0.0)) * Yr[(6 * f + b) * zp];
+          if (f > 0 && !G.dof(i - 1, b)) s += k_ab(KL, b, a) * Yr[(6 * (f - 1) + b) * zp];
+          if (right && !G.dof(i + 1, b)) s += k_ab(KR, a, b) * Yr[(6 * (f + 1) + b) * zp];
+        }
+        kx[a] = s;
+      }
+      double ay[3] = {0, 0, 0};
+      int lo = 0, hi = nc;
+      while (lo < hi) { const int mid = (lo + hi) >> 1; if (d.ct_node[cb + mid] < i) lo = mid + 1; else hi = mid; }
+      for (int c = lo; c < nc && d.ct_node[cb + c] == i; ++c)
+        for (int a = 0; a < 3; ++a) ay[a] += yo[c] * d.ct_n[3 * (cb + c) + a];
+      for (int a = 0; a < 6; ++a) {
+        if (G.dof(i, a)) continue;
+        const double aya = a < 3 ? ay[a] : 0.0;
+        const double bq = b0[6 * f + a];
+        rd = fmax(rd, fabs(kx[a] - bq + aya));
+        sKx = fmax(sKx, fabs(kx[a]));
+        sAy = fmax(sAy, fabs(aya));
+        sq = fmax(sq, fabs(bq));
+      }
+    }
+    rd = warp_max(rd); sKx = warp_max(sKx); sAy = warp_max(sAy); sq = warp_max(sq);
+    const bool stop = rp <= eps + eps * fmax(sAx, sz) && rd <= eps + eps * fmax(sKx, fmax(sAy, sq));
+    if (stop) { ++it; break; }
+    __syncthreads();
+  }
+  __syncthreads();
+  // ---------------------------------------------------------------- result
+  for (int64_t k = lane; k < 6 * nf; k += NT) b0[k] = Yr[k * zp];
+  for (int c = lane; c < nc; c += NT) d.ct_y[cb + c] = -yo[c];
+  if (lane == 0) {
+    d.st_nact[r] = 0;           // the step kernels take x as the whole step
+    d.st_mx[r] = 0ull;          // the step's largest node translation is taken afresh
+    d.st_qpit[r] += it;
+  }
+}
+
 // phases of one Newton step: 0 check + right-hand sides, 1 factor, 2 substitute, 3 update
 void launch_solve_phase(const Dev& d, int phase, hipStream_t s) {
   switch (phase) {
     case 0: hipLaunchKernelGGL(check_rhs_kernel, dim3(d.B), dim3(NT), 0, s, d); break;
-    case 1: hipLaunchKernelGGL(factor_kernel, dim3(d.B), dim3(4 * NT), 0, s, d); break;
-    case 2: hipLaunchKernelGGL(subst_kernel, dim3(d.B, (d.cap + NT) / NT), dim3(2 * NT), 0, s, d); break;
+    case 1:
+      if (d.qp_admm) hipLaunchKernelGGL(admm_kernel, dim3(d.B), dim3(NT), 0, s, d);
+      else hipLaunchKernelGGL(factor_kernel, dim3(d.B), dim3(4 * NT), 0, s, d);
+      break;
+    case 2:
+      if (!d.qp_admm)
+        hipLaunchKernelGGL(subst_kernel, dim3(d.B, (d.cap + NT) / NT), dim3(2 * NT), 0, s, d);
+      break;
     default:
-      hipLaunchKernelGGL(update_kernel, dim3(d.B), dim3(NT), 0, s, d);
-      if (d.cap > LCPM) hipLaunchKernelGGL(update_wide_kernel, dim3(d.B), dim3(NT), 0, s, d);
-      if (d.cap > NPW) hipLaunchKernelGGL(update_big_kernel, dim3(d.B), dim3(NT), 0, s, d);
+      if (!d.qp_admm) {
+        hipLaunchKernelGGL(update_kernel, dim3(d.B), dim3(NT), 0, s, d);
+        if (d.cap > LCPM) hipLaunchKernelGGL(update_wide_kernel, dim3(d.B), dim3(NT), 0, s, d);
+        if (d.cap > NPW) hipLaunchKernelGGL(update_big_kernel, dim3(d.B), dim3(NT), 0, s, d);
+      }
       hipLaunchKernelGGL(step_dx_kernel, dim3((unsigned)((d.Ntot + 255) / 256)), dim3(256), 0, s, d);
       hipLaunchKernelGGL(step_apply_kernel, dim3((unsigned)((d.Ntot + 255) / 256)), dim3(256), 0, s, d);
       break;

@@ -15,6 +15,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libaccfem.
 
 FEM_OK, FEM_E_INVAL, FEM_E_NOMEM, FEM_E_HIP, FEM_E_STATE, FEM_E_NOCONV = 0, -1, -2, -3, -4, -5
 FEM_FP64, FEM_MIXED = 0, 1
+FEM_QP_EXACT, FEM_QP_ADMM = 0, 1
 FEM_ACT_CABLES, FEM_ACT_TIP_WRENCH_LOCAL, FEM_ACT_TIP_WRENCH_GLOBAL, FEM_ACT_CABLE_WRENCH = 0, 1, 2, 3
 ROBOT_OK, ROBOT_NOCONV, ROBOT_LCPFAIL, ROBOT_NONSPD, ROBOT_OVERFLOW = 0, 1, 2, 3, 4
 
@@ -46,6 +47,11 @@ class fem_params(C.Structure):
         ("hip_stream", C.c_void_p),
         ("io_on_device", C.c_int32),
         ("profile", C.c_int32),
+        ("autotune", C.c_int32),
+        ("qp_solver", C.c_int32),
+        ("admm_rho", C.c_double),
+        ("admm_eps", C.c_double),
+        ("admm_max_iter", C.c_int32),
     ]
 
 
@@ -54,7 +60,7 @@ class fem_solve_info(C.Structure):
                 ("n_limited", C.c_int32), ("res_norm", C.c_double),
                 ("steps_converged", C.c_int32), ("steps_total", C.c_int32),
                 ("iters_total", C.c_int64), ("rhs_total", C.c_int64), ("rhs_fused", C.c_int64),
-                ("sweep_passes", C.c_int64)]
+                ("sweep_passes", C.c_int64), ("qp_iters_total", C.c_int64)]
 
 
 class fem_contact(C.Structure):
@@ -102,10 +108,11 @@ def lib():
         L.fem_total_nodes.restype = C.c_int64
         L.fem_lcp.argtypes = [P, P, C.c_int32, P, C.POINTER(C.c_int32)]
         L.fem_lcp_noalloc.argtypes = [P, P, C.c_int32, P, C.POINTER(C.c_int32), P]
+        L.fem_tuning.argtypes = [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), P]
         for f in ("fem_create", "fem_set_lumen", "fem_set_actuation", "fem_solve",
                   "fem_solve_schedule", "fem_contacts",
                   "fem_get_state", "fem_set_state", "fem_eval", "fem_profile", "fem_grad", "fem_lcp",
-                  "fem_lcp_noalloc"):
+                  "fem_lcp_noalloc", "fem_tuning"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -113,7 +120,7 @@ def lib():
 
 EXPORTED = ("fem_create", "fem_destroy", "fem_last_error", "fem_set_lumen", "fem_set_actuation",
             "fem_solve", "fem_solve_schedule", "fem_contacts", "fem_get_state", "fem_set_state", "fem_eval",
-            "fem_profile", "fem_grad", "fem_total_nodes", "fem_lcp", "fem_lcp_noalloc")
+            "fem_profile", "fem_grad", "fem_total_nodes", "fem_lcp", "fem_lcp_noalloc", "fem_tuning")
 FEM_LCP_NOALLOC_MAX_M = 512
 
 
@@ -170,6 +177,11 @@ class Context:
         p.hip_stream = params.get("hip_stream", None)
         p.io_on_device = int(params.get("io_on_device", 0))
         p.profile = int(params.get("profile", 0))
+        p.autotune = int(params.get("autotune", 0))
+        p.qp_solver = int(params.get("qp_solver", 0))
+        p.admm_rho = float(params.get("admm_rho", 0.0))
+        p.admm_eps = float(params.get("admm_eps", 0.0))
+        p.admm_max_iter = int(params.get("admm_max_iter", 0))
         self.io_on_device = p.io_on_device
         self.B = B
         self.n_cables = p.n_cables
@@ -322,6 +334,15 @@ class Context:
         if not self.io_on_device:
             X = _f64(X, self.n_nodes * 7)
         return self._check(lib().fem_set_state(self._h, _ptr(X)))
+
+    def fem_tuning(self):
+        """Launch shapes: (threads per block of the element update, lanes per node of
+        detection, measured times [6] in us or NaN before tuning)."""
+        b = C.c_int32(0)
+        l = C.c_int32(0)
+        t = np.full(6, np.nan)
+        self._check(lib().fem_tuning(self._h, C.byref(b), C.byref(l), _ptr(t)))
+        return b.value, l.value, t
 
     def fem_profile(self, kernel, reset=False):
         ms = C.c_double(0.0)

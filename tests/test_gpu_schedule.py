@@ -66,3 +66,33 @@ def test_schedule_invalid_calls():
         ctx.fem_solve_schedule(fem.FEM_ACT_TIP_WRENCH_LOCAL, np.zeros((3, 1, 6)))
     assert e.value.status == fem.FEM_E_INVAL
     ctx.close()
+
+
+def test_autotuned_launch_shapes_give_identical_results():
+    """A context created with autotune = 1 times the candidate launch shapes of the element
+    update (64/128/256 threads per block) and of detection (4/8/16 lanes per node) during its
+    first solve and keeps the fastest; the results are bit-identical to those of the default
+    shapes (256, 8), on 64 robots of the batched insertion through 12 load steps (tuned at the
+    end of the first call, which is shorter than the tuning point) and 12 more."""
+    from paper_2503_06922_amd import fem
+    rb, V, T = make_config(3)
+    sub = rb.subset(np.arange(0, 4096, 64))
+    kw = dict(precision=fem.FEM_MIXED, newton_tol=1e-10, stag_tol=1e-9, max_newton=60,
+              contact_capacity=512)
+    a = gpu_context(sub, V, T, **kw)
+    b = gpu_context(sub, V, T, autotune=1, **kw)
+    assert a.fem_tuning()[:2] == (256, 8) and np.all(np.isnan(a.fem_tuning()[2]))
+    vals, deps = schedule_table(sub, 24)
+    a.fem_solve_schedule(fem.FEM_ACT_CABLES, vals[:12], deps[:12])
+    b.fem_solve_schedule(fem.FEM_ACT_CABLES, vals[:12], deps[:12])
+    oa = a.fem_solve_schedule(fem.FEM_ACT_CABLES, vals[12:], deps[12:])
+    ob = b.fem_solve_schedule(fem.FEM_ACT_CABLES, vals[12:], deps[12:])
+    blk, lanes, t = b.fem_tuning()
+    print("tuned shapes", blk, lanes, "times us", t)
+    assert blk in (64, 128, 256) and lanes in (4, 8, 16) and np.all(np.isfinite(t)) and np.all(t > 0)
+    assert np.array_equal(oa["state"], ob["state"])
+    assert oa["info"] == ob["info"]
+    assert np.array_equal(oa["rec_tip"], ob["rec_tip"])
+    assert same_contacts(a.fem_contacts(-1), b.fem_contacts(-1))
+    a.close()
+    b.close()
