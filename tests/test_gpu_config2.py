@@ -6,10 +6,10 @@ are checked, at sampled load steps, against what the oracle computes at any size
     GPU's contact forces, vanishes over the free DOFs (to the Newton tolerance or the rounding
     floor of the stagnation test) and equals the residual the GPU reported;
   * detection (Sec. III-C): the oracle's brute-force (k-d-tree culled) detection at the GPU
-    state finds the GPU's contact set, outside nodes with near-threshold decisions (an
-    edge/vertex contact may carry another triangle whose nearest point is the same within
-    1e-9 m, with the same gap: the codes break such ties differently); any other GPU entry is
-    a persisting contact still within the band of its triangle;
+    state finds the GPU's contact set, keyed by node and mesh feature (an edge/vertex contact
+    constrains against the edge or vertex that holds the nearest point, whichever of the
+    triangles sharing it carries the index), outside nodes with near-threshold decisions; any
+    other GPU entry is a persisting contact still within the band of its triangle;
   * the contact conditions of eq. 12: forces >= 0, gaps >= 0 to the tolerance, force x gap = 0;
   * mixed precision against the FP64 GPU path: relative tip error <= 1e-5.
 """
@@ -18,7 +18,7 @@ import pytest
 
 from oracle import solver, collision
 from workloads import make_config, load_schedule
-from tests.gpu_helpers import gpu_context, oracle_robots
+from tests.gpu_helpers import gpu_context, oracle_robots, check_equilibrium_state
 
 pytestmark = pytest.mark.gpu
 
@@ -58,55 +58,13 @@ def test_config2_mixed_matches_fp64(config2_runs):
 
 
 def test_config2_equilibrium_detection_complementarity(config2_runs):
-    from paper_2503_06922_amd.fem import state_to_PR
     rb, rob, samples = config2_runs
-    band = rob.r_c + rob.delta
-    tol = max(10 * 1e-10, solver.stagnation_tol(rob, 1e-9))
     checked = 0
     n_contacts = 0
     for s in samples:
         if s["info_m"]["status"] != 0:
             continue
-        P, R = state_to_PR(s["X_m"])
-        guided = rob.guided(s["depth"])
-        cts = s["contacts_m"]
-        # equilibrium with the GPU's contact forces, from the oracle's own force evaluation
-        F = solver.out_of_balance(rob, P, R, 0, s["t"])
-        y = np.array([c["force"] for c in cts])
-        r = solver.contact_residual(F, cts, y, rob, guided)
-        rn = float(np.linalg.norm(r))
-        assert rn <= tol * 1.001, (s["k"], rn, tol)
-        assert abs(rn - s["info_m"]["res_norm"]) <= 1e-9, (s["k"], rn, s["info_m"]["res_norm"])
-        # detection at the GPU state
-        det = collision.detect(P, rob.mesh, rob.r_c, rob.delta, skip=guided)
-        amb = {c["node"] for c in det if c["ambiguous"]}
-        orc = {(c["node"], c["tri"], c["kind"]) for c in det if c["tri"] >= 0 and c["node"] not in amb}
-        gpu = {(c["node"], c["tri"], c["kind"]) for c in cts if c["node"] not in amb}
-        # an oracle contact missing from the GPU set must be the same constraint under another
-        # triangle: the fallback's nearest point on an edge or vertex shared by two triangles is
-        # the same point, and which index wins the rounding-level tie differs between the codes
-        same_geom = set()
-        for (node, tri, kind) in sorted(orc - gpu):
-            oc = next(c for c in det if (c["node"], c["tri"], c["kind"]) == (node, tri, kind))
-            dist = oc["gap"] + rob.r_c               # contact point p - dist n, the same within 1e-9 m
-            alt = [c for c in cts if c["node"] == node and c["kind"] == kind
-                   and dist * np.linalg.norm(np.asarray(c["n"]) - oc["n"]) <= 1e-9
-                   and abs(c["gap"] - oc["gap"]) <= 1e-9]
-            assert alt, (s["k"], (node, tri, kind), oc["n"], oc["gap"],
-                         [(c["tri"], c["kind"], list(c["n"]), c["gap"]) for c in cts if c["node"] == node])
-            same_geom.add((node, alt[0]["tri"], kind))
-        for (node, tri, kind) in sorted(gpu - orc - same_geom):
-            # a persisting contact: the oracle's closest point of that triangle is within the
-            # band; an edge/vertex one also has the node on the triangle's inner side
-            cpt, _, _ = collision.closest_points(P[node], rob.mesh, np.array([tri]))
-            assert np.linalg.norm(P[node] - cpt[0]) <= band + 1e-12, (s["k"], node, tri)
-            if kind != 0:
-                assert rob.mesh.n[tri] @ (P[node] - rob.mesh.v0[tri]) > 0.0, (s["k"], node, tri, kind)
-        # contact conditions
-        for c in cts:
-            assert c["force"] >= 0.0
-            assert c["gap"] >= -1e-9, (s["k"], c)
-            assert c["force"] * c["gap"] <= 1e-9 * max(c["force"], 1e-12) + 1e-15, (s["k"], c)
-        n_contacts += len(cts)
+        n_contacts += check_equilibrium_state(rob, s["X_m"], s["contacts_m"], s["info_m"], s["depth"],
+                                              s["t"])
         checked += 1
     assert checked >= 6 and n_contacts > 0

@@ -7,12 +7,14 @@ bronchial insertion).  It contains none of the method's arithmetic (no element
 forces, no collision predicate, no solver), so that the oracle and the HIP path
 can both consume it without sharing any of the computation under test.
 """
-from .robots import RobotBatch, robots_for_config, load_schedule, schedule_table
+from .robots import (RobotBatch, robots_for_config, load_schedule, schedule_table, sensor_nodes,
+                     sensor_targets)
 from .lumen import straight_cylinder_mesh, branching_lumen_mesh, lumen_for_config
 from .configs import CONFIGS, make_config
 
 __all__ = [
-    "RobotBatch", "robots_for_config", "load_schedule", "schedule_table",
+    "RobotBatch", "robots_for_config", "load_schedule", "schedule_table", "sensor_nodes",
+    "sensor_targets",
     "straight_cylinder_mesh", "branching_lumen_mesh", "lumen_for_config",
     "CONFIGS", "make_config",
 ]

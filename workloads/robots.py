@@ -138,3 +138,30 @@ def robots_for_config(cfg: int, n_robots: int | None = None) -> RobotBatch:
             base_dir=d, base_up=up, tensions=T, depth=depth, n_load_steps=100,
             tension_ramp_steps=10, depth_ramp_steps=100, guide_len=0.60, tip_len=0.07)
     raise ValueError(f"unknown configuration {cfg}")
+
+
+# Sensor nodes of the differentiation workload: the nodes 0.0088 m and 0.0728 m from the tip,
+# the offsets of the two distal sensor rows of the paper's material table (Table I), at the
+# 2 mm element length of that workload (4 and 36 elements from the tip).
+SENSOR_OFFSETS = (0.0088, 0.0728)
+
+
+def sensor_nodes(rb: RobotBatch, b: int = 0):
+    """Node indices counted from the tip (-1 = tip) of the sensors of robot b."""
+    l0 = float(rb.length[b]) / int(rb.n_elem[b])
+    return np.array([-1 - int(round(s / l0)) for s in SENSOR_OFFSETS], np.int32)
+
+
+def sensor_targets(rb: RobotBatch, seed=(4, 2)):
+    """Target positions [B, n_sensors, 3] of the sensors: their straight inserted positions
+    (base position + (depth + arc length) along the base direction) plus N(0, 5 mm) per axis,
+    seeded; defined from geometry only, without a solve."""
+    rng = np.random.default_rng(list(seed))
+    out = np.empty((rb.n_robots, len(SENSOR_OFFSETS), 3))
+    for b in range(rb.n_robots):
+        l0 = float(rb.length[b]) / int(rb.n_elem[b])
+        n = int(rb.n_elem[b]) + 1
+        for s, i in enumerate(sensor_nodes(rb, b)):
+            arc = (n + int(i)) * l0
+            out[b, s] = rb.base_pos[b] + (float(rb.depth[b]) + arc) * rb.base_dir[b]
+    return out + rng.normal(scale=5e-3, size=out.shape)
