@@ -91,12 +91,14 @@ def byte_models(u, sb):
 
 
 def traffic_key(kernel, capacity):
-    """What the counters of `kernel` depend on: its source, the shared device header and the
+    """What the counters of `kernel` depend on: its source, every device header and the
     contact capacity of the run (hashed together)."""
+    import glob
     import hashlib
     h = hashlib.sha256()
-    for name in (KERNEL_SOURCE[kernel], "fem_device.h"):
-        with open(os.path.join(ROOT, "paper_2503_06922_amd", "csrc", name), "rb") as f:
+    csrc = os.path.join(ROOT, "paper_2503_06922_amd", "csrc")
+    for path in [os.path.join(csrc, KERNEL_SOURCE[kernel])] + sorted(glob.glob(os.path.join(csrc, "*.h"))):
+        with open(path, "rb") as f:
             h.update(f.read())
     h.update(b"capacity=%d" % capacity)
     return h.hexdigest()
@@ -117,7 +119,10 @@ def measured_traffic(kernel, capacity):
 
 
 def make_context(fem, rb, prec, args, V, T, **kw):
+    """A context of the batch with inputs and outputs on the device; the launch shapes of the
+    element update and detection are autotuned at its first solve."""
     import torch
+    kw.setdefault("autotune", 1)
     ctx = fem.Context(fem.params_from_batch(rb, precision=prec, newton_tol=1e-10, stag_tol=1e-9,
                                             max_newton=args.max_newton,
                                             contact_capacity=args.capacity, io_on_device=1, **kw))
@@ -142,43 +147,58 @@ def cpu_model():
     return "unknown"
 
 
-def _cpu_worker(args):
-    """One robot of the batched workload through all load steps with the FP64 oracle
-    (a process of its own, one BLAS thread)."""
-    b, n_steps = args
+def _cpu_worker(job):
+    """One load step of one robot of the batched workload, re-solved by the FP64 oracle from the
+    oracle's own converged state after the previous load step (stored with the oracle's
+    trajectories under tests/golden/bench_oracle); a process of its own, one BLAS thread."""
+    path, q = job
     os.environ["OMP_NUM_THREADS"] = "1"
     from oracle import solver, collision
     from workloads import make_config, load_schedule
+    from paper_2503_06922_amd.fem import state_to_PR
+    with np.load(path) as z:
+        b = int(z["robot"])
+        k = int(z["restart_after"][q]) + 1
+        X = z["restart_state"][q]
     rb, V, T = make_config(3)
     sub = rb.subset([b])
     rob = solver.robots_from_batch(sub, collision.Mesh(V, T))[0]
-    sched = lambda k: (lambda d, t: (d[0], t[0]))(*load_schedule(sub, k))
+    d, t = load_schedule(sub, k)
+    P, R = state_to_PR(X)
     t0 = time.perf_counter()
-    _, _, traj = solver.solve_robot(rob, sched, n_steps, tol=1e-10, stag_tol=1e-9, max_iter=60)
-    return sum(1 for s in traj if s["info"]["status"] == solver.OK), time.perf_counter() - t0
+    _, _, _, _, info = solver.solve_load_step(rob, P, R, rob.base_target(d[0]), 0, t[0], tol=1e-10,
+                                              stag_tol=1e-9, max_iter=60, guided=rob.guided(d[0]))
+    return int(info["status"] == solver.OK), time.perf_counter() - t0, info["iters"]
 
 
-def cpu_baseline(n_robots, n_steps, workers, total_solves_gpu):
-    """The FP64 oracle on the host cores: a seeded sample of the batch's robots, each through
-    n_steps load steps in a process of its own (pool of `workers`)."""
+def cpu_baseline(workers, total_solves_gpu):
+    """The FP64 oracle on the host cores, on a bounded sample of the batched workload spread
+    over its schedule: sixteen seeded robots (four per quarter of the element-count range), each
+    re-solving load steps 25, 50, 75 and 100 from the oracle's own state after the previous load
+    step, at the benchmark's tolerances; one process per solve in a pool of `workers`."""
+    import glob
     import multiprocessing as mp
-    rng = np.random.default_rng([3, 7])
-    pick = sorted(rng.choice(4096, size=n_robots, replace=False).tolist())
+    files = sorted(glob.glob(os.path.join(ROOT, "tests", "golden", "bench_oracle", "robot_*.npz")))
+    if not files:
+        return None
+    jobs = [(f, q) for f in files for q in range(4)]
     ctx = mp.get_context("spawn")
     t0 = time.perf_counter()
     with ctx.Pool(workers) as pool:
-        res = pool.map(_cpu_worker, [(b, n_steps) for b in pick], chunksize=1)
+        res = pool.map(_cpu_worker, jobs, chunksize=1)
     wall = time.perf_counter() - t0
     conv = sum(r[0] for r in res)
     rate = conv / wall
-    return dict(value=rate, unit="solves/s", cores=workers, kind="oracle",
-                cpu=cpu_model(),
-                sample=f"{n_robots} seeded robots of the batched workload x {n_steps} load steps, "
-                       f"one process per robot on {workers} cores ({conv} converged solves in "
-                       f"{wall:.1f} s wall, {sum(r[1] for r in res):.0f} s CPU)",
+    return dict(value=rate, unit="solves/s", cores=workers, kind="oracle", cpu=cpu_model(),
+                sample=f"{len(files)} seeded robots of the batched workload (4 per quarter of the "
+                       f"element-count range) x load steps 25, 50, 75, 100, each re-solved from "
+                       f"the oracle's own state after the previous load step, one process per "
+                       f"solve on {workers} cores: {conv} of {len(jobs)} converged in {wall:.1f} s "
+                       f"wall ({sum(r[1] for r in res):.0f} s CPU, "
+                       f"{sum(r[2] for r in res) / len(res):.1f} Newton iterations per solve)",
                 extrapolated_batch_s=total_solves_gpu / rate if rate > 0 else None,
-                extrapolation="time the oracle would take for the batch's converged solves "
-                              "at the sample's rate (extrapolated, not measured)")
+                extrapolation="time the oracle would take for the batch's converged solves at "
+                              "the sample's rate (extrapolated, not measured)")
 
 
 def config2(args):
@@ -214,6 +234,96 @@ def config2(args):
     return out
 
 
+PHASES = ["element", "detection", "convergence+rhs", "factorisation", "substitution", "schur+lcp+step"]
+
+
+def contact_sweep(args, n_nodes=(100, 200, 300, 400), per_size=2):
+    """Time per Newton iteration against the number of active contacts, per phase, for single
+    robots of 100/200/300/400 nodes (the speed claim of Sec. IV-A: how the cost of the
+    element update, the factorisation and the contact solve grows with the contact count).
+
+    Each robot (L = 0.6 m, shaft + tube tip, tensions and base frame of a robot of the
+    batched workload, inserted 0.5 m over 100 load steps into the 50k-triangle lumen) runs in
+    a context of its own in plain FP64 with HIP events around every kernel class; per load
+    step the phase times divided by its Newton iterations give the time per iteration, binned
+    by the active contacts (force > 0) at the end of that load step."""
+    from paper_2503_06922_amd import fem
+    from workloads import make_config, schedule_table
+    rb3, V, T = make_config(3)
+    edges = [0, 1, 6, 11, 21, 31, 41, 61, 10 ** 9]
+    out = {"unit": "ms per Newton iteration", "phases": PHASES, "bins_active_contacts": edges[:-1],
+           "sizes": {}}
+    for nn in n_nodes:
+        rows = []
+        for j in range(per_size):
+            sub = rb3.subset([j])
+            sub.n_elem = np.array([nn - 1], np.int32)
+            sub.depth = np.array([0.5])
+            vals, deps = schedule_table(sub, 100)
+            ctx = fem.Context(fem.params_from_batch(sub, precision=fem.FEM_FP64, newton_tol=1e-10,
+                                                    stag_tol=1e-9, max_newton=args.max_newton,
+                                                    contact_capacity=args.capacity, profile=1))
+            ctx.fem_set_lumen(V, T)
+            for k in range(6):
+                ctx.fem_profile(k, reset=True)
+            for k in range(100):
+                ctx.fem_set_actuation(0, vals[k].ravel(), deps[k])
+                o = ctx.fem_solve(1, state=False)
+                it = o["info"][0]["iters"]
+                ms = [ctx.fem_profile(c, reset=True)[0] for c in range(6)]
+                n_act = sum(1 for c in ctx.fem_contacts(0) if c["force"] > 0)
+                if it > 0 and o["info"][0]["status"] == 0:
+                    # element update, detection and convergence test run once more than the
+                    # Newton steps (the final check of the load step)
+                    rows.append((n_act, [m / (it + 1) for m in ms[:3]] + [m / it for m in ms[3:]]))
+            ctx.close()
+        bins = []
+        for lo, hi in zip(edges[:-1], edges[1:]):
+            sel = [r[1] for r in rows if lo <= r[0] < hi]
+            if sel:
+                bins.append([lo, len(sel)] + [float("%.4g" % v) for v in np.mean(sel, axis=0)])
+        out["sizes"][str(nn)] = bins
+    out["columns"] = ["active_contacts_from", "load_steps"] + PHASES
+    return out
+
+
+def qp_variants(args):
+    """The linear step's QP solved exactly (Schur complement + LCP) and by the paper's OSQP
+    iteration (qp_solver = FEM_QP_ADMM, rho = 1 N/m, tolerance 1e-11) at the same Newton
+    tolerance (1e-10 N): the straight-tube robot through its 20-step tension ramp and two
+    robots of the batched workload through their first 12 load steps; time per Newton
+    iteration (single-robot contexts are latency-bound), Newton and ADMM iteration counts."""
+    from paper_2503_06922_amd import fem
+    from workloads import make_config, load_schedule
+    out = {}
+    for name, cfg, pick, n_steps in (("straight tube, 20 elements", 0, None, 20),
+                                     ("batched workload robots 527 and 2767", 3, [527, 2767], 12)):
+        rb, V, T = make_config(cfg)
+        if pick is not None:
+            rb = rb.subset(pick)
+        row = {}
+        for qp, label in ((fem.FEM_QP_EXACT, "exact"), (fem.FEM_QP_ADMM, "admm")):
+            ctx = fem.Context(fem.params_from_batch(rb, newton_tol=1e-10, stag_tol=1e-9, max_newton=100,
+                                                    contact_capacity=args.capacity, qp_solver=qp,
+                                                    admm_rho=1.0, admm_eps=1e-11))
+            ctx.fem_set_lumen(V, T)
+            t_tot = 0.0
+            for k in range(1, n_steps + 1):
+                d, t = load_schedule(rb, k)
+                ctx.fem_set_actuation(0, t.ravel(), d)
+                t0 = time.perf_counter()
+                o = ctx.fem_solve(1, state=False)
+                t_tot += time.perf_counter() - t0
+            it = sum(i["iters_total"] for i in o["info"])
+            row[label] = {"ms_per_newton_iter": 1e3 * t_tot / max(it, 1), "newton_iters": it,
+                          "converged": sum(i["steps_converged"] for i in o["info"]),
+                          "admm_iters": sum(i["qp_iters_total"] for i in o["info"])}
+            ctx.close()
+        row["admm_slowdown"] = row["admm"]["ms_per_newton_iter"] / row["exact"]["ms_per_newton_iter"]
+        out[name] = row
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,15 +333,19 @@ def main():
     ap.add_argument("--load-steps", type=int, default=100)
     ap.add_argument("--max-newton", type=int, default=60)
     ap.add_argument("--capacity", type=int, default=512)
-    ap.add_argument("--cpu-robots", type=int, default=0, help="oracle sample size (0 = one per core)")
-    ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--cpu-workers", type=int, default=0, help="0 = the host's cores, at most 16")
     ap.add_argument("--single-robots", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-single", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true",
+                    help="skip the FP64 reference schedule (value then counts every converged solve)")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel timing schedule")
     ap.add_argument("--no-config2", action="store_true",
                     help="skip the 1000-element robot on the 200k-triangle lumen")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the time-per-iteration against contact count sweep")
+    ap.add_argument("--no-qp-variants", action="store_true",
+                    help="skip the exact vs ADMM linear-step comparison")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
@@ -272,6 +386,10 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     print(f"bench: timed schedules done ({dt:.1f} s)", file=sys.stderr, flush=True)
+    tb, tl, tt = ctx.fem_tuning()
+    launch_shapes = {"elem_threads_per_block": tb, "detect_lanes_per_node": tl,
+                     "tuning_us": {"elem_64_128_256": [round(float(v), 1) for v in tt[:3]],
+                                   "detect_4_8_16": [round(float(v), 1) for v in tt[3:]]}}
     info = out["info"]                      # counters of the last schedule (fem_set_state resets)
     conv = sum(i["steps_converged"] for i in info)
     total = sum(i["steps_total"] for i in info)
@@ -279,44 +397,57 @@ def main():
     st_m = out["rec_status"].cpu().numpy()
     tip_m = out["rec_tip"].cpu().numpy()
 
-    # the same schedule in plain FP64 (batched): throughput and the per-step reference tips
-    c64 = make_context(fem, rb, fem.FEM_FP64, args, V, T)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    o64 = run_schedule(c64, X0, vals, deps, records=True)
-    t64 = time.perf_counter() - t1
-    print(f"bench: FP64 schedule done ({t64:.1f} s)", file=sys.stderr, flush=True)
-    conv64 = sum(i["steps_converged"] for i in o64["info"])
-    st_64 = o64["rec_status"].cpu().numpy()
-    tip_64 = o64["rec_tip"].cpu().numpy()
-    c64.close()
-    err = np.linalg.norm(tip_m - tip_64, axis=2) / rb.length[None, :]      # [steps, robots]
-    both = (st_m == 0) & (st_64 == 0)
-    valid = both & (err <= TIP_TOL)
-    value = int(valid.sum()) * args.steps / dt
-    p50, p99, pmax = [], [], []
-    for k in range(nls):
-        e = err[k][both[k]]
-        p50.append(float(np.median(e)) if e.size else None)
-        p99.append(float(np.percentile(e, 99)) if e.size else None)
-        pmax.append(float(e.max()) if e.size else None)
-    apart = np.any(both & (err > TIP_TOL), axis=0)
-    first_apart = [int(np.argmax(both[:, b] & (err[:, b] > TIP_TOL))) + 1 for b in np.nonzero(apart)[0]]
-    tip_err = {
-        "per_step_p50": [float("%.2g" % v) if v is not None else None for v in p50],
-        "per_step_p99": [float("%.2g" % v) if v is not None else None for v in p99],
-        "per_step_max": [float("%.2g" % v) if v is not None else None for v in pmax],
-        "solves_compared": int(both.sum()), "solves_within_1e-5": int(valid.sum()),
-        "robots_ever_apart": int(apart.sum()),
-        "first_step_apart_quartiles": (np.percentile(first_apart, [25, 50, 75]).tolist()
-                                       if first_apart else None),
-    }
+    it_m = out["rec_iters"].cpu().numpy()
+    conv_it = it_m[st_m == 0]
+    iters_hist = {"bins": [0, 5, 10, 15, 20, 30, 40, 50, 60],
+                  "converged_solves": np.histogram(conv_it, bins=[0, 5, 10, 15, 20, 30, 40, 50, 60,
+                                                                  10 ** 6])[0].tolist()}
+    tip_err = None
+    fp64 = {}
+    if args.no_fp64:
+        value = conv * args.steps / dt
+    else:
+        # the same schedule in plain FP64 (batched): throughput and the per-step reference tips
+        c64 = make_context(fem, rb, fem.FEM_FP64, args, V, T)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        o64 = run_schedule(c64, X0, vals, deps, records=True)
+        t64 = time.perf_counter() - t1
+        print(f"bench: FP64 schedule done ({t64:.1f} s)", file=sys.stderr, flush=True)
+        conv64 = sum(i["steps_converged"] for i in o64["info"])
+        st_64 = o64["rec_status"].cpu().numpy()
+        tip_64 = o64["rec_tip"].cpu().numpy()
+        c64.close()
+        err = np.linalg.norm(tip_m - tip_64, axis=2) / rb.length[None, :]      # [steps, robots]
+        both = (st_m == 0) & (st_64 == 0)
+        valid = both & (err <= TIP_TOL)
+        value = int(valid.sum()) * args.steps / dt
+        p50, p99, pmax = [], [], []
+        for k in range(nls):
+            e = err[k][both[k]]
+            p50.append(float(np.median(e)) if e.size else None)
+            p99.append(float(np.percentile(e, 99)) if e.size else None)
+            pmax.append(float(e.max()) if e.size else None)
+        apart = np.any(both & (err > TIP_TOL), axis=0)
+        first_apart = [int(np.argmax(both[:, b] & (err[:, b] > TIP_TOL))) + 1 for b in np.nonzero(apart)[0]]
+        tip_err = {
+            "per_step_p50": [float("%.2g" % v) if v is not None else None for v in p50],
+            "per_step_p99": [float("%.2g" % v) if v is not None else None for v in p99],
+            "per_step_max": [float("%.2g" % v) if v is not None else None for v in pmax],
+            "solves_compared": int(both.sum()), "solves_within_1e-5": int(valid.sum()),
+            "robots_ever_apart": int(apart.sum()),
+            "first_step_apart_quartiles": (np.percentile(first_apart, [25, 50, 75]).tolist()
+                                           if first_apart else None),
+        }
+        fp64 = {"fp64_batched_solves_per_s": conv64 / t64,
+                "mixed_vs_fp64_batched": (conv * args.steps / dt) / (conv64 / t64)}
 
     res = {
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64 (f32 tangent storage + f32 detection screen)",
+        "dtype": "f64 + f32 (f32 element forces far from convergence, f32 tangent storage and "
+                 "detection screen)",
         "data": "synthetic",
         "config": {"workload": "batched insertion: %d robots x %d load steps, 50-400 elements "
                                "(Table I shaft + 70 mm tube tip), moment-only cable load (eq. 16), "
@@ -325,11 +456,15 @@ def main():
                    "robots": int(rb.n_robots), "load_steps": nls, "precision": "mixed",
                    "max_newton": args.max_newton, "contact_capacity": args.capacity,
                    "nodes": int(ctx.n_nodes)},
+        "value_basis": ("converged mixed-precision solves (no FP64 reference run)" if args.no_fp64 else
+                        "converged mixed-precision solves whose tip is within 1e-5 of the robot "
+                        "length of the FP64 batch's tip at that load step (both converged)"),
         "solves_converged_per_s": conv * args.steps / dt,
         "converged_fraction": conv / max(total, 1),
         "newton_iters_per_solve": iters / max(total, 1),
-        "fp64_batched_solves_per_s": conv64 / t64,
-        "mixed_vs_fp64_batched": (conv * args.steps / dt) / (conv64 / t64),
+        "newton_iters_histogram": iters_hist,
+        "launch_shapes": launch_shapes,
+        **fp64,
         "tip_err_mixed_vs_fp64": tip_err,
     }
 
@@ -390,10 +525,15 @@ def main():
     if not args.no_config2:
         res["config2"] = config2(args)
         print("bench: 1000-element robot done", file=sys.stderr, flush=True)
+    if not args.no_sweep:
+        res["contact_sweep"] = contact_sweep(args)
+        print("bench: contact sweep done", file=sys.stderr, flush=True)
+    if not args.no_qp_variants:
+        res["qp_variants"] = qp_variants(args)
+        print("bench: QP variants done", file=sys.stderr, flush=True)
     if not args.no_cpu:
         workers = args.cpu_workers or min(16, os.cpu_count() or 1)
-        n_cpu = args.cpu_robots or workers
-        res["cpu_baseline"] = cpu_baseline(n_cpu, min(args.cpu_steps, nls), workers, conv)
+        res["cpu_baseline"] = cpu_baseline(workers, conv)
         print("bench: oracle sample done", file=sys.stderr, flush=True)
     print(json.dumps(res), flush=True)
 

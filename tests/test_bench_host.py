@@ -21,7 +21,7 @@ def test_traffic_records_are_used_only_for_their_sources_and_capacity():
     import bench
     with open(os.path.join(ROOT, "profiles", "hbm_traffic.json")) as f:
         rec = json.load(f)
-    assert set(rec) == {"elem_kernel", "factor_kernel", "subst_kernel"}
+    assert {"elem_kernel", "factor_kernel", "subst_kernel"} <= set(rec)
     for k, v in rec.items():
         cap = v["contact_capacity"]
         current = bench.traffic_key(k, cap) == v["key_sha256"]
