@@ -38,16 +38,18 @@ HBM_PEAK_GBS = 8000.0
 TIP_TOL = 1e-5
 
 KERNELS = ["elem_kernel", "collide_kernel", "check_rhs_kernel", "factor_kernel", "subst_kernel",
-           "update_kernel"]
+           "update_kernel", "step_solve_kernel"]
 KERNEL_SOURCE = {"elem_kernel": "elem.hip", "collide_kernel": "collide.hip", "check_rhs_kernel": "solve.hip",
-                 "factor_kernel": "solve.hip", "subst_kernel": "solve.hip", "update_kernel": "solve.hip"}
+                 "factor_kernel": "solve.hip", "subst_kernel": "solve.hip", "update_kernel": "solve.hip",
+                 "step_solve_kernel": "solve.hip"}
 
 
 def launch_units(info, n_nodes):
     """Work units of one schedule, summed over robots: node-iterations of the element update
     (every pass of a load step, the final check included), free node-steps of the Newton step
     (one per Newton iteration and free node), free-node right-hand sides, those swept forward
-    inside the factorisation, and free-node substitution passes."""
+    inside the factorisation, free-node substitution passes (Newton steps with contacts only),
+    and the contact products the substitution writes."""
     free = [int(n) - 1 for n in n_nodes]
     return dict(
         elem_node_iters=sum((i["iters_total"] + i["steps_total"]) * int(n_nodes[b]) for b, i in enumerate(info)),
@@ -55,6 +57,13 @@ def launch_units(info, n_nodes):
         free_node_rhs=sum(i["rhs_total"] * free[b] for b, i in enumerate(info)),
         free_node_rhs_fused=sum(i["rhs_fused"] * free[b] for b, i in enumerate(info)),
         free_node_passes=sum(i["sweep_passes"] * free[b] for b, i in enumerate(info)),
+        contact_products=sum(i["products_total"] for i in info),
+        free_node_steps_with_contacts=sum(i["contact_steps_total"] * free[b] for b, i in enumerate(info)),
+        # a Newton step without contacts has the one right-hand side b, swept in the factorisation
+        free_node_rhs_with_contacts=sum((i["rhs_total"] - i["iters_total"] + i["contact_steps_total"]) * free[b]
+                                        for b, i in enumerate(info)),
+        free_node_rhs_fused_with_contacts=sum((i["rhs_fused"] - i["iters_total"] + i["contact_steps_total"])
+                                              * free[b] for b, i in enumerate(info)),
     )
 
 
@@ -66,27 +75,40 @@ def byte_models(u, sb):
     blocks D (21) and S (36) in the element precision, 560 B (FP64) / 280 B (FP32) per node;
     the block Cholesky reads and writes the 57 unique block values per free node (912 B);
     the multi-right-hand-side solve reads L twice per free node, shared by all right-hand
-    sides of the step (912 B).
+    sides of the step (912 B); so does the step's own solve after the LCP.
     "design": what this design's kernels must move: the element update writes the chord
     direction (3 x sb) instead of D and S; the factorisation reads the element (3 x sb + 6
     FP64 constants) and column 0's right-hand side and writes L[i,i] and the coupling block,
-    plus 6 FP64 of forward values per node for each of the first 64 right-hand sides; the
-    substitution reads L per pass of 64 right-hand sides and reads y / writes x per node and
-    right-hand side (plus the forward values of those beyond the first 64).
+    plus a checkpoint of 6 FP64 forward values per 6 nodes (8 B per node) for each of the first
+    64 right-hand sides; the substitution stages L[i,i] and 7/6 coupling blocks per node and
+    pass of 64 right-hand sides (624 B), reads column 0's right-hand side once per step (48 B),
+    reads the checkpoints of every right-hand side (8 B per node), sweeps the right-hand sides
+    beyond the first 64 forward (L[i,i] and the coupling block, 576 B per node and pass, and
+    8 B of checkpoints per node and right-hand side) and writes 8 B per contact product (an
+    upper bound: the backward sweeps stop at the outermost contact nodes).
     Returns {kernel: {"scope": (bytes_per_unit, unit, total), "design": (...)}}."""
     el_scope = 8 * (7 + 6) + (21 + 36) * (8 if sb == 8 else 4)
     el_design = 8 * (7 + 6) + 3 * sb
     fa_design = 3 * sb + 8 * 6 + 8 * (21 + 36) + 8 * 6
+    extra_passes = u["free_node_passes"] - u["free_node_steps_with_contacts"]   # beyond the first
     return {
         "elem_kernel": {"scope": (el_scope, "node-iteration", el_scope * u["elem_node_iters"]),
                         "design": (el_design, "node-iteration", el_design * u["elem_node_iters"])},
         "factor_kernel": {"scope": (912, "free node-step", 912 * u["free_node_steps"]),
-                          "design": ([fa_design, 48], "free node-step, fused rhs",
-                                     fa_design * u["free_node_steps"] + 48 * u["free_node_rhs_fused"])},
+                          "design": ([fa_design, 8], "free node-step, fused rhs",
+                                     fa_design * u["free_node_steps"] + 8 * u["free_node_rhs_fused"])},
         "subst_kernel": {"scope": (912, "free node-step", 912 * u["free_node_steps"]),
-                         "design": ([456, 96, 48], "free node-pass, node-rhs, node-rhs beyond 64",
-                                    456 * u["free_node_passes"] + 96 * u["free_node_rhs"]
-                                    + 48 * (u["free_node_rhs"] - u["free_node_rhs_fused"]))},
+                         "design": ([624, 48, 8, 576, 8, 8],
+                                    "free node-pass, node-step with contacts, node-rhs, node-pass "
+                                    "beyond the first, node-rhs beyond 64, contact product",
+                                    624 * u["free_node_passes"] + 48 * u["free_node_steps_with_contacts"]
+                                    + 8 * u["free_node_rhs_with_contacts"] + 576 * extra_passes
+                                    + 8 * (u["free_node_rhs_with_contacts"] - u["free_node_rhs_fused_with_contacts"])
+                                    + 8 * u["contact_products"])},
+        # forward and backward: the coupling block and the rows of L[i,i] (288 B each, whole
+        # cache lines), the vector read and written (48 B each), per free node-step
+        "step_solve_kernel": {"scope": (912, "free node-step", 912 * u["free_node_steps"]),
+                              "design": (1344, "free node-step", 1344 * u["free_node_steps"])},
     }
 
 
@@ -234,7 +256,7 @@ def config2(args):
     return out
 
 
-PHASES = ["element", "detection", "convergence+rhs", "factorisation", "substitution", "schur+lcp+step"]
+PHASES = ["element", "detection", "convergence+rhs", "factorisation", "substitution", "lcp", "step"]
 
 
 def contact_sweep(args, n_nodes=(100, 200, 300, 400), per_size=2):
@@ -264,13 +286,13 @@ def contact_sweep(args, n_nodes=(100, 200, 300, 400), per_size=2):
                                                     stag_tol=1e-9, max_newton=args.max_newton,
                                                     contact_capacity=args.capacity, profile=1))
             ctx.fem_set_lumen(V, T)
-            for k in range(6):
+            for k in range(len(KERNELS)):
                 ctx.fem_profile(k, reset=True)
             for k in range(100):
                 ctx.fem_set_actuation(0, vals[k].ravel(), deps[k])
                 o = ctx.fem_solve(1, state=False)
                 it = o["info"][0]["iters"]
-                ms = [ctx.fem_profile(c, reset=True)[0] for c in range(6)]
+                ms = [ctx.fem_profile(c, reset=True)[0] for c in range(len(KERNELS))]
                 n_act = sum(1 for c in ctx.fem_contacts(0) if c["force"] > 0)
                 if it > 0 and o["info"][0]["status"] == 0:
                     # element update, detection and convergence test run once more than the
@@ -474,11 +496,11 @@ def main():
         cp = make_context(fem, rb, fem.FEM_MIXED, args, V, T, profile=1)
         op = run_schedule(cp, X0, vals, deps)
         print("bench: profiled schedule done", file=sys.stderr, flush=True)
-        prof = [cp.fem_profile(k) for k in range(6)]
+        prof = [cp.fem_profile(k) for k in range(len(KERNELS))]
         cp.close()
         kern = {KERNELS[k]: dict(total_ms=prof[k][0], launches=prof[k][1],
-                                 avg_us=1e3 * prof[k][0] / max(prof[k][1], 1)) for k in range(6)}
-        dom = KERNELS[max(range(6), key=lambda k: prof[k][0])]
+                                 avg_us=1e3 * prof[k][0] / max(prof[k][1], 1)) for k in range(len(KERNELS))}
+        dom = KERNELS[max(range(len(KERNELS)), key=lambda k: prof[k][0])]
         n_nodes = np.asarray(rb.n_elem, np.int64) + 1
         units = launch_units(op["info"], n_nodes)
         models = byte_models(units, 4)

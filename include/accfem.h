@@ -146,8 +146,12 @@ typedef struct {
   int64_t rhs_total;        /* right-hand sides solved (1 + contacts per Newton step), same span */
   int64_t rhs_fused;        /* of those, swept forward inside the factorisation (the first 64
                                of each Newton step), same span */
-  int64_t sweep_passes;     /* substitution passes of 64 right-hand sides, same span */
+  int64_t sweep_passes;     /* substitution passes of 64 right-hand sides (none for a Newton
+                               step without contacts), same span */
   int64_t qp_iters_total;   /* FEM_QP_ADMM iterations, same span (0 for FEM_QP_EXACT) */
+  int64_t products_total;   /* contact products n_i . x formed by the substitution, (1 +
+                               contacts) x contacts per Newton step, same span */
+  int64_t contact_steps_total; /* Newton steps with at least one contact, same span */
 } fem_solve_info;
 
 typedef struct {
@@ -287,9 +291,9 @@ fem_status fem_eval(fem_ctx* c, double* F, double* KD, double* KS);
 
 /* Measurement, not part of the method.  Kernel timing of a context created with
  * profile = 1: for kernel class k
- * (0 = element update, 1 = contact detection, 2..5 = the Newton step's phases:
- * convergence test + right-hand sides, block Cholesky, substitutions, contact
- * Schur complement + LCP + update) the
+ * (0 = element update, 1 = contact detection, 2..6 = the Newton step's phases:
+ * convergence test + right-hand sides, block Cholesky, substitutions (contact
+ * products), contact forces (LCP), step solve + state update) the
  * accumulated device time in ms measured with HIP events on the context's
  * stream, and the number of launches, since the last call with reset = 1. */
 fem_status fem_profile(fem_ctx* c, int32_t kernel, double* total_ms, int64_t* launches,

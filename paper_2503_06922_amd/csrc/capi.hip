@@ -290,8 +290,8 @@ struct fem_ctx {
   // per-kernel event timing
   bool profile = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  double prof_ms[6] = {0, 0, 0, 0, 0, 0};
-  int64_t prof_n[6] = {0, 0, 0, 0, 0, 0};
+  double prof_ms[7] = {0, 0, 0, 0, 0, 0, 0};
+  int64_t prof_n[7] = {0, 0, 0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -424,7 +424,7 @@ void launch_pass(const Dev& d, hipStream_t s) {
   hipLaunchKernelGGL(advance_kernel, dim3(nblk(d.B, 256)), dim3(256), 0, s, d);
   launch_elem(d, s);
   launch_collide(d, s);
-  for (int ph = 0; ph < 4; ++ph) launch_solve_phase(d, ph, s);
+  for (int ph = 0; ph < 5; ++ph) launch_solve_phase(d, ph, s);
 }
 
 // Run the n load steps of a call: every robot advances through them on its own (a robot whose
@@ -452,7 +452,7 @@ fem_status run_load_steps(fem_ctx* c, int n) {
         return s;
       if ((s = timed(c, xs, 0, [&] { launch_elem(d, xs); })) != FEM_OK) return s;
       if ((s = timed(c, xs, 1, [&] { launch_collide(d, xs); })) != FEM_OK) return s;
-      for (int ph = 0; ph < 4; ++ph)
+      for (int ph = 0; ph < 5; ++ph)
         if ((s = timed(c, xs, 2 + ph, [&] { launch_solve_phase(d, ph, xs); })) != FEM_OK) return s;
       HIP_TRY(c, hipGetLastError());
       ++pass;
@@ -643,6 +643,17 @@ static fem_status create_impl(fem_ctx* c, const fem_params* p) {
   d.stag_r = stag_d;
   d.off = off_d; d.robot_of = robot_of; d.l0 = l0_d; d.base_pos = bp_d; d.base_dir = bd_d;
   d.base_up = bu_d; d.guide_axis = gax_d;
+  {
+    // robots by decreasing length: the step solve runs neighbours in this order side by side
+    std::vector<int32_t> order(B);
+    for (int r = 0; r < B; ++r) order[r] = r;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return c->h_nelem[a] > c->h_nelem[b]; });
+    int32_t* order_d;
+    ALLOC(order_d, B);
+    HIP_TRY(c, hipMemcpy(order_d, order.data(), B * sizeof(int32_t), hipMemcpyHostToDevice));
+    d.solve_order = order_d;
+  }
   ALLOC(c->length_d, B);
   HIP_TRY(c, hipMemcpy(c->length_d, c->h_len.data(), B * sizeof(double), hipMemcpyHostToDevice));
   double *EA, *EI, *GJ;
@@ -689,7 +700,7 @@ static fem_status create_impl(fem_ctx* c, const fem_params* p) {
   ALLOC(d.cp_gap, BC); ALLOC(d.cp_y, BC);
   std::vector<int64_t> zoff(B);
   int64_t zt = 0;
-  for (int r = 0; r < B; ++r) { zoff[r] = zt; zt += (int64_t)(1 + cap) * 6 * (c->h_nelem[r] + 1); }
+  for (int r = 0; r < B; ++r) { zoff[r] = zt; zt += 6 * (int64_t)(c->h_nelem[r] + 1); }
   int64_t* zoff_d;
   ALLOC(zoff_d, B);
   HIP_TRY(c, hipMemcpy(zoff_d, zoff.data(), B * sizeof(int64_t), hipMemcpyHostToDevice));
@@ -697,13 +708,14 @@ static fem_status create_impl(fem_ctx* c, const fem_params* p) {
   d.zp = ((int64_t)cap + 1 + 7) / 8 * 8;
   ALLOC(d.Y, 6 * d.zp * N);
   ALLOC(d.Z, zt);
-  ALLOC(d.W, (int64_t)B * cap * cap + (int64_t)B * lcp_ws_doubles(cap));
+  ALLOC(d.XM, (int64_t)B * SOLVE_THREADS * 6);
+  ALLOC(d.W, (int64_t)B * cap * d.zp + (int64_t)B * lcp_ws_doubles(cap));
   ALLOC(d.q, BC);
   ALLOC(d.ac_idx, BC); ALLOC(d.ac_y, BC);
   ALLOC(d.st_nact, B); ALLOC(d.st_mx, B); ALLOC(d.st_big, B);
   HIP_TRY(c, hipMemset(d.st_big, 0, B * sizeof(int32_t)));
   ALLOC(d.st_status, B); ALLOC(d.st_done, B); ALLOC(d.st_nc, B); ALLOC(d.st_ncp, B);
-  ALLOC(d.st_limited, B); ALLOC(d.st_nlim, B); ALLOC(d.st_nswitch, B); ALLOC(d.st_iters, B); ALLOC(d.st_rhs, 3 * B);
+  ALLOC(d.st_limited, B); ALLOC(d.st_nlim, B); ALLOC(d.st_nswitch, B); ALLOC(d.st_iters, B); ALLOC(d.st_rhs, 5 * B);
   ALLOC(d.st_rn, B); ALLOC(d.st_rnprev, B); ALLOC(d.n_done, 1);
   ALLOC(d.st_step, B); ALLOC(d.st_it, B); ALLOC(d.st_fin, B);
   HIP_TRY(c, hipMemset(d.st_step, 0, B * sizeof(int32_t)));
@@ -728,7 +740,7 @@ static fem_status create_impl(fem_ctx* c, const fem_params* p) {
   HIP_TRY(c, hipMemset(d.st_ncp, 0, B * sizeof(int32_t)));
   HIP_TRY(c, hipMemset(d.st_nlim, 0, B * sizeof(int32_t)));
   HIP_TRY(c, hipMemset(d.st_iters, 0, B * sizeof(int32_t)));
-  HIP_TRY(c, hipMemset(d.st_rhs, 0, 3 * B * sizeof(int64_t)));
+  HIP_TRY(c, hipMemset(d.st_rhs, 0, 5 * B * sizeof(int64_t)));
   HIP_TRY(c, hipMemset(d.st_rn, 0, B * sizeof(double)));
   ALLOC(c->steps_conv, B); ALLOC(c->steps_tot, B); ALLOC(c->iters_tot, B);
   d.steps_conv = c->steps_conv; d.steps_tot = c->steps_tot; d.iters_tot = c->iters_tot;
@@ -926,7 +938,7 @@ fem_status fem_set_state(fem_ctx* c, const double* node_state) {
   HIP_TRY(c, hipMemsetAsync(c->steps_conv, 0, c->B * sizeof(int32_t), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->steps_tot, 0, c->B * sizeof(int32_t), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->iters_tot, 0, c->B * sizeof(int64_t), c->stream));
-  HIP_TRY(c, hipMemsetAsync(c->d.st_rhs, 0, 3 * c->B * sizeof(int64_t), c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d.st_rhs, 0, 5 * c->B * sizeof(int64_t), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->d.st_qpit, 0, c->B * sizeof(int64_t), c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->solved = false;
@@ -958,18 +970,20 @@ static fem_status solve_epilogue(fem_ctx* c, double* node_state, fem_solve_info*
     HIP_TRY(c, hipMemcpy(sc.data(), c->steps_conv, B * sizeof(int32_t), hipMemcpyDeviceToHost));
     HIP_TRY(c, hipMemcpy(stt.data(), c->steps_tot, B * sizeof(int32_t), hipMemcpyDeviceToHost));
     HIP_TRY(c, hipMemcpy(itt.data(), c->iters_tot, B * sizeof(int64_t), hipMemcpyDeviceToHost));
-    std::vector<int64_t> rhs(3 * B), qpit(B);
-    HIP_TRY(c, hipMemcpy(rhs.data(), d.st_rhs, 3 * B * sizeof(int64_t), hipMemcpyDeviceToHost));
+    std::vector<int64_t> rhs(5 * B), qpit(B);
+    HIP_TRY(c, hipMemcpy(rhs.data(), d.st_rhs, 5 * B * sizeof(int64_t), hipMemcpyDeviceToHost));
     HIP_TRY(c, hipMemcpy(qpit.data(), d.st_qpit, B * sizeof(int64_t), hipMemcpyDeviceToHost));
     std::vector<fem_solve_info> hi(B);
     for (int r = 0; r < B; ++r) {
       hi[r].status = st[r]; hi[r].iters = it[r]; hi[r].n_contacts = nc[r]; hi[r].n_limited = nl[r];
       hi[r].res_norm = rn[r]; hi[r].steps_converged = sc[r]; hi[r].steps_total = stt[r];
       hi[r].iters_total = itt[r];
-      hi[r].rhs_total = rhs[3 * r];
-      hi[r].rhs_fused = rhs[3 * r + 1];
-      hi[r].sweep_passes = rhs[3 * r + 2];
+      hi[r].rhs_total = rhs[5 * r];
+      hi[r].rhs_fused = rhs[5 * r + 1];
+      hi[r].sweep_passes = rhs[5 * r + 2];
       hi[r].qp_iters_total = qpit[r];
+      hi[r].products_total = rhs[5 * r + 3];
+      hi[r].contact_steps_total = rhs[5 * r + 4];
     }
     if (c->io_dev) {
       HIP_TRY(c, hipMemcpy(info, hi.data(), B * sizeof(fem_solve_info), hipMemcpyHostToDevice));
@@ -1135,7 +1149,7 @@ fem_status fem_grad(fem_ctx* c, const int32_t* sensor_nodes, int32_t n_sensors,
 fem_status fem_profile(fem_ctx* c, int32_t kernel, double* total_ms, int64_t* launches,
                        int32_t reset) {
   if (!c) return FEM_E_INVAL;
-  if (kernel < 0 || kernel > 5) return fail(c, FEM_E_INVAL, "kernel class must be 0..5");
+  if (kernel < 0 || kernel > 6) return fail(c, FEM_E_INVAL, "kernel class must be 0..6");
   if (!c->profile) return fail(c, FEM_E_STATE, "context was created without profile = 1");
   if (total_ms) *total_ms = c->prof_ms[kernel];
   if (launches) *launches = c->prof_n[kernel];

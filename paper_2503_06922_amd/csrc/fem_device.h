@@ -42,6 +42,7 @@ struct Dev {
   const double* base_dir;  // [3B] unit
   const double* base_up;   // [3B]
   const int32_t* guide_axis;  // [B] coordinate axis of base_dir, -1 if not axis aligned
+  const int32_t* solve_order; // [B] robots by decreasing number of elements
   // element rigidities
   double* EA;
   double* EI;
@@ -104,16 +105,22 @@ struct Dev {
   double* cp_n;
   double* cp_gap;
   double* cp_y;
-  // solutions: robot r owns Z[zoff[r] .. zoff[r] + (1+cap)*6*N_r), column-major: column c
-  // (0 = the free increment, 1 + j = contact j) at zoff[r] + c*6*N_r, row 6 f + k of free node f
+  // right-hand side and step: robot r owns Z[zoff[r] .. zoff[r] + 6*N_r), row 6 f + k of free
+  // node f: the right-hand side b of the linear step (check_rhs_kernel), then the step dx
   const int64_t* zoff;
   double* Z;
-  // forward-swept values of every column, node-major: row 6 f + k of robot r is the zp
-  // doubles at Y + (6 off[r] + 6 f + k) * zp, one per column, so that a wavefront's columns
-  // are contiguous (column 0's right-hand side itself is written to Z's column 0)
+  // forward-swept values of the right-hand-side columns (0 = b, 1 + j = contact j) at the
+  // checkpoint nodes of the substitution, node-major: row 6 f + k of robot r is the zp doubles
+  // at Y + (6 off[r] + 6 f + k) * zp, one per column, so that a wavefront's columns are
+  // contiguous
   double* Y;
   int64_t zp;
-  double* W;          // [B*cap*cap]
+  double* XM;         // [B*SOLVE_THREADS*6] middle node's solution of the columns swept
+                      // forward inside the factorisation
+  // contact products: row i of robot r is the zp doubles at W + (r*cap + i)*zp, column 0 =
+  // n_i . dx_free(node of i), column 1 + j = n_i . Z_j(node of i), Z_j = K^-1 A^T e_j; then
+  // the wide LCP's per-robot workspaces (lcp_ws_doubles(cap) each)
+  double* W;
   double* q;          // [B*cap]
   int32_t* ac_idx;    // [B*cap] contacts with force > 0 after the LCP, in index order ...
   double* ac_y;       // ... and their forces
@@ -129,8 +136,9 @@ struct Dev {
   int32_t* st_nact;     // active contacts of the current step
   int32_t* st_big;      // the wide LCP's active set outgrew its LDS factor this iteration
   unsigned long long* st_mx;  // largest node translation of the step (bits of a double >= 0)
-  int64_t* st_rhs;      // [3B] right-hand sides, those swept forward in the factorisation, and
-                        // substitution passes, since creation / the last state reset
+  int64_t* st_rhs;      // [5B] right-hand sides, those swept forward in the factorisation,
+                        // passes of the substitution, contact products it forms and Newton
+                        // steps with contacts, since creation / the last state reset
   double* st_rn;        // residual norm at the last check
   double* st_rnprev;
   int32_t* n_done;      // [1] robots that finished every load step of the current call
@@ -161,6 +169,11 @@ struct Dev {
   int coll_lanes;           // lanes per node in contact detection: 4, 8 or 16
   int elem_block;           // threads per block of the element update: 64, 128 or 256
 };
+
+// the wide LCP's workspace of robot r (after every robot's contact products)
+__device__ __forceinline__ double* lcp_ws(const Dev& d, int r) {
+  return d.W + (int64_t)d.B * d.cap * d.zp + (int64_t)r * lcp_ws_doubles(d.cap);
+}
 
 // ------------------------------------------------------------------ vectors
 struct V3 { double x, y, z; };

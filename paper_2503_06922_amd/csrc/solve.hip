@@ -10,10 +10,12 @@
 // K = L L^T (6x6 blocks, serial over nodes), dx_free = -K^-1 r, Z = K^-1 A^T,
 // W = A Z (SPD) and q = g + A dx_free, the contact forces solve LCP(q, W); the
 // primal active-set method used here (Lawson-Hanson style, with a dense
-// Cholesky of the active block) terminates finitely for SPD W.  Then
-// dx = dx_free + Z y, and if max_i |dp_i| > beta the step and y are scaled by
-// beta / max_i |dp_i| (eq. 25-27), beta = beta0 halved every 10 contact-set
-// changes within the load step (down to beta0/64).
+// Cholesky of the active block) terminates finitely for SPD W.  Only the values of
+// dx_free and Z at the contact nodes are needed for W and q: the substitution keeps the
+// products n_i . (column)(node of i) and never stores whole columns.  Then
+// dx = K^-1 (-r + A^T y) = dx_free + Z y by one more solve, and if max_i |dp_i| > beta the
+// step and y are scaled by beta / max_i |dp_i| (eq. 25-27), beta = beta0 halved every 10
+// contact-set changes within the load step (down to beta0/64).
 //
 // Convergence (checked at the start of the next iteration, after the state
 // update, element update and detection): residual F - A_prev^T y_prev over the
@@ -30,7 +32,15 @@ constexpr int CH = 16;                     // nodes per staged chunk
 constexpr int PF = (CH * 36 + NT - 1) / NT;  // prefetch registers per lane and array
 constexpr int CHF = 32;                    // nodes per staged chunk of the factorisation sweep
 constexpr int CHS = 6;                     // chunk of the substitution sweeps (register budget)
-constexpr int PFS = (CHS * 36 + NT - 1) / NT;
+constexpr int PFS = ((CHS + 1) * 36 + NT - 1) / NT;
+
+// Forward values are stored at checkpoint nodes only: the base side's sweep (ascending f)
+// keeps the last node of every CHS-aligned chunk, the tip side's (descending f) the first, so
+// that a backward sweep recomputes a chunk's forward values from the checkpoint before it
+// with the factor blocks it stages anyway.
+__device__ __forceinline__ bool checkpoint_node(bool tip_side, int64_t f) {
+  return tip_side ? (f % CHS) == 0 : (f % CHS) == CHS - 1;
+}
 
 __device__ __forceinline__ double warp_sum(double v) {
 #pragma unroll
@@ -219,9 +229,13 @@ __global__ void __launch_bounds__(NT) check_rhs_kernel(Dev d) {
   }
   __syncthreads();
   if (lane == 0) {
-    d.st_rhs[3 * r] += 1 + nc;                      // right-hand sides
-    d.st_rhs[3 * r + 1] += min(1 + nc, NT);         // forward-swept inside the factorisation
-    d.st_rhs[3 * r + 2] += (1 + nc + NT - 1) / NT;  // column passes of the substitution
+    d.st_rhs[5 * r] += 1 + nc;                      // right-hand sides
+    d.st_rhs[5 * r + 1] += min(1 + nc, NT);         // forward-swept inside the factorisation
+    // column passes of the substitution and the contact products they form (none without
+    // contacts), and the steps with contacts
+    d.st_rhs[5 * r + 2] += nc > 0 ? (1 + nc + NT - 1) / NT : 0;
+    d.st_rhs[5 * r + 3] += (int64_t)(1 + nc) * nc;
+    d.st_rhs[5 * r + 4] += nc > 0 ? 1 : 0;
   }
 
   // ---------------------------------------------------------------- right-hand side
@@ -324,10 +338,10 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 // The factoring wave also puts L_ii and X into small LDS rings; between the same two barriers
 // of step k, its side's forward wave (one lane per right-hand side) takes step k-1,
 // y = L_ii^-1 (b - X_prev y_prev), from the rings, reading b of column 0 from Z and generating
-// the contact columns (n_c at the contact node), and writes y to Y.  At the middle node the
-// forward values of both sides meet: z_m = L_m^-1 (b_m - X_top y_top - X_bot y_bot), and the
-// middle node's solution x_m = L_m^-T z_m goes to Z, where the substitution starts both sides'
-// backward sweeps.
+// the contact columns (n_c at the contact node), and keeps y at the checkpoint nodes in Y.
+// At the middle node the forward values of both sides meet: z_m = L_m^-1 (b_m - X_top y_top -
+// X_bot y_bot), and the middle node's solution x_m = L_m^-T z_m goes to XM, where the
+// substitution starts both sides' backward sweeps.
 __global__ void __launch_bounds__(4 * NT) __attribute__((amdgpu_waves_per_eu(3))) factor_kernel(Dev d) {
   const int r = blockIdx.x;
   const int w = threadIdx.x / NT, lane = threadIdx.x % NT;
@@ -417,7 +431,7 @@ __global__ void __launch_bounds__(4 * NT) __attribute__((amdgpu_waves_per_eu(3))
 #pragma unroll
       for (int p = q + 1; p < 6; ++p) bv[p] -= Ld[p * 6 + q] * y;
     }
-    if (col) {
+    if (col && checkpoint_node(sd == 1, j)) {
 #pragma unroll
       for (int q = 0; q < 6; ++q) z[(6 * j + q) * zp] = yp[q];
     }
@@ -610,7 +624,7 @@ __global__ void __launch_bounds__(4 * NT) __attribute__((amdgpu_waves_per_eu(3))
       for (int p = 0; p < q; ++p) bv[p] -= sLm[q * 6 + p] * x;
     }
     if (col) {
-      double* zx = d.Z + d.zoff[r] + (int64_t)lane * (6 * n) + 6 * m;
+      double* zx = d.XM + ((int64_t)r * NT + lane) * 6;
 #pragma unroll
       for (int q = 0; q < 6; ++q) zx[q] = xm[q];
     }
@@ -620,65 +634,165 @@ __global__ void __launch_bounds__(4 * NT) __attribute__((amdgpu_waves_per_eu(3))
   if (s_fail) finish(d, r, 3, d.st_it[r], d.st_rn[r]);
 }
 
-// phase 3: substitution of all right-hand sides with the two-ended factor of phase 2.
-// One lane per right-hand side (column c of Z), each lane holding its column's 6-vector.
-// Backward sweeps run from the middle node outwards: on the base side x_f = L_f^-T (y_f -
-// X_f^T x_{f+1}) for f = m-1 .. 0, on the tip side x_f = L_f^-T (y_f - X_f^T x_{f-1}) for
-// f = m+1 .. nf-1 (X_f, the block stored with node f, couples it towards the middle), starting
-// from the middle node's x_m.  Per chunk of CHS nodes (aligned at multiples of CHS) the factor
-// blocks are staged through LDS (broadcast to all lanes), the next chunk's blocks in flight in
-// registers meanwhile; the lanes' forward values (Y, node-major: one contiguous row segment per
-// wavefront load) are double-buffered in registers; the solutions go to Z (column-major).
+// phase 3: substitution of all right-hand sides with the two-ended factor of phase 2, kept
+// only where the LCP needs it: the contact products W[i, c] = n_i . x_c(node of i) of every
+// column c (column 0 = the free increment dx_free, 1 + j = Z_j = K^-1 A^T e_j).
+// One lane per right-hand side, each lane holding its column's 6-vector.  Backward sweeps run
+// from the middle node outwards: on the base side x_f = L_f^-T (y_f - X_f^T x_{f+1}) for f =
+// m-1 .. f_lo, on the tip side x_f = L_f^-T (y_f - X_f^T x_{f-1}) for f = m+1 .. f_hi (X_f, the
+// block stored with node f, couples it towards the middle; f_lo and f_hi are the outermost
+// contact nodes, beyond which no product is needed), starting from the middle node's x_m.
+// Per chunk of CHS nodes (aligned at multiples of CHS) the factor blocks are staged through
+// LDS (broadcast to all lanes), the next chunk's blocks in flight in registers meanwhile; the
+// chunk's forward values are recomputed from the checkpoint before it (b of column 0 read
+// from Z, the contact columns generated), then swept back, and at each contact node the
+// lanes write that contact's row of products (contiguous over the wavefront's columns).
 // One block per robot and pass of NT columns, one wavefront per side.  The first NT columns
 // were swept forward in phase 2, which also wrote x_m: their block only sweeps back.  Columns
 // from NT on are contact columns (n_c at the contact node, zero elsewhere): their block sweeps
 // them forward (generating the right-hand side, over the part of each side that the contact
-// node reaches), combines the two sides at the middle node, then sweeps back.
+// node reaches, keeping the checkpoints), combines the two sides at the middle node, then
+// sweeps back.
 
-// chunks of CHS nodes (aligned at multiples of CHS) that a side's sweep from f_begin visits
-__device__ __forceinline__ int64_t side_chunks(bool up, int64_t f_begin, int64_t nf) {
-  if (up) return f_begin >= nf ? 0 : (nf - 1) / CHS - f_begin / CHS + 1;
-  return f_begin < 0 ? 0 : f_begin / CHS + 1;
+// chunks of CHS nodes (aligned at multiples of CHS) between nodes f_a <= f_b, 0 if f_a > f_b
+__device__ __forceinline__ int64_t chunk_span(int64_t f_a, int64_t f_b) {
+  return f_a > f_b ? 0 : f_b / CHS - f_a / CHS + 1;
 }
 
-// backward sweep of one side; UP: f = f_begin .. nf-1 ascending (tip side), else f = f_begin
-// .. 0 descending (base side); ylo..yhi: nodes whose forward value is stored (zero elsewhere).
-// Every wavefront of the block must pass the same `trips` (>= this side's chunk count).
+// first index of the robot's contact list (sorted by node) whose free node is >= f
+__device__ __forceinline__ int first_contact_at(const int32_t* node, int nc, int64_t f) {
+  int lo = 0, hi = nc;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if ((int64_t)node[mid] - 1 < f) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// the lane's column: right-hand side generation and the contact rows it writes
+struct SweepCol {
+  bool act;               // the lane holds a column
+  bool col0;              // column 0: right-hand side b from Z
+  int c;                  // column index
+  int64_t fcn;            // contact column: its contact's free node
+  double cn0, cn1, cn2;   // and normal
+  const double* zb;       // column 0's b (Z), NULL in blocks without column 0
+  const double* yv;       // the column in Y (checkpoints)
+  int64_t zp;
+  const int32_t* node;    // the robot's contact list
+  const double* nrm;
+  double* W;              // the robot's rows of contact products
+  int nc;
+};
+
+// the contact rows at free node f: W[i, c] = n_i . x (translations), contacts i in sweep order
 template <bool UP>
-__device__ void bwd_side(const Dev& d, int64_t o, int64_t nf, int64_t f_begin, double* z,
-                         const double* yv, int64_t zp, bool act, int64_t ylo, int64_t yhi,
-                         double (&xn)[6], double* sKD, double* sKS, int64_t trips) {
+__device__ __forceinline__ void write_rows(const SweepCol& sc, int64_t f, int& ci, const double (&x)[6]) {
+  if (UP) {
+    while (ci < sc.nc && (int64_t)sc.node[ci] - 1 == f) {
+      if (sc.act)
+        sc.W[(int64_t)ci * sc.zp + sc.c] = sc.nrm[3 * ci] * x[0] + sc.nrm[3 * ci + 1] * x[1] +
+                                           sc.nrm[3 * ci + 2] * x[2];
+      ++ci;
+    }
+  } else {
+    while (ci >= 0 && (int64_t)sc.node[ci] - 1 == f) {
+      if (sc.act)
+        sc.W[(int64_t)ci * sc.zp + sc.c] = sc.nrm[3 * ci] * x[0] + sc.nrm[3 * ci + 1] * x[1] +
+                                           sc.nrm[3 * ci + 2] * x[2];
+      --ci;
+    }
+  }
+}
+
+// backward sweep of one side; UP: f = f_begin .. f_end ascending (tip side), else f = f_begin ..
+// f_end descending (base side).  ci: the first contact the side meets (tip side: the first at
+// a node >= f_begin; base side: the last at a node <= f_begin).  Every wavefront of the block
+// must pass the same `trips` (>= this side's chunk count).  sB: LDS for column 0's right-hand
+// side of a chunk (CHS * 6 doubles).
+template <bool UP>
+__device__ void bwd_side(const Dev& d, int64_t o, int64_t nf, int64_t f_begin, int64_t f_end,
+                         const SweepCol& sc, int ci, double (&xn)[6], double* sKD, double* sKS,
+                         double* sB, int64_t trips) {
   const int lane = threadIdx.x % NT;
-  double pd[PFS], ps[PFS];
+  // staged per chunk [f0, f0 + CHS): LD of its nodes at u = 0..CHS-1, LS of nodes f0 - 1 + u
+  // (base side) or f0 + u (tip side) at u = 0..CHS (the forward sweep's coupling to the
+  // previous node and the backward sweep's coupling towards the middle), column 0's b
+  double pd[PFS], ps[PFS], pb;
   auto stageK = [&]() {
 #pragma unroll
     for (int u = 0; u < PFS; ++u) { sKD[lane + u * NT] = pd[u]; sKS[lane + u * NT] = ps[u]; }
+    if (lane < CHS * 6) sB[lane] = pb;
   };
-  auto fetchK = [&](int64_t f0) {        // LD and LS of nodes f0 .. f0+CHS-1 (within the robot)
-    const int64_t cnt = min((int64_t)CHS, nf - f0) * 36;
-    const double* ldp = d.LD + (o + 1 + f0) * 36;
-    const double* lsp = d.LS + (o + 1 + f0) * 36;
+  auto fetchK = [&](int64_t ch) {
+    const int64_t f0 = ch * CHS;
+    const int64_t s0 = UP ? f0 : f0 - 1;             // first node of the LS blocks
 #pragma unroll
     for (int u = 0; u < PFS; ++u) {
       const int64_t idx = lane + (int64_t)u * NT;
-      pd[u] = idx < cnt ? ldp[idx] : 0.0;
-      ps[u] = idx < cnt ? lsp[idx] : 0.0;
+      const int64_t fd = f0 + idx / 36, fs = s0 + idx / 36;
+      pd[u] = (idx < CHS * 36 && fd < nf) ? d.LD[(o + 1 + fd) * 36 + idx % 36] : 0.0;
+      ps[u] = (idx < (CHS + 1) * 36 && fs >= 0 && fs < nf) ? d.LS[(o + 1 + fs) * 36 + idx % 36] : 0.0;
     }
+    pb = (sc.zb && lane < CHS * 6 && f0 + lane / 6 < nf) ? sc.zb[6 * f0 + lane] : 0.0;
   };
-  auto loadZ = [&](double (&zz)[CHS * 6], int64_t f0) {
+  // the lane's forward value at the checkpoint before chunk ch (zero before its contact node)
+  auto loadCk = [&](double (&cp)[6], int64_t ch) {
+    const int64_t f0 = ch * CHS;
+    const int64_t cpn = UP ? f0 + CHS : f0 - 1;
+    const bool valid = sc.act && cpn >= 0 && cpn < nf &&
+                       (sc.col0 || (UP ? cpn <= sc.fcn : cpn >= sc.fcn));
 #pragma unroll
-    for (int u = 0; u < CHS; ++u)
+    for (int k = 0; k < 6; ++k) cp[k] = valid ? sc.yv[(6 * cpn + k) * sc.zp] : 0.0;
+  };
+  double zz[CHS * 6];                               // the chunk's forward values
+  // forward values of the chunk's nodes on this side from the checkpoint
+  auto recompute = [&](const double (&cp)[6], int64_t ch) {
+    const int64_t f0 = ch * CHS;
+    double yp[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) yp[k] = cp[k];
+    auto fnode = [&](int u, int us, int64_t f) {    // us: staged LS index of the previous node
+      double bv[6];
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
-        const int64_t f = f0 + u;
-        zz[u * 6 + k] = (act && f < nf && f >= ylo && f <= yhi) ? yv[(6 * f + k) * zp] : 0.0;
+        double g = (sc.act && f == sc.fcn && k < 3) ? (k == 0 ? sc.cn0 : (k == 1 ? sc.cn1 : sc.cn2)) : 0.0;
+        bv[k] = sc.col0 ? sB[u * 6 + k] : g;
       }
+      const double* Ls = sKS + us * 36;
+#pragma unroll
+      for (int p = 0; p < 6; ++p)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) bv[p] -= Ls[p * 6 + k] * yp[k];
+      const double* Ld = sKD + u * 36;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        const double y = bv[k] * Ld[k * 7];
+        yp[k] = y;
+        zz[u * 6 + k] = y;
+#pragma unroll
+        for (int p = k + 1; p < 6; ++p) bv[p] -= Ld[p * 6 + k] * y;
+      }
+    };
+    if (UP) {
+#pragma unroll
+      for (int u = CHS - 1; u >= 0; --u) {
+        const int64_t f = f0 + u;
+        if (f < nf && f >= f_begin) fnode(u, u + 1, f);
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < CHS; ++u) {
+        const int64_t f = f0 + u;
+        if (f <= f_begin) fnode(u, u, f);
+      }
+    }
   };
-  auto node = [&](const double (&zz)[CHS * 6], int u, int64_t f) {
+  auto bnode = [&](int u, int us, int64_t f) {
     double bv[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) bv[k] = zz[u * 6 + k];
-    const double* Ls = sKS + u * 36;                      // X_f: b -= X_f^T x_neighbour
+    const double* Ls = sKS + us * 36;                      // X_f: b -= X_f^T x_neighbour
 #pragma unroll
     for (int k = 0; k < 6; ++k)
 #pragma unroll
@@ -691,58 +805,58 @@ __device__ void bwd_side(const Dev& d, int64_t o, int64_t nf, int64_t f_begin, d
 #pragma unroll
       for (int p = 0; p < k; ++p) bv[p] -= Ld[k * 6 + p] * x;
     }
-    if (act) {
-#pragma unroll
-      for (int k = 0; k < 6; ++k) z[6 * f + k] = xn[k];
-    }
+    write_rows<UP>(sc, f, ci, xn);
   };
-  // chunk of CHS nodes with index ch covers f in [ch*CHS, ch*CHS + CHS) intersected with the side
-  auto chunk = [&](const double (&zz)[CHS * 6], int64_t ch) {
+  auto backward = [&](int64_t ch) {
     const int64_t f0 = ch * CHS;
     if (UP) {
 #pragma unroll
       for (int u = 0; u < CHS; ++u) {
         const int64_t f = f0 + u;
-        if (f >= f_begin && f < nf) node(zz, u, f);
+        if (f >= f_begin && f <= f_end) bnode(u, u, f);
       }
     } else {
 #pragma unroll
       for (int u = CHS - 1; u >= 0; --u) {
         const int64_t f = f0 + u;
-        if (f <= f_begin && f >= 0) node(zz, u, f);
+        if (f <= f_begin && f >= f_end) bnode(u, u + 1, f);
       }
     }
   };
-  // chunk trips: this side's chunks (first = the one holding f_begin, towards the end), then idle
-  // trips up to `trips` (the other side's count in a two-wavefront block) with the same barriers
-  const int64_t mine = side_chunks(UP, f_begin, nf);
-  const int64_t ch_first = mine > 0 ? f_begin / CHS : 0;
+  const int64_t mine = UP ? chunk_span(f_begin, f_end) : chunk_span(f_end, f_begin);
+  const int64_t ch_first = f_begin / CHS;
   const int64_t step = UP ? 1 : -1;
-  double za[CHS * 6], zb[CHS * 6];
+  double ca[6], cb2[6];
   if (mine > 0) {
-    fetchK(ch_first * CHS);
-    loadZ(za, ch_first * CHS);
+    fetchK(ch_first);
+    loadCk(ca, ch_first);
   }
-  // two trips per pass of the loop so that the two buffers keep fixed registers
+  // two trips per pass of the loop so that the two checkpoint buffers keep fixed registers
   for (int64_t t = 0; t < trips; t += 2) {
     const int64_t ch = ch_first + t * step;
     __syncthreads();
     if (t < mine) stageK();
     __syncthreads();
     if (t + 1 < mine) {
-      fetchK((ch + step) * CHS);
-      loadZ(zb, (ch + step) * CHS);
+      fetchK(ch + step);
+      loadCk(cb2, ch + step);
     }
-    if (t < mine) chunk(za, ch);
+    if (t < mine) {
+      recompute(ca, ch);
+      backward(ch);
+    }
     if (t + 1 >= trips) break;
     __syncthreads();
     if (t + 1 < mine) stageK();
     __syncthreads();
     if (t + 2 < mine) {
-      fetchK((ch + 2 * step) * CHS);
-      loadZ(za, (ch + 2 * step) * CHS);
+      fetchK(ch + 2 * step);
+      loadCk(ca, ch + 2 * step);
     }
-    if (t + 1 < mine) chunk(zb, ch + step);
+    if (t + 1 < mine) {
+      recompute(cb2, ch + step);
+      backward(ch + step);
+    }
   }
 }
 
@@ -752,28 +866,36 @@ __global__ void __launch_bounds__(2 * NT) subst_kernel(Dev d) {
   const int w = threadIdx.x / NT, lane = threadIdx.x % NT;
   if (d.st_done[r]) return;
   const int nc = d.st_nc[r];
+  if (nc == 0) return;                   // no contact: no product is needed
   const int ncol = 1 + nc;
   const int c0 = blockIdx.y * NT;
   if (c0 >= ncol) return;
   const int64_t o = d.off[r], n = d.off[r + 1] - o;
   const int64_t nf = n - 1, m = nf / 2;
-  const int64_t ld = 6 * n;
   const int c = c0 + lane;
-  const bool act = c < ncol;
-  double* z = d.Z + d.zoff[r] + (int64_t)(act ? c : 0) * ld;
+  const int64_t cb = (int64_t)r * d.cap;
   const int64_t zp = d.zp;
-  double* yv = d.Y + 6 * o * zp + (act ? c : 0);
+  SweepCol sc;
+  sc.act = c < ncol;
+  sc.col0 = c == 0;
+  sc.c = sc.act ? c : 0;
+  sc.fcn = -1;
+  sc.cn0 = sc.cn1 = sc.cn2 = 0.0;
+  sc.zb = c0 == 0 ? d.Z + d.zoff[r] : nullptr;   // column 0's b (the first block only)
+  sc.zp = zp;
+  sc.yv = d.Y + 6 * o * zp + sc.c;
+  sc.node = d.ct_node + cb;
+  sc.nrm = d.ct_n + 3 * cb;
+  sc.W = d.W + cb * zp;
+  sc.nc = nc;
+  double* yv = d.Y + 6 * o * zp + sc.c;
   __shared__ double sKD[2][PFS * NT], sKS[2][PFS * NT];
-  __shared__ double sXT[6 * NT], sXM[6 * NT];
-  const int64_t trips = max(side_chunks(false, m - 1, nf), side_chunks(true, m + 1, nf));
+  __shared__ double sXT[6 * NT], sXM[6 * NT], sB[2][CHS * 6];
   const bool fwd = c0 > 0;                // the first NT columns were swept forward in phase 2
-  // this lane's contact: free node and normal (inactive lanes: no contact)
-  int64_t fcn = -1;
-  double cn0 = 0.0, cn1 = 0.0, cn2 = 0.0;
-  if (fwd && act) {
-    const int64_t ci = (int64_t)r * d.cap + (c - 1);
-    fcn = d.ct_node[ci] - 1;
-    cn0 = d.ct_n[3 * ci]; cn1 = d.ct_n[3 * ci + 1]; cn2 = d.ct_n[3 * ci + 2];
+  if (sc.act && c > 0) {
+    const int64_t ci = cb + (c - 1);
+    sc.fcn = d.ct_node[ci] - 1;
+    sc.cn0 = d.ct_n[3 * ci]; sc.cn1 = d.ct_n[3 * ci + 1]; sc.cn2 = d.ct_n[3 * ci + 2];
   }
   // ---------------------------------------------------------------- forward sweeps
   // base side: f = fs .. m-1 ascending, b - X_{f-1} y_{f-1}; tip side: f = fe .. m+1
@@ -784,6 +906,8 @@ __global__ void __launch_bounds__(2 * NT) subst_kernel(Dev d) {
     double* KS = sKS[w];
     double pd[PFS], ps[PFS];
     const bool up = w == 0;
+    const int64_t fcn = sc.fcn;
+    const bool act = sc.act;
     int64_t lim;                          // first (base side) / last (tip side) contact node
     {
       long long v = act ? fcn : (up ? (long long)nf : -1ll);
@@ -810,7 +934,7 @@ __global__ void __launch_bounds__(2 * NT) subst_kernel(Dev d) {
     };
     auto fnode = [&](int u, int64_t f) {
       const bool here = f == fcn;
-      double bv[6] = {here ? cn0 : 0.0, here ? cn1 : 0.0, here ? cn2 : 0.0, 0.0, 0.0, 0.0};
+      double bv[6] = {here ? sc.cn0 : 0.0, here ? sc.cn1 : 0.0, here ? sc.cn2 : 0.0, 0.0, 0.0, 0.0};
       const double* Ls = KS + u * 36;
 #pragma unroll
       for (int p = 0; p < 6; ++p)
@@ -824,7 +948,7 @@ __global__ void __launch_bounds__(2 * NT) subst_kernel(Dev d) {
 #pragma unroll
         for (int p = k + 1; p < 6; ++p) bv[p] -= Ldd[p * 6 + k] * y;
       }
-      if (act) {
+      if (act && checkpoint_node(!up, f)) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) yv[(6 * f + k) * zp] = yp[k];
       }
@@ -878,11 +1002,12 @@ __global__ void __launch_bounds__(2 * NT) subst_kernel(Dev d) {
   }
   // ---------------------------------------------------------------- middle node
   // z_m = L_m^-1 (b_m - X_{m-1} y_{m-1} - X_{m+1} y_{m+1}), x_m = L_m^-T z_m (phase 2 wrote
-  // it for the first NT columns)
+  // it to XM for the first NT columns)
   if (!fwd) {
     if (w == 0) {
+      const double* xm = d.XM + ((int64_t)r * NT + lane) * 6;
 #pragma unroll
-      for (int k = 0; k < 6; ++k) sXM[k * NT + lane] = act ? z[6 * m + k] : 0.0;
+      for (int k = 0; k < 6; ++k) sXM[k * NT + lane] = sc.act ? xm[k] : 0.0;
     }
   } else if (w == 1) {
 #pragma unroll
@@ -890,8 +1015,8 @@ __global__ void __launch_bounds__(2 * NT) subst_kernel(Dev d) {
   }
   __syncthreads();
   if (fwd && w == 0) {
-    const bool here = m == fcn;
-    double bv[6] = {here ? cn0 : 0.0, here ? cn1 : 0.0, here ? cn2 : 0.0, 0.0, 0.0, 0.0};
+    const bool here = m == sc.fcn;
+    double bv[6] = {here ? sc.cn0 : 0.0, here ? sc.cn1 : 0.0, here ? sc.cn2 : 0.0, 0.0, 0.0, 0.0};
     const bool ht = m >= 1, hb = m + 1 < nf;
     const double* Xt = d.LS + (o + 1 + (ht ? m - 1 : m)) * 36;   // X_{m-1} (base side), if any
     const double* Xb = d.LS + (o + 1 + (hb ? m + 1 : m)) * 36;   // X_{m+1} (tip side), if any
@@ -914,7 +1039,6 @@ __global__ void __launch_bounds__(2 * NT) subst_kernel(Dev d) {
     for (int k = 5; k >= 0; --k) {
       const double x = bv[k] * Lm[k * 7];
       sXM[k * NT + lane] = x;
-      if (act) z[6 * m + k] = x;
 #pragma unroll
       for (int p = 0; p < k; ++p) bv[p] -= Lm[k * 6 + p] * x;
     }
@@ -924,10 +1048,17 @@ __global__ void __launch_bounds__(2 * NT) subst_kernel(Dev d) {
   double xn[6];
 #pragma unroll
   for (int k = 0; k < 6; ++k) xn[k] = sXM[k * NT + lane];
-  // forward values are stored from the contact node on (base side) / up to it (tip side)
-  const int64_t ylo = fwd ? (act ? fcn : nf) : 0, yhi = fwd ? (act ? fcn : -1) : nf - 1;
-  if (w == 0) bwd_side<false>(d, o, nf, m - 1, z, yv, zp, act, ylo, nf - 1, xn, sKD[0], sKS[0], trips);
-  else bwd_side<true>(d, o, nf, m + 1, z, yv, zp, act, 0, yhi, xn, sKD[1], sKS[1], trips);
+  // the outermost contact nodes bound the sweeps; contacts at the middle node take x_m
+  const int64_t f_lo = (int64_t)sc.node[0] - 1, f_hi = (int64_t)sc.node[nc - 1] - 1;
+  const int i_mid = first_contact_at(sc.node, nc, m);
+  const int i_tip = first_contact_at(sc.node, nc, m + 1);
+  if (w == 0) {
+    int ci = i_mid;
+    write_rows<true>(sc, m, ci, xn);
+  }
+  const int64_t trips = max(chunk_span(f_lo, m - 1), chunk_span(m + 1, f_hi));
+  if (w == 0) bwd_side<false>(d, o, nf, m - 1, f_lo, sc, i_mid - 1, xn, sKD[0], sKS[0], sB[0], trips);
+  else bwd_side<true>(d, o, nf, m + 1, f_hi, sc, i_tip, xn, sKD[1], sKS[1], sB[1], trips);
 }
 
 // phase 4: contact Schur complement, LCP, step limit and state update
@@ -1124,14 +1255,10 @@ __device__ bool lcp_parallel(LcpLds& S, const double* q, int m, bool warm, doubl
   return true;
 }
 
-// q_c = gap_c + n_c . dx_free(node of c) for the nc contacts of robot r
-__device__ void contact_q(const Dev& d, int64_t cb, int nc, const double* Zr, double* qv) {
-  for (int a = threadIdx.x; a < nc; a += NT) {
-    const int64_t f = d.ct_node[cb + a] - 1;
-    const double* z0 = Zr + 6 * f;
-    qv[a] = d.ct_gap[cb + a] + d.ct_n[3 * (cb + a)] * z0[0] + d.ct_n[3 * (cb + a) + 1] * z0[1] +
-            d.ct_n[3 * (cb + a) + 2] * z0[2];
-  }
+// q_c = gap_c + n_c . dx_free(node of c) for the nc contacts of robot r (Wr: the robot's rows
+// of contact products, column 0 = n_c . dx_free)
+__device__ void contact_q(const Dev& d, int64_t cb, int nc, const double* Wr, double* qv) {
+  for (int a = threadIdx.x; a < nc; a += NT) qv[a] = d.ct_gap[cb + a] + Wr[(int64_t)a * d.zp];
 }
 
 // After the LCP of robot r (one wavefront): the contacts with force > 0 in index order
@@ -1180,8 +1307,8 @@ __device__ __forceinline__ void step_max(const Dev& d, int r, double v) {
   }
 }
 
-// phase 4b, one thread per node: dx = dx_free + sum over active contacts of y_c Z_c (in
-// place in Z's column 0, contacts in index order) and the robot's largest node translation
+// phase 4b of the ADMM variant, one thread per node: the robot's largest node translation of
+// the step dx in Z's column 0
 __global__ void __launch_bounds__(256) step_dx_kernel(Dev d) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool in = g < d.Ntot;
@@ -1196,27 +1323,271 @@ __global__ void __launch_bounds__(256) step_dx_kernel(Dev d) {
       base_increment(d, r, o, dx0);
       v = sqrt(dx0[0] * dx0[0] + dx0[1] * dx0[1] + dx0[2] * dx0[2]);
     } else {
-      const int64_t n = d.off[r + 1] - o;
-      const int64_t ld = 6 * n;
-      const int64_t cb = (int64_t)r * d.cap;
-      double* z = d.Z + d.zoff[r] + 6 * (i - 1);
-      double dx[6];
-#pragma unroll
-      for (int k = 0; k < 6; ++k) dx[k] = z[k];
-      const int nact = d.st_nact[r];
-      for (int a = 0; a < nact; ++a) {
-        const double ya = d.ac_y[cb + a];
-        const double* zc = z + (int64_t)(1 + d.ac_idx[cb + a]) * ld;
-#pragma unroll
-        for (int k = 0; k < 6; ++k) dx[k] += ya * zc[k];
-      }
-#pragma unroll
-      for (int k = 0; k < 6; ++k) z[k] = dx[k];
-      v = sqrt(dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2]);
+      const double* z = d.Z + d.zoff[r] + 6 * (i - 1);
+      v = sqrt(z[0] * z[0] + z[1] * z[1] + z[2] * z[2]);
       if (!(v >= 0.0)) v = -1.0;
     }
   }
   step_max(d, r, v);
+}
+
+// phase 4b of the exact method: the step dx = K^-1 (b + A^T y), with b the right-hand side that
+// check_rhs_kernel wrote to Z's column 0 and y the forces of the active contacts, through the
+// two-ended factor of phase 2, in place in Z's column 0, and each robot's largest node
+// translation.  First every free node adds the forces of its active contacts to b (one thread
+// per node); then each side of a robot is a chain of dependent 6x6 block steps: forward from
+// its end to the middle (base side f = 0 .. m-1, tip side f = nf-1 .. m+1), the middle node
+// combines both, backward from the middle out.  A group of SSC lanes runs one chain: per chunk
+// of SSN positions, one per lane, every lane turns its position's blocks into the step's affine
+// map (forward y = c - G y_prev with G = L^-1 X, c = L^-1 b; backward x = c - H x_prev with
+// H = L^-T X^T, c = L^-T y) and stages it in LDS; the group's first lane then runs the chain of
+// 6x6 products while the group's loads of the next chunk are in flight.  Two robots per
+// wavefront, neighbours in order of decreasing length.
+__global__ void __launch_bounds__(256) add_forces_kernel(Dev d) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= d.Ntot) return;
+  const int r = d.robot_of[g];
+  if (d.st_done[r]) return;
+  const int64_t o = d.off[r], i = g - o;
+  const int nact = d.st_nact[r];
+  if (i == 0 || nact == 0) return;
+  const int64_t cb = (int64_t)r * d.cap;
+  int lo = 0, hi = nact;               // first active contact at node >= i (the list is by node)
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (d.ct_node[cb + d.ac_idx[cb + mid]] < i) lo = mid + 1; else hi = mid;
+  }
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  bool any = false;
+  for (int a = lo; a < nact; ++a) {
+    const int64_t ci = cb + d.ac_idx[cb + a];
+    if (d.ct_node[ci] != i) break;
+    const double y = d.ac_y[cb + a];
+    a0 += y * d.ct_n[3 * ci];
+    a1 += y * d.ct_n[3 * ci + 1];
+    a2 += y * d.ct_n[3 * ci + 2];
+    any = true;
+  }
+  if (any) {
+    double* z = d.Z + d.zoff[r] + 6 * (i - 1);
+    z[0] += a0;
+    z[1] += a1;
+    z[2] += a2;
+  }
+}
+
+constexpr int SSC = 16;                    // lanes per chain
+constexpr int SSR = 64 / (2 * SSC);        // robots per wavefront
+constexpr int SSN = SSC;                   // positions per staged chunk, one per lane
+constexpr int SSG = 36 + 6;                // staged entries per position: G and c
+
+__global__ void __launch_bounds__(64) step_solve_kernel(Dev d) {
+  const int lane = threadIdx.x;
+  const int g = lane / SSC, j = lane % SSC;   // chain g of the wavefront, lane j in its group
+  const int k = blockIdx.x * SSR + g / 2;
+  const bool tip = (g & 1) != 0;
+  const int r = k < d.B ? d.solve_order[k] : 0;
+  const bool live = k < d.B && !d.st_done[r];
+  if (__ballot(live) == 0ull) return;
+  const int64_t o = d.off[r], n = d.off[r + 1] - o, nf = n - 1, m = nf / 2;
+  double* z = d.Z + d.zoff[r];
+  const double* LD = d.LD + (o + 1) * 36;     // block of free node f at LD + 36 f
+  const double* LS = d.LS + (o + 1) * 36;
+  // this side's positions p = 0 .. cnt-1 from its end towards the middle, node f(p)
+  const int64_t cnt = live ? (tip ? nf - 1 - m : m) : 0;
+  const int64_t nch = (cnt + SSN - 1) / SSN;
+  long long mc = nch;
+#pragma unroll
+  for (int sh = 32; sh > 0; sh >>= 1) mc = max(mc, (long long)__shfl_xor(mc, sh));
+  const int64_t trips = mc;
+  auto fnode = [&](int64_t p) { return tip ? nf - 1 - p : p; };
+  __shared__ double sC[2 * SSR][SSN * SSG];
+  double* C = sC[g];
+  double px[36], pl[21], pv[6];
+  // lane j of the group loads position ch * SSN + j of chunk ch (forward: p, backward: the
+  // position cnt-1-p from the middle): the coupling X (forward: of the previous node, backward:
+  // of the node), L's lower triangle by rows and the vector (forward: b, backward: y)
+  auto fetch = [&](int64_t ch, bool fwd) {
+    const int64_t pos = ch * SSN + j;
+    const bool in = pos < cnt;
+    const int64_t p = in ? (fwd ? pos : cnt - 1 - pos) : 0;
+    const int64_t f = fnode(p);
+    const int64_t xs = fwd ? (p >= 1 ? fnode(p - 1) : -1) : f;
+    const bool hx = in && xs >= 0;
+    const double* X = LS + 36 * (hx ? xs : 0);
+    const double* L = LD + 36 * f;
+#pragma unroll
+    for (int q = 0; q < 36; ++q) px[q] = hx ? X[q] : 0.0;
+#pragma unroll
+    for (int a = 0, q = 0; a < 6; ++a)
+#pragma unroll
+      for (int b = 0; b <= a; ++b, ++q) pl[q] = in ? L[a * 6 + b] : 1.0;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) pv[q] = in ? z[6 * f + q] : 0.0;
+  };
+  auto Lr = [&](int a, int b) { return pl[a * (a + 1) / 2 + b]; };   // b <= a; diagonal: 1/L_aa
+  // forward: G = L^-1 X and c = L^-1 b of the lane's position into LDS
+  auto prep_fwd = [&]() {
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+      double col[6];
+#pragma unroll
+      for (int a = 0; a < 6; ++a) {
+        double v = px[a * 6 + b];
+#pragma unroll
+        for (int q = 0; q < a; ++q) v -= Lr(a, q) * col[q];
+        col[a] = v * Lr(a, a);
+      }
+#pragma unroll
+      for (int a = 0; a < 6; ++a) C[j * SSG + a * 6 + b] = col[a];
+    }
+    double cv[6];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      double v = pv[a];
+#pragma unroll
+      for (int q = 0; q < a; ++q) v -= Lr(a, q) * cv[q];
+      cv[a] = v * Lr(a, a);
+    }
+#pragma unroll
+    for (int a = 0; a < 6; ++a) C[j * SSG + 36 + a] = cv[a];
+  };
+  // backward: H = L^-T X^T and c = L^-T y of the lane's position into LDS
+  auto prep_bwd = [&]() {
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+      double col[6];
+#pragma unroll
+      for (int a = 5; a >= 0; --a) {
+        double v = px[b * 6 + a];                    // X^T (a, b)
+#pragma unroll
+        for (int q = a + 1; q < 6; ++q) v -= Lr(q, a) * col[q];
+        col[a] = v * Lr(a, a);
+      }
+#pragma unroll
+      for (int a = 0; a < 6; ++a) C[j * SSG + a * 6 + b] = col[a];
+    }
+    double cv[6];
+#pragma unroll
+    for (int a = 5; a >= 0; --a) {
+      double v = pv[a];
+#pragma unroll
+      for (int q = a + 1; q < 6; ++q) v -= Lr(q, a) * cv[q];
+      cv[a] = v * Lr(a, a);
+    }
+#pragma unroll
+    for (int a = 0; a < 6; ++a) C[j * SSG + 36 + a] = cv[a];
+  };
+  // the chain step v <- c - G v of staged position u
+  auto chain = [&](int u, double (&v)[6]) {
+    double nv[6];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      double s = C[u * SSG + 36 + a];
+#pragma unroll
+      for (int b = 0; b < 6; ++b) s -= C[u * SSG + a * 6 + b] * v[b];
+      nv[a] = s;
+    }
+#pragma unroll
+    for (int a = 0; a < 6; ++a) v[a] = nv[a];
+  };
+  // ---------------------------------------------------------------- forward sweeps
+  // y_p = L^-1 (b_p - X y_{p-1}) = c_p - G_p y_{p-1}
+  double yp[6] = {0, 0, 0, 0, 0, 0};
+  if (nch > 0) fetch(0, true);
+  for (int64_t t = 0; t < trips; ++t) {
+    __syncthreads();
+    if (t < nch) prep_fwd();
+    __syncthreads();
+    if (t + 1 < nch) fetch(t + 1, true);
+    if (j == 0 && t < nch) {
+      for (int u = 0; u < SSN; ++u) {
+        const int64_t p = t * SSN + u;
+        if (p >= cnt) break;
+        chain(u, yp);
+        double* zf = z + 6 * fnode(p);
+#pragma unroll
+        for (int a = 0; a < 6; ++a) zf[a] = yp[a];
+      }
+    }
+  }
+  // ---------------------------------------------------------------- middle node
+  const int base_lead = (g & ~1) * SSC, tip_lead = (g | 1) * SSC;
+  double yt[6];                                       // the tip side's last forward value
+#pragma unroll
+  for (int a = 0; a < 6; ++a) yt[a] = __shfl(yp[a], tip_lead);
+  double xm[6] = {0, 0, 0, 0, 0, 0};
+  if (live && !tip && j == 0) {
+    double bv[6];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) bv[a] = z[6 * m + a];
+    const bool ht = m >= 1, hb = m + 1 < nf;
+    const double* Xt = LS + 36 * (ht ? m - 1 : m);    // X_{m-1} (base side), if any
+    const double* Xb = LS + 36 * (hb ? m + 1 : m);    // X_{m+1} (tip side), if any
+#pragma unroll
+    for (int a = 0; a < 6; ++a)
+#pragma unroll
+      for (int b = 0; b < 6; ++b) {
+        if (ht) bv[a] -= Xt[a * 6 + b] * yp[b];
+        if (hb) bv[a] -= Xb[a * 6 + b] * yt[b];
+      }
+    const double* Lm = LD + 36 * m;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      const double y = bv[a] * Lm[a * 7];
+      bv[a] = y;
+#pragma unroll
+      for (int b = a + 1; b < 6; ++b) bv[b] -= Lm[b * 6 + a] * y;
+    }
+#pragma unroll
+    for (int a = 5; a >= 0; --a) {
+      const double x = bv[a] * Lm[a * 7];
+      xm[a] = x;
+      z[6 * m + a] = x;
+#pragma unroll
+      for (int b = 0; b < a; ++b) bv[b] -= Lm[a * 6 + b] * x;
+    }
+  }
+  double xn[6];
+#pragma unroll
+  for (int a = 0; a < 6; ++a) xn[a] = __shfl(xm[a], base_lead);
+  // the largest translation: the base node's increment and the middle node (base side)
+  double mx = -1.0;
+  if (live && !tip && j == 0) {
+    double dx0[3];
+    base_increment(d, r, o, dx0);
+    const double vb = sqrt(dx0[0] * dx0[0] + dx0[1] * dx0[1] + dx0[2] * dx0[2]);
+    const double vm = sqrt(xn[0] * xn[0] + xn[1] * xn[1] + xn[2] * xn[2]);
+    if (vb >= 0.0) mx = fmax(mx, vb);
+    if (vm >= 0.0) mx = fmax(mx, vm);
+  }
+  __syncthreads();                                    // the forward values are in Z
+  // ---------------------------------------------------------------- backward sweeps
+  // position p = cnt-1-pos: x_f = L_f^-T (y_f - X_f^T x_neighbour) = c_f - H_f x_neighbour
+  if (nch > 0) fetch(0, false);
+  for (int64_t t = 0; t < trips; ++t) {
+    __syncthreads();
+    if (t < nch) prep_bwd();
+    __syncthreads();
+    if (t + 1 < nch) fetch(t + 1, false);
+    if (j == 0 && t < nch) {
+      for (int u = 0; u < SSN; ++u) {
+        const int64_t pos = t * SSN + u;
+        if (pos >= cnt) break;
+        chain(u, xn);
+        double* zf = z + 6 * fnode(cnt - 1 - pos);
+#pragma unroll
+        for (int a = 0; a < 6; ++a) zf[a] = xn[a];
+        const double v = sqrt(xn[0] * xn[0] + xn[1] * xn[1] + xn[2] * xn[2]);
+        if (v >= 0.0) mx = fmax(mx, v);
+      }
+    }
+  }
+  const double mt = __shfl(mx, tip_lead);
+  if (live && !tip && j == 0) {
+    const double v = fmax(mx, mt);
+    d.st_mx[r] = v >= 0.0 ? (unsigned long long)__double_as_longlong(v) : 0ull;
+  }
 }
 
 // phase 4c, one thread per node: the step-size limit (eq. 25-27: scale the step so that no
@@ -1289,26 +1660,19 @@ __global__ void __launch_bounds__(NT) update_kernel(Dev d) {
   if (d.st_done[r]) return;
   const int nc = d.st_nc[r];
   if (nc > LCPM) return;               // update_wide_kernel
-  const int64_t n = d.off[r + 1] - d.off[r];
   const int64_t cb = (int64_t)r * d.cap;
-  double* Zr = d.Z + d.zoff[r];
-  const int64_t ld = 6 * n;
+  const double* Wr = d.W + cb * d.zp;
   __shared__ LcpLds S;
   __shared__ int s_lcp_ok;
   double* qv = d.q + cb;
   double* y = d.ct_y + cb;
-  contact_q(d, cb, nc, Zr, qv);
-  // W packed in LDS: lane a computes its row, W(a, b) = n_a . Z_b(node of a), b <= a
+  contact_q(d, cb, nc, Wr, qv);
+  // W packed in LDS: lane a takes its row of products, W(a, b) = n_a . Z_b(node of a), b <= a
   bool warm = false;
   if (lane < nc) {
-    const int64_t f = d.ct_node[cb + lane] - 1;
-    const double n0 = d.ct_n[3 * (cb + lane)], n1 = d.ct_n[3 * (cb + lane) + 1],
-                 n2 = d.ct_n[3 * (cb + lane) + 2];
+    const double* wa = Wr + (int64_t)lane * d.zp + 1;
 #pragma unroll 8
-    for (int b = 0; b <= lane; ++b) {
-      const double* zb = Zr + (int64_t)(1 + b) * ld + 6 * f;
-      S.W[pk(lane, b)] = n0 * zb[0] + n1 * zb[1] + n2 * zb[2];
-    }
+    for (int b = 0; b <= lane; ++b) S.W[pk(lane, b)] = wa[b];
     warm = d.ct_warm[cb + lane] != 0;
   }
   __syncthreads();
@@ -1328,9 +1692,8 @@ __global__ void __launch_bounds__(NT) update_kernel(Dev d) {
 // ---------------------------------------------------------------- wide LCP (nc > LCPM)
 // The same primal active-set method for contact sets beyond LCPM, one wavefront per robot.
 // Constraint i is handled by lane i % NT; active position p by lane p % NT (SP per lane).
-// W is never formed whole: column t, W(i, t), is made available when t first enters the
-// active set (for a robot's contact set it is computed from Z and cached in device memory,
-// column-major, ld = cap).  The Cholesky factor of the active block, packed with rows in
+// W is read by columns (column t at Wc + t * ld; for a robot's contact set the rows of
+// contact products that the substitution wrote, W being symmetric).  The Cholesky factor of the active block, packed with rows in
 // order of entry, lives in LDS up to NPW positions; a set that outgrows it is solved again
 // with the factor in device memory (up to every constraint).
 constexpr int NPW = 128;
@@ -1357,70 +1720,15 @@ struct LcpWs {
   int npmax;
 };
 
-// W columns and warm-start flags of a robot's contact set: W(i, t) = n_i . Z_t(node of i),
-// computed from Z when t is first needed and cached in Wc (column-major, ld = cap).  Each lane
-// keeps the free node and normal of its constraints i = lane + NT s (s < CSL) in registers, so
-// that a column is one round of independent loads; larger sets read them per column.
-constexpr int CSL = 4;
+// the contact products of a robot's contact set, formed by the substitution: "column" t is
+// read as the contiguous row of contact t, W(t, i) = n_t . Z_i(node of t), which equals
+// W(i, t) (W is symmetric) up to rounding; warm-start flags from the contact list
 struct RobotLcpSource {
   const Dev* d;
-  int r;
   int64_t cb;
-  const double* Zr;
-  int64_t ld;
-  int m;
-  int64_t fs[CSL];
-  double nx[CSL], ny[CSL], nz[CSL];
-  __device__ RobotLcpSource(const Dev* d_, int r_, int64_t cb_, const double* Zr_, int64_t ld_, int m_)
-      : d(d_), r(r_), cb(cb_), Zr(Zr_), ld(ld_), m(m_) {
-#pragma unroll
-    for (int s = 0; s < CSL; ++s) {
-      const int i = (int)(threadIdx.x % NT) + NT * s;
-      const bool v = i < m;
-      const int64_t e = cb + (v ? i : 0);
-      fs[s] = v ? d->ct_node[e] - 1 : 0;
-      nx[s] = v ? d->ct_n[3 * e] : 0.0;
-      ny[s] = v ? d->ct_n[3 * e + 1] : 0.0;
-      nz[s] = v ? d->ct_n[3 * e + 2] : 0.0;
-    }
-  }
-  __device__ void fill(double* Wc, int cap, int t) const {   // column t into Wc
-    const double* zt = Zr + (int64_t)(1 + t) * ld;
-    double* wt = Wc + (int64_t)t * cap;
-    const int lane = threadIdx.x % NT;
-    if (m <= CSL * NT) {
-#pragma unroll
-      for (int s = 0; s < CSL; ++s) {
-        const int i = lane + NT * s;
-        if (i < m) wt[i] = nx[s] * zt[6 * fs[s]] + ny[s] * zt[6 * fs[s] + 1] + nz[s] * zt[6 * fs[s] + 2];
-      }
-    } else {
-      for (int i = lane; i < m; i += NT) {
-        const int64_t f = d->ct_node[cb + i] - 1;
-        wt[i] = d->ct_n[3 * (cb + i)] * zt[6 * f] + d->ct_n[3 * (cb + i) + 1] * zt[6 * f + 1] +
-                d->ct_n[3 * (cb + i) + 2] * zt[6 * f + 2];
-      }
-    }
-  }
-  __device__ void column(LcpWideLds& S, double* Wc, int cap, int, int t) const {
-    if (S.Val[t]) return;
-    fill(Wc, cap, t);
-    __syncthreads();
-    if (threadIdx.x == 0) S.Val[t] = 1;
-    __syncthreads();
-  }
+  __device__ void column(LcpWideLds&, double*, int, int, int) const {}
+  __device__ void columns(LcpWideLds&, double*, int, int, const int*, int) const {}
   __device__ bool warm(int i) const { return d->ct_warm[cb + i] != 0; }
-  // the columns of the listed constraints, computed together (one barrier)
-  __device__ void columns(LcpWideLds& S, double* Wc, int cap, int, const int* list, int cnt) const {
-#pragma unroll 2
-    for (int a = 0; a < cnt; ++a) {
-      const int t = list[a];
-      if (!S.Val[t]) fill(Wc, cap, t);
-    }
-    __syncthreads();
-    for (int a = threadIdx.x; a < cnt; a += NT) S.Val[list[a]] = 1;
-    __syncthreads();
-  }
 };
 
 // a given dense W (column-major, ld = cap), no warm start
@@ -1768,21 +2076,16 @@ __global__ void __launch_bounds__(NT) update_wide_kernel(Dev d) {
   if (d.st_done[r]) return;
   const int nc = d.st_nc[r];
   if (nc <= LCPM) return;              // update_kernel
-  const int64_t n = d.off[r + 1] - d.off[r];
-  const int cap = d.cap;
-  const int64_t cb = (int64_t)r * cap;
-  double* Zr = d.Z + d.zoff[r];
-  const int64_t ld = 6 * n;
+  const int64_t cb = (int64_t)r * d.cap;
   __shared__ LcpWideLds S;
   double* qv = d.q + cb;
   double* y = d.ct_y + cb;
-  double* Wc = d.W + (int64_t)r * cap * cap;
-  double* scratch = d.W + (int64_t)d.B * cap * cap + (int64_t)r * lcp_ws_doubles(cap);
-  contact_q(d, cb, nc, Zr, qv);
+  double* Wr = d.W + cb * d.zp;
+  contact_q(d, cb, nc, Wr, qv);
   __syncthreads();
-  const RobotLcpSource src(&d, r, cb, Zr, ld, nc);
+  const RobotLcpSource src{&d, cb};
   const LcpWs wl{S.L, S.Rd, S.Yp, S.P, NPW};
-  const int code = lcp_wide<SPL>(src, S, wl, Wc, cap, qv, nc, y, true);
+  const int code = lcp_wide<SPL>(src, S, wl, Wr + 1, (int)d.zp, qv, nc, y, true);
   if (threadIdx.x == 0) d.st_big[r] = code == 2 ? 1 : 0;
   if (code == 1) {
     finish(d, r, 2, d.st_it[r], d.st_rn[r]);
@@ -1799,18 +2102,13 @@ __global__ void __launch_bounds__(NT) update_big_kernel(Dev d) {
   if (d.st_done[r]) return;
   const int nc = d.st_nc[r];
   if (nc <= LCPM || !d.st_big[r]) return;
-  const int64_t n = d.off[r + 1] - d.off[r];
-  const int cap = d.cap;
-  const int64_t cb = (int64_t)r * cap;
-  double* Zr = d.Z + d.zoff[r];
-  const int64_t ld = 6 * n;
+  const int64_t cb = (int64_t)r * d.cap;
   __shared__ LcpWideLds S;
   const double* qv = d.q + cb;                  // written by update_wide_kernel
   double* y = d.ct_y + cb;
-  double* Wc = d.W + (int64_t)r * cap * cap;
-  double* scratch = d.W + (int64_t)d.B * cap * cap + (int64_t)r * lcp_ws_doubles(cap);
-  const RobotLcpSource src(&d, r, cb, Zr, ld, nc);
-  if (lcp_wide<SPG>(src, S, global_ws(scratch, nc), Wc, cap, qv, nc, y, true) != 0) {
+  double* Wr = d.W + cb * d.zp;
+  const RobotLcpSource src{&d, cb};
+  if (lcp_wide<SPG>(src, S, global_ws(lcp_ws(d, r), nc), Wr + 1, (int)d.zp, qv, nc, y, true) != 0) {
     finish(d, r, 2, d.st_it[r], d.st_rn[r]);
     return;
   }
@@ -1934,7 +2232,7 @@ __global__ void __launch_bounds__(NT) admm_kernel(Dev d) {
   const int64_t zp = d.zp;
   double* Yr = d.Y + 6 * o * zp;                 // per free DOF row: x, xt, v, K x in columns 0..3
   double* b0 = d.Z + d.zoff[r];                  // b (free DOF rows), then the result x
-  double* ws = d.W + (int64_t)d.B * cap * cap + (int64_t)r * lcp_ws_doubles(cap);
+  double* ws = lcp_ws(d, r);
   double* zc = ws;                               // z, y_o per contact
   double* yo = ws + cap;
   const double rho = d.admm_rho, eps = d.admm_eps;
@@ -2129,7 +2427,8 @@ __global__ void __launch_bounds__(NT) admm_kernel(Dev d) {
   }
 }
 
-// phases of one Newton step: 0 check + right-hand sides, 1 factor, 2 substitute, 3 update
+// phases of one Newton step: 0 check + right-hand sides, 1 factor, 2 substitute, 3 contact
+// forces, 4 step and state update
 void launch_solve_phase(const Dev& d, int phase, hipStream_t s) {
   switch (phase) {
     case 0: hipLaunchKernelGGL(check_rhs_kernel, dim3(d.B), dim3(NT), 0, s, d); break;
@@ -2141,13 +2440,20 @@ void launch_solve_phase(const Dev& d, int phase, hipStream_t s) {
       if (!d.qp_admm)
         hipLaunchKernelGGL(subst_kernel, dim3(d.B, (d.cap + NT) / NT), dim3(2 * NT), 0, s, d);
       break;
-    default:
+    case 3:
       if (!d.qp_admm) {
         hipLaunchKernelGGL(update_kernel, dim3(d.B), dim3(NT), 0, s, d);
         if (d.cap > LCPM) hipLaunchKernelGGL(update_wide_kernel, dim3(d.B), dim3(NT), 0, s, d);
         if (d.cap > NPW) hipLaunchKernelGGL(update_big_kernel, dim3(d.B), dim3(NT), 0, s, d);
       }
-      hipLaunchKernelGGL(step_dx_kernel, dim3((unsigned)((d.Ntot + 255) / 256)), dim3(256), 0, s, d);
+      break;
+    default:
+      if (d.qp_admm)
+        hipLaunchKernelGGL(step_dx_kernel, dim3((unsigned)((d.Ntot + 255) / 256)), dim3(256), 0, s, d);
+      else {
+        hipLaunchKernelGGL(add_forces_kernel, dim3((unsigned)((d.Ntot + 255) / 256)), dim3(256), 0, s, d);
+        hipLaunchKernelGGL(step_solve_kernel, dim3((unsigned)((d.B + SSR - 1) / SSR)), dim3(64), 0, s, d);
+      }
       hipLaunchKernelGGL(step_apply_kernel, dim3((unsigned)((d.Ntot + 255) / 256)), dim3(256), 0, s, d);
       break;
   }

@@ -60,7 +60,8 @@ class fem_solve_info(C.Structure):
                 ("n_limited", C.c_int32), ("res_norm", C.c_double),
                 ("steps_converged", C.c_int32), ("steps_total", C.c_int32),
                 ("iters_total", C.c_int64), ("rhs_total", C.c_int64), ("rhs_fused", C.c_int64),
-                ("sweep_passes", C.c_int64), ("qp_iters_total", C.c_int64)]
+                ("sweep_passes", C.c_int64), ("qp_iters_total", C.c_int64),
+                ("products_total", C.c_int64), ("contact_steps_total", C.c_int64)]
 
 
 class fem_contact(C.Structure):
