@@ -1,7 +1,9 @@
 // Per-robot Newton step: contact gather, convergence test, block-tridiagonal
 // Cholesky of the QP tangent, multi-right-hand-side solves, contact-space Schur
 // complement, exact contact forces by an active-set method, step-size limit and
-// state update.  One wavefront (64 lanes) per robot.
+// state update.  One wavefront (64 lanes) per robot.  Kernels with a block per robot take
+// the robots in order of decreasing length (the longest start first, so that the short
+// ones fill in behind them).
 //
 // Linear step (eq. 20-23): with the base node prescribed (clamp + insertion,
 // eq. 14-15) and the lateral DOFs of guided nodes prescribed on the guide axis,
@@ -145,7 +147,7 @@ __device__ __forceinline__ void finish(const Dev& d, int r, int status, int iter
 
 // phase 1: contact gather, convergence test, right-hand sides (col 0 = -r, contact columns)
 __global__ void __launch_bounds__(NT) check_rhs_kernel(Dev d) {
-  const int r = blockIdx.x;
+  const int r = d.solve_order[blockIdx.x];   // longest robots first
   const int lane = threadIdx.x;
   if (d.st_done[r]) return;
   const int it = d.st_it[r];
@@ -343,7 +345,7 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 // X_bot y_bot), and the middle node's solution x_m = L_m^-T z_m goes to XM, where the
 // substitution starts both sides' backward sweeps.
 __global__ void __launch_bounds__(4 * NT) __attribute__((amdgpu_waves_per_eu(3))) factor_kernel(Dev d) {
-  const int r = blockIdx.x;
+  const int r = d.solve_order[blockIdx.x];   // longest robots first
   const int w = threadIdx.x / NT, lane = threadIdx.x % NT;
   const int sd = w >> 1;                      // side: 0 from the base, 1 from the tip
   const bool fw = (w & 1) != 0;               // the side's forward-substitution wave
@@ -647,12 +649,21 @@ __global__ void __launch_bounds__(4 * NT) __attribute__((amdgpu_waves_per_eu(3))
 // chunk's forward values are recomputed from the checkpoint before it (b of column 0 read
 // from Z, the contact columns generated), then swept back, and at each contact node the
 // lanes write that contact's row of products (contiguous over the wavefront's columns).
-// One block per robot and pass of NT columns, one wavefront per side.  The first NT columns
-// were swept forward in phase 2, which also wrote x_m: their block only sweeps back.  Columns
+// One block per robot and pass of NT columns, one wavefront per side; the two meet only at the
+// middle node (each stages its own blocks).  The first NT columns were swept forward in phase
+// 2, which also wrote x_m: their block only sweeps back.  Columns
 // from NT on are contact columns (n_c at the contact node, zero elsewhere): their block sweeps
 // them forward (generating the right-hand side, over the part of each side that the contact
 // node reaches, keeping the checkpoints), combines the two sides at the middle node, then
 // sweeps back.
+
+// LDS staged by the lanes of a wavefront for itself: a wavefront's LDS operations take effect
+// in order, so keeping the compiler from moving them across this point is enough
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // chunks of CHS nodes (aligned at multiples of CHS) between nodes f_a <= f_b, 0 if f_a > f_b
 __device__ __forceinline__ int64_t chunk_span(int64_t f_a, int64_t f_b) {
@@ -707,13 +718,12 @@ __device__ __forceinline__ void write_rows(const SweepCol& sc, int64_t f, int& c
 
 // backward sweep of one side; UP: f = f_begin .. f_end ascending (tip side), else f = f_begin ..
 // f_end descending (base side).  ci: the first contact the side meets (tip side: the first at
-// a node >= f_begin; base side: the last at a node <= f_begin).  Every wavefront of the block
-// must pass the same `trips` (>= this side's chunk count).  sB: LDS for column 0's right-hand
-// side of a chunk (CHS * 6 doubles).
+// a node >= f_begin; base side: the last at a node <= f_begin).  sKD, sKS, sB: the wavefront's
+// own staging arrays (sB: column 0's right-hand side of a chunk, CHS * 6 doubles).
 template <bool UP>
 __device__ void bwd_side(const Dev& d, int64_t o, int64_t nf, int64_t f_begin, int64_t f_end,
                          const SweepCol& sc, int ci, double (&xn)[6], double* sKD, double* sKS,
-                         double* sB, int64_t trips) {
+                         double* sB) {
   const int lane = threadIdx.x % NT;
   // staged per chunk [f0, f0 + CHS): LD of its nodes at u = 0..CHS-1, LS of nodes f0 - 1 + u
   // (base side) or f0 + u (tip side) at u = 0..CHS (the forward sweep's coupling to the
@@ -831,38 +841,34 @@ __device__ void bwd_side(const Dev& d, int64_t o, int64_t nf, int64_t f_begin, i
     fetchK(ch_first);
     loadCk(ca, ch_first);
   }
-  // two trips per pass of the loop so that the two checkpoint buffers keep fixed registers
-  for (int64_t t = 0; t < trips; t += 2) {
+  // two chunks per pass of the loop so that the two checkpoint buffers keep fixed registers
+  for (int64_t t = 0; t < mine; t += 2) {
     const int64_t ch = ch_first + t * step;
-    __syncthreads();
-    if (t < mine) stageK();
-    __syncthreads();
+    wave_sync();
+    stageK();
+    wave_sync();
     if (t + 1 < mine) {
       fetchK(ch + step);
       loadCk(cb2, ch + step);
     }
-    if (t < mine) {
-      recompute(ca, ch);
-      backward(ch);
-    }
-    if (t + 1 >= trips) break;
-    __syncthreads();
-    if (t + 1 < mine) stageK();
-    __syncthreads();
+    recompute(ca, ch);
+    backward(ch);
+    if (t + 1 >= mine) break;
+    wave_sync();
+    stageK();
+    wave_sync();
     if (t + 2 < mine) {
       fetchK(ch + 2 * step);
       loadCk(ca, ch + 2 * step);
     }
-    if (t + 1 < mine) {
-      recompute(cb2, ch + step);
-      backward(ch + step);
-    }
+    recompute(cb2, ch + step);
+    backward(ch + step);
   }
 }
 
 // block (r, p) takes columns p*NT .. p*NT + NT-1: wave 0 the base side, wave 1 the tip side
 __global__ void __launch_bounds__(2 * NT) subst_kernel(Dev d) {
-  const int r = blockIdx.x;
+  const int r = d.solve_order[blockIdx.x];   // longest robots first
   const int w = threadIdx.x / NT, lane = threadIdx.x % NT;
   if (d.st_done[r]) return;
   const int nc = d.st_nc[r];
@@ -957,32 +963,16 @@ __global__ void __launch_bounds__(2 * NT) subst_kernel(Dev d) {
     const int64_t lo = up ? lim : m + 1;
     const int64_t hi = up ? m - 1 : lim;
     const int64_t nch_lo = lo / CHS, nch_hi = hi >= 0 ? hi / CHS : -1;
-    // both waves take the same number of chunk trips so that their barriers match
     const int64_t mine = (lo <= hi) ? nch_hi - nch_lo + 1 : 0;
-    int64_t other = 0;
-    {
-      // the other side's count, from the same quantities
-      long long v = act ? fcn : (!up ? (long long)nf : -1ll);
-#pragma unroll
-      for (int sh = 32; sh > 0; sh >>= 1) {
-        const long long ov = __shfl_xor(v, sh);
-        v = !up ? min(v, ov) : max(v, ov);
-      }
-      const int64_t olo = !up ? v : m + 1, ohi = !up ? m - 1 : v;
-      other = (olo <= ohi) ? (ohi / CHS) - (olo / CHS) + 1 : 0;
-    }
-    const int64_t trips = max(mine, other);
     if (mine > 0) fetchF((up ? nch_lo : nch_hi) * CHS);
-    for (int64_t t = 0; t < trips; ++t) {
+    for (int64_t t = 0; t < mine; ++t) {
       const int64_t ch = up ? nch_lo + t : nch_hi - t;
-      __syncthreads();
-      if (t < mine) {
+      wave_sync();
 #pragma unroll
-        for (int u = 0; u < PFS; ++u) { KD[lane + u * NT] = pd[u]; KS[lane + u * NT] = ps[u]; }
-      }
-      __syncthreads();
+      for (int u = 0; u < PFS; ++u) { KD[lane + u * NT] = pd[u]; KS[lane + u * NT] = ps[u]; }
+      wave_sync();
       if (t + 1 < mine) fetchF((up ? ch + 1 : ch - 1) * CHS);
-      if (t < mine) {
+      {
         const int64_t f0 = ch * CHS;
         if (up) {
 #pragma unroll
@@ -1056,9 +1046,8 @@ __global__ void __launch_bounds__(2 * NT) subst_kernel(Dev d) {
     int ci = i_mid;
     write_rows<true>(sc, m, ci, xn);
   }
-  const int64_t trips = max(chunk_span(f_lo, m - 1), chunk_span(m + 1, f_hi));
-  if (w == 0) bwd_side<false>(d, o, nf, m - 1, f_lo, sc, i_mid - 1, xn, sKD[0], sKS[0], sB[0], trips);
-  else bwd_side<true>(d, o, nf, m + 1, f_hi, sc, i_tip, xn, sKD[1], sKS[1], sB[1], trips);
+  if (w == 0) bwd_side<false>(d, o, nf, m - 1, f_lo, sc, i_mid - 1, xn, sKD[0], sKS[0], sB[0]);
+  else bwd_side<true>(d, o, nf, m + 1, f_hi, sc, i_tip, xn, sKD[1], sKS[1], sB[1]);
 }
 
 // phase 4: contact Schur complement, LCP, step limit and state update
@@ -1655,7 +1644,7 @@ __global__ void __launch_bounds__(256) step_apply_kernel(Dev d) {
 
 // phase 4 for robots with at most LCPM contacts: W packed in LDS, the wavefront LCP
 __global__ void __launch_bounds__(NT) update_kernel(Dev d) {
-  const int r = blockIdx.x;
+  const int r = d.solve_order[blockIdx.x];   // longest robots first
   const int lane = threadIdx.x;
   if (d.st_done[r]) return;
   const int nc = d.st_nc[r];
@@ -1903,8 +1892,28 @@ __device__ int lcp_wide(const Src& src, LcpWideLds& S, const LcpWs& w, double* W
         const int i = i0 + lane + u * NT;
         wv[u] = i < m ? q[i] : 0.0;
       }
-#pragma unroll 2
-      for (int a = 0; a < np; ++a) {
+      // eight columns at a time: their 32 loads are in flight together (accumulation order
+      // unchanged)
+      int a = 0;
+      for (; a + 8 <= np; a += 8) {
+        double ya[8], cv[8][4];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          ya[e] = w.Yp[a + e];
+          const double* col = Wc + (int64_t)w.P[a + e] * cap;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int i = i0 + lane + u * NT;
+            cv[e][u] = i < m ? col[i] : 0.0;
+          }
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (i0 + lane + u * NT < m) wv[u] += cv[e][u] * ya[e];
+      }
+      for (; a < np; ++a) {
         const double ya = w.Yp[a];
         const double* col = Wc + (int64_t)w.P[a] * cap;
 #pragma unroll
@@ -2072,7 +2081,7 @@ __device__ __forceinline__ LcpWs global_ws(double* g, int m) {
 
 // phase 4 for robots with more than LCPM contacts
 __global__ void __launch_bounds__(NT) update_wide_kernel(Dev d) {
-  const int r = blockIdx.x;
+  const int r = d.solve_order[blockIdx.x];   // longest robots first
   if (d.st_done[r]) return;
   const int nc = d.st_nc[r];
   if (nc <= LCPM) return;              // update_kernel
@@ -2098,7 +2107,7 @@ __global__ void __launch_bounds__(NT) update_wide_kernel(Dev d) {
 // factor in the robot's device workspace (up to every constraint).  A kernel of its own, so
 // that the common path keeps its registers (this one holds 16 positions per lane).
 __global__ void __launch_bounds__(NT) update_big_kernel(Dev d) {
-  const int r = blockIdx.x;
+  const int r = d.solve_order[blockIdx.x];   // longest robots first
   if (d.st_done[r]) return;
   const int nc = d.st_nc[r];
   if (nc <= LCPM || !d.st_big[r]) return;
@@ -2221,7 +2230,7 @@ __device__ void admm_diag_block(const Dev& d, int r, int64_t o, int64_t n, int64
 }
 
 __global__ void __launch_bounds__(NT) admm_kernel(Dev d) {
-  const int r = blockIdx.x;
+  const int r = d.solve_order[blockIdx.x];   // longest robots first
   const int lane = threadIdx.x;
   if (d.st_done[r]) return;
   const int64_t o = d.off[r], n = d.off[r + 1] - o, nf = n - 1;
