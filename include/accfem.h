@@ -132,6 +132,10 @@ typedef struct {
   double admm_rho;            /* FEM_QP_ADMM penalty (N/m); 0 = 1 */
   double admm_eps;            /* FEM_QP_ADMM tolerance; 0 = 1e-11 */
   int32_t admm_max_iter;      /* FEM_QP_ADMM iteration limit per linear step; 0 = 20000 */
+  int32_t contact_along_elements; /* 1: contacts anywhere along an element as well (eq. 3-7
+                                 with 0 < xi < l0): the chord of every element whose two
+                                 nodes are contact nodes against the edges and vertices of
+                                 the wall, kind 2; needs FEM_QP_EXACT */
 } fem_params;
 
 typedef struct {
@@ -156,10 +160,14 @@ typedef struct {
 
 typedef struct {
   int32_t robot, node, tri; /* node index within its robot; triangle index of the lumen */
-  int32_t kind;             /* 0 = face contact, 1 = edge/vertex contact */
+  int32_t kind;             /* 0 = face contact, 1 = edge/vertex contact (at the node),
+                               2 = contact along the element from node to node + 1 */
   double n[3];              /* unit normal pointing from the wall into the lumen */
   double gap;               /* gap at the last iterate (m) */
   double force;             /* contact force magnitude y >= 0 (N) of the last linear step */
+  double s;                 /* kind 2: the contact point's position xi / l0 along the element
+                               (0 < s < 1; row (1 - s) n^T on node, s n^T on node + 1);
+                               0 for the other kinds */
 } fem_contact;
 
 /* Create a context for a batch of robots (Sec. II-B: each robot is split into
@@ -258,7 +266,9 @@ fem_status fem_contacts(const fem_ctx* c, int32_t robot, fem_contact* out,
  * A_act lam = 0 with the exact Jacobian J of the out-of-balance force (element
  * material and geometric stiffness plus the follower-load stiffness), the active
  * contacts (force > 0) held as planes at their normals and the base and guided
- * lateral DOFs fixed, then dL/du_j = lam . dF_a/du_j.  Always FP64.
+ * lateral DOFs fixed, then dL/du_j = lam . dF_a/du_j.  Always FP64.  A robot with an
+ * active contact along an element (kind 2) is not supported: its entries are NaN and the
+ * call returns FEM_E_NOCONV.
  *   sensor_nodes [n_sensors] host memory: node index i >= 0 counts from the base,
  *                i < 0 from the tip (-1 = tip), the same for every robot
  *   dL_dp        [B*n_sensors*3] robot-major, then sensor, then x y z

@@ -14,6 +14,10 @@ nearest point q of a fixed edge line or vertex (gap rho - r_c), whose normal
 n = (p - q)/rho turns with the node: dn/dp = (I - n n^T - t t^T)/rho for an edge
 of unit direction t, (I - n n^T)/rho for a vertex, so the contact force -y n
 adds -y dn/dp to the node's translation block of J (the constraint curvature).
+A contact along element i constrains the distance from the chord point p(s*) to the fixed
+edge line or vertex (s* its nearest point on the chord); its row is (1 - s*) n, s* n on the
+two nodes' translations (element_gap_gradient) and its curvature, the 6x6 Hessian of that
+distance, is taken by central differences of the gradient.
 Fixed DOFs (base node, guided lateral DOFs) are removed.  J is taken by central
 finite differences of the out-of-balance force (banded, Richardson-extrapolated), the KKT system is
 solved densely.  Independent check: central differences of complete re-solves.
@@ -76,6 +80,49 @@ def normal_derivative(p, mesh, tri):
     return H / rho
 
 
+def element_gap_gradient(xa, xb, q1, q2=None):
+    """Gradient [6] of the distance from the chord xa-xb to the line through q1, q2 (or the
+    point q1) with respect to (xa, xb): (1 - s) n, s n, where s is the chord parameter of the
+    closest pair (unclamped) and n the unit vector from the line (point) to the chord point."""
+    d1 = xb - xa
+    a = float(d1 @ d1)
+    if q2 is None:
+        s = float((q1 - xa) @ d1) / a
+        q = q1
+    else:
+        d2 = q2 - q1
+        r = xa - q1
+        e, b, c, f = float(d2 @ d2), float(d1 @ d2), float(d1 @ r), float(d2 @ r)
+        s = (b * f - c * e) / (a * e - b * b)
+        q = q1 + ((b * s + f) / e) * d2
+    p = xa + s * d1
+    n = (p - q) / np.linalg.norm(p - q)
+    return np.concatenate([(1.0 - s) * n, s * n])
+
+
+def element_curvature(xa, xb, mesh, tri, h=1e-7):
+    """Hessian [6, 6] of the element contact's distance at (xa, xb) by central differences
+    of element_gap_gradient, against the edge line or vertex of triangle `tri` that holds
+    the nearest point of the chord point (zero when that point lies inside the face: a
+    plane, whose distance is linear in the nodes at fixed s)."""
+    s, p, _, _, region, _, _, _ = collision.element_contact_geometry(xa, xb, mesh, tri)
+    if region == collision.FACE:
+        return np.zeros((6, 6))
+    vs = {collision.VERT_A: (mesh.v0,), collision.VERT_B: (mesh.v1,), collision.VERT_C: (mesh.v2,),
+          collision.EDGE_AB: (mesh.v0, mesh.v1), collision.EDGE_AC: (mesh.v0, mesh.v2),
+          collision.EDGE_BC: (mesh.v1, mesh.v2)}[region]
+    feat = tuple(v[tri] for v in vs)
+    x = np.concatenate([xa, xb])
+    H = np.zeros((6, 6))
+    for k in range(6):
+        e = np.zeros(6)
+        e[k] = h
+        gp = element_gap_gradient((x + e)[0:3], (x + e)[3:6], *feat)
+        gm = element_gap_gradient((x - e)[0:3], (x - e)[3:6], *feat)
+        H[:, k] = (gp - gm) / (2.0 * h)
+    return 0.5 * (H + H.T)
+
+
 def loss_gradient_x(P, sensor_nodes, dL_dp):
     """Scatter dL/dp of the sensor nodes [n_s, 3] into a 6N vector."""
     g = np.zeros(6 * P.shape[0])
@@ -91,7 +138,12 @@ def tension_gradient(robot, P, R, contacts, y, act_values, sensor_nodes, dL_dp, 
     N = P.shape[0]
     J = jacobian(robot, P, R, act_kind, act_values)
     for c, yy in zip(contacts, y):
-        if yy > active_tol and c["kind"] != 0:
+        if yy > active_tol and c["kind"] == collision.ELEMENT:
+            i = c["node"]
+            H = element_curvature(P[i], P[i + 1], robot.mesh, c["tri"])
+            idx = np.r_[6 * i:6 * i + 3, 6 * i + 6:6 * i + 9]
+            J[np.ix_(idx, idx)] -= yy * H
+        elif yy > active_tol and c["kind"] != 0:
             i = c["node"]
             J[6 * i:6 * i + 3, 6 * i:6 * i + 3] -= yy * normal_derivative(P[i], robot.mesh, c["tri"])
     m = free_mask(robot, N, guided)
@@ -101,8 +153,9 @@ def tension_gradient(robot, P, R, contacts, y, act_values, sensor_nodes, dL_dp, 
     idx_free = np.cumsum(m) - 1
     A = np.zeros((len(act), int(m.sum())))
     for k, c in enumerate(act):
-        for d in range(3):
-            A[k, idx_free[6 * c["node"] + d]] = c["n"][d]
+        for i, wgt in collision.row_entries(c):
+            for d in range(3):
+                A[k, idx_free[6 * i + d]] += wgt * c["n"][d]
     nf = Jf.shape[0]
     na = A.shape[0]
     K = np.zeros((nf + na, nf + na))

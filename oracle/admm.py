@@ -22,7 +22,7 @@ u = +inf, and OSQP's multiplier y_o equals minus the contact force.  Per iterati
 stopping when the primal residual |A x - z|_inf and the dual residual
 |K x + q + A^T y_o|_inf (both over the free DOFs) are below eps_abs + eps_rel times the
 scale OSQP uses.  The matrix K + sigma I + rho A^T A stays block tridiagonal (every contact row
-lies on one node), so it is factored once (banded Cholesky) and every iteration is one
+lies on one node, or two adjacent ones), so it is factored once (banded Cholesky) and every iteration is one
 solve.  The prescribed DOFs keep identity rows and their increments throughout.
 """
 from __future__ import annotations
@@ -70,12 +70,7 @@ def qp_data(robot, P, R, F, ab, base_target, contacts, guided=None):
                 Kf[11 + j - k, k] = 0.0
             Kf[11, j] = 1.0
             b[j] = v
-    nc = len(contacts)
-    A = np.zeros((nc, nf))
-    g = np.zeros(nc)
-    for c, ct in enumerate(contacts):
-        A[c, 6 * (ct["node"] - 1):6 * (ct["node"] - 1) + 3] = ct["n"]
-        g[c] = ct["gap"]
+    A, g = solver.contact_rows(contacts, nf)
     for j in pres:
         A[:, j] = 0.0
     return Kf, b, A, g, sorted(pres), dx0
@@ -90,7 +85,8 @@ def admm_qp(Kf, b, A, g, fixed, rho, eps_abs=1e-10, eps_rel=1e-10, max_iter=1000
     free[list(fixed)] = False
     M = Kf.copy()
     M[11, :] += np.where(free, SIGMA, 0.0)
-    # rho A^T A: every contact row lies on one node's translations, inside the band
+    # rho A^T A: every contact row lies on the translations of one node or of two adjacent
+    # ones (a contact along an element), inside the band
     AtA = rho * (A.T @ A)
     for d in range(12):
         M[11 - d, d:] += np.diagonal(AtA, offset=d)

@@ -25,7 +25,9 @@ Reading of the unstated detection rule (the GPU path implements the same rule):
   centre sits r_c off a convex ridge of the wall lies in neither face region
   and slips through the wedge between them;
 * the clamped base node and nodes held by the insertion guide are never
-  contact nodes.  Contacts are ordered by node, then triangle index.
+  contact nodes.  Contacts are ordered by node, then triangle index;
+* contacts along an element (eq. 3-7 at 0 < xi < l0, optional): see
+  detect_elements below.
 """
 from __future__ import annotations
 
@@ -189,3 +191,125 @@ def contact_set(contacts):
 
 def active(contacts):
     return [c for c in contacts if c["tri"] >= 0]
+
+
+# ---------------------------------------------------------------- contact along an element
+# Eq. 3-7 put the contact point anywhere on an element, at xi in [0, l0] from its base-side
+# node, with N_i(xi) interpolating the two nodes' positions (B_i extracts their translations).
+# Reading: N_i acts in the element's chord frame, where both nodes lie on the axis, so its
+# Hermite transverse blend P3 + P4 = 1 returns their common transverse coordinate and the
+# point is the chord point p(s) = (1 - s) x_i + s x_{i+1}, s = xi / l0.  Node contacts are the
+# cases s = 0 and s = 1; on a triangle mesh the chord's interior comes closest to a convex
+# edge or vertex of the wall (against a plane the gap is linear in s, so the nearest point of
+# the chord to it is an end), which is what the element contacts below detect:
+#  * for every element whose two nodes are both contact nodes (not the clamped base, not held
+#    by the insertion guide) and every triangle t: the closest points of the chord and each
+#    of t's three edges (segment-segment, Ericson 2005, Real-Time Collision Detection, Sec.
+#    5.1.9), the nearest edge giving s* and the chord point p = p(s*);
+#  * a candidate when 0 < s* < 1, p lies in front of t (n_t . (p - v0) > 0), the closest
+#    point c of t to p lies on its boundary (edge or vertex region) and |p - c| <= r_c + delta;
+#    an edge (nearly) parallel to the chord, sin^2 of their angle below SEG_PARALLEL, gives
+#    none (the closest pair is not unique; the nodes' own contacts hold such a chord);
+#  * the element's contact is its nearest candidate (ties to the lowest triangle index):
+#    kind 2, stored at its base-side node i with s = s*, normal n = (p - c)/|p - c|, gap
+#    |p - c| - r_c; its constraint row is (1 - s) n^T on node i's translations and s n^T on
+#    node i+1's (the derivative of the gap of p(s) at fixed s), so that the contact force
+#    (eq. 11) acts as (1 - s) y n and s y n on the two nodes, statically equivalent to y n
+#    at p.
+SEG_PARALLEL = 1e-6
+ELEMENT = 2
+
+
+def segment_closest(p1, p2, q1, q2):
+    """Closest points of the segments p1p2 and q1q2 (both of positive length): parameters
+    (s, u) in [0, 1]^2 of p1 + s (p2 - p1) and q1 + u (q2 - q1), their distance and the
+    squared sine of the segments' angle.  The unconstrained minimiser of the squared distance
+    (a 2x2 linear system) is clamped to the square, one parameter at a time."""
+    d1 = p2 - p1
+    d2 = q2 - q1
+    r = p1 - q1
+    a = float(d1 @ d1)
+    e = float(d2 @ d2)
+    b = float(d1 @ d2)
+    c = float(d1 @ r)
+    f = float(d2 @ r)
+    den = a * e - b * b
+    sin2 = den / (a * e)
+    s = min(max((b * f - c * e) / den, 0.0), 1.0) if den > 0.0 else 0.0
+    u = (b * s + f) / e
+    if u < 0.0:
+        u = 0.0
+        s = min(max(-c / a, 0.0), 1.0)
+    elif u > 1.0:
+        u = 1.0
+        s = min(max((b - c) / a, 0.0), 1.0)
+    dist = float(np.linalg.norm(p1 + s * d1 - (q1 + u * d2)))
+    return s, u, dist, sin2
+
+
+def element_contact_geometry(xa, xb, mesh, t):
+    """Chord xa-xb against triangle t: (s*, p, sin2 of the nearest edge, closest point c of t
+    to p, its region, the region margin, the signed distance n_t . (p - v0), |p - c|)."""
+    verts = (mesh.v0[t], mesh.v1[t], mesh.v2[t])
+    best = None
+    for ea, eb in ((0, 1), (0, 2), (1, 2)):
+        s, u, dist, sin2 = segment_closest(xa, xb, verts[ea], verts[eb])
+        if best is None or dist < best[2]:
+            best = (s, u, dist, sin2)
+    s, _, _, sin2 = best
+    p = xa + s * (xb - xa)
+    cpt, region, margin = closest_points(p, mesh, np.array([t]))
+    front = float(mesh.n[t] @ (p - mesh.v0[t]))
+    d = float(np.linalg.norm(p - cpt[0]))
+    return s, p, sin2, cpt[0], int(region[0]), float(margin[0]), front, d
+
+
+def detect_elements(P, mesh, r_c, delta, cull=True, first_node=1, skip=None):
+    """Element contacts of one robot (kind 2, node = the element's base-side node, s = the
+    contact point's position along the element), ordered by node; entries flagged ambiguous
+    when a decision lies within AMBIG_TOL metres of a threshold."""
+    out = []
+    band = r_c + delta
+    reach = band + float(np.max(mesh.circum)) + 1e-6
+    for i in range(first_node, P.shape[0] - 1):
+        if skip is not None and (skip[i] or skip[i + 1]):
+            continue
+        xa, xb = P[i], P[i + 1]
+        ln = float(np.linalg.norm(xb - xa))
+        if cull:
+            idx = np.asarray(mesh.tree.query_ball_point(0.5 * (xa + xb), reach + 0.5 * ln), dtype=np.int64)
+            idx.sort()
+        else:
+            idx = np.arange(mesh.T.shape[0])
+        cands = []
+        amb = False
+        for t in idx:
+            s, p, sin2, c, region, margin, front, d = element_contact_geometry(xa, xb, mesh, int(t))
+            ok = (sin2 >= SEG_PARALLEL and 0.0 < s < 1.0 and front > 0.0 and region != FACE
+                  and d <= band)
+            near = d <= band + AMBIG_TOL and front >= -AMBIG_TOL
+            if near and (abs(sin2 - SEG_PARALLEL) <= 1e-9 or min(s, 1.0 - s) * ln <= AMBIG_TOL
+                         or abs(front) <= AMBIG_TOL or margin <= AMBIG_TOL or abs(d - band) <= AMBIG_TOL):
+                amb = True
+            if ok:
+                cands.append((d, int(t), s, p, c))
+        if cands:
+            cands.sort(key=lambda x: (x[0], x[1]))
+            d, t, s, p, c = cands[0]
+            if len(cands) > 1 and abs(cands[1][0] - d) <= AMBIG_TOL and (
+                    abs(cands[1][2] - s) * ln > AMBIG_TOL or np.linalg.norm(cands[1][4] - c) > AMBIG_TOL):
+                amb = True
+            out.append(dict(node=i, tri=t, kind=ELEMENT, s=float(s), n=(p - c) / d,
+                            gap=float(d - r_c), ambiguous=amb))
+        elif amb:
+            out.append(dict(node=i, tri=-1, kind=-1, n=None, gap=np.nan, s=0.0, ambiguous=True))
+    return out
+
+
+def row_entries(ct):
+    """The constraint row of a contact as (node, weight) pairs: (node, 1) for a node contact,
+    (i, 1 - s) and (i + 1, s) for a contact along element i."""
+    s = float(ct.get("s", 0.0))
+    if ct["kind"] == ELEMENT and s > 0.0:
+        return [(ct["node"], 1.0 - s), (ct["node"] + 1, s)]
+    return [(ct["node"], 1.0)]

@@ -51,6 +51,7 @@ class Robot:
     beta0: float
     guide_len: float = 0.0
     mesh: collision.Mesh | None = None
+    elements: bool = False            # contacts along elements (collision.detect_elements)
     l0: float = field(init=False)
     K12: np.ndarray = field(init=False)
     K7: np.ndarray = field(init=False)
@@ -119,6 +120,10 @@ def detect(robot, P, guided=None, prev=None):
     if robot.mesh is None:
         return []
     det = collision.active(collision.detect(P, robot.mesh, robot.r_c, robot.delta, skip=guided))
+    if robot.elements:
+        det = det + collision.active(collision.detect_elements(P, robot.mesh, robot.r_c, robot.delta,
+                                                               skip=guided))
+        det.sort(key=lambda c: (c["node"], c["kind"], c["tri"]))
     if prev is None:
         return det
     return persist_faces(robot, P, det, *prev)
@@ -142,7 +147,11 @@ def persist_faces(robot, P, det, cont_prev, y_prev):
         n = (p - q) / |p - q|, gap |p - q| - r_c, while the node is on the triangle's inner
         side (n_t . (p - v0_t) > 0, the fallback's own condition).
     It is dropped when a detected contact at the node has the same plane (normals and gaps
-    equal within PLANE_TOL: coplanar neighbours).
+    equal within PLANE_TOL: coplanar neighbours).  A contact along element i (kind 2) is
+    re-evaluated against its triangle with the chord's current position: it stays while
+    0 < s* < 1, the chord point p(s*) lies in front of the triangle and within r_c + delta of
+    it (normal and gap from the triangle's nearest point to p), unless a detected contact of
+    the same element has the same normal, gap and s within PLANE_TOL.
     """
     mesh = robot.mesh
     band = robot.r_c + robot.delta
@@ -156,6 +165,18 @@ def persist_faces(robot, P, det, cont_prev, y_prev):
         if not (y > 0.0) or key in keys:
             continue
         i, t = c["node"], c["tri"]
+        if c["kind"] == collision.ELEMENT:
+            s, p, _, cp, _, _, front, dist = collision.element_contact_geometry(P[i], P[i + 1], mesh, t)
+            if not (0.0 < s < 1.0 and front > 0.0 and 0.0 < dist <= band):
+                continue
+            n, gap = (p - cp) / dist, dist - robot.r_c
+            if any(o["kind"] == collision.ELEMENT and abs(float(n @ o["n"]) - 1.0) <= PLANE_TOL
+                   and abs(o["gap"] - gap) <= PLANE_TOL and abs(o["s"] - s) <= PLANE_TOL
+                   for o in by_node.get(i, [])):
+                continue
+            amb = any(o.get("ambiguous", False) for o in by_node.get(i, []))
+            extra.append(dict(node=i, tri=t, kind=c["kind"], s=float(s), n=n, gap=gap, ambiguous=amb))
+            continue
         p = P[i]
         cpt, _, _ = collision.closest_points(p, mesh, np.array([t]))
         dist = float(np.linalg.norm(p - cpt[0]))
@@ -233,12 +254,7 @@ def linear_step(robot, P, R, F, ab, base_target, contacts, guided=None, beta=Non
                 Kf[11 + j - k, k] = 0.0
             Kf[11, j] = 1.0
             rhs[j] = v
-    nc = len(contacts)
-    A = np.zeros((nc, nf))
-    g = np.zeros(nc)
-    for c, ct in enumerate(contacts):
-        A[c, 6 * (ct["node"] - 1):6 * (ct["node"] - 1) + 3] = ct["n"]
-        g[c] = ct["gap"]
+    A, g = contact_rows(contacts, nf)
     cb = scipy.linalg.cholesky_banded(Kf, lower=False)
     sol = scipy.linalg.cho_solve_banded((cb, False), np.column_stack([rhs, A.T]))
     dxf = sol[:, 0]
@@ -258,12 +274,26 @@ def linear_step(robot, P, R, F, ab, base_target, contacts, guided=None, beta=Non
     return dX, y, limited
 
 
+def contact_rows(contacts, nf):
+    """The rows A (eq. 9) and gaps g of the contacts over the nf free DOFs: n^T on the
+    translations of each node of the contact's row (collision.row_entries), times its weight."""
+    nc = len(contacts)
+    A = np.zeros((nc, nf))
+    g = np.zeros(nc)
+    for c, ct in enumerate(contacts):
+        for i, wgt in collision.row_entries(ct):
+            A[c, 6 * (i - 1):6 * (i - 1) + 3] += wgt * np.asarray(ct["n"])
+        g[c] = ct["gap"]
+    return A, g
+
+
 def contact_residual(F, contacts, y, robot=None, guided=None):
     """Residual over the free DOFs: F - F_a - A^T y, with guided lateral DOFs zeroed
     (their out-of-balance is the guide's reaction)."""
     r = F[1:].copy()
     for c, ct in enumerate(contacts):
-        r[ct["node"] - 1, 0:3] -= y[c] * ct["n"]
+        for i, wgt in collision.row_entries(ct):
+            r[i - 1, 0:3] -= wgt * y[c] * ct["n"]
     if guided is not None and np.any(guided):
         ax = int(np.argmax(np.abs(robot.base_dir)))
         lat = [k for k in range(3) if k != ax]

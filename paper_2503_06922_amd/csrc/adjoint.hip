@@ -225,8 +225,9 @@ __global__ void __launch_bounds__(256) adj_basis_kernel(Dev d, const int32_t* se
       if (d.cp_node[cb + mid] < i) lo = mid + 1; else hi = mid;
     }
     for (int c = lo; c < d.st_ncp[r] && d.cp_node[cb + c] == i; ++c)
-      if (d.cp_y[cb + c] > 0.0)
-        add_normal(d.cp_n[3 * (cb + c)], d.cp_n[3 * (cb + c) + 1], d.cp_n[3 * (cb + c) + 2]);
+      if (d.cp_y[cb + c] > 0.0 && d.cp_kind[cb + c] != K_ELEM)   // (robots with active contacts
+        add_normal(d.cp_n[3 * (cb + c)], d.cp_n[3 * (cb + c) + 1],   // along an element are
+                   d.cp_n[3 * (cb + c) + 2]);                        // not supported)
     fixed = k;
   }
   // complete the basis
@@ -355,6 +356,15 @@ __global__ void __launch_bounds__(64) adj_sweep_kernel(Dev d, const double* JL, 
   const int lane = threadIdx.x;
   const int64_t o = d.off[r], n = d.off[r + 1] - o;
   const int nv = d.act_nv;
+  // an active contact along an element couples two nodes: not supported by this elimination
+  int elem = 0;
+  {
+    const int64_t cb = (int64_t)r * d.cap;
+    for (int c = lane; c < d.st_ncp[r]; c += 64)
+      elem |= (d.cp_kind[cb + c] == K_ELEM && d.cp_y[cb + c] > 0.0) ? 1 : 0;
+#pragma unroll
+    for (int o2 = 32; o2 > 0; o2 >>= 1) elem |= __shfl_xor(elem, o2);
+  }
   double v[6] = {0, 0, 0, 0, 0, 0};  // G_{i-1} column (lanes 6..11), h_{i-1} (lane 12)
   bool bad = false;
   for (int64_t i = 0; i < n; ++i) {
@@ -416,7 +426,7 @@ __global__ void __launch_bounds__(64) adj_sweep_kernel(Dev d, const double* JL, 
     lam[3] = v[3]; lam[4] = v[4]; lam[5] = v[5];
     double p[3], R[9];
     node_pR(d, gt, p, R);
-    const bool ok = !bad && d.st_status[r] == 0;
+    const bool ok = !bad && d.st_status[r] == 0 && !elem;
     double* y = out + (int64_t)r * nv;
     if (d.act_kind == 0 || d.act_kind == 3) {
       for (int j = 0; j < d.n_cables; ++j) {
@@ -442,7 +452,7 @@ __global__ void __launch_bounds__(64) adj_sweep_kernel(Dev d, const double* JL, 
 #pragma unroll
       for (int j = 0; j < 6; ++j) y[j] = ok ? lam[j] : NAN;
     }
-    rstat[r] = bad ? 1 : (d.st_status[r] != 0 ? 2 : 0);
+    rstat[r] = bad ? 1 : (d.st_status[r] != 0 ? 2 : (elem ? 3 : 0));
   }
 }
 

@@ -569,6 +569,10 @@ static fem_status create_impl(fem_ctx* c, const fem_params* p) {
     return bad("max_newton or contact_capacity out of range");
   if (!(p->newton_tol > 0.0) || !(p->stag_tol >= 0.0)) return bad("tolerances out of range");
   if (p->qp_solver != FEM_QP_EXACT && p->qp_solver != FEM_QP_ADMM) return bad("unknown qp_solver");
+  if (p->contact_along_elements != 0 && p->contact_along_elements != 1)
+    return bad("contact_along_elements must be 0 or 1");
+  if (p->contact_along_elements && p->qp_solver != FEM_QP_EXACT)
+    return bad("contacts along elements need qp_solver = FEM_QP_EXACT");
   if (p->admm_rho < 0.0 || p->admm_eps < 0.0 || p->admm_max_iter < 0)
     return bad("ADMM parameters out of range");
   c->p = *p;
@@ -680,6 +684,7 @@ static fem_status create_impl(fem_ctx* c, const fem_params* p) {
   d.act_cur = c->act_cur; d.depth_cur = c->dep_cur; d.act_kind = 0; d.act_nv = p->n_cables;
   d.guide_len = p->guide_len;
   d.r_c = p->contact_radius; d.delta = p->contact_margin; d.beta0 = p->beta0;
+  d.elements = p->contact_along_elements;
   d.newton_tol = p->newton_tol; d.stag_tol = p->stag_tol; d.max_newton = p->max_newton;
   d.cap = cap;
   d.mixed = (p->precision == FEM_MIXED) ? 1 : 0;
@@ -691,13 +696,13 @@ static fem_status create_impl(fem_ctx* c, const fem_params* p) {
   c->kc = kc;
   ALLOC(d.LD, 36 * N); ALLOC(d.LS, 36 * N);
   ALLOC(d.CC, N); ALLOC(d.CT, MAXC * N); ALLOC(d.CK, MAXC * N); ALLOC(d.CN, 3 * MAXC * N);
-  ALLOC(d.CG, MAXC * N); ALLOC(d.CW, MAXC * N);
+  ALLOC(d.CG, MAXC * N); ALLOC(d.CS, MAXC * N); ALLOC(d.CW, MAXC * N);
   HIP_TRY(c, hipMemset(d.CC, 0, N * sizeof(int32_t)));
   const int64_t BC = (int64_t)B * cap;
   ALLOC(d.ct_node, BC); ALLOC(d.ct_tri, BC); ALLOC(d.ct_kind, BC); ALLOC(d.ct_n, 3 * BC);
-  ALLOC(d.ct_gap, BC); ALLOC(d.ct_y, BC); ALLOC(d.ct_warm, BC);
+  ALLOC(d.ct_gap, BC); ALLOC(d.ct_y, BC); ALLOC(d.ct_s, BC); ALLOC(d.ct_warm, BC);
   ALLOC(d.cp_node, BC); ALLOC(d.cp_tri, BC); ALLOC(d.cp_kind, BC); ALLOC(d.cp_n, 3 * BC);
-  ALLOC(d.cp_gap, BC); ALLOC(d.cp_y, BC);
+  ALLOC(d.cp_gap, BC); ALLOC(d.cp_y, BC); ALLOC(d.cp_s, BC);
   std::vector<int64_t> zoff(B);
   int64_t zt = 0;
   for (int r = 0; r < B; ++r) { zoff[r] = zt; zt += 6 * (int64_t)(c->h_nelem[r] + 1); }
@@ -1142,7 +1147,8 @@ fem_status fem_grad(fem_ctx* c, const int32_t* sensor_nodes, int32_t n_sensors,
   int n_bad = 0;
   for (int r = 0; r < B; ++r) n_bad += (rs[r] != 0);
   if (n_bad) return fail(c, FEM_E_NOCONV, "fem_grad: " + std::to_string(n_bad) +
-                                              " robot(s) not converged or with a singular adjoint system");
+                                              " robot(s) not converged, with a singular adjoint system or"
+                                              " with an active contact along an element");
   return FEM_OK;
 }
 
@@ -1215,7 +1221,7 @@ fem_status fem_contacts(const fem_ctx* cc, int32_t robot, fem_contact* out, int3
   std::vector<fem_contact> h;
   h.reserve(std::min<int64_t>(total, capacity));
   std::vector<int32_t> nd(cap), tr(cap), kd(cap);
-  std::vector<double> nn(3 * cap), gp(cap), yy(cap);
+  std::vector<double> nn(3 * cap), gp(cap), yy(cap), ss(cap);
   for (int r = r0; r < r1 && (int64_t)h.size() < capacity; ++r) {
     const int n = ncp[r];
     if (n == 0) continue;
@@ -1226,11 +1232,12 @@ fem_status fem_contacts(const fem_ctx* cc, int32_t robot, fem_contact* out, int3
     HIP_TRY(c, hipMemcpy(nn.data(), d.cp_n + 3 * cb, 3 * n * sizeof(double), hipMemcpyDeviceToHost));
     HIP_TRY(c, hipMemcpy(gp.data(), d.cp_gap + cb, n * sizeof(double), hipMemcpyDeviceToHost));
     HIP_TRY(c, hipMemcpy(yy.data(), d.cp_y + cb, n * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(ss.data(), d.cp_s + cb, n * sizeof(double), hipMemcpyDeviceToHost));
     for (int k = 0; k < n && (int64_t)h.size() < capacity; ++k) {
       fem_contact ct;
       ct.robot = r; ct.node = nd[k]; ct.tri = tr[k]; ct.kind = kd[k];
       ct.n[0] = nn[3 * k]; ct.n[1] = nn[3 * k + 1]; ct.n[2] = nn[3 * k + 2];
-      ct.gap = gp[k]; ct.force = yy[k];
+      ct.gap = gp[k]; ct.force = yy[k]; ct.s = ss[k];
       h.push_back(ct);
     }
   }

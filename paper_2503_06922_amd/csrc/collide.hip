@@ -144,6 +144,7 @@ __global__ void __launch_bounds__(256) collide_kernel(Dev d) {
         d.CK[pos * N + g] = 0;
         d.CW[pos * N + g] = 0;
         d.CG[pos * N + g] = tt.s - d.r_c;
+        d.CS[pos * N + g] = 0.0;
         d.CN[(3 * pos + 0) * N + g] = tt.n.x;
         d.CN[(3 * pos + 1) * N + g] = tt.n.y;
         d.CN[(3 * pos + 2) * N + g] = tt.n.z;
@@ -167,6 +168,7 @@ __global__ void __launch_bounds__(256) collide_kernel(Dev d) {
         d.CK[g] = 1;
         d.CW[g] = 0;
         d.CG[g] = best_d - d.r_c;
+        d.CS[g] = 0.0;
         const double inv = 1.0 / best_d;
         d.CN[0 * N + g] = (p.x - best_cp.x) * inv;
         d.CN[1 * N + g] = (p.y - best_cp.y) * inv;
@@ -195,6 +197,7 @@ __global__ void __launch_bounds__(256) collide_kernel(Dev d) {
     if (!(d.cp_y[cb + c] > 0.0)) continue;
     const int32_t t = d.cp_tri[cb + c];
     const int32_t kc = d.cp_kind[cb + c];
+    if (kc == K_ELEM) continue;           // contacts along the element: collide_elem_kernel
     // detected again: it starts the LCP's active set
     bool found = false;
     for (int q = 0; q < ndet; ++q)
@@ -227,6 +230,7 @@ __global__ void __launch_bounds__(256) collide_kernel(Dev d) {
       d.CK[cnt * N + g] = kc;
       d.CW[cnt * N + g] = 1;
       d.CG[cnt * N + g] = gap;
+      d.CS[cnt * N + g] = 0.0;
       d.CN[(3 * cnt + 0) * N + g] = nc.x;
       d.CN[(3 * cnt + 1) * N + g] = nc.y;
       d.CN[(3 * cnt + 2) * N + g] = nc.z;
@@ -257,6 +261,250 @@ __global__ void __launch_bounds__(256) collide_kernel(Dev d) {
     d.CN[(3 * (b + 1) + 2) * N + g] = n2;
   }
   d.CC[g] = cnt;  // > MAXC flags an overflow for the gather step
+}
+
+// ---------------------------------------------------------------- contacts along elements
+// Eq. 3-7 with 0 < xi < l0: the contact point on element g -> g+1 is the chord point
+// p(s) = (1 - s) x_g + s x_{g+1} (N_i in the element's chord frame, where both nodes lie on the
+// axis).  Per element whose two nodes are contact nodes, every triangle of the grid cells the
+// chord crosses: the closest points of the chord and each of the triangle's edges (segment-
+// segment, Ericson 2005, Sec. 5.1.9), the nearest edge giving s*; a candidate when 0 < s* < 1,
+// the edge is not (nearly) parallel to the chord (sin^2 >= SEG_PARALLEL), p(s*) lies in front
+// of the triangle, its nearest point c on the triangle is on an edge or vertex and |p - c| <=
+// r_c + delta.  The element's contact is the group's nearest candidate (ties to the lowest
+// triangle): kind 2 at node g with s = s*, normal (p - c)/|p - c| and gap |p - c| - r_c.  A
+// contact along the element that carried force at the previous iterate and is not detected
+// again persists while 0 < s* < 1, p(s*) lies in front of its triangle and within the band of
+// it (unless the detected one has the same normal, gap and s), as node contacts do.  The
+// entries follow the node's own contacts (ordered by triangle).
+
+// closest points of segments p1p2 and q1q2: the chord parameter s, the squared sine of their
+// angle, the distance (the unconstrained minimiser clamped to [0,1]^2 one parameter at a time)
+__device__ __forceinline__ double seg_closest(P3<double> p1, P3<double> p2, P3<double> q1, P3<double> q2,
+                                              double* s_out, double* sin2_out) {
+  const P3<double> d1 = sub(p2, p1), d2 = sub(q2, q1), r = sub(p1, q1);
+  const double a = dotp(d1, d1), e = dotp(d2, d2), b = dotp(d1, d2);
+  const double c = dotp(d1, r), f = dotp(d2, r);
+  const double den = a * e - b * b;
+  double s = den > 0.0 ? fmin(fmax((b * f - c * e) / den, 0.0), 1.0) : 0.0;
+  double u = (b * s + f) / e;
+  if (u < 0.0) {
+    u = 0.0;
+    s = fmin(fmax(-c / a, 0.0), 1.0);
+  } else if (u > 1.0) {
+    u = 1.0;
+    s = fmin(fmax((b - c) / a, 0.0), 1.0);
+  }
+  *s_out = s;
+  *sin2_out = den / (a * e);
+  const P3<double> dd = sub(axpy(p1, s, d1), axpy(q1, u, d2));
+  return sqrt(dotp(dd, dd));
+}
+
+struct ElemTest { double s, sin2, front, dist; int region; P3<double> p, cp; };
+
+// chord xa-xb against triangle t
+__device__ __forceinline__ ElemTest elem_tri(const Dev& d, int64_t t, P3<double> xa, P3<double> xb) {
+  const double4* rec = reinterpret_cast<const double4*>(d.tv + 12 * t);
+  const double4 A = rec[0], B = rec[1], C = rec[2];
+  const P3<double> a{A.x, A.y, A.z}, b{B.x, B.y, B.z}, c{C.x, C.y, C.z};
+  const P3<double> nt{A.w, B.w, C.w};
+  ElemTest r;
+  double s1, w1, s2, w2, s3, w3;
+  const double d1 = seg_closest(xa, xb, a, b, &s1, &w1);
+  const double d2 = seg_closest(xa, xb, a, c, &s2, &w2);
+  const double d3 = seg_closest(xa, xb, b, c, &s3, &w3);
+  // the nearest edge, the first of equally near ones in the order ab, ac, bc
+  r.s = s1; r.sin2 = w1;
+  double dm = d1;
+  if (d2 < dm) { dm = d2; r.s = s2; r.sin2 = w2; }
+  if (d3 < dm) { r.s = s3; r.sin2 = w3; }
+  r.p = axpy(xa, r.s, sub(xb, xa));
+  r.region = closest_on_tri(r.p, a, b, c, &r.cp);
+  r.front = dotp(nt, sub(r.p, a));
+  const P3<double> dv = sub(r.p, r.cp);
+  r.dist = sqrt(dotp(dv, dv));
+  return r;
+}
+
+// the chord x0-x1 meets the box [lo, hi] (slab test, widened by a relative 1e-9 so that a
+// rounding never drops a cell)
+__device__ __forceinline__ bool chord_meets_box(P3<double> x0, P3<double> x1, const double* lo, const double* hi) {
+  double t0 = 0.0, t1 = 1.0;
+  const double p0[3] = {x0.x, x0.y, x0.z}, dp[3] = {x1.x - x0.x, x1.y - x0.y, x1.z - x0.z};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double w = 1e-9 * (hi[k] - lo[k]);
+    const double l = lo[k] - w, h = hi[k] + w;
+    if (dp[k] == 0.0) {
+      if (p0[k] < l || p0[k] > h) return false;
+    } else {
+      double ta = (l - p0[k]) / dp[k], tb = (h - p0[k]) / dp[k];
+      if (ta > tb) { const double x = ta; ta = tb; tb = x; }
+      t0 = fmax(t0, ta);
+      t1 = fmin(t1, tb);
+      if (t0 > t1) return false;
+    }
+  }
+  return true;
+}
+
+template <int CL>
+__global__ void __launch_bounds__(256) collide_elem_kernel(Dev d) {
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t g = gt / CL;
+  const int j = (int)(gt % CL);
+  if (g >= d.Ntot) return;
+  const int r = d.robot_of[g];
+  if (d.st_done[r]) return;
+  const int64_t N = d.Ntot;
+  const int64_t i = g - d.off[r], n = d.off[r + 1] - d.off[r];
+  if (i == 0 || i + 1 >= n || d.n_tris == 0) return;
+  if (d.guide_axis[r] >= 0) {
+    // node i inside the guide (the guided nodes are the first ones, so node i + 1 may be too)
+    const double s = __dadd_rn(__dmul_rn((double)i, d.l0[r]), d.depth_cur[r]);
+    if (s < d.guide_len) return;
+  }
+  const P3<double> xa{d.X[g], d.X[N + g], d.X[2 * N + g]};
+  const P3<double> xb{d.X[g + 1], d.X[N + g + 1], d.X[2 * N + g + 1]};
+  const double band = d.r_c + d.delta;
+  const P3<double> ab = sub(xb, xa);
+  const double ab2 = dotp(ab, ab);
+  // grid cells of the chord's bounding box
+  int c0[3], c1[3];
+  {
+    const double lo[3] = {fmin(xa.x, xb.x), fmin(xa.y, xb.y), fmin(xa.z, xb.z)};
+    const double hi[3] = {fmax(xa.x, xb.x), fmax(xa.y, xb.y), fmax(xa.z, xb.z)};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      c0[k] = max(0, (int)floor((lo[k] - d.g_org[k]) / d.g_h));
+      c1[k] = min(d.g_dim[k] - 1, (int)floor((hi[k] - d.g_org[k]) / d.g_h));
+    }
+  }
+  int best_t = 0x7fffffff;
+  double best_d = INFINITY, best_s = 0.0;
+  P3<double> best_p{0, 0, 0}, best_cp{0, 0, 0};
+  for (int cz = c0[2]; cz <= c1[2]; ++cz)
+    for (int cy = c0[1]; cy <= c1[1]; ++cy)
+      for (int cx = c0[0]; cx <= c1[0]; ++cx) {
+        const double blo[3] = {d.g_org[0] + cx * d.g_h, d.g_org[1] + cy * d.g_h, d.g_org[2] + cz * d.g_h};
+        const double bhi[3] = {blo[0] + d.g_h, blo[1] + d.g_h, blo[2] + d.g_h};
+        if (!chord_meets_box(xa, xb, blo, bhi)) continue;
+        const int64_t cell = ((int64_t)cz * d.g_dim[1] + cy) * d.g_dim[0] + cx;
+        const int32_t b0 = d.cell_start[cell], b1 = d.cell_start[cell + 1];
+        for (int32_t k = b0 + j; k < b1; k += CL) {
+          const int32_t t = d.cell_tris[k];
+          // bounding sphere against the chord: its centre's distance to the segment
+          const double4 S = d.cell_sd[k];
+          const P3<double> sc{S.x, S.y, S.z};
+          const double tt = ab2 > 0.0 ? fmin(fmax(dotp(sub(sc, xa), ab) / ab2, 0.0), 1.0) : 0.0;
+          const P3<double> dq = sub(sc, axpy(xa, tt, ab));
+          const double rr = (S.w + band) * (1.0 + 1e-12);
+          if (dotp(dq, dq) > rr * rr) continue;
+          const ElemTest e = elem_tri(d, t, xa, xb);
+          const bool ok = e.sin2 >= SEG_PARALLEL && e.s > 0.0 && e.s < 1.0 && e.front > 0.0 &&
+                          e.region != R_FACE && e.dist <= band;
+          if (ok && (e.dist < best_d || (e.dist == best_d && t < best_t))) {
+            best_d = e.dist; best_t = t; best_s = e.s; best_p = e.p; best_cp = e.cp;
+          }
+        }
+      }
+  // the group's nearest candidate, ties to the lowest triangle index
+  double bd = best_d;
+  int bt = best_t;
+#pragma unroll
+  for (int o = 1; o < CL; o <<= 1) {
+    const double od = __shfl_xor(bd, o);
+    const int ot = __shfl_xor(bt, o);
+    if (od < bd || (od == bd && ot < bt)) { bd = od; bt = ot; }
+  }
+  // the winning lane hands its point over to the group's first lane through registers
+  const int gl = (int)(threadIdx.x & 63) & ~(CL - 1);
+  const unsigned long long win = __ballot(bt != 0x7fffffff && best_t == bt && best_d == bd) &
+                                 (((1ull << CL) - 1ull) << gl);
+  const int wl = win ? __ffsll((long long)win) - 1 : gl;
+  const double ws = __shfl(best_s, wl), wpx = __shfl(best_p.x, wl), wpy = __shfl(best_p.y, wl),
+               wpz = __shfl(best_p.z, wl), wcx = __shfl(best_cp.x, wl), wcy = __shfl(best_cp.y, wl),
+               wcz = __shfl(best_cp.z, wl);
+  if (j != 0) return;
+  int cnt = d.CC[g];
+  const int base = cnt;
+  auto put = [&](int32_t t, int32_t warm, double gap, double s, P3<double> nc) {
+    if (cnt < MAXC) {
+      d.CT[cnt * N + g] = t;
+      d.CK[cnt * N + g] = K_ELEM;
+      d.CW[cnt * N + g] = warm;
+      d.CG[cnt * N + g] = gap;
+      d.CS[cnt * N + g] = s;
+      d.CN[(3 * cnt + 0) * N + g] = nc.x;
+      d.CN[(3 * cnt + 1) * N + g] = nc.y;
+      d.CN[(3 * cnt + 2) * N + g] = nc.z;
+    }
+    ++cnt;
+  };
+  const int64_t cb = (int64_t)r * d.cap;
+  const int ncp = d.st_ncp[r];
+  const bool fresh = d.st_it[r] == 0;
+  int lo = 0, hi = ncp;
+  while (lo < hi) {
+    const int m = (lo + hi) >> 1;
+    if (d.cp_node[cb + m] < i) lo = m + 1; else hi = m;
+  }
+  double det_gap = 0.0, det_s = 0.0;
+  P3<double> det_n{0, 0, 0};
+  const bool have = bt != 0x7fffffff;
+  if (have) {
+    int32_t warm = 0;
+    for (int c = lo; c < ncp && d.cp_node[cb + c] == i; ++c)
+      warm |= (d.cp_kind[cb + c] == K_ELEM && d.cp_tri[cb + c] == bt && d.cp_y[cb + c] > 0.0) ? 1 : 0;
+    const double inv = 1.0 / bd;
+    det_n = P3<double>{(wpx - wcx) * inv, (wpy - wcy) * inv, (wpz - wcz) * inv};
+    det_gap = bd - d.r_c;
+    det_s = ws;
+    put(bt, warm, det_gap, det_s, det_n);
+  }
+  if (!fresh) {
+    for (int c = lo; c < ncp && d.cp_node[cb + c] == i; ++c) {
+      if (d.cp_kind[cb + c] != K_ELEM || !(d.cp_y[cb + c] > 0.0)) continue;
+      const int32_t t = d.cp_tri[cb + c];
+      if (have && t == bt) continue;
+      const ElemTest e = elem_tri(d, t, xa, xb);
+      if (!(e.s > 0.0 && e.s < 1.0 && e.front > 0.0 && e.dist > 0.0 && e.dist <= band)) continue;
+      const double inv = 1.0 / e.dist;
+      const P3<double> nc{(e.p.x - e.cp.x) * inv, (e.p.y - e.cp.y) * inv, (e.p.z - e.cp.z) * inv};
+      const double gap = e.dist - d.r_c;
+      if (have && fabs(dotp(nc, det_n) - 1.0) <= PLANE_TOL && fabs(gap - det_gap) <= PLANE_TOL &&
+          fabs(e.s - det_s) <= PLANE_TOL)
+        continue;
+      put(t, 1, gap, e.s, nc);
+    }
+  }
+  // order the element's entries by triangle (insertion sort of the few appended)
+  const int e1 = min(cnt, MAXC);
+  for (int a = base + 1; a < e1; ++a) {
+    const int32_t ta = d.CT[a * N + g], wa = d.CW[a * N + g];
+    const double ga = d.CG[a * N + g], sa = d.CS[a * N + g], n0 = d.CN[(3 * a) * N + g],
+                 n1 = d.CN[(3 * a + 1) * N + g], n2 = d.CN[(3 * a + 2) * N + g];
+    int b = a - 1;
+    while (b >= base && d.CT[b * N + g] > ta) {
+      d.CT[(b + 1) * N + g] = d.CT[b * N + g];
+      d.CK[(b + 1) * N + g] = d.CK[b * N + g];
+      d.CW[(b + 1) * N + g] = d.CW[b * N + g];
+      d.CG[(b + 1) * N + g] = d.CG[b * N + g];
+      d.CS[(b + 1) * N + g] = d.CS[b * N + g];
+      for (int k = 0; k < 3; ++k) d.CN[(3 * (b + 1) + k) * N + g] = d.CN[(3 * b + k) * N + g];
+      --b;
+    }
+    d.CT[(b + 1) * N + g] = ta;
+    d.CK[(b + 1) * N + g] = K_ELEM;
+    d.CW[(b + 1) * N + g] = wa;
+    d.CG[(b + 1) * N + g] = ga;
+    d.CS[(b + 1) * N + g] = sa;
+    d.CN[(3 * (b + 1)) * N + g] = n0;
+    d.CN[(3 * (b + 1) + 1) * N + g] = n1;
+    d.CN[(3 * (b + 1) + 2) * N + g] = n2;
+  }
+  d.CC[g] = cnt;
 }
 
 // triangle planes: vertices to SoA, unit inward normals (FP64 and FP32 copies)
@@ -306,6 +554,8 @@ void launch_collide(const Dev& d, hipStream_t s) {
   if (cl == 4) hipLaunchKernelGGL(collide_kernel<4>, dim3((unsigned)blocks), dim3(T), 0, s, d);
   else if (cl == 16) hipLaunchKernelGGL(collide_kernel<16>, dim3((unsigned)blocks), dim3(T), 0, s, d);
   else hipLaunchKernelGGL(collide_kernel<8>, dim3((unsigned)blocks), dim3(T), 0, s, d);
+  if (d.elements)
+    hipLaunchKernelGGL(collide_elem_kernel<8>, dim3((unsigned)((d.Ntot * 8 + T - 1) / T)), dim3(T), 0, s, d);
 }
 
 __global__ void cell_spheres_kernel(const int32_t* cell_tris, int64_t n, const double4* tsd,

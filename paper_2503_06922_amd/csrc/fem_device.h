@@ -7,8 +7,9 @@
 //   tangent      E1[k*Ntot + g], k = 0..2: chord direction of element g -> g+1 (FP64, or
 //                E1f in FP32 in mixed precision); KC[k*Ntot + g], k = 0..5: its constants
 //   factor       LD[g*36 + k], LS[g*36 + k]: Cholesky blocks L[g,g] and L[g+1,g]
-//   node contacts (detection output, up to MAXC per node): CC[g], CT/CK/CG[s*Ntot+g],
-//                CN[(3*s+d)*Ntot + g]
+//   node contacts (detection output, up to MAXC per node): CC[g], CT/CK/CG/CS[s*Ntot+g],
+//                CN[(3*s+d)*Ntot + g]; a contact along the element g -> g+1 is an entry of
+//                node g with kind 2 and its position CS along the element
 //   per-robot contact lists, solutions and Schur matrices live at per-robot
 //   offsets (robot r: contacts at r*cap, right-hand sides / solutions at zoff[r]).
 #pragma once
@@ -22,6 +23,10 @@ namespace accfem {
 __host__ __device__ inline int64_t lcp_ws_doubles(int cap) {
   return (int64_t)cap * (cap + 1) / 2 + 3 * (int64_t)cap;
 }
+// contact kinds: a face, an edge or vertex of the wall (both at a node), along an element
+enum { K_FACE = 0, K_FEAT = 1, K_ELEM = 2 };
+constexpr double SEG_PARALLEL = 1e-6;  // an edge this parallel to a chord (sin^2) gives no
+                                       // contact along the element
 constexpr int MAXC = 48;         // contact candidates kept per node (a node in a branch
                                  // narrower than the band meets a ring of facets)
 constexpr int SOLVE_THREADS = 64;  // one wavefront per robot in the solve kernel
@@ -59,6 +64,7 @@ struct Dev {
   double guide_len;
   // contact rule
   double r_c, delta, beta0;
+  int elements;             // contacts along elements as well (kind 2)
   double newton_tol, stag_tol;
   const double* stag_r;     // [B] stagnation level per robot
   int max_newton;
@@ -90,6 +96,7 @@ struct Dev {
   int32_t* CK;
   double* CN;
   double* CG;
+  double* CS;           // kind 2: position s of the contact point along the element (else 0)
   int32_t* CW;          // entry carried force at the previous iterate (warm start of the LCP)
   // per robot contact lists (current and previous), capacity cap each
   int32_t* ct_node;   // [B*cap]
@@ -98,6 +105,7 @@ struct Dev {
   double* ct_n;       // [B*cap*3]
   double* ct_gap;
   double* ct_y;
+  double* ct_s;         // kind 2: row (1 - s) n on node, s n on node + 1; else s = 0
   int32_t* ct_warm;     // contact carried force at the previous iterate
   int32_t* cp_node;
   int32_t* cp_tri;
@@ -105,6 +113,7 @@ struct Dev {
   double* cp_n;
   double* cp_gap;
   double* cp_y;
+  double* cp_s;
   // right-hand side and step: robot r owns Z[zoff[r] .. zoff[r] + 6*N_r), row 6 f + k of free
   // node f: the right-hand side b of the linear step (check_rhs_kernel), then the step dx
   const int64_t* zoff;

@@ -8,7 +8,8 @@
 // Linear step (eq. 20-23): with the base node prescribed (clamp + insertion,
 // eq. 14-15) and the lateral DOFs of guided nodes prescribed on the guide axis,
 //     K dx = -r + A^T y,   0 <= y  _|_  g + A dx >= 0,
-// where A has one row n_c^T on the translations of each contact node.  With
+// where A has one row n_c^T on the translations of each contact node (along an element:
+// (1 - s) n_c^T on its base-side node and s n_c^T on the next).  With
 // K = L L^T (6x6 blocks, serial over nodes), dx_free = -K^-1 r, Z = K^-1 A^T,
 // W = A Z (SPD) and q = g + A dx_free, the contact forces solve LCP(q, W); the
 // primal active-set method used here (Lawson-Hanson style, with a dense
@@ -126,6 +127,7 @@ __device__ void gather_contacts(const Dev& d, int r, int* nc_out, bool* overflow
         d.ct_kind[base + pos] = d.CK[s * N + g];
         d.ct_warm[base + pos] = d.CW[s * N + g];
         d.ct_gap[base + pos] = d.CG[s * N + g];
+        d.ct_s[base + pos] = d.CS[s * N + g];
         d.ct_n[3 * (base + pos) + 0] = d.CN[(3 * s + 0) * N + g];
         d.ct_n[3 * (base + pos) + 1] = d.CN[(3 * s + 1) * N + g];
         d.ct_n[3 * (base + pos) + 2] = d.CN[(3 * s + 2) * N + g];
@@ -186,20 +188,22 @@ __global__ void __launch_bounds__(NT) check_rhs_kernel(Dev d) {
     const int64_t chunk = (nf + NT - 1) / NT;
     const int64_t f0 = min(nf, (int64_t)lane * chunk), f1 = min(nf, f0 + chunk);
     double ss = 0.0;
+    // contacts of node i (weight 1 - s) and contacts along the element i-1 -> i (weight s)
     int cp = 0;
-    while (cp < ncp && d.cp_node[cb + cp] < f0 + 1) ++cp;
+    while (cp < ncp && d.cp_node[cb + cp] < f0) ++cp;
     for (int64_t f = f0; f < f1; ++f) {
       const int64_t i = f + 1, g = o + i;
       double rv[6];
 #pragma unroll
       for (int k = 0; k < 6; ++k) rv[k] = d.F[k * N + g];
-      while (cp < ncp && d.cp_node[cb + cp] == i) {
-        const double y = d.cp_y[cb + cp];
-        rv[0] -= y * d.cp_n[3 * (cb + cp) + 0];
-        rv[1] -= y * d.cp_n[3 * (cb + cp) + 1];
-        rv[2] -= y * d.cp_n[3 * (cb + cp) + 2];
-        ++cp;
+      for (int c = cp; c < ncp && d.cp_node[cb + c] <= i; ++c) {
+        const double sv = d.cp_s[cb + c];
+        const double y = d.cp_y[cb + c] * (d.cp_node[cb + c] == i ? 1.0 - sv : sv);
+        rv[0] -= y * d.cp_n[3 * (cb + c) + 0];
+        rv[1] -= y * d.cp_n[3 * (cb + c) + 1];
+        rv[2] -= y * d.cp_n[3 * (cb + c) + 2];
       }
+      while (cp < ncp && d.cp_node[cb + cp] < i) ++cp;     // node i's contacts start node i+1's
 #pragma unroll
       for (int k = 0; k < 6; ++k)
         if (!G.dof(i, k)) ss += rv[k] * rv[k];
@@ -340,7 +344,8 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 // The factoring wave also puts L_ii and X into small LDS rings; between the same two barriers
 // of step k, its side's forward wave (one lane per right-hand side) takes step k-1,
 // y = L_ii^-1 (b - X_prev y_prev), from the rings, reading b of column 0 from Z and generating
-// the contact columns (n_c at the contact node), and keeps y at the checkpoint nodes in Y.
+// the contact columns (n_c at the contact node; (1 - s) n_c and s n_c at the two nodes of a
+// contact along an element), and keeps y at the checkpoint nodes in Y.
 // At the middle node the forward values of both sides meet: z_m = L_m^-1 (b_m - X_top y_top -
 // X_bot y_bot), and the middle node's solution x_m = L_m^-T z_m goes to XM, where the
 // substitution starts both sides' backward sweeps.
@@ -361,6 +366,7 @@ __global__ void __launch_bounds__(4 * NT) __attribute__((amdgpu_waves_per_eu(3))
   __shared__ double rD[2][2][36], rS[2][3][36];   // L_ii by step % 2, X by step % 3, per side
   __shared__ int32_t sFC[NT];
   __shared__ double sNC[3 * NT];
+  __shared__ double sSC[NT];                  // contact column's s (row on nodes fc, fc + 1)
   __shared__ double sYB[6 * NT];              // the tip side's last forward values
   __shared__ double sLm[36];
   __shared__ int s_fail;
@@ -382,14 +388,16 @@ __global__ void __launch_bounds__(4 * NT) __attribute__((amdgpu_waves_per_eu(3))
   const double* z0 = d.Z + d.zoff[r];                // column 0's right-hand side (Z, contiguous)
   if (w == 1) {
     int32_t fc = -1;
-    double n0 = 0.0, n1 = 0.0, n2 = 0.0;
+    double n0 = 0.0, n1 = 0.0, n2 = 0.0, sv = 0.0;
     if (col && lane > 0) {
       const int64_t cb = (int64_t)r * d.cap + (lane - 1);
       fc = d.ct_node[cb] - 1;
       n0 = d.ct_n[3 * cb]; n1 = d.ct_n[3 * cb + 1]; n2 = d.ct_n[3 * cb + 2];
+      sv = d.ct_s[cb];
     }
     sFC[lane] = fc;
     sNC[lane] = n0; sNC[NT + lane] = n1; sNC[2 * NT + lane] = n2;
+    sSC[lane] = sv;
   }
   __syncthreads();
   double yp[6] = {0, 0, 0, 0, 0, 0}, zn[6] = {0, 0, 0, 0, 0, 0};
@@ -398,9 +406,12 @@ __global__ void __launch_bounds__(4 * NT) __attribute__((amdgpu_waves_per_eu(3))
 #pragma unroll
       for (int q = 0; q < 6; ++q) v[q] = col ? z0[6 * j + q] : 0.0;
     } else {
-      const bool here = j == (int64_t)sFC[lane];
-      v[0] = here ? sNC[lane] : 0.0; v[1] = here ? sNC[NT + lane] : 0.0;
-      v[2] = here ? sNC[2 * NT + lane] : 0.0;
+      // the row's weight at node j: 1 - s at the contact node, s at the next one
+      const int64_t fcl = sFC[lane];
+      const double sv = sSC[lane];
+      const double wgt = j == fcl ? 1.0 - sv : ((sv > 0.0 && j == fcl + 1) ? sv : 0.0);
+      v[0] = wgt * sNC[lane]; v[1] = wgt * sNC[NT + lane];
+      v[2] = wgt * sNC[2 * NT + lane];
       v[3] = 0.0; v[4] = 0.0; v[5] = 0.0;
     }
   };
@@ -685,32 +696,55 @@ struct SweepCol {
   bool act;               // the lane holds a column
   bool col0;              // column 0: right-hand side b from Z
   int c;                  // column index
-  int64_t fcn;            // contact column: its contact's free node
+  int64_t fcn;            // contact column: its contact's free node ...
+  int64_t fhi;            // ... and the last node of its row (fcn + 1 along an element)
   double cn0, cn1, cn2;   // and normal
+  double cs;              // along an element: the row is (1 - s) n at fcn, s n at fcn + 1
   const double* zb;       // column 0's b (Z), NULL in blocks without column 0
   const double* yv;       // the column in Y (checkpoints)
   int64_t zp;
   const int32_t* node;    // the robot's contact list
   const double* nrm;
+  const double* s;
   double* W;              // the robot's rows of contact products
   int nc;
+  // the right-hand side's translation component k at free node f (contact columns)
+  __device__ __forceinline__ double gen(int64_t f, int k) const {
+    const double nk = k == 0 ? cn0 : (k == 1 ? cn1 : cn2);
+    if (!act || k >= 3) return 0.0;
+    if (f == fcn) return (1.0 - cs) * nk;
+    return (cs > 0.0 && f == fcn + 1) ? cs * nk : 0.0;
+  }
+  // W[i, c] = (1 - s_i) n_i . x(node of i) + s_i n_i . x(next node): xa at the contact's node,
+  // xb at the next one (unused for a node contact)
+  __device__ __forceinline__ void put(int i, const double (&xa)[6], const double (&xb)[6]) const {
+    if (!act) return;
+    const double si = s[i];
+    const double* ni = nrm + 3 * i;
+    double v = (1.0 - si) * (ni[0] * xa[0] + ni[1] * xa[1] + ni[2] * xa[2]);
+    if (si > 0.0) v += si * (ni[0] * xb[0] + ni[1] * xb[1] + ni[2] * xb[2]);
+    W[(int64_t)i * zp + c] = v;
+  }
 };
 
-// the contact rows at free node f: W[i, c] = n_i . x (translations), contacts i in sweep order
+// the contact rows completed at free node f, contacts i in sweep order.  Base side (f
+// descending, x the solution at f, xp the one at f + 1): the contacts of node f.  Tip side (f
+// ascending, xp the solution at f - 1): the node contacts of node f and the contacts along the
+// element f-1 -> f (sorted last at node f-1, so they come first).
 template <bool UP>
-__device__ __forceinline__ void write_rows(const SweepCol& sc, int64_t f, int& ci, const double (&x)[6]) {
+__device__ __forceinline__ void write_rows(const SweepCol& sc, int64_t f, int& ci, const double (&x)[6],
+                                           const double (&xp)[6]) {
   if (UP) {
-    while (ci < sc.nc && (int64_t)sc.node[ci] - 1 == f) {
-      if (sc.act)
-        sc.W[(int64_t)ci * sc.zp + sc.c] = sc.nrm[3 * ci] * x[0] + sc.nrm[3 * ci + 1] * x[1] +
-                                           sc.nrm[3 * ci + 2] * x[2];
+    while (ci < sc.nc) {
+      const int64_t fi = (int64_t)sc.node[ci] - 1;
+      if (fi == f - 1 && sc.s[ci] > 0.0) sc.put(ci, xp, x);
+      else if (fi == f && !(sc.s[ci] > 0.0)) sc.put(ci, x, x);
+      else break;
       ++ci;
     }
   } else {
     while (ci >= 0 && (int64_t)sc.node[ci] - 1 == f) {
-      if (sc.act)
-        sc.W[(int64_t)ci * sc.zp + sc.c] = sc.nrm[3 * ci] * x[0] + sc.nrm[3 * ci + 1] * x[1] +
-                                           sc.nrm[3 * ci + 2] * x[2];
+      sc.put(ci, x, xp);
       --ci;
     }
   }
@@ -751,7 +785,7 @@ __device__ void bwd_side(const Dev& d, int64_t o, int64_t nf, int64_t f_begin, i
     const int64_t f0 = ch * CHS;
     const int64_t cpn = UP ? f0 + CHS : f0 - 1;
     const bool valid = sc.act && cpn >= 0 && cpn < nf &&
-                       (sc.col0 || (UP ? cpn <= sc.fcn : cpn >= sc.fcn));
+                       (sc.col0 || (UP ? cpn <= sc.fhi : cpn >= sc.fcn));
 #pragma unroll
     for (int k = 0; k < 6; ++k) cp[k] = valid ? sc.yv[(6 * cpn + k) * sc.zp] : 0.0;
   };
@@ -765,10 +799,7 @@ __device__ void bwd_side(const Dev& d, int64_t o, int64_t nf, int64_t f_begin, i
     auto fnode = [&](int u, int us, int64_t f) {    // us: staged LS index of the previous node
       double bv[6];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        double g = (sc.act && f == sc.fcn && k < 3) ? (k == 0 ? sc.cn0 : (k == 1 ? sc.cn1 : sc.cn2)) : 0.0;
-        bv[k] = sc.col0 ? sB[u * 6 + k] : g;
-      }
+      for (int k = 0; k < 6; ++k) bv[k] = sc.col0 ? sB[u * 6 + k] : sc.gen(f, k);
       const double* Ls = sKS + us * 36;
 #pragma unroll
       for (int p = 0; p < 6; ++p)
@@ -799,9 +830,9 @@ __device__ void bwd_side(const Dev& d, int64_t o, int64_t nf, int64_t f_begin, i
     }
   };
   auto bnode = [&](int u, int us, int64_t f) {
-    double bv[6];
+    double bv[6], xp[6];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) bv[k] = zz[u * 6 + k];
+    for (int k = 0; k < 6; ++k) { bv[k] = zz[u * 6 + k]; xp[k] = xn[k]; }
     const double* Ls = sKS + us * 36;                      // X_f: b -= X_f^T x_neighbour
 #pragma unroll
     for (int k = 0; k < 6; ++k)
@@ -815,7 +846,7 @@ __device__ void bwd_side(const Dev& d, int64_t o, int64_t nf, int64_t f_begin, i
 #pragma unroll
       for (int p = 0; p < k; ++p) bv[p] -= Ld[k * 6 + p] * x;
     }
-    write_rows<UP>(sc, f, ci, xn);
+    write_rows<UP>(sc, f, ci, xn, xp);
   };
   auto backward = [&](int64_t ch) {
     const int64_t f0 = ch * CHS;
@@ -886,12 +917,15 @@ __global__ void __launch_bounds__(2 * NT) subst_kernel(Dev d) {
   sc.col0 = c == 0;
   sc.c = sc.act ? c : 0;
   sc.fcn = -1;
+  sc.fhi = -1;
   sc.cn0 = sc.cn1 = sc.cn2 = 0.0;
+  sc.cs = 0.0;
   sc.zb = c0 == 0 ? d.Z + d.zoff[r] : nullptr;   // column 0's b (the first block only)
   sc.zp = zp;
   sc.yv = d.Y + 6 * o * zp + sc.c;
   sc.node = d.ct_node + cb;
   sc.nrm = d.ct_n + 3 * cb;
+  sc.s = d.ct_s + cb;
   sc.W = d.W + cb * zp;
   sc.nc = nc;
   double* yv = d.Y + 6 * o * zp + sc.c;
@@ -902,6 +936,8 @@ __global__ void __launch_bounds__(2 * NT) subst_kernel(Dev d) {
     const int64_t ci = cb + (c - 1);
     sc.fcn = d.ct_node[ci] - 1;
     sc.cn0 = d.ct_n[3 * ci]; sc.cn1 = d.ct_n[3 * ci + 1]; sc.cn2 = d.ct_n[3 * ci + 2];
+    sc.cs = d.ct_s[ci];
+    sc.fhi = sc.fcn + (sc.cs > 0.0 ? 1 : 0);
   }
   // ---------------------------------------------------------------- forward sweeps
   // base side: f = fs .. m-1 ascending, b - X_{f-1} y_{f-1}; tip side: f = fe .. m+1
@@ -914,9 +950,9 @@ __global__ void __launch_bounds__(2 * NT) subst_kernel(Dev d) {
     const bool up = w == 0;
     const int64_t fcn = sc.fcn;
     const bool act = sc.act;
-    int64_t lim;                          // first (base side) / last (tip side) contact node
+    int64_t lim;                          // first (base side) / last (tip side) row node
     {
-      long long v = act ? fcn : (up ? (long long)nf : -1ll);
+      long long v = act ? (up ? fcn : sc.fhi) : (up ? (long long)nf : -1ll);
 #pragma unroll
       for (int sh = 32; sh > 0; sh >>= 1) {
         const long long ov = __shfl_xor(v, sh);
@@ -939,8 +975,7 @@ __global__ void __launch_bounds__(2 * NT) subst_kernel(Dev d) {
       }
     };
     auto fnode = [&](int u, int64_t f) {
-      const bool here = f == fcn;
-      double bv[6] = {here ? sc.cn0 : 0.0, here ? sc.cn1 : 0.0, here ? sc.cn2 : 0.0, 0.0, 0.0, 0.0};
+      double bv[6] = {sc.gen(f, 0), sc.gen(f, 1), sc.gen(f, 2), 0.0, 0.0, 0.0};
       const double* Ls = KS + u * 36;
 #pragma unroll
       for (int p = 0; p < 6; ++p)
@@ -1005,8 +1040,7 @@ __global__ void __launch_bounds__(2 * NT) subst_kernel(Dev d) {
   }
   __syncthreads();
   if (fwd && w == 0) {
-    const bool here = m == sc.fcn;
-    double bv[6] = {here ? sc.cn0 : 0.0, here ? sc.cn1 : 0.0, here ? sc.cn2 : 0.0, 0.0, 0.0, 0.0};
+    double bv[6] = {sc.gen(m, 0), sc.gen(m, 1), sc.gen(m, 2), 0.0, 0.0, 0.0};
     const bool ht = m >= 1, hb = m + 1 < nf;
     const double* Xt = d.LS + (o + 1 + (ht ? m - 1 : m)) * 36;   // X_{m-1} (base side), if any
     const double* Xb = d.LS + (o + 1 + (hb ? m + 1 : m)) * 36;   // X_{m+1} (tip side), if any
@@ -1038,13 +1072,17 @@ __global__ void __launch_bounds__(2 * NT) subst_kernel(Dev d) {
   double xn[6];
 #pragma unroll
   for (int k = 0; k < 6; ++k) xn[k] = sXM[k * NT + lane];
-  // the outermost contact nodes bound the sweeps; contacts at the middle node take x_m
-  const int64_t f_lo = (int64_t)sc.node[0] - 1, f_hi = (int64_t)sc.node[nc - 1] - 1;
+  // the outermost row nodes bound the sweeps (the list is by node, a node's contacts along
+  // its element last); the middle node's own contacts take x_m, a contact along the element
+  // m -> m+1 is completed by the tip side
+  const int64_t f_lo = (int64_t)sc.node[0] - 1;
+  const int64_t f_hi = (int64_t)sc.node[nc - 1] - 1 + (sc.s[nc - 1] > 0.0 ? 1 : 0);
   const int i_mid = first_contact_at(sc.node, nc, m);
-  const int i_tip = first_contact_at(sc.node, nc, m + 1);
+  int i_tip = i_mid;
+  while (i_tip < nc && (int64_t)sc.node[i_tip] - 1 == m && !(sc.s[i_tip] > 0.0)) ++i_tip;
   if (w == 0) {
     int ci = i_mid;
-    write_rows<true>(sc, m, ci, xn);
+    write_rows<true>(sc, m, ci, xn, xn);
   }
   if (w == 0) bwd_side<false>(d, o, nf, m - 1, f_lo, sc, i_mid - 1, xn, sKD[0], sKS[0], sB[0]);
   else bwd_side<true>(d, o, nf, m + 1, f_hi, sc, i_tip, xn, sKD[1], sKS[1], sB[1]);
@@ -1324,7 +1362,7 @@ __global__ void __launch_bounds__(256) step_dx_kernel(Dev d) {
 // check_rhs_kernel wrote to Z's column 0 and y the forces of the active contacts, through the
 // two-ended factor of phase 2, in place in Z's column 0, and each robot's largest node
 // translation.  First every free node adds the forces of its active contacts to b (one thread
-// per node); then each side of a robot is a chain of dependent 6x6 block steps: forward from
+// per node; a contact along an element gives (1 - s) y n and s y n to its two nodes); then each side of a robot is a chain of dependent 6x6 block steps: forward from
 // its end to the middle (base side f = 0 .. m-1, tip side f = nf-1 .. m+1), the middle node
 // combines both, backward from the middle out.  A group of SSC lanes runs one chain: per chunk
 // of SSN positions, one per lane, every lane turns its position's blocks into the step's affine
@@ -1341,17 +1379,22 @@ __global__ void __launch_bounds__(256) add_forces_kernel(Dev d) {
   const int nact = d.st_nact[r];
   if (i == 0 || nact == 0) return;
   const int64_t cb = (int64_t)r * d.cap;
-  int lo = 0, hi = nact;               // first active contact at node >= i (the list is by node)
+  // the active contacts of node i (weight 1 - s) and along the element i-1 -> i (weight s);
+  // the active list is in contact order, i.e. by node
+  int lo = 0, hi = nact;               // first active contact at node >= i - 1
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
-    if (d.ct_node[cb + d.ac_idx[cb + mid]] < i) lo = mid + 1; else hi = mid;
+    if (d.ct_node[cb + d.ac_idx[cb + mid]] < i - 1) lo = mid + 1; else hi = mid;
   }
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   bool any = false;
   for (int a = lo; a < nact; ++a) {
     const int64_t ci = cb + d.ac_idx[cb + a];
-    if (d.ct_node[ci] != i) break;
-    const double y = d.ac_y[cb + a];
+    const int64_t ic = d.ct_node[ci];
+    if (ic > i) break;
+    const double sv = d.ct_s[ci];
+    if (ic < i && !(sv > 0.0)) continue;
+    const double y = d.ac_y[cb + a] * (ic == i ? 1.0 - sv : sv);
     a0 += y * d.ct_n[3 * ci];
     a1 += y * d.ct_n[3 * ci + 1];
     a2 += y * d.ct_n[3 * ci + 2];
@@ -1630,6 +1673,7 @@ __global__ void __launch_bounds__(256) step_apply_kernel(Dev d) {
     d.cp_kind[cb + c] = d.ct_kind[cb + c];
     d.cp_gap[cb + c] = d.ct_gap[cb + c];
     d.cp_y[cb + c] = sc * d.ct_y[cb + c];
+    d.cp_s[cb + c] = d.ct_s[cb + c];
     for (int k = 0; k < 3; ++k) d.cp_n[3 * (cb + c) + k] = d.ct_n[3 * (cb + c) + k];
   }
   if (i == 0) {
@@ -2181,6 +2225,7 @@ __global__ void __launch_bounds__(NT) gather_kernel(Dev d) {
       d.cp_kind[cb + c] = d.ct_kind[cb + c];
       d.cp_gap[cb + c] = d.ct_gap[cb + c];
       d.cp_y[cb + c] = 0.0;
+      d.cp_s[cb + c] = d.ct_s[cb + c];
       for (int k = 0; k < 3; ++k) d.cp_n[3 * (cb + c) + k] = d.ct_n[3 * (cb + c) + k];
     }
   }

@@ -52,6 +52,7 @@ class fem_params(C.Structure):
         ("admm_rho", C.c_double),
         ("admm_eps", C.c_double),
         ("admm_max_iter", C.c_int32),
+        ("contact_along_elements", C.c_int32),
     ]
 
 
@@ -67,7 +68,7 @@ class fem_solve_info(C.Structure):
 class fem_contact(C.Structure):
     _fields_ = [("robot", C.c_int32), ("node", C.c_int32), ("tri", C.c_int32),
                 ("kind", C.c_int32), ("n", C.c_double * 3), ("gap", C.c_double),
-                ("force", C.c_double)]
+                ("force", C.c_double), ("s", C.c_double)]
 
 
 _lib = None
@@ -183,6 +184,7 @@ class Context:
         p.admm_rho = float(params.get("admm_rho", 0.0))
         p.admm_eps = float(params.get("admm_eps", 0.0))
         p.admm_max_iter = int(params.get("admm_max_iter", 0))
+        p.contact_along_elements = int(params.get("contact_along_elements", 0))
         self.io_on_device = p.io_on_device
         self.B = B
         self.n_cables = p.n_cables
@@ -319,7 +321,7 @@ class Context:
             self._check(lib().fem_contacts(self._h, int(robot), C.cast(buf, C.c_void_p), n.value,
                                            C.byref(n)))
         return [dict(robot=c.robot, node=c.node, tri=c.tri, kind=c.kind, n=np.array(c.n[:]),
-                     gap=c.gap, force=c.force) for c in buf[:n.value]]
+                     gap=c.gap, force=c.force, s=c.s) for c in buf[:n.value]]
 
     def fem_get_state(self):
         if self.io_on_device:

@@ -33,10 +33,12 @@ def displacement_error(P_gpu, P_orc, P_ref):
 
 
 def node_forces(contacts, n_nodes, ykey="force"):
-    """Per-node contact force vectors sum_c y_c n_c (unique even when y is not)."""
+    """Per-node contact force vectors sum_c y_c n_c (unique even when y is not); a contact
+    along an element gives (1 - s) y n and s y n to its two nodes."""
     f = np.zeros((n_nodes, 3))
     for c in contacts:
-        f[c["node"]] += c[ykey] * np.asarray(c["n"])
+        for i, w in collision.row_entries(c):
+            f[i] += w * c[ykey] * np.asarray(c["n"])
     return f
 
 
@@ -52,8 +54,18 @@ def feature_key(c, P, mesh):
     triangle whose index won the tie."""
     if c["kind"] == 0:
         return (c["node"], "F", c["tri"])
-    _, reg, _ = collision.closest_points(np.asarray(P[c["node"]], float), mesh, np.array([c["tri"]]))
     tv = mesh.T[c["tri"]]
+    if c["kind"] == collision.ELEMENT:
+        # the feature that holds the nearest point of the chord point on the triangle
+        reg = collision.element_contact_geometry(np.asarray(P[c["node"]], float),
+                                                 np.asarray(P[c["node"] + 1], float), mesh, c["tri"])[4]
+        if reg in _EDGE_VERTS:
+            a, b = _EDGE_VERTS[reg]
+            return (c["node"], "SE", int(min(tv[a], tv[b])), int(max(tv[a], tv[b])))
+        if reg in _VERT:
+            return (c["node"], "SV", int(tv[_VERT[reg]]))
+        return (c["node"], "Sf", c["tri"])
+    _, reg, _ = collision.closest_points(np.asarray(P[c["node"]], float), mesh, np.array([c["tri"]]))
     reg = int(reg[0])
     if reg in _EDGE_VERTS:
         a, b = _EDGE_VERTS[reg]
@@ -65,14 +77,21 @@ def feature_key(c, P, mesh):
 
 def compare_contact_keys(gpu_contacts, orc_contacts, P_orc, rob, P_gpu=None):
     """Active contact sets equal, keyed by node and mesh feature, outside nodes with
-    near-threshold decisions; returns (n_compared, n_excluded)."""
+    near-threshold decisions (element contacts: elements with near-threshold decisions);
+    returns (n_compared, n_excluded)."""
     det = collision.detect(P_orc, rob.mesh, rob.r_c, rob.delta) if rob.mesh is not None else []
     amb = {c["node"] for c in det if c["ambiguous"]}
+    if rob.mesh is not None and rob.elements:
+        amb_e = {c["node"] for c in collision.detect_elements(P_orc, rob.mesh, rob.r_c, rob.delta)
+                 if c["ambiguous"]}
+    else:
+        amb_e = set()
+    skip = lambda c: (c["node"] in amb_e) if c["kind"] == collision.ELEMENT else (c["node"] in amb)
     Pg = P_orc if P_gpu is None else P_gpu
-    g = {feature_key(c, Pg, rob.mesh) for c in gpu_contacts if c["force"] > 0 and c["node"] not in amb}
-    o = {feature_key(c, P_orc, rob.mesh) for c, y in orc_contacts if y > 0 and c["node"] not in amb}
-    assert g == o, (sorted(g ^ o), sorted(amb))
-    return len(o), len(amb)
+    g = {feature_key(c, Pg, rob.mesh) for c in gpu_contacts if c["force"] > 0 and not skip(c)}
+    o = {feature_key(c, P_orc, rob.mesh) for c, y in orc_contacts if y > 0 and not skip(c)}
+    assert g == o, (sorted(g ^ o), sorted(amb), sorted(amb_e))
+    return len(o), len(amb) + len(amb_e)
 
 
 def same_contacts(a, b):
