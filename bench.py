@@ -309,6 +309,30 @@ def contact_sweep(args, n_nodes=(100, 200, 300, 400), per_size=2):
     return out
 
 
+def element_variant(fem, rb, args, V, T, X0, vals, deps):
+    """The same batched insertion (mixed precision) with contacts along elements as well
+    (contact_along_elements = 1, eq. 3-7 at 0 < xi < l0): one timed schedule; converged
+    solves per second, the converged fraction, Newton iterations per solve and the active
+    element contacts at the end of the insertion."""
+    import torch
+    ce = make_context(fem, rb, fem.FEM_MIXED, args, V, T, contact_along_elements=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    oe = run_schedule(ce, X0, vals, deps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    info = oe["info"]
+    conv = sum(i["steps_converged"] for i in info)
+    total = sum(i["steps_total"] for i in info)
+    iters = sum(i["iters_total"] for i in info)
+    act = [c for c in ce.fem_contacts(-1) if c["kind"] == 2 and c["force"] > 0]
+    ce.close()
+    return {"ms_per_step": 1e3 * dt, "solves_converged_per_s": conv / dt,
+            "converged_fraction": conv / max(total, 1), "newton_iters_per_solve": iters / max(total, 1),
+            "active_element_contacts_at_end": len(act),
+            "robots_with_active_element_contact_at_end": len({c["robot"] for c in act})}
+
+
 def qp_variants(args):
     """The linear step's QP solved exactly (Schur complement + LCP) and by the paper's OSQP
     iteration (qp_solver = FEM_QP_ADMM, rho = 1 N/m, tolerance 1e-11) at the same Newton
@@ -368,6 +392,8 @@ def main():
                     help="skip the time-per-iteration against contact count sweep")
     ap.add_argument("--no-qp-variants", action="store_true",
                     help="skip the exact vs ADMM linear-step comparison")
+    ap.add_argument("--no-elements", action="store_true",
+                    help="skip the batched insertion with contacts along elements")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
@@ -550,6 +576,9 @@ def main():
     if not args.no_sweep:
         res["contact_sweep"] = contact_sweep(args)
         print("bench: contact sweep done", file=sys.stderr, flush=True)
+    if not args.no_elements:
+        res["element_contacts"] = element_variant(fem, rb, args, V, T, X0, vals, deps)
+        print("bench: element-contact schedule done", file=sys.stderr, flush=True)
     if not args.no_qp_variants:
         res["qp_variants"] = qp_variants(args)
         print("bench: QP variants done", file=sys.stderr, flush=True)
