@@ -60,6 +60,15 @@ class Mesh:
                                        np.linalg.norm(self.v1 - cen, axis=1),
                                        np.linalg.norm(self.v2 - cen, axis=1)], 1), axis=1)
         self._tree = None
+        self._sharp = None
+
+    @property
+    def sharp(self):
+        """Sharp convex features, [T, 6] booleans: edges ab, ac, bc, then vertices a, b, c
+        (see sharp_features)."""
+        if self._sharp is None:
+            self._sharp = sharp_features(self)
+        return self._sharp
 
     @property
     def tree(self):
@@ -207,7 +216,8 @@ def active(contacts):
 #    of t's three edges (segment-segment, Ericson 2005, Real-Time Collision Detection, Sec.
 #    5.1.9), the nearest edge giving s* and the chord point p = p(s*);
 #  * a candidate when 0 < s* < 1, p lies in front of t (n_t . (p - v0) > 0), the closest
-#    point c of t to p lies on its boundary (edge or vertex region) and |p - c| <= r_c + delta;
+#    point c of t to p lies on its boundary (edge or vertex region), on a sharp convex feature
+#    of the wall (sharp_features), and |p - c| <= r_c + delta;
 #    an edge (nearly) parallel to the chord, sin^2 of their angle below SEG_PARALLEL, gives
 #    none (the closest pair is not unique; the nodes' own contacts hold such a chord);
 #  * the element's contact is its nearest candidate (ties to the lowest triangle index):
@@ -218,6 +228,47 @@ def active(contacts):
 #    at p.
 SEG_PARALLEL = 1e-6
 ELEMENT = 2
+SHARP_FOLD_COS = float(np.cos(np.radians(10.0)))
+
+
+def sharp_features(mesh):
+    """Which edges and vertices of each triangle are sharp convex features of the wall, where a
+    contact along an element is made: an edge shared by two triangles whose far vertex of the
+    neighbour lies behind the triangle's plane (convex seen from the lumen) and whose normals
+    are at least 10 degrees apart (cos <= SHARP_FOLD_COS); an edge of one triangle only (the rim
+    of an opening) or of more than two; a vertex on such an edge.  At a shallower fold the
+    nodes' own face contacts hold a chord to within (l / 2) tan(fold / 2) of the wall, and a
+    contact there would be nearly parallel to them (W close to singular).  [T, 6] booleans:
+    edges ab, ac, bc, vertices a, b, c."""
+    T = mesh.T
+    owners = {}
+    for t in range(T.shape[0]):
+        for e, (i, j) in enumerate(((0, 1), (0, 2), (1, 2))):
+            u, v = int(T[t, i]), int(T[t, j])
+            owners.setdefault((min(u, v), max(u, v)), []).append((t, e))
+    sharp = np.zeros((T.shape[0], 6), bool)
+    for (u, v), own in owners.items():
+        if len(own) == 2:
+            (t, e), (t2, _) = own
+            far = [w for w in T[t2] if w != u and w != v]
+            far2 = [w for w in T[t] if w != u and w != v]
+            convex = (float(mesh.n[t] @ (mesh.V[far[0]] - mesh.V[u])) < 0.0
+                      and float(mesh.n[t2] @ (mesh.V[far2[0]] - mesh.V[u])) < 0.0)
+            flag = convex and float(mesh.n[t] @ mesh.n[t2]) <= SHARP_FOLD_COS
+        else:
+            flag = True
+        for t, e in own:
+            sharp[t, e] = flag
+    # vertices: on any sharp edge of any triangle
+    vsharp = np.zeros(mesh.V.shape[0], bool)
+    for (u, v), own in owners.items():
+        if sharp[own[0][0], own[0][1]]:
+            vsharp[u] = vsharp[v] = True
+    sharp[:, 3:6] = vsharp[T]
+    return sharp
+
+
+_FEATURE_COL = {EDGE_AB: 0, EDGE_AC: 1, EDGE_BC: 2, VERT_A: 3, VERT_B: 4, VERT_C: 5}
 
 
 def segment_closest(p1, p2, q1, q2):
@@ -286,7 +337,7 @@ def detect_elements(P, mesh, r_c, delta, cull=True, first_node=1, skip=None):
         for t in idx:
             s, p, sin2, c, region, margin, front, d = element_contact_geometry(xa, xb, mesh, int(t))
             ok = (sin2 >= SEG_PARALLEL and 0.0 < s < 1.0 and front > 0.0 and region != FACE
-                  and d <= band)
+                  and d <= band and bool(mesh.sharp[int(t), _FEATURE_COL[region]]))
             near = d <= band + AMBIG_TOL and front >= -AMBIG_TOL
             if near and (abs(sin2 - SEG_PARALLEL) <= 1e-9 or min(s, 1.0 - s) * ln <= AMBIG_TOL
                          or abs(front) <= AMBIG_TOL or margin <= AMBIG_TOL or abs(d - band) <= AMBIG_TOL):

@@ -774,6 +774,60 @@ static fem_status create_impl(fem_ctx* c, const fem_params* p) {
   return FEM_OK;
 }
 
+// Sharp convex features of the wall (where a contact along an element is made): an edge shared
+// by two triangles that each have the other's far vertex behind their plane (convex seen from
+// the lumen) and whose unit normals have a dot product <= cos 10 deg; an edge of one triangle
+// (a rim) or of more than two; a vertex on such an edge.  Per triangle: bits 0-2 the edges ab,
+// ac, bc, bits 3-5 the vertices a, b, c.
+static void sharp_features(const std::vector<double>& V, const std::vector<int32_t>& T,
+                           const std::vector<double>& n, int64_t n_tris, int64_t n_verts,
+                           std::vector<uint8_t>& out) {
+  const double cos_fold = std::cos(10.0 * 3.14159265358979323846 / 180.0);
+  const int ei[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+  std::vector<std::pair<uint64_t, int64_t>> edges;       // (key, 3 t + e)
+  edges.reserve(3 * n_tris);
+  for (int64_t t = 0; t < n_tris; ++t)
+    for (int e = 0; e < 3; ++e) {
+      const uint64_t u = (uint32_t)T[3 * t + ei[e][0]], v = (uint32_t)T[3 * t + ei[e][1]];
+      edges.emplace_back((std::min(u, v) << 32) | std::max(u, v), 3 * t + e);
+    }
+  std::sort(edges.begin(), edges.end());
+  out.assign(n_tris, 0);
+  std::vector<uint8_t> vsharp(n_verts, 0);
+  for (size_t i = 0; i < edges.size();) {
+    size_t j = i;
+    while (j < edges.size() && edges[j].first == edges[i].first) ++j;
+    bool flag = true;
+    if (j - i == 2) {
+      const int64_t t = edges[i].second / 3, t2 = edges[i + 1].second / 3;
+      const int64_t u = edges[i].first >> 32, v = edges[i].first & 0xffffffffull;
+      auto far = [&](int64_t tt) {
+        for (int k = 0; k < 3; ++k)
+          if (T[3 * tt + k] != u && T[3 * tt + k] != v) return (int64_t)T[3 * tt + k];
+        return (int64_t)T[3 * tt];
+      };
+      auto behind = [&](int64_t tt, int64_t w) {   // n_tt . (V_w - V_u) < 0
+        double s = 0.0;
+        for (int k = 0; k < 3; ++k) s += n[3 * tt + k] * (V[3 * w + k] - V[3 * u + k]);
+        return s < 0.0;
+      };
+      double dn = 0.0;
+      for (int k = 0; k < 3; ++k) dn += n[3 * t + k] * n[3 * t2 + k];
+      flag = behind(t, far(t2)) && behind(t2, far(t)) && dn <= cos_fold;
+    }
+    for (size_t k = i; k < j; ++k)
+      if (flag) out[edges[k].second / 3] |= (uint8_t)(1u << (edges[k].second % 3));
+    if (flag) {
+      vsharp[edges[i].first >> 32] = 1;
+      vsharp[edges[i].first & 0xffffffffull] = 1;
+    }
+    i = j;
+  }
+  for (int64_t t = 0; t < n_tris; ++t)
+    for (int k = 0; k < 3; ++k)
+      if (vsharp[T[3 * t + k]]) out[t] |= (uint8_t)(1u << (3 + k));
+}
+
 fem_status fem_set_lumen(fem_ctx* c, const double* verts, int64_t n_verts, const int32_t* tris,
                          int64_t n_tris) {
   if (!c) return FEM_E_INVAL;
@@ -823,6 +877,26 @@ fem_status fem_set_lumen(fem_ctx* c, const double* verts, int64_t n_verts, const
   HIP_TRY(c, hipMemcpy(T_d, ht.data(), ht.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   launch_tri_setup(V_d, T_d, n_tris, tv, tsd, tsf, tqf, c->stream);
   HIP_TRY(c, hipGetLastError());
+  // sharp convex features, where contacts along elements are made: per triangle bits 0-2 the
+  // edges ab, ac, bc, bits 3-5 the vertices a, b, c
+  {
+    std::vector<double> nrm(3 * n_tris);
+    for (int64_t t = 0; t < n_tris; ++t) {
+      const double* a = &hv[3 * (int64_t)ht[3 * t]];
+      const double* b = &hv[3 * (int64_t)ht[3 * t + 1]];
+      const double* e = &hv[3 * (int64_t)ht[3 * t + 2]];
+      const double u[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]}, v[3] = {e[0] - a[0], e[1] - a[1], e[2] - a[2]};
+      const double x[3] = {u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2], u[0] * v[1] - u[1] * v[0]};
+      const double l = std::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+      for (int k = 0; k < 3; ++k) nrm[3 * t + k] = x[k] / l;
+    }
+    std::vector<uint8_t> hs;
+    sharp_features(hv, ht, nrm, n_tris, n_verts, hs);
+    uint8_t* ts_d;
+    if (A(&ts_d, n_tris)) return FEM_E_NOMEM;
+    HIP_TRY(c, hipMemcpy(ts_d, hs.data(), n_tris, hipMemcpyHostToDevice));
+    d.tsharp = ts_d;
+  }
   // uniform grid: every triangle in each cell its box grown by the band overlaps
   const double band = c->p.contact_radius + c->p.contact_margin;
   double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};

@@ -270,8 +270,9 @@ __global__ void __launch_bounds__(256) collide_kernel(Dev d) {
 // chord crosses: the closest points of the chord and each of the triangle's edges (segment-
 // segment, Ericson 2005, Sec. 5.1.9), the nearest edge giving s*; a candidate when 0 < s* < 1,
 // the edge is not (nearly) parallel to the chord (sin^2 >= SEG_PARALLEL), p(s*) lies in front
-// of the triangle, its nearest point c on the triangle is on an edge or vertex and |p - c| <=
-// r_c + delta.  The element's contact is the group's nearest candidate (ties to the lowest
+// of the triangle, its nearest point c on the triangle is on an edge or vertex that is a
+// sharp convex feature of the wall (tsharp: a fold of at least 10 degrees, a rim) and
+// |p - c| <= r_c + delta.  The element's contact is the group's nearest candidate (ties to the lowest
 // triangle): kind 2 at node g with s = s*, normal (p - c)/|p - c| and gap |p - c| - r_c.  A
 // contact along the element that carried force at the previous iterate and is not detected
 // again persists while 0 < s* < 1, p(s*) lies in front of its triangle and within the band of
@@ -301,7 +302,7 @@ __device__ __forceinline__ double seg_closest(P3<double> p1, P3<double> p2, P3<d
   return sqrt(dotp(dd, dd));
 }
 
-struct ElemTest { double s, sin2, front, dist; int region; P3<double> p, cp; };
+struct ElemTest { double s, sin2, front, dist; int region, feature; P3<double> p, cp; };
 
 // chord xa-xb against triangle t
 __device__ __forceinline__ ElemTest elem_tri(const Dev& d, int64_t t, P3<double> xa, P3<double> xb) {
@@ -320,7 +321,8 @@ __device__ __forceinline__ ElemTest elem_tri(const Dev& d, int64_t t, P3<double>
   if (d2 < dm) { dm = d2; r.s = s2; r.sin2 = w2; }
   if (d3 < dm) { r.s = s3; r.sin2 = w3; }
   r.p = axpy(xa, r.s, sub(xb, xa));
-  r.region = closest_on_tri(r.p, a, b, c, &r.cp);
+  r.feature = closest_feature(r.p, a, b, c, &r.cp);
+  r.region = feature_region(r.feature);
   r.front = dotp(nt, sub(r.p, a));
   const P3<double> dv = sub(r.p, r.cp);
   r.dist = sqrt(dotp(dv, dv));
@@ -402,8 +404,10 @@ __global__ void __launch_bounds__(256) collide_elem_kernel(Dev d) {
           const double rr = (S.w + band) * (1.0 + 1e-12);
           if (dotp(dq, dq) > rr * rr) continue;
           const ElemTest e = elem_tri(d, t, xa, xb);
+          // F_AB..F_C = 1..6: bits 0-5 of the triangle's sharp-feature mask
           const bool ok = e.sin2 >= SEG_PARALLEL && e.s > 0.0 && e.s < 1.0 && e.front > 0.0 &&
-                          e.region != R_FACE && e.dist <= band;
+                          e.region != R_FACE && e.dist <= band &&
+                          ((d.tsharp[t] >> (e.feature - 1)) & 1);
           if (ok && (e.dist < best_d || (e.dist == best_d && t < best_t))) {
             best_d = e.dist; best_t = t; best_s = e.s; best_p = e.p; best_cp = e.cp;
           }

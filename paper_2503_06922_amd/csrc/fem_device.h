@@ -75,6 +75,7 @@ struct Dev {
   const double4* tsd; // [T] bounding sphere (centroid, radius) for the FP64 screen
   const float4* tsf;  // [T] the same in FP32 (radius rounded up)
   const float4* tqf;  // [4*T] FP32 normal and vertices a, b, c for the mixed-precision screen
+  const uint8_t* tsharp;  // [T] sharp convex edges (bits 0-2: ab, ac, bc) and vertices (3-5)
   // grid
   double g_org[3];
   double g_h;

@@ -186,3 +186,24 @@ def test_element_detection_cull_keeps_every_contact():
     key = lambda c: (c["node"], c["tri"], c["kind"], c["ambiguous"])
     assert [key(c) for c in a] == [key(c) for c in b]
     assert sum(1 for c in b if c["tri"] >= 0) >= 3
+
+
+def test_sharp_features_of_folds():
+    """Two triangles folded about their common edge: a convex fold of 30 degrees is a sharp
+    feature (its edge and both end vertices), 5 degrees or a flat pair or a concave fold of 30
+    degrees is not; the other edges (rims) are."""
+    def fold(deg):
+        a = np.radians(deg)
+        # common edge along y; one face in the plane z = 0 (x < 0), the other turned by a about y
+        V = np.array([[0, -1, 0], [0, 1, 0], [-1, 0, 0], [np.cos(a), 0, -np.sin(a)]], float)
+        T = np.array([[0, 1, 2], [1, 0, 3]])
+        return collision.Mesh(V, T)
+    for deg, sharp in ((30.0, True), (5.0, False), (0.0, False), (-30.0, False)):
+        m = fold(deg)
+        assert m.n[0][2] > 0 and m.n[1][2] > 0             # both face the lumen (+z)
+        assert bool(m.sharp[0, 0]) == sharp and bool(m.sharp[1, 0]) == sharp, deg
+        assert bool(m.sharp[0, 3]) and bool(m.sharp[0, 4])   # the vertices also lie on rims
+        assert m.sharp[0, 1] and m.sharp[0, 2] and m.sharp[1, 1] and m.sharp[1, 2]
+    # the knife-edge ridge of the propped cantilever is sharp
+    rb, V, T, a = knife_edge_case()
+    assert collision.Mesh(V, T).sharp[0, 0]
