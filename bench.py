@@ -447,6 +447,8 @@ def main():
 
     it_m = out["rec_iters"].cpu().numpy()
     conv_it = it_m[st_m == 0]
+    status_counts = {name: int(np.sum(st_m == k)) for k, name in
+                     enumerate(("ok", "noconv", "lcpfail", "nonspd", "overflow"))}
     iters_hist = {"bins": [0, 5, 10, 15, 20, 30, 40, 50, 60],
                   "converged_solves": np.histogram(conv_it, bins=[0, 5, 10, 15, 20, 30, 40, 50, 60,
                                                                   10 ** 6])[0].tolist()}
@@ -511,6 +513,7 @@ def main():
         "converged_fraction": conv / max(total, 1),
         "newton_iters_per_solve": iters / max(total, 1),
         "newton_iters_histogram": iters_hist,
+        "load_step_status": status_counts,
         "launch_shapes": launch_shapes,
         **fp64,
         "tip_err_mixed_vs_fp64": tip_err,

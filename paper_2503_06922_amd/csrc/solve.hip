@@ -60,6 +60,13 @@ __device__ __forceinline__ double warp_min(double v) {
   for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
   return v;
 }
+// v of lane l (l the same on every lane): two scalar lane reads instead of a shuffle through LDS
+__device__ __forceinline__ double lane_read(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 __device__ __forceinline__ int warp_sum_i(int v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -1134,23 +1141,30 @@ struct LcpLds {
   int In[LCPM];
 };
 
+// Cholesky of W(P, P) by columns: lane p forms l_pj = (w_pj - sum_{k<j} l_pk l_jk) / l_jj from
+// its own row and the finished row j, subtracting in the order k = 0, 1, ... (the rounding of
+// the elimination by rows); the reads of a column are independent of each other, so they are
+// in flight together.  The diagonal keeps the pivot, Rd its reciprocal square root.
 __device__ bool lcp_factor(LcpLds& S, int np) {
   const int lane = threadIdx.x;
   if (lane < np)
     for (int b = 0; b <= lane; ++b) S.L[pk(lane, b)] = S.W[pks(S.P[lane], S.P[b])];
   __syncthreads();
   bool ok = true;
-  for (int k = 0; k < np; ++k) {
-    const double piv = S.L[pk(k, k)];
+  double* Lp = S.L + pk(lane < np ? lane : 0, 0);
+  for (int j = 0; j < np; ++j) {
+    const double* Lj = S.L + pk(j, 0);
+    double a = 0.0;
+    if (lane >= j && lane < np) {
+      a = Lp[j];
+#pragma unroll 8
+      for (int k = 0; k < j; ++k) a -= Lp[k] * Lj[k];
+    }
+    const double piv = lane_read(a, j);
     if (!(piv > 0.0)) ok = false;
     const double rk = rsqrt_nr(piv > 0.0 ? piv : 1.0);
-    if (lane > k && lane < np) S.L[pk(lane, k)] *= rk;
-    if (lane == 0) S.Rd[k] = rk;
-    __syncthreads();
-    if (lane > k && lane < np) {
-      const double lak = S.L[pk(lane, k)];
-      for (int j = k + 1; j <= lane; ++j) S.L[pk(lane, j)] -= lak * S.L[pk(j, k)];
-    }
+    if (lane >= j && lane < np) Lp[j] = lane == j ? a : a * rk;
+    if (lane == 0) S.Rd[j] = rk;
     __syncthreads();
   }
   return ok;
@@ -1160,12 +1174,12 @@ __device__ bool lcp_factor(LcpLds& S, int np) {
 __device__ __forceinline__ double lcp_solve(const LcpLds& S, int np, double bv) {
   const int lane = threadIdx.x;
   for (int k = 0; k < np; ++k) {
-    const double xk = __shfl(bv, k) * S.Rd[k];
+    const double xk = lane_read(bv, k) * S.Rd[k];
     if (lane == k) bv = xk;
     else if (lane > k && lane < np) bv -= S.L[pk(lane, k)] * xk;
   }
   for (int k = np - 1; k >= 0; --k) {
-    const double zk = __shfl(bv, k) * S.Rd[k];
+    const double zk = lane_read(bv, k) * S.Rd[k];
     if (lane == k) bv = zk;
     else if (lane < k) bv -= S.L[pk(k, lane)] * zk;
   }
@@ -1211,7 +1225,7 @@ __device__ bool lcp_parallel(LcpLds& S, const double* q, int m, bool warm, doubl
     // append t: new factor row l solves L l = W(P, t)
     double bv = lane < np ? S.W[pks(S.P[lane], t)] : 0.0;
     for (int k = 0; k < np; ++k) {
-      const double xk = __shfl(bv, k) * S.Rd[k];
+      const double xk = lane_read(bv, k) * S.Rd[k];
       if (lane == k) bv = xk;
       else if (lane > k && lane < np) bv -= S.L[pk(lane, k)] * xk;
     }
@@ -1785,7 +1799,7 @@ template <int SP>
 __device__ __forceinline__ void wide_fwd(const LcpWs& w, int np, double (&bv)[SP]) {
   const int lane = threadIdx.x;
   for (int k = 0; k < np; ++k) {
-    const double xk = __shfl(wide_pick<SP>(bv, k / NT), k % NT) * w.Rd[k];
+    const double xk = lane_read(wide_pick<SP>(bv, k / NT), k % NT) * w.Rd[k];
 #pragma unroll
     for (int s = 0; s < SP; ++s) {
       if (s * NT >= np) break;
@@ -1802,7 +1816,7 @@ template <int SP>
 __device__ __forceinline__ void wide_bwd(const LcpWs& w, int np, double (&bv)[SP]) {
   const int lane = threadIdx.x;
   for (int k = np - 1; k >= 0; --k) {
-    const double xk = __shfl(wide_pick<SP>(bv, k / NT), k % NT) * w.Rd[k];
+    const double xk = lane_read(wide_pick<SP>(bv, k / NT), k % NT) * w.Rd[k];
 #pragma unroll
     for (int s = 0; s < SP; ++s) {
       if (s * NT > k) break;
@@ -1813,7 +1827,7 @@ __device__ __forceinline__ void wide_bwd(const LcpWs& w, int np, double (&bv)[SP
   }
 }
 
-// Cholesky of W(P, P) over np positions
+// Cholesky of W(P, P) over np positions, by columns as lcp_factor (position p on lane p % NT)
 template <int SP>
 __device__ bool wide_factor(const LcpWs& w, const double* Wc, int cap, int np) {
   const int lane = threadIdx.x;
@@ -1828,25 +1842,35 @@ __device__ bool wide_factor(const LcpWs& w, const double* Wc, int cap, int np) {
   }
   __syncthreads();
   bool ok = true;
-  for (int k = 0; k < np; ++k) {
-    const double piv = w.L[pk(k, k)];
+  for (int j = 0; j < np; ++j) {
+    const double* Lj = w.L + pk(j, 0);
+    double a[SP];
+#pragma unroll
+    for (int s = 0; s < SP; ++s) a[s] = 0.0;
+#pragma unroll
+    for (int s = 0; s < SP; ++s) {
+      if (s * NT >= np) break;
+      if ((s + 1) * NT <= j) continue;
+      const int p = lane + NT * s;
+      if (p >= j && p < np) {
+        const double* Lp = w.L + pk(p, 0);
+        double v = Lp[j];
+#pragma unroll 8
+        for (int k = 0; k < j; ++k) v -= Lp[k] * Lj[k];
+        a[s] = v;
+      }
+    }
+    const double piv = lane_read(wide_pick<SP>(a, j / NT), j % NT);
     if (!(piv > 0.0)) ok = false;
     const double rk = rsqrt_nr(piv > 0.0 ? piv : 1.0);
 #pragma unroll
     for (int s = 0; s < SP; ++s) {
+      if (s * NT >= np) break;
+      if ((s + 1) * NT <= j) continue;
       const int p = lane + NT * s;
-      if (p > k && p < np) w.L[pk(p, k)] *= rk;
+      if (p >= j && p < np) w.L[pk(p, j)] = p == j ? a[s] : a[s] * rk;
     }
-    if (lane == 0) w.Rd[k] = rk;
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < SP; ++s) {
-      const int p = lane + NT * s;
-      if (p > k && p < np) {
-        const double lak = w.L[pk(p, k)];
-        for (int j = k + 1; j <= p; ++j) w.L[pk(p, j)] -= lak * w.L[pk(j, k)];
-      }
-    }
+    if (lane == 0) w.Rd[j] = rk;
     __syncthreads();
   }
   return ok;
