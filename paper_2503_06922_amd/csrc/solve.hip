@@ -1137,53 +1137,109 @@ struct LcpLds {
   double Rd[LCPM];
   double Yp[LCPM];
   double Yc[LCPM];
+  double Q[LCPM];
   int P[LCPM];
   int In[LCPM];
 };
 
-// Cholesky of W(P, P) by columns: lane p forms l_pj = (w_pj - sum_{k<j} l_pk l_jk) / l_jj from
-// its own row and the finished row j, subtracting in the order k = 0, 1, ... (the rounding of
-// the elimination by rows); the reads of a column are independent of each other, so they are
-// in flight together.  The diagonal keeps the pivot, Rd its reciprocal square root.
-__device__ bool lcp_factor(LcpLds& S, int np) {
+// Cholesky by columns of the block gathered into the packed rows of L (np <= NT, row p on lane
+// p): l_pj = (w_pj - sum_{k<j} l_pk l_jk) / l_jj, subtracting in the order k = 0, 1, ... (the
+// rounding of the elimination by rows).  Software-pipelined: the sum over k < j - 1 of the
+// next column is read from LDS while the pivot's reciprocal square root is formed, and the
+// last term comes from registers (each lane keeps its newest entry; row j's by a lane read),
+// so the serial chain per column holds no LDS access.  The diagonal keeps the pivot, Rd its
+// reciprocal square root.  Returns false on a non-positive pivot.
+__device__ bool chol_cols1(double* L, double* Rd, int np) {
   const int lane = threadIdx.x;
-  if (lane < np)
-    for (int b = 0; b <= lane; ++b) S.L[pk(lane, b)] = S.W[pks(S.P[lane], S.P[b])];
-  __syncthreads();
+  const double* Lp = L + pk(lane, 0);            // this lane's row (read inside the triangle)
   bool ok = true;
-  double* Lp = S.L + pk(lane < np ? lane : 0, 0);
+  double part = np > 0 ? Lp[0] : 0.0;            // column 0: nothing to subtract
+  double last = 0.0;                             // l_{p, j-1}
   for (int j = 0; j < np; ++j) {
-    const double* Lj = S.L + pk(j, 0);
-    double a = 0.0;
-    if (lane >= j && lane < np) {
-      a = Lp[j];
-#pragma unroll 8
-      for (int k = 0; k < j; ++k) a -= Lp[k] * Lj[k];
-    }
+    const double a = j > 0 ? part - last * lane_read(last, j) : part;
     const double piv = lane_read(a, j);
+    // next column's sum over k < j (rows p and j + 1, columns finished before this one)
+    double nxt = 0.0;
+    if (j + 1 < np) {
+      const double* Lj1 = L + pk(j + 1, 0);
+      nxt = Lp[j + 1];
+#pragma unroll 8
+      for (int k = 0; k < j; ++k) nxt -= Lp[k] * Lj1[k];
+    }
     if (!(piv > 0.0)) ok = false;
     const double rk = rsqrt_nr(piv > 0.0 ? piv : 1.0);
-    if (lane >= j && lane < np) Lp[j] = lane == j ? a : a * rk;
-    if (lane == 0) S.Rd[j] = rk;
+    const double lpj = lane == j ? a : a * rk;
+    if (lane >= j && lane < np) L[pk(lane, j)] = lpj;
+    if (lane == 0) Rd[j] = rk;
+    last = lpj;
+    part = nxt;
     __syncthreads();
   }
   return ok;
 }
 
+// Cholesky of W(P, P): the block gathered from the packed W, then factored by columns
+__device__ bool lcp_factor(LcpLds& S, int np) {
+  const int lane = threadIdx.x;
+  // W(P, P) into the packed rows, eight reads in flight before their writes
+  const int pl = lane < np ? S.P[lane] : 0;
+  for (int b0 = 0; b0 < np; b0 += 8) {
+    double v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int b = b0 + e < np ? b0 + e : 0;
+      v[e] = S.W[pks(pl, __builtin_amdgcn_readlane(pl, b))];
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      if (lane < np && b0 + e <= lane) S.L[pk(lane, b0 + e)] = v[e];
+  }
+  __syncthreads();
+  return chol_cols1(S.L, S.Rd, np);
+}
+
+// Triangular solves with a packed lower factor L (rows by position, true off-diagonal entries)
+// and its reciprocal diagonal Rd, position p on lane p, np <= NT.  A serial chain over the
+// positions: each step takes x_k from lane k by a lane read and updates the other lanes
+// without branches, the next step's Rd and L entries already in flight.  Every lane reads
+// inside the packed triangle of NT rows (entries it does not use among them).
+// L x = b, in place
+__device__ __forceinline__ double tri_fwd1(const double* L, const double* Rd, int np, double b) {
+  const int lane = threadIdx.x;
+  if (np <= 0) return b;
+  const double* Lr = L + pk(lane, 0);            // this lane's row: entry k at Lr[k]
+  double rd = Rd[0], l = Lr[0];
+  for (int k = 0; k < np; ++k) {
+    const int kn = k + 1 < np ? k + 1 : k;
+    const double rdn = Rd[kn], ln = Lr[kn];
+    const double xk = lane_read(b, k) * rd;
+    const double u = b - l * xk;
+    b = lane == k ? xk : (lane > k && lane < np ? u : b);
+    rd = rdn;
+    l = ln;
+  }
+  return b;
+}
+// L^T x = b, in place
+__device__ __forceinline__ double tri_bwd1(const double* L, const double* Rd, int np, double b) {
+  const int lane = threadIdx.x;
+  if (np <= 0) return b;
+  double rd = Rd[np - 1], l = L[pk(np - 1, lane)];
+  for (int k = np - 1; k >= 0; --k) {
+    const int kn = k > 0 ? k - 1 : 0;
+    const double rdn = Rd[kn], ln = L[pk(kn, lane)];
+    const double xk = lane_read(b, k) * rd;
+    const double u = b - l * xk;
+    b = lane == k ? xk : (lane < k ? u : b);
+    rd = rdn;
+    l = ln;
+  }
+  return b;
+}
+
 // lanes a < np: solve L L^T z = b (b, z by position)
 __device__ __forceinline__ double lcp_solve(const LcpLds& S, int np, double bv) {
-  const int lane = threadIdx.x;
-  for (int k = 0; k < np; ++k) {
-    const double xk = lane_read(bv, k) * S.Rd[k];
-    if (lane == k) bv = xk;
-    else if (lane > k && lane < np) bv -= S.L[pk(lane, k)] * xk;
-  }
-  for (int k = np - 1; k >= 0; --k) {
-    const double zk = lane_read(bv, k) * S.Rd[k];
-    if (lane == k) bv = zk;
-    else if (lane < k) bv -= S.L[pk(k, lane)] * zk;
-  }
-  return bv;
+  return tri_bwd1(S.L, S.Rd, np, tri_fwd1(S.L, S.Rd, np, bv));
 }
 
 __device__ bool lcp_parallel(LcpLds& S, const double* q, int m, bool warm, double& y_out) {
@@ -1191,7 +1247,8 @@ __device__ bool lcp_parallel(LcpLds& S, const double* q, int m, bool warm, doubl
   const double qi = lane < m ? q[lane] : 0.0;
   const double tolw = 1e-12 * warp_max(fabs(qi));
   int np = 0;
-  if (lane < LCPM) { S.In[lane] = 0; S.Yc[lane] = 0.0; }
+  if (lane < LCPM) { S.In[lane] = 0; S.Yc[lane] = 0.0; S.Q[lane] = qi; }
+  __syncthreads();
   // warm start: solve on the flagged set, drop the constraints whose y is not positive and
   // solve again, until every y is positive (a feasible start) or the set is empty
   unsigned long long wm = __ballot(warm && lane < m);
@@ -1202,7 +1259,7 @@ __device__ bool lcp_parallel(LcpLds& S, const double* q, int m, bool warm, doubl
     if (mine) S.P[pos] = lane;
     __syncthreads();
     if (!lcp_factor(S, cnt)) break;
-    const double z = lcp_solve(S, cnt, lane < cnt ? -q[S.P[lane]] : 0.0);
+    const double z = lcp_solve(S, cnt, lane < cnt ? -S.Q[S.P[lane]] : 0.0);
     const unsigned long long bad = __ballot(lane < cnt && !(z > 0.0));
     if (bad == 0ull) {
       if (lane < cnt) { S.Yp[lane] = z; S.In[S.P[lane]] = 1; }
@@ -1216,19 +1273,21 @@ __device__ bool lcp_parallel(LcpLds& S, const double* q, int m, bool warm, doubl
   bool done = false, failed = false;
   for (int outer = 0; outer < 4 * m + 8 && !done && !failed; ++outer) {
     // most violated inactive constraint
+    // the active set's indices and forces by lane reads: the products' loads are independent
+    const int pl = lane < np ? S.P[lane] : 0;
+    const double yl = lane < np ? S.Yp[lane] : 0.0;
+    const int row = lane < m ? lane : 0;
     double w = qi;
-    for (int a = 0; a < np; ++a) w += S.W[pks(lane < m ? lane : 0, S.P[a])] * S.Yp[a];
+#pragma unroll 4
+    for (int a = 0; a < np; ++a)
+      w += S.W[pks(row, __builtin_amdgcn_readlane(pl, a))] * lane_read(yl, a);
     double v = (lane < m && !S.In[lane] && w < -tolw) ? w : INFINITY;
     int t = lane;
     wave_argmin(v, t);
     if (!(v < INFINITY)) { done = true; break; }
     // append t: new factor row l solves L l = W(P, t)
     double bv = lane < np ? S.W[pks(S.P[lane], t)] : 0.0;
-    for (int k = 0; k < np; ++k) {
-      const double xk = lane_read(bv, k) * S.Rd[k];
-      if (lane == k) bv = xk;
-      else if (lane > k && lane < np) bv -= S.L[pk(lane, k)] * xk;
-    }
+    bv = tri_fwd1(S.L, S.Rd, np, bv);
     const double dtt = S.W[pk(t, t)] - warp_sum(lane < np ? bv * bv : 0.0);
     __syncthreads();
     if (dtt > 0.0) {
@@ -1262,7 +1321,7 @@ __device__ bool lcp_parallel(LcpLds& S, const double* q, int m, bool warm, doubl
       if (!lcp_factor(S, np)) { failed = true; break; }
     }
     for (int inner = 0; inner < 4 * m + 8; ++inner) {
-      const double z = lcp_solve(S, np, lane < np ? -q[S.P[lane]] : 0.0);
+      const double z = lcp_solve(S, np, lane < np ? -S.Q[S.P[lane]] : 0.0);
       if (__ballot(lane < np && !(z > 0.0)) == 0ull) {
         if (lane < np) S.Yp[lane] = z;
         __syncthreads();
@@ -1753,8 +1812,9 @@ struct LcpWideLds {
   double Rd[NPW];
   double Yp[NPW];
   int P[NPW];
+  double Q[CAPW];                      // q by constraint
   unsigned char In[CAPW];              // constraint i is in the active set
-  unsigned char Val[CAPW];             // column i of W is available
+  unsigned char Wm[CAPW];              // constraint i starts in the active set (warm start)
 };
 
 // where the factor of the active block lives: packed lower L (true off-diagonal entries),
@@ -1773,15 +1833,11 @@ struct LcpWs {
 struct RobotLcpSource {
   const Dev* d;
   int64_t cb;
-  __device__ void column(LcpWideLds&, double*, int, int, int) const {}
-  __device__ void columns(LcpWideLds&, double*, int, int, const int*, int) const {}
   __device__ bool warm(int i) const { return d->ct_warm[cb + i] != 0; }
 };
 
 // a given dense W (column-major, ld = cap), no warm start
 struct DenseLcpSource {
-  __device__ void column(LcpWideLds&, double*, int, int, int) const {}
-  __device__ void columns(LcpWideLds&, double*, int, int, const int*, int) const {}
   __device__ bool warm(int) const { return false; }
 };
 
@@ -1798,6 +1854,10 @@ __device__ __forceinline__ double wide_pick(const double (&v)[SP], int s) {
 template <int SP>
 __device__ __forceinline__ void wide_fwd(const LcpWs& w, int np, double (&bv)[SP]) {
   const int lane = threadIdx.x;
+  if (np <= NT) {                      // one position per lane
+    bv[0] = tri_fwd1(w.L, w.Rd, np, bv[0]);
+    return;
+  }
   for (int k = 0; k < np; ++k) {
     const double xk = lane_read(wide_pick<SP>(bv, k / NT), k % NT) * w.Rd[k];
 #pragma unroll
@@ -1815,6 +1875,10 @@ __device__ __forceinline__ void wide_fwd(const LcpWs& w, int np, double (&bv)[SP
 template <int SP>
 __device__ __forceinline__ void wide_bwd(const LcpWs& w, int np, double (&bv)[SP]) {
   const int lane = threadIdx.x;
+  if (np <= NT) {
+    bv[0] = tri_bwd1(w.L, w.Rd, np, bv[0]);
+    return;
+  }
   for (int k = np - 1; k >= 0; --k) {
     const double xk = lane_read(wide_pick<SP>(bv, k / NT), k % NT) * w.Rd[k];
 #pragma unroll
@@ -1827,20 +1891,40 @@ __device__ __forceinline__ void wide_bwd(const LcpWs& w, int np, double (&bv)[SP
   }
 }
 
-// Cholesky of W(P, P) over np positions, by columns as lcp_factor (position p on lane p % NT)
+// Cholesky of W(P, P) over np positions, by columns (position p on lane p % NT): up to NT
+// positions by chol_cols1, beyond that with the sums of a column formed directly
 template <int SP>
 __device__ bool wide_factor(const LcpWs& w, const double* Wc, int cap, int np) {
   const int lane = threadIdx.x;
+  // W(P, P) into the packed rows: the constraint indices by lane reads, eight loads in flight
+  // per lane before their writes
+  int pr[SP];
+#pragma unroll
+  for (int s = 0; s < SP; ++s) pr[s] = lane + NT * s < np ? w.P[lane + NT * s] : 0;
 #pragma unroll
   for (int s = 0; s < SP; ++s) {
+    if (s * NT >= np) break;
     const int p = lane + NT * s;
-    if (p < np) {
-      const int pp = w.P[p];
-#pragma unroll 8
-      for (int b = 0; b <= p; ++b) w.L[pk(p, b)] = Wc[(int64_t)w.P[b] * cap + pp];
+    const int bend = np < (s + 1) * NT ? np : (s + 1) * NT;   // b <= p < bend
+    for (int b0 = 0; b0 < bend; b0 += 8) {
+      double v[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int b = b0 + e < bend ? b0 + e : 0;
+        int pb = pr[0];
+#pragma unroll
+        for (int u = 1; u < SP; ++u)
+          if (b / NT == u) pb = pr[u];
+        pb = __builtin_amdgcn_readlane(pb, b % NT);
+        v[e] = p < np && b0 + e <= p ? Wc[(int64_t)pb * cap + pr[s]] : 0.0;
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        if (p < np && b0 + e <= p) w.L[pk(p, b0 + e)] = v[e];
     }
   }
   __syncthreads();
+  if (np <= NT) return chol_cols1(w.L, w.Rd, np);
   bool ok = true;
   for (int j = 0; j < np; ++j) {
     const double* Lj = w.L + pk(j, 0);
@@ -1877,16 +1961,20 @@ __device__ bool wide_factor(const LcpWs& w, const double* Wc, int cap, int np) {
 }
 
 // 0: solved (y written), 1: non-positive pivot or iteration limit, 2: active set beyond npmax.
-// fresh: forget the cached columns (a new W).
 template <int SP, class Src>
-__device__ int lcp_wide(const Src& src, LcpWideLds& S, const LcpWs& w, double* Wc, int cap,
-                        const double* q, int m, double* y, bool fresh) {
+__device__ int lcp_wide(const Src& src, LcpWideLds& S, const LcpWs& w, const double* Wc, int cap,
+                        const double* q, int m, double* y) {
   const int lane = threadIdx.x;
+  // q and the warm-start flags staged in LDS (their loads in flight together)
   double qmax = 0.0;
+#pragma unroll 4
   for (int i = lane; i < m; i += NT) {
-    qmax = fmax(qmax, fabs(q[i]));
+    const double qq = q[i];
+    const bool wf = src.warm(i);
+    qmax = fmax(qmax, fabs(qq));
+    S.Q[i] = qq;
     S.In[i] = 0;
-    if (fresh) S.Val[i] = 0;
+    S.Wm[i] = wf ? 1 : 0;
   }
   const double tolw = 1e-12 * warp_max(qmax);
   __syncthreads();
@@ -1896,7 +1984,7 @@ __device__ int lcp_wide(const Src& src, LcpWideLds& S, const LcpWs& w, double* W
     int cnt = 0;
     for (int i0 = 0; i0 < m; i0 += NT) {
       const int i = i0 + lane;
-      const bool wf = i < m && src.warm(i);
+      const bool wf = i < m && S.Wm[i] != 0;
       const unsigned long long wm = __ballot(wf);
       const int pos = cnt + __popcll(wm & ((1ull << lane) - 1ull));
       if (wf && pos < w.npmax) w.P[pos] = i;
@@ -1904,7 +1992,6 @@ __device__ int lcp_wide(const Src& src, LcpWideLds& S, const LcpWs& w, double* W
     }
     __syncthreads();
     if (cnt > w.npmax) cnt = 0;
-    src.columns(S, Wc, cap, m, w.P, cnt);
     // solve on the set, drop the constraints whose y is not positive, solve again
     while (cnt > 0) {
       if (!wide_factor<SP>(w, Wc, cap, cnt)) break;
@@ -1912,7 +1999,7 @@ __device__ int lcp_wide(const Src& src, LcpWideLds& S, const LcpWs& w, double* W
 #pragma unroll
       for (int s = 0; s < SP; ++s) {
         const int p = lane + NT * s;
-        z[s] = p < cnt ? -q[w.P[p]] : 0.0;
+        z[s] = p < cnt ? -S.Q[w.P[p]] : 0.0;
       }
       wide_fwd<SP>(w, cnt, z);
       wide_bwd<SP>(w, cnt, z);
@@ -1958,37 +2045,28 @@ __device__ int lcp_wide(const Src& src, LcpWideLds& S, const LcpWs& w, double* W
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int i = i0 + lane + u * NT;
-        wv[u] = i < m ? q[i] : 0.0;
+        wv[u] = i < m ? S.Q[i] : 0.0;
       }
-      // eight columns at a time: their 32 loads are in flight together (accumulation order
-      // unchanged)
-      int a = 0;
-      for (; a + 8 <= np; a += 8) {
+      // eight columns at a time, the last group masked: their 32 loads are in flight together
+      // (accumulation in column order)
+      for (int a = 0; a < np; a += 8) {
         double ya[8], cv[8][4];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          ya[e] = w.Yp[a + e];
-          const double* col = Wc + (int64_t)w.P[a + e] * cap;
+          const bool ce = a + e < np;
+          ya[e] = ce ? w.Yp[a + e] : 0.0;
+          const double* col = Wc + (int64_t)(ce ? w.P[a + e] : 0) * cap;
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const int i = i0 + lane + u * NT;
-            cv[e][u] = i < m ? col[i] : 0.0;
+            cv[e][u] = ce && i < m ? col[i] : 0.0;
           }
         }
 #pragma unroll
         for (int e = 0; e < 8; ++e)
 #pragma unroll
           for (int u = 0; u < 4; ++u)
-            if (i0 + lane + u * NT < m) wv[u] += cv[e][u] * ya[e];
-      }
-      for (; a < np; ++a) {
-        const double ya = w.Yp[a];
-        const double* col = Wc + (int64_t)w.P[a] * cap;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int i = i0 + lane + u * NT;
-          if (i < m) wv[u] += col[i] * ya;
-        }
+            if (a + e < np && i0 + lane + u * NT < m) wv[u] += cv[e][u] * ya[e];
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -1999,7 +2077,6 @@ __device__ int lcp_wide(const Src& src, LcpWideLds& S, const LcpWs& w, double* W
     wave_argmin(v, t);
     if (!(v < INFINITY)) { done = true; break; }
     if (np == w.npmax) { full = true; break; }
-    src.column(S, Wc, cap, m, t);
     // append t: the new factor row l solves L l = W(P, t)
     double bv[SP];
 #pragma unroll
@@ -2070,7 +2147,7 @@ __device__ int lcp_wide(const Src& src, LcpWideLds& S, const LcpWs& w, double* W
 #pragma unroll
       for (int s = 0; s < SP; ++s) {
         const int p = lane + NT * s;
-        z[s] = p < np ? -q[w.P[p]] : 0.0;
+        z[s] = p < np ? -S.Q[w.P[p]] : 0.0;
       }
       wide_fwd<SP>(w, np, z);
       wide_bwd<SP>(w, np, z);
@@ -2162,7 +2239,7 @@ __global__ void __launch_bounds__(NT) update_wide_kernel(Dev d) {
   __syncthreads();
   const RobotLcpSource src{&d, cb};
   const LcpWs wl{S.L, S.Rd, S.Yp, S.P, NPW};
-  const int code = lcp_wide<SPL>(src, S, wl, Wr + 1, (int)d.zp, qv, nc, y, true);
+  const int code = lcp_wide<SPL>(src, S, wl, Wr + 1, (int)d.zp, qv, nc, y);
   if (threadIdx.x == 0) d.st_big[r] = code == 2 ? 1 : 0;
   if (code == 1) {
     finish(d, r, 2, d.st_it[r], d.st_rn[r]);
@@ -2185,7 +2262,7 @@ __global__ void __launch_bounds__(NT) update_big_kernel(Dev d) {
   double* y = d.ct_y + cb;
   double* Wr = d.W + cb * d.zp;
   const RobotLcpSource src{&d, cb};
-  if (lcp_wide<SPG>(src, S, global_ws(lcp_ws(d, r), nc), Wr + 1, (int)d.zp, qv, nc, y, true) != 0) {
+  if (lcp_wide<SPG>(src, S, global_ws(lcp_ws(d, r), nc), Wr + 1, (int)d.zp, qv, nc, y) != 0) {
     finish(d, r, 2, d.st_it[r], d.st_rn[r]);
     return;
   }
@@ -2210,7 +2287,7 @@ __global__ void __launch_bounds__(NT) lcp_wide_check_kernel(double* W, const dou
                                                             double* y, int* code) {
   __shared__ LcpWideLds S;
   const LcpWs wl{S.L, S.Rd, S.Yp, S.P, NPW};
-  const int c = lcp_wide<SPL>(DenseLcpSource{}, S, wl, W, m, q, m, y, true);
+  const int c = lcp_wide<SPL>(DenseLcpSource{}, S, wl, W, m, q, m, y);
   if (threadIdx.x == 0) *code = c == 0 ? 1 : (c == 2 ? 2 : -1);
 }
 
@@ -2219,7 +2296,7 @@ __global__ void __launch_bounds__(NT) lcp_big_check_kernel(double* W, const doub
                                                            double* y, double* gws, int* code) {
   if (*code != 2) return;
   __shared__ LcpWideLds S;
-  const int c = lcp_wide<SPG>(DenseLcpSource{}, S, global_ws(gws, m), W, m, q, m, y, true);
+  const int c = lcp_wide<SPG>(DenseLcpSource{}, S, global_ws(gws, m), W, m, q, m, y);
   __syncthreads();
   if (threadIdx.x == 0) *code = c == 0 ? 2 : -1;
 }
