@@ -717,8 +717,11 @@ static fem_status create_impl(fem_ctx* c, const fem_params* p) {
   ALLOC(d.W, (int64_t)B * cap * d.zp + (int64_t)B * lcp_ws_doubles(cap));
   ALLOC(d.q, BC);
   ALLOC(d.ac_idx, BC); ALLOC(d.ac_y, BC);
-  ALLOC(d.st_nact, B); ALLOC(d.st_mx, B); ALLOC(d.st_big, B);
-  HIP_TRY(c, hipMemset(d.st_big, 0, B * sizeof(int32_t)));
+  ALLOC(d.st_nact, B); ALLOC(d.st_mx, B);
+  ALLOC(d.wl, (int64_t)WL_SUB * B);
+  ALLOC(d.wl_sub, (int64_t)B * ((cap + SOLVE_THREADS) / SOLVE_THREADS));
+  ALLOC(d.wl_cnt, 8);
+  HIP_TRY(c, hipMemset(d.wl_cnt, 0, 8 * sizeof(int32_t)));
   ALLOC(d.st_status, B); ALLOC(d.st_done, B); ALLOC(d.st_nc, B); ALLOC(d.st_ncp, B);
   ALLOC(d.st_limited, B); ALLOC(d.st_nlim, B); ALLOC(d.st_nswitch, B); ALLOC(d.st_iters, B); ALLOC(d.st_rhs, 5 * B);
   ALLOC(d.st_rn, B); ALLOC(d.st_rnprev, B); ALLOC(d.n_done, 1);

@@ -30,6 +30,7 @@ constexpr double SEG_PARALLEL = 1e-6;  // an edge this parallel to a chord (sin^
 constexpr int MAXC = 48;         // contact candidates kept per node (a node in a branch
                                  // narrower than the band meets a ring of facets)
 constexpr int SOLVE_THREADS = 64;  // one wavefront per robot in the solve kernel
+enum { WL_ACT = 0, WL_SMALL = 1, WL_WIDE = 2, WL_BIG = 3, WL_SUB = 4, WL_N = 5 };
 // Mixed precision: a robot whose residual at the last check is above this level (N, N m) has
 // its element forces evaluated in FP32 with FP32 accumulation; below it, and for the
 // convergence decision, in FP64 (the FP64 refinement of the Newton iteration).  FP32 forces
@@ -48,6 +49,15 @@ struct Dev {
   const double* base_up;   // [3B]
   const int32_t* guide_axis;  // [B] coordinate axis of base_dir, -1 if not axis aligned
   const int32_t* solve_order; // [B] robots by decreasing number of elements
+  // work lists of the current pass (rebuilt after the convergence test, in solve order): the
+  // robots taking the Newton step (WL_ACT), those among them whose contact set takes the LDS
+  // LCP (WL_SMALL) or the wide one (WL_WIDE), those whose wide LCP outgrew its LDS factor
+  // (WL_BIG, appended by the wide LCP); lists at wl + k B, entry counts in wl_cnt[k]; the
+  // substitution's items (robot | pass << 24, a robot's passes together) at wl_sub, count
+  // wl_cnt[WL_SUB].  Blocks of the per-robot kernels beyond a list's count return at once.
+  int32_t* wl;
+  int32_t* wl_sub;
+  int32_t* wl_cnt;
   // element rigidities
   double* EA;
   double* EI;
@@ -144,7 +154,6 @@ struct Dev {
   int32_t* st_nswitch;
   int32_t* st_iters;
   int32_t* st_nact;     // active contacts of the current step
-  int32_t* st_big;      // the wide LCP's active set outgrew its LDS factor this iteration
   unsigned long long* st_mx;  // largest node translation of the step (bits of a double >= 0)
   int64_t* st_rhs;      // [5B] right-hand sides, those swept forward in the factorisation,
                         // passes of the substitution, contact products it forms and Newton

@@ -357,7 +357,8 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 // X_bot y_bot), and the middle node's solution x_m = L_m^-T z_m goes to XM, where the
 // substitution starts both sides' backward sweeps.
 __global__ void __launch_bounds__(4 * NT) __attribute__((amdgpu_waves_per_eu(3))) factor_kernel(Dev d) {
-  const int r = d.solve_order[blockIdx.x];   // longest robots first
+  if ((int)blockIdx.x >= d.wl_cnt[WL_ACT]) return;
+  const int r = d.wl[WL_ACT * d.B + blockIdx.x];   // longest robots first
   const int w = threadIdx.x / NT, lane = threadIdx.x % NT;
   const int sd = w >> 1;                      // side: 0 from the base, 1 from the tip
   const bool fw = (w & 1) != 0;               // the side's forward-substitution wave
@@ -906,13 +907,15 @@ __device__ void bwd_side(const Dev& d, int64_t o, int64_t nf, int64_t f_begin, i
 
 // block (r, p) takes columns p*NT .. p*NT + NT-1: wave 0 the base side, wave 1 the tip side
 __global__ void __launch_bounds__(2 * NT) subst_kernel(Dev d) {
-  const int r = d.solve_order[blockIdx.x];   // longest robots first
+  if ((int)blockIdx.x >= d.wl_cnt[WL_SUB]) return;
+  const int item = d.wl_sub[blockIdx.x];     // a pass of a robot with contacts, longest first
+  const int r = item & 0xffffff;
   const int w = threadIdx.x / NT, lane = threadIdx.x % NT;
   if (d.st_done[r]) return;
   const int nc = d.st_nc[r];
   if (nc == 0) return;                   // no contact: no product is needed
   const int ncol = 1 + nc;
-  const int c0 = blockIdx.y * NT;
+  const int c0 = (item >> 24) * NT;
   if (c0 >= ncol) return;
   const int64_t o = d.off[r], n = d.off[r + 1] - o;
   const int64_t nf = n - 1, m = nf / 2;
@@ -1491,8 +1494,9 @@ __global__ void __launch_bounds__(64) step_solve_kernel(Dev d) {
   const int g = lane / SSC, j = lane % SSC;   // chain g of the wavefront, lane j in its group
   const int k = blockIdx.x * SSR + g / 2;
   const bool tip = (g & 1) != 0;
-  const int r = k < d.B ? d.solve_order[k] : 0;
-  const bool live = k < d.B && !d.st_done[r];
+  const int na = d.wl_cnt[WL_ACT];
+  const int r = k < na ? d.wl[WL_ACT * d.B + k] : 0;   // neighbours in the list: similar lengths
+  const bool live = k < na && !d.st_done[r];
   if (__ballot(live) == 0ull) return;
   const int64_t o = d.off[r], n = d.off[r + 1] - o, nf = n - 1, m = nf / 2;
   double* z = d.Z + d.zoff[r];
@@ -1761,7 +1765,8 @@ __global__ void __launch_bounds__(256) step_apply_kernel(Dev d) {
 
 // phase 4 for robots with at most LCPM contacts: W packed in LDS, the wavefront LCP
 __global__ void __launch_bounds__(NT) update_kernel(Dev d) {
-  const int r = d.solve_order[blockIdx.x];   // longest robots first
+  if ((int)blockIdx.x >= d.wl_cnt[WL_SMALL]) return;
+  const int r = d.wl[WL_SMALL * d.B + blockIdx.x];   // longest robots first
   const int lane = threadIdx.x;
   if (d.st_done[r]) return;
   const int nc = d.st_nc[r];
@@ -2226,7 +2231,8 @@ __device__ __forceinline__ LcpWs global_ws(double* g, int m) {
 
 // phase 4 for robots with more than LCPM contacts
 __global__ void __launch_bounds__(NT) update_wide_kernel(Dev d) {
-  const int r = d.solve_order[blockIdx.x];   // longest robots first
+  if ((int)blockIdx.x >= d.wl_cnt[WL_WIDE]) return;
+  const int r = d.wl[WL_WIDE * d.B + blockIdx.x];   // longest robots first
   if (d.st_done[r]) return;
   const int nc = d.st_nc[r];
   if (nc <= LCPM) return;              // update_kernel
@@ -2240,7 +2246,7 @@ __global__ void __launch_bounds__(NT) update_wide_kernel(Dev d) {
   const RobotLcpSource src{&d, cb};
   const LcpWs wl{S.L, S.Rd, S.Yp, S.P, NPW};
   const int code = lcp_wide<SPL>(src, S, wl, Wr + 1, (int)d.zp, qv, nc, y);
-  if (threadIdx.x == 0) d.st_big[r] = code == 2 ? 1 : 0;
+  if (threadIdx.x == 0 && code == 2) d.wl[WL_BIG * d.B + atomicAdd(&d.wl_cnt[WL_BIG], 1)] = r;
   if (code == 1) {
     finish(d, r, 2, d.st_it[r], d.st_rn[r]);
     return;
@@ -2252,10 +2258,11 @@ __global__ void __launch_bounds__(NT) update_wide_kernel(Dev d) {
 // factor in the robot's device workspace (up to every constraint).  A kernel of its own, so
 // that the common path keeps its registers (this one holds 16 positions per lane).
 __global__ void __launch_bounds__(NT) update_big_kernel(Dev d) {
-  const int r = d.solve_order[blockIdx.x];   // longest robots first
+  if ((int)blockIdx.x >= d.wl_cnt[WL_BIG]) return;
+  const int r = d.wl[WL_BIG * d.B + blockIdx.x];
   if (d.st_done[r]) return;
   const int nc = d.st_nc[r];
-  if (nc <= LCPM || !d.st_big[r]) return;
+  if (nc <= LCPM) return;
   const int64_t cb = (int64_t)r * d.cap;
   __shared__ LcpWideLds S;
   const double* qv = d.q + cb;                  // written by update_wide_kernel
@@ -2584,16 +2591,81 @@ __global__ void __launch_bounds__(NT) admm_kernel(Dev d) {
 
 // phases of one Newton step: 0 check + right-hand sides, 1 factor, 2 substitute, 3 contact
 // forces, 4 step and state update
+// The work lists of the pass, after the convergence test: one block scans the robots in solve
+// order (still iterating, contact count) and writes every list in that order.
+constexpr int WLT = 1024;
+__global__ void __launch_bounds__(WLT) build_lists_kernel(Dev d) {
+  __shared__ int sTot[WLT / NT][4];
+  __shared__ int sBase[4];
+  const int t = threadIdx.x, lane = t % NT, wv = t / NT;
+  if (t < 4) sBase[t] = 0;
+  __syncthreads();
+  for (int i0 = 0; i0 < d.B; i0 += WLT) {
+    const int i = i0 + t;
+    int r = 0, v[4] = {0, 0, 0, 0};   // active, small LCP, wide LCP, substitution passes
+    if (i < d.B) {
+      r = d.solve_order[i];
+      if (!d.st_done[r]) {
+        const int nc = d.st_nc[r];
+        v[0] = 1;
+        v[1] = nc <= LCPM ? 1 : 0;
+        v[2] = nc > LCPM ? 1 : 0;
+        v[3] = nc > 0 ? (nc + NT) / NT : 0;   // ceil((1 + nc) / NT)
+      }
+    }
+    int ex[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      int x = v[f];
+#pragma unroll
+      for (int o = 1; o < NT; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+      }
+      if (lane == NT - 1) sTot[wv][f] = x;
+      ex[f] = x - v[f];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      int b = sBase[f];
+      for (int u = 0; u < wv; ++u) b += sTot[u][f];
+      ex[f] += b;
+    }
+    if (v[0]) d.wl[WL_ACT * d.B + ex[0]] = r;
+    if (v[1]) d.wl[WL_SMALL * d.B + ex[1]] = r;
+    if (v[2]) d.wl[WL_WIDE * d.B + ex[2]] = r;
+    for (int p = 0; p < v[3]; ++p) d.wl_sub[ex[3] + p] = r | (p << 24);
+    __syncthreads();
+    if (t < 4) {
+      int b = 0;
+      for (int u = 0; u < WLT / NT; ++u) b += sTot[u][t];
+      sBase[t] += b;
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    d.wl_cnt[WL_ACT] = sBase[0];
+    d.wl_cnt[WL_SMALL] = sBase[1];
+    d.wl_cnt[WL_WIDE] = sBase[2];
+    d.wl_cnt[WL_SUB] = sBase[3];
+    d.wl_cnt[WL_BIG] = 0;
+  }
+}
+
 void launch_solve_phase(const Dev& d, int phase, hipStream_t s) {
   switch (phase) {
-    case 0: hipLaunchKernelGGL(check_rhs_kernel, dim3(d.B), dim3(NT), 0, s, d); break;
+    case 0:
+      hipLaunchKernelGGL(check_rhs_kernel, dim3(d.B), dim3(NT), 0, s, d);
+      hipLaunchKernelGGL(build_lists_kernel, dim3(1), dim3(WLT), 0, s, d);
+      break;
     case 1:
       if (d.qp_admm) hipLaunchKernelGGL(admm_kernel, dim3(d.B), dim3(NT), 0, s, d);
       else hipLaunchKernelGGL(factor_kernel, dim3(d.B), dim3(4 * NT), 0, s, d);
       break;
     case 2:
       if (!d.qp_admm)
-        hipLaunchKernelGGL(subst_kernel, dim3(d.B, (d.cap + NT) / NT), dim3(2 * NT), 0, s, d);
+        hipLaunchKernelGGL(subst_kernel, dim3(d.B * ((d.cap + NT) / NT)), dim3(2 * NT), 0, s, d);
       break;
     case 3:
       if (!d.qp_admm) {
