@@ -75,7 +75,8 @@ def byte_models(u, sb):
     blocks D (21) and S (36) in the element precision, 560 B (FP64) / 280 B (FP32) per node;
     the block Cholesky reads and writes the 57 unique block values per free node (912 B);
     the multi-right-hand-side solve reads L twice per free node, shared by all right-hand
-    sides of the step (912 B); so does the step's own solve after the LCP.
+    sides of the step (912 B); so does the step's own solve after the LCP; the contact LCP
+    (the update kernels) reads the contact products once, W and q (8 B per product).
     "design": what this design's kernels must move: the element update writes the chord
     direction (3 x sb) instead of D and S; the factorisation reads the element (3 x sb + 6
     FP64 constants) and column 0's right-hand side and writes L[i,i] and the coupling block,
@@ -105,6 +106,9 @@ def byte_models(u, sb):
                                     + 8 * u["free_node_rhs_with_contacts"] + 576 * extra_passes
                                     + 8 * (u["free_node_rhs_with_contacts"] - u["free_node_rhs_fused_with_contacts"])
                                     + 8 * u["contact_products"])},
+        # W and q read once; the active-set iterations re-read columns of W from L2
+        "update_kernel": {"scope": (8, "contact product", 8 * u["contact_products"]),
+                          "design": (8, "contact product", 8 * u["contact_products"])},
         # forward and backward: the coupling block and the rows of L[i,i] (288 B each, whole
         # cache lines), the vector read and written (48 B each), per free node-step
         "step_solve_kernel": {"scope": (912, "free node-step", 912 * u["free_node_steps"]),

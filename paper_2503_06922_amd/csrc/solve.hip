@@ -1836,9 +1836,8 @@ struct LcpWs {
 // read as the contiguous row of contact t, W(t, i) = n_t . Z_i(node of t), which equals
 // W(i, t) (W is symmetric) up to rounding; warm-start flags from the contact list
 struct RobotLcpSource {
-  const Dev* d;
-  int64_t cb;
-  __device__ bool warm(int i) const { return d->ct_warm[cb + i] != 0; }
+  const decltype(Dev::ct_warm) wf;     // the robot's warm-start flags
+  __device__ bool warm(int i) const { return wf[i] != 0; }
 };
 
 // a given dense W (column-major, ld = cap), no warm start
@@ -2243,7 +2242,7 @@ __global__ void __launch_bounds__(NT) update_wide_kernel(Dev d) {
   double* Wr = d.W + cb * d.zp;
   contact_q(d, cb, nc, Wr, qv);
   __syncthreads();
-  const RobotLcpSource src{&d, cb};
+  const RobotLcpSource src{d.ct_warm + cb};
   const LcpWs wl{S.L, S.Rd, S.Yp, S.P, NPW};
   const int code = lcp_wide<SPL>(src, S, wl, Wr + 1, (int)d.zp, qv, nc, y);
   if (threadIdx.x == 0 && code == 2) d.wl[WL_BIG * d.B + atomicAdd(&d.wl_cnt[WL_BIG], 1)] = r;
@@ -2268,7 +2267,7 @@ __global__ void __launch_bounds__(NT) update_big_kernel(Dev d) {
   const double* qv = d.q + cb;                  // written by update_wide_kernel
   double* y = d.ct_y + cb;
   double* Wr = d.W + cb * d.zp;
-  const RobotLcpSource src{&d, cb};
+  const RobotLcpSource src{d.ct_warm + cb};
   if (lcp_wide<SPG>(src, S, global_ws(lcp_ws(d, r), nc), Wr + 1, (int)d.zp, qv, nc, y) != 0) {
     finish(d, r, 2, d.st_it[r], d.st_rn[r]);
     return;
