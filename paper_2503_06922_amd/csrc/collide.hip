@@ -106,19 +106,32 @@ __global__ void __launch_bounds__(256) collide_kernel(Dev d) {
   P3<float> pf{(float)p.x, (float)p.y, (float)p.z};
   // FP32 screen allowance: coordinates ~1 m carry ~1e-7 m of rounding
   const float slack = 1e-5f;
+  // a list entry's triangle and bounding sphere are loaded together, one step ahead: the next
+  // entries are in flight while this lane tests the current one
+  const bool mixed = d.mixed;
+  const float4 no_sf = make_float4(0.f, 0.f, 0.f, -1.f);
+  const double4 no_sd = make_double4(0.0, 0.0, 0.0, -1.0);
+  int32_t t_nx = b0 + j < b1 ? d.cell_tris[b0 + j] : -1;
+  float4 sf_nx = mixed && b0 + j < b1 ? d.cell_sf[b0 + j] : no_sf;
+  double4 sd_nx = !mixed && b0 + j < b1 ? d.cell_sd[b0 + j] : no_sd;
   for (int32_t k0 = b0; k0 < b1; k0 += CL) {
-    const int32_t k = k0 + j;
-    const int32_t t = k < b1 ? d.cell_tris[k] : -1;
+    const int32_t t = t_nx;
+    const float4 Sf = sf_nx;
+    const double4 Sd = sd_nx;
+    {
+      const int32_t k2 = k0 + CL + j;
+      t_nx = k2 < b1 ? d.cell_tris[k2] : -1;
+      sf_nx = mixed && k2 < b1 ? d.cell_sf[k2] : no_sf;
+      sd_nx = !mixed && k2 < b1 ? d.cell_sd[k2] : no_sd;
+    }
     bool near;
-    if (d.mixed) {
-      const float4 S = t >= 0 ? d.cell_sf[k] : make_float4(0.f, 0.f, 0.f, -1.f);
+    if (mixed) {
       const float bf = (float)band + slack;
-      const float sx = pf.x - S.x, sy = pf.y - S.y, sz = pf.z - S.z, rr = S.w + bf;
+      const float sx = pf.x - Sf.x, sy = pf.y - Sf.y, sz = pf.z - Sf.z, rr = Sf.w + bf;
       near = t >= 0 && sx * sx + sy * sy + sz * sz <= rr * rr;
     } else {
-      const double4 S = t >= 0 ? d.cell_sd[k] : make_double4(0.0, 0.0, 0.0, -1.0);
-      const double sx = p.x - S.x, sy = p.y - S.y, sz = p.z - S.z;
-      const double rr = (S.w + band) * (1.0 + 1e-12);
+      const double sx = p.x - Sd.x, sy = p.y - Sd.y, sz = p.z - Sd.z;
+      const double rr = (Sd.w + band) * (1.0 + 1e-12);
       near = t >= 0 && sx * sx + sy * sy + sz * sz <= rr * rr;
     }
     if (near && d.mixed && !screen32(d, t, pf, (float)band, slack)) near = false;
