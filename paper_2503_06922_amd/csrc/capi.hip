@@ -17,6 +17,8 @@ namespace accfem {
 void launch_elem(const Dev& d, hipStream_t s);
 void launch_collide(const Dev& d, hipStream_t s);
 void launch_solve_phase(const Dev& d, int phase, hipStream_t s);
+void launch_lcp_small(const Dev& d, hipStream_t s);
+void launch_lcp_wide(const Dev& d, hipStream_t s);
 void launch_gather(const Dev& d, hipStream_t s);
 void launch_adjoint(const Dev& d, const int32_t* sens, int n_s, const double* dLdp, double* JL,
                     double* JD, double* JU, double* QB, int32_t* KF, double* GP, double* out,
@@ -271,6 +273,10 @@ struct fem_ctx {
   // load-stepping loop: the stream it runs on when the caller gave none, the captured graph
   // of `graph_iters` passes and the Dev it was captured with
   hipStream_t own_stream = nullptr;
+  // a second stream (default priority) and fork/join events: inside a captured pass the
+  // element update runs beside the detection and the LDS LCP beside the wide one
+  hipStream_t side_stream = nullptr;
+  hipEvent_t fork_ev[4] = {nullptr, nullptr, nullptr, nullptr};
   hipGraphExec_t graph_exec = nullptr;
   Dev graph_dev{};
   int graph_iters = 0;
@@ -419,12 +425,28 @@ fem_status autotune(fem_ctx* c, hipStream_t s) {
 }
 
 // one pass of the loop over every robot: load-step advance, element update, detection and
-// the Newton step's phases
-void launch_pass(const Dev& d, hipStream_t s) {
+// the Newton step's phases.  Two pairs of launches are independent and run on two streams
+// (captured as parallel branches of the graph): the element update and the detection (both
+// read the state; their outputs are disjoint), and the LDS LCP and the wide LCP (disjoint
+// robot lists).
+void launch_pass(const Dev& d, hipStream_t s, hipStream_t side, const hipEvent_t* ev) {
   hipLaunchKernelGGL(advance_kernel, dim3(nblk(d.B, 256)), dim3(256), 0, s, d);
-  launch_elem(d, s);
+  (void)hipEventRecord(ev[0], s);
+  (void)hipStreamWaitEvent(side, ev[0], 0);
+  launch_elem(d, side);
   launch_collide(d, s);
-  for (int ph = 0; ph < 5; ++ph) launch_solve_phase(d, ph, s);
+  (void)hipEventRecord(ev[1], side);
+  (void)hipStreamWaitEvent(s, ev[1], 0);
+  for (int ph = 0; ph < 3; ++ph) launch_solve_phase(d, ph, s);
+  if (!d.qp_admm) {
+    (void)hipEventRecord(ev[2], s);
+    (void)hipStreamWaitEvent(side, ev[2], 0);
+    launch_lcp_small(d, side);
+    launch_lcp_wide(d, s);
+    (void)hipEventRecord(ev[3], side);
+    (void)hipStreamWaitEvent(s, ev[3], 0);
+  }
+  launch_solve_phase(d, 4, s);
 }
 
 // Run the n load steps of a call: every robot advances through them on its own (a robot whose
@@ -477,7 +499,7 @@ fem_status run_load_steps(fem_ctx* c, int n) {
       }
       hipGraph_t g = nullptr;
       HIP_TRY(c, hipStreamBeginCapture(xs, hipStreamCaptureModeThreadLocal));
-      for (int k = 0; k < K; ++k) launch_pass(d, xs);
+      for (int k = 0; k < K; ++k) launch_pass(d, xs, c->side_stream, c->fork_ev);
       hipError_t e = hipStreamEndCapture(xs, &g);
       if (e != hipSuccess) return fail(c, FEM_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
       e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
@@ -529,6 +551,9 @@ void fem_destroy(fem_ctx* c) {
   if (c->own_stream) hipStreamSynchronize(c->own_stream);
   if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
   if (c->own_stream) hipStreamDestroy(c->own_stream);
+  if (c->side_stream) hipStreamDestroy(c->side_stream);
+  for (hipEvent_t e : c->fork_ev)
+    if (e) hipEventDestroy(e);
   if (c->h_done) hipHostFree(c->h_done);
   if (c->sched_buf) hipFree(c->sched_buf);
   if (c->rec_buf) hipFree(c->rec_buf);
@@ -769,6 +794,8 @@ static fem_status create_impl(fem_ctx* c, const fem_params* p) {
   }
   HIP_TRY(c, hipHostMalloc((void**)&c->h_done, sizeof(int32_t), hipHostMallocDefault));
   if (!c->stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking));
+  HIP_TRY(c, hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking));
+  for (hipEvent_t& e : c->fork_ev) HIP_TRY(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
   hipLaunchKernelGGL(init_state_kernel, dim3(nblk(N, 256)), dim3(256), 0, c->stream, d, p->r_out,
                      p->r_in, p->E, p->nu, p->tip_len, p->shaft_E, p->shaft_A, p->shaft_I,
                      (const double*)c->length_d, c->kc);

@@ -2652,6 +2652,17 @@ __global__ void __launch_bounds__(WLT) build_lists_kernel(Dev d) {
   }
 }
 
+// phase 3 in two parts on disjoint robot lists, which may run on two streams: the LDS LCP,
+// and the wide LCP followed by its big-set rerun
+void launch_lcp_small(const Dev& d, hipStream_t s) {
+  if (!d.qp_admm) hipLaunchKernelGGL(update_kernel, dim3(d.B), dim3(NT), 0, s, d);
+}
+void launch_lcp_wide(const Dev& d, hipStream_t s) {
+  if (d.qp_admm) return;
+  if (d.cap > LCPM) hipLaunchKernelGGL(update_wide_kernel, dim3(d.B), dim3(NT), 0, s, d);
+  if (d.cap > NPW) hipLaunchKernelGGL(update_big_kernel, dim3(d.B), dim3(NT), 0, s, d);
+}
+
 void launch_solve_phase(const Dev& d, int phase, hipStream_t s) {
   switch (phase) {
     case 0:
@@ -2667,11 +2678,8 @@ void launch_solve_phase(const Dev& d, int phase, hipStream_t s) {
         hipLaunchKernelGGL(subst_kernel, dim3(d.B * ((d.cap + NT) / NT)), dim3(2 * NT), 0, s, d);
       break;
     case 3:
-      if (!d.qp_admm) {
-        hipLaunchKernelGGL(update_kernel, dim3(d.B), dim3(NT), 0, s, d);
-        if (d.cap > LCPM) hipLaunchKernelGGL(update_wide_kernel, dim3(d.B), dim3(NT), 0, s, d);
-        if (d.cap > NPW) hipLaunchKernelGGL(update_big_kernel, dim3(d.B), dim3(NT), 0, s, d);
-      }
+      launch_lcp_small(d, s);
+      launch_lcp_wide(d, s);
       break;
     default:
       if (d.qp_admm)
